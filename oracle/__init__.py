@@ -1,0 +1,327 @@
+"""FP64 CPU oracle for the Convergent-Born-Series (CBS) operator.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The GPU library never
+calls it and shares no code with it.
+
+Everything is plain PyTorch CPU arithmetic in complex128, written to be read
+against the paper:
+
+  * 2D DFT by explicit DFT matrices with the phase index j*n reduced modulo N
+    in exact integer arithmetic (no FFT library);
+  * Fourier pseudospectral reference operator L_eta = -Laplacian - (k0^2 + i eta),
+    symbol lambda_n = |xi_n|^2 - k0^2 - i eta, xi = 2 pi n / N,
+    n in {-N/2, ..., N/2 - 1} (App. E, "Periodic grid and Fourier modes" and
+    "Discrete symbol"; App. D, Helmholtz case);
+  * Green operator G q = F^-1 (F q / lambda) (App. E, the three-step recipe);
+  * potential V = k^2 - k0^2 - i eta (Sec. 3.1 coefficient-only split; App. E);
+  * CBS fixed-point step u <- u + gamma (G (V u + s) - u)  (Sec. 3.1, Eq. CBS)
+    with gamma = i V / eta (the paper only says gamma is derived from V;
+    this is the Osnabrugge et al. 2016 choice cited there);
+  * Born residual r = G (V u + s) - u = G (s - A u)  (Sec. 4.1, Eqs.
+    npbs_integral and npbs_iter);
+  * FGMRES (Saad 1993, cited in Sec. 5.1.3) on B u = G s with B = I - G V
+    (Prop. 3.1) and a flexible right preconditioner of K CBS sweeps;
+  * the metric-matched residual loss (Sec. 4.2) and its gradient by torch
+    autograd through this forward.
+
+Notation: the paper's eta is the damping called eps here.  Fields are
+(N, N) arrays indexed [y, x].
+"""
+from __future__ import annotations
+
+import functools
+import math
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+CDT = torch.complex128
+RDT = torch.float64
+
+
+def as_c(x) -> torch.Tensor:
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(x)
+    return torch.as_tensor(x).to(CDT)
+
+
+# ---------------------------------------------------------------------------
+# Grid, DFT and symbol (App. E)
+# ---------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=32)
+def dft_matrix(n: int) -> torch.Tensor:
+    """F[j, k] = exp(-2 pi i ((j k) mod n) / n); the phase index is reduced
+    exactly in integers before scaling."""
+    j = torch.arange(n, dtype=torch.int64)
+    e = (j[:, None] * j[None, :]) % n
+    ang = (-2.0 * math.pi / n) * e.to(RDT)
+    return torch.polar(torch.ones_like(ang), ang)
+
+
+def dft2(x: torch.Tensor) -> torch.Tensor:
+    """Unnormalised forward 2D DFT along both axes: F x F^T (F is symmetric)."""
+    f = dft_matrix(x.shape[-1])
+    return f @ x @ f
+
+
+def idft2(x: torch.Tensor) -> torch.Tensor:
+    """Inverse 2D DFT: conj(F)/N on both axes."""
+    n = x.shape[-1]
+    fi = dft_matrix(n).conj() / n
+    return fi @ x @ fi
+
+
+def mode_index(n: int) -> torch.Tensor:
+    """Signed Fourier index for DFT bin k: k for k < N/2, k - N otherwise, so
+    the Nyquist bin maps to -N/2 (App. E)."""
+    k = torch.arange(n, dtype=torch.int64)
+    return torch.where(k >= n // 2, k - n, k)
+
+
+def xi_squared(n: int) -> torch.Tensor:
+    """|xi_n|^2 on the (N, N) grid of DFT bins, xi = 2 pi n / N (h = 1)."""
+    m = mode_index(n).to(RDT)
+    xi = 2.0 * math.pi * m / n
+    return xi[:, None] ** 2 + xi[None, :] ** 2
+
+
+def symbol(n: int, k0sq: float, eps: float) -> torch.Tensor:
+    """lambda_n = |xi_n|^2 - (k0^2 + i eps)."""
+    return xi_squared(n).to(CDT) - complex(k0sq, eps)
+
+
+def green(q: torch.Tensor, k0sq: float, eps: float) -> torch.Tensor:
+    """G q = F^-1 (F q / lambda)."""
+    return idft2(dft2(q) / symbol(q.shape[-1], k0sq, eps))
+
+
+def green_adjoint(q: torch.Tensor, k0sq: float, eps: float) -> torch.Tensor:
+    """G^H q = F^-1 (F q / conj(lambda))  (App. D: G = F^-1 Lambda^-1 F)."""
+    return idft2(dft2(q) / symbol(q.shape[-1], k0sq, eps).conj())
+
+
+def laplacian(u: torch.Tensor) -> torch.Tensor:
+    """-Laplacian u = F^-1 (|xi|^2 F u)  (App. E, relation to A)."""
+    return idft2(dft2(u) * xi_squared(u.shape[-1]).to(CDT))
+
+
+# ---------------------------------------------------------------------------
+# Potential, preconditioner and operators (Sec. 3.1, Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def potential(k2, k0sq: float, eps: float) -> torch.Tensor:
+    """V = k^2 - k0^2 - i eps."""
+    return as_c(k2) - complex(k0sq, eps)
+
+
+def gamma(k2, k0sq: float, eps: float) -> torch.Tensor:
+    """gamma = i V / eps."""
+    return 1j * potential(k2, k0sq, eps) / eps
+
+
+def choose_eps(k2, k0sq: float) -> float:
+    """Damping rule used throughout: eps = max over cells of |k^2 - k0^2|
+    (the smallest eps for which the CBS contraction argument holds)."""
+    return float(torch.max(torch.abs(as_c(k2) - k0sq)))
+
+
+def cbs_apply(k2, k0sq, eps, u, s=None) -> torch.Tensor:
+    """y = G (V u + s)."""
+    q = potential(k2, k0sq, eps) * as_c(u)
+    if s is not None:
+        q = q + as_c(s)
+    return green(q, k0sq, eps)
+
+
+def cbs_residual(k2, k0sq, eps, u, s=None, rhs=None) -> torch.Tensor:
+    """Born residual r = G (V u + s) - u (+ rhs)."""
+    r = cbs_apply(k2, k0sq, eps, u, s) - as_c(u)
+    if rhs is not None:
+        r = r + as_c(rhs)
+    return r
+
+
+def cbs_sweep(k2, k0sq, eps, u, s=None, rhs=None) -> torch.Tensor:
+    """One CBS step u + gamma * r(u)."""
+    return as_c(u) + gamma(k2, k0sq, eps) * cbs_residual(k2, k0sq, eps, u, s, rhs)
+
+
+def helmholtz(k2, u) -> torch.Tensor:
+    """A u = -Laplacian u - k^2 u (pseudospectral)."""
+    return laplacian(as_c(u)) - as_c(k2) * as_c(u)
+
+
+def physical_relres(k2, u, s) -> float:
+    """Paper's stopping quantity rTol = ||s - A u|| / ||s||  (Sec. 5)."""
+    s = as_c(s)
+    return float(torch.linalg.vector_norm(s - helmholtz(k2, u)) / torch.linalg.vector_norm(s))
+
+
+def norm(x) -> float:
+    return float(torch.linalg.vector_norm(as_c(x)))
+
+
+def born_relres(k2, k0sq, eps, u, s) -> float:
+    """||G (V u + s) - u|| / ||G s||, the preconditioned relative residual."""
+    return norm(cbs_residual(k2, k0sq, eps, u, s)) / norm(green(as_c(s), k0sq, eps))
+
+
+# ---------------------------------------------------------------------------
+# Stationary CBS (Sec. 3.1, Eq. CBS)
+# ---------------------------------------------------------------------------
+
+def cbs_iterate(k2, k0sq, eps, s, u0=None, max_sweeps: int = 2500, rtol: float = 1e-6,
+                history: bool = False):
+    """Run u <- u + gamma r(u) from u0 (zeros by default) until
+    ||r(u_m)|| / ||G s|| <= rtol.  Returns (u, sweeps, relres[, history]).
+    `sweeps` is the number of updates applied; relres is that of the returned u."""
+    s = as_c(s)
+    u = torch.zeros_like(s) if u0 is None else as_c(u0).clone()
+    g = gamma(k2, k0sq, eps)
+    bnorm = norm(green(s, k0sq, eps))
+    hist = []
+    m = 0
+    while True:
+        r = cbs_residual(k2, k0sq, eps, u, s)
+        rel = norm(r) / bnorm
+        hist.append(rel)
+        if rel <= rtol or m >= max_sweeps or not math.isfinite(rel):
+            break
+        u = u + g * r
+        m += 1
+    if history:
+        return u, m, rel, hist
+    return u, m, rel
+
+
+# ---------------------------------------------------------------------------
+# Dense matrices for tiny grids (brute force pins)
+# ---------------------------------------------------------------------------
+
+def operator_matrix(fn: Callable[[torch.Tensor], torch.Tensor], n: int) -> torch.Tensor:
+    """Dense (n^2, n^2) matrix of a linear map on (n, n) fields (row-major)."""
+    eye = torch.eye(n * n, dtype=CDT).reshape(n * n, n, n)
+    cols = fn(eye).reshape(n * n, n * n)     # row c = fn(e_c)
+    return cols.T.contiguous()
+
+
+def dense_solve(k2, s) -> torch.Tensor:
+    """Exact solution of the pseudospectral system A u = s by LAPACK."""
+    s = as_c(s)
+    n = s.shape[-1]
+    a = operator_matrix(lambda e: helmholtz(k2, e), n)
+    return torch.linalg.solve(a, s.reshape(-1)).reshape(n, n)
+
+
+# ---------------------------------------------------------------------------
+# FGMRES on the Born-preconditioned system (Sec. 5.1.3; Saad 1993)
+# ---------------------------------------------------------------------------
+
+def born_operator(k2, k0sq, eps, x) -> torch.Tensor:
+    """B x = x - G (V x) = G A x  (Prop. 3.1)."""
+    return as_c(x) - cbs_apply(k2, k0sq, eps, x)
+
+
+def cbs_precondition(k2, k0sq, eps, v, sweeps: int) -> torch.Tensor:
+    """P_K(v): K CBS sweeps z <- z + gamma (G V z + v - z) from z = 0, an
+    approximate inverse of B (K = 1 gives z = gamma v)."""
+    z = torch.zeros_like(as_c(v))
+    for _ in range(sweeps):
+        z = cbs_sweep(k2, k0sq, eps, z, None, v)
+    return z
+
+
+def _inner(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    return torch.sum(a.conj() * b)
+
+
+def fgmres(k2, k0sq, eps, s, x0=None, restart: int = 30, sweeps: int = 4,
+           max_iters: int = 2500, rtol: float = 1e-6, history: bool = False):
+    """Flexible GMRES(m) for B x = b, b = G s, right-preconditioned by P_K.
+
+    Classical Gram-Schmidt applied twice (CGS2).  The small least-squares
+    problem min ||beta e1 - H y|| is solved with LAPACK at every step (the
+    definition; no Givens recurrence).  Returns (x, iterations, relres)
+    where relres = ||b - B x|| / ||b|| of the returned x."""
+    s = as_c(s)
+    b = green(s, k0sq, eps)
+    bnorm = norm(b)
+    x = torch.zeros_like(s) if x0 is None else as_c(x0).clone()
+    its = 0
+    hist = []
+    while True:
+        r = b - born_operator(k2, k0sq, eps, x)
+        beta = norm(r)
+        rel = beta / bnorm
+        hist.append(rel)
+        if rel <= rtol or its >= max_iters:
+            break
+        vs = [r / beta]
+        zs = []
+        h = torch.zeros(restart + 1, restart, dtype=CDT)
+        y = None
+        for j in range(restart):
+            z = cbs_precondition(k2, k0sq, eps, vs[j], sweeps)
+            zs.append(z)
+            w = born_operator(k2, k0sq, eps, z)
+            for _ in range(2):
+                coef = torch.stack([_inner(v, w) for v in vs])
+                for i, v in enumerate(vs):
+                    w = w - coef[i] * v
+                h[: j + 1, j] += coef
+            hn = norm(w)
+            h[j + 1, j] = hn
+            its += 1
+            rhs = torch.zeros(j + 2, dtype=CDT)
+            rhs[0] = beta
+            y = torch.linalg.lstsq(h[: j + 2, : j + 1], rhs.unsqueeze(1)).solution.squeeze(1)
+            est = norm(rhs - h[: j + 2, : j + 1] @ y) / bnorm
+            hist.append(est)
+            if est <= rtol or its >= max_iters or hn == 0.0:
+                break
+            vs.append(w / hn)
+        for i in range(len(y)):
+            x = x + y[i] * zs[i]
+    if history:
+        return x, its, rel, hist
+    return x, its, rel
+
+
+# ---------------------------------------------------------------------------
+# Metric-matched loss and its gradient (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+def unrolled_loss(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma",
+                  normalise: bool = False) -> torch.Tensor:
+    """ell = || W * (G s - (I - G V) u_K) ||^2 with u_{m+1} = u_m + gamma r(u_m).
+
+    weight "gamma" uses W = gamma; "one" uses W = 1.  With normalise=True the
+    squared norm is divided by ||G s||^2 (the ratio form of L_bs^{R_eta} with
+    the probe r = s).  eps and k0^2 are constants; k2 and u0 may require grad.
+    """
+    u = as_c(u0) if not torch.is_tensor(u0) else u0
+    for _ in range(steps):
+        u = cbs_sweep(k2, k0sq, eps, u, s)
+    r = cbs_residual(k2, k0sq, eps, u, s)
+    if weight == "gamma":
+        r = gamma(k2, k0sq, eps) * r
+    elif weight != "one":
+        raise ValueError(weight)
+    val = torch.sum(r.real ** 2 + r.imag ** 2)
+    if normalise:
+        g = green(as_c(s), k0sq, eps)
+        val = val / torch.sum(g.real ** 2 + g.imag ** 2)
+    return val
+
+
+def loss_and_grad(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma"):
+    """Returns (loss, dl/du0, dl/dk2) with PyTorch's complex-gradient
+    convention dl/dRe + i dl/dIm, computed by autograd through the oracle."""
+    k2t = as_c(k2).clone().requires_grad_(True)
+    u0t = as_c(u0).clone().requires_grad_(True)
+    val = unrolled_loss(k2t, k0sq, eps, u0t, as_c(s), steps, weight)
+    gu, gk = torch.autograd.grad(val, (u0t, k2t))
+    return float(val.detach()), gu, gk
