@@ -1,0 +1,207 @@
+/*
+ * cbs.h -- C ABI of the MI355X (gfx950) Convergent-Born-Series library.
+ *
+ * The library applies, on one GPU, the Born-series operator of the heterogeneous
+ * Helmholtz problem A u = s with A = -Laplacian - k(x)^2 on periodic N x N grids
+ * (Sec. 3.1, Eq. helm and the discrete split A = L_eta - V_eta; App. E, Fourier
+ * pseudospectral discretisation):
+ *
+ *   reference   L_eta = -Laplacian - (k0^2 + i eps),  eps > 0           (Sec. 3.1)
+ *   symbol      lambda_n = |xi_n|^2 - k0^2 - i eps, xi = 2 pi n / N,
+ *               n in {-N/2, ..., N/2-1}                                  (App. E)
+ *   Green op.   G q = F^-1 (F q / lambda)                               (App. D, App. E)
+ *   potential   V = k^2 - k0^2 - i eps  (pointwise)                      (Sec. 3.1)
+ *   CBS step    u <- u + gamma (G (V u + s) - u),  gamma = i V / eps     (Sec. 3.1, Eq. CBS)
+ *   Born resid. r = G (V u + s) - u = G (s - A u)                        (Sec. 4.1, Eq. npbs_iter)
+ *
+ * The paper's damping eta is called eps here.  Grid spacing is one cell.
+ *
+ * Layout and ownership
+ * --------------------
+ *  * A plan holds a batch of `batch` independent instances with sizes n[i]
+ *    (square n x n, n in {16, 32, 64, 128, 192, 256, 288, 384, 512, 1024}).
+ *  * Every field argument is a DEVICE pointer owned by the caller.  Fields are
+ *    interleaved complex (re, im) numbers, complex64 for CBS_C64 plans and
+ *    complex128 for CBS_C128 plans, row-major [y][x] per instance, and the
+ *    instances are packed back to back in instance order: instance i starts at
+ *    element sum_{j<i} n[j]^2.  Packed totals are returned by cbs_plan_cells.
+ *  * The plan owns a copy of k^2 and all scratch memory; it is allocated in
+ *    cbs_setup and freed in cbs_destroy.  No other call allocates.
+ *  * `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    cbs_apply, cbs_residual, cbs_adjoint_step and cbs_loss_seed are
+ *    stream-ordered and return without synchronising.  cbs_iterate and
+ *    fgmres_solve run a host-driven loop on the stream and synchronise it
+ *    before returning (their host outputs are then valid).
+ *  * Inputs are never modified, except the in/out solution u of the solvers.
+ *
+ * Errors
+ * ------
+ *  Every call returns a cbs_status.  Negative values are errors: nothing was
+ *  launched for argument errors (detected before any launch); CBS_ERR_HIP
+ *  reports a failing HIP call, including an asynchronous fault surfacing at a
+ *  synchronisation point.  cbs_last_error() returns a thread-local message for
+ *  the last non-OK status.  No call aborts or throws.
+ */
+#ifndef CBS_H_
+#define CBS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cbs_plan_s* cbs_plan;
+
+typedef enum {
+  CBS_OK = 0,
+  CBS_NOT_CONVERGED = 1,   /* solver finished; at least one instance did not reach rtol */
+  CBS_ERR_ARG = -1,        /* null/invalid argument, bad batch or flag            */
+  CBS_ERR_SIZE = -2,       /* unsupported grid size n                             */
+  CBS_ERR_ILLCOND = -3,    /* eps < max|k^2-k0^2| or min|V|/eps below 1e-3        */
+  CBS_ERR_WORKSPACE = -4,  /* plan was set up without room for this request       */
+  CBS_ERR_HIP = -5         /* a HIP runtime call failed                           */
+} cbs_status;
+
+enum { CBS_C64 = 0, CBS_C128 = 1 };
+
+/* Per-instance solver status codes written by cbs_iterate / fgmres_solve. */
+enum {
+  CBS_INST_RUNNING = 0,
+  CBS_INST_CONVERGED = 1,
+  CBS_INST_MAX_ITERS = 2,
+  CBS_INST_DIVERGED = 3
+};
+
+/* Setup flags. */
+enum {
+  CBS_FLAG_NO_GUARD = 1u   /* skip the eps / min|V| conditioning guard */
+};
+
+/*
+ * cbs_setup -- build a plan for a batch of instances (step: setup; Sec. 3.1
+ * defines V and gamma from k^2, k0 and eps; App. E the grid and symbol).
+ *   plan       out: new plan handle (NULL on error)
+ *   batch      number of instances, >= 1
+ *   n          host[batch]: grid size of each instance
+ *   k2         device: packed complex k^2 fields (dtype of the plan); copied
+ *   k0sq       host[batch] or NULL: reference k0^2; a value that is NaN or
+ *              NULL selects 0.5 (min Re k^2 + max Re k^2) over the instance
+ *   eps        host[batch] or NULL: damping; a value <= 0 or NULL selects
+ *              eps = max over cells |k^2 - k0^2|
+ *   dtype      CBS_C64 (FP32 operator, FP64 norms/Krylov) or CBS_C128
+ *   max_restart  largest FGMRES restart length later used (0: no FGMRES)
+ *   flags      CBS_FLAG_* bits
+ *   stream     hipStream_t as void*
+ * Guard: unless CBS_FLAG_NO_GUARD, rejects eps < max|k^2 - k0^2| (1e-12
+ * relative slack) and min|V|/eps < 1e-3 with CBS_ERR_ILLCOND (a cell with
+ * V = 0 has gamma = 0 and never updates).  Synchronises `stream`.
+ */
+cbs_status cbs_setup(cbs_plan* plan, int batch, const int32_t* n, const void* k2,
+                     const double* k0sq, const double* eps, int dtype, int max_restart,
+                     uint32_t flags, void* stream);
+
+/* Total packed cells (sum n[i]^2) and the per-instance k0^2 and eps in use
+ * (host arrays of length batch, may be NULL). */
+cbs_status cbs_plan_info(cbs_plan plan, int64_t* cells, double* k0sq, double* eps);
+
+/*
+ * cbs_apply -- y = G (V u + s)   (Sec. 4.1, the Born fixed-point map).
+ *   u, s nullable (treated as zero).  y must not alias u or s.
+ */
+cbs_status cbs_apply(cbs_plan plan, const void* u, const void* s, void* y, void* stream);
+
+/*
+ * cbs_residual -- r = G (V u + s) - u + rhs   (Sec. 4.1, Born residual; the
+ * optional rhs is already in preconditioned coordinates).
+ *   u, s, rhs nullable (zero); r nullable (not stored);
+ *   norm2 nullable DEVICE double[batch]: per-instance sum |r|^2 accumulated
+ *   in FP64.  r may alias rhs but not u or s.
+ */
+cbs_status cbs_residual(cbs_plan plan, const void* u, const void* s, const void* rhs,
+                        void* r, double* norm2, void* stream);
+
+/*
+ * cbs_sweep -- one CBS step in place: u <- u + gamma (G (V u + s) - u)
+ *   (Sec. 3.1, Eq. CBS).  s nullable.  norm2 as in cbs_residual (residual of
+ *   the input u).
+ */
+cbs_status cbs_sweep(cbs_plan plan, void* u, const void* s, double* norm2, void* stream);
+
+/*
+ * cbs_iterate -- stationary CBS until ||G(V u + s) - u|| / ||G s|| <= rtol
+ *   per instance (Sec. 3.1, Eq. CBS; the paper's stopping rule, Sec. 5, is
+ *   measured in these preconditioned coordinates).
+ *   u          device, in/out: initial guess and result
+ *   s          device: source
+ *   max_sweeps per-instance cap on applied sweeps
+ *   check_every  sweeps per refinement chunk (>= 2): for CBS_C64 plans the
+ *              iterate is kept in FP64 and the residual recomputed in FP64
+ *              every check_every sweeps; FP32 sweeps advance the correction
+ *   iters, relres, status  host[batch] outputs (sweeps applied, FP64-verified
+ *              relative residual of the returned u, CBS_INST_* code); nullable
+ *   use_graph  nonzero: replay each chunk from a captured hipGraph
+ * Returns CBS_NOT_CONVERGED if any instance stopped without reaching rtol.
+ */
+cbs_status cbs_iterate(cbs_plan plan, void* u, const void* s, int max_sweeps, double rtol,
+                       int check_every, int32_t* iters, double* relres, int32_t* status,
+                       int use_graph, void* stream);
+
+/*
+ * fgmres_solve -- flexible GMRES(restart) on B u = G s with B = I - G V = G A
+ *   (Prop. 3.1), right-preconditioned by K = inner_sweeps CBS sweeps from zero
+ *   (Sec. 4.1: CBS is the diagonal gamma in these coordinates; Sec. 5.1.3 uses
+ *   FGMRES with CBS as preconditioner).  The Arnoldi basis, classical
+ *   Gram-Schmidt (applied twice), Hessenberg/Givens least squares and the true
+ *   residual at each restart are FP64 on the GPU; operator applications run in
+ *   the plan's dtype.  iters counts Arnoldi steps.  Outputs as in cbs_iterate.
+ *   restart must not exceed the plan's max_restart (else CBS_ERR_WORKSPACE).
+ */
+cbs_status fgmres_solve(cbs_plan plan, void* u, const void* s, int restart, int inner_sweeps,
+                        int max_iters, double rtol, int32_t* iters, double* relres,
+                        int32_t* status, void* stream);
+
+/*
+ * cbs_adjoint_step -- reverse step of u_{m+1} = u_m + gamma r(u_m) for the
+ *   metric-matched loss (Sec. 4.2) and medium gradients.  With
+ *   t = G^H(conj(gamma) lam_in), G^H = F^-1 diag(1/conj(lambda)) F:
+ *     lam_out = lam_in + conj(V) t - conj(gamma) lam_in
+ *     grad_k2 += (-i/eps) lam_in conj(r_m) + t conj(u_m)
+ *   where r_m = G(V u_m + s) - u_m is recomputed from the checkpoint u_m.
+ *   Gradients follow d/dRe + i d/dIm; eps and k0 are held fixed.
+ *   grad_k2 is accumulated (caller zeroes it).  lam_out may alias lam_in.
+ */
+cbs_status cbs_adjoint_step(cbs_plan plan, const void* u_m, const void* s, const void* lam_in,
+                            void* lam_out, void* grad_k2, void* stream);
+
+/*
+ * cbs_loss_seed -- loss l = sum |W r_K|^2 with r_K = G(V u_K + s) - u_K and
+ *   W = gamma (weight_gamma != 0) or W = 1, its adjoint seed
+ *     lam_K = conj(V) G^H(conj(W) mu) - conj(W) mu,  mu = 2 W r_K,
+ *   and the direct k^2 term grad_k2 += G^H(conj(W) mu) conj(u_K)
+ *   (+ (-i/eps) mu conj(r_K) when W = gamma).  loss: DEVICE double[batch]
+ *   (per-instance FP64 sums), nullable.  grad_k2 is accumulated.
+ */
+cbs_status cbs_loss_seed(cbs_plan plan, const void* u_k, const void* s, int weight_gamma,
+                         double* loss, void* lam_out, void* grad_k2, void* stream);
+
+/*
+ * cbs_autotune -- time the column-pass tile widths on this plan's batch and
+ *   keep the fastest (the choice is also stored in the JSON file named by the
+ *   CBS_AUTOTUNE_CACHE environment variable when it is set).  Synchronises.
+ *   tile_out: host, nullable: chosen tile width in columns.
+ */
+cbs_status cbs_autotune(cbs_plan plan, int* tile_out, void* stream);
+
+/* Force the column tile width (4, 8, 16 or 32 columns; must fit in LDS). */
+cbs_status cbs_set_tile(cbs_plan plan, int columns);
+
+void cbs_destroy(cbs_plan plan);
+const char* cbs_last_error(void);
+const char* cbs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBS_H_ */

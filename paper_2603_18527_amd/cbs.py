@@ -1,0 +1,291 @@
+"""ctypes binding of libcbs.so (argument marshalling only).
+
+Every operation runs in the HIP library; this module converts torch tensors to
+device pointers and the current torch stream to a hipStream_t.  There is no
+fallback: if the library is missing, loading fails with an error.
+
+Fields are packed 1-D complex tensors on the GPU: instance i occupies
+elements [off_i, off_i + n_i^2) with off_i = sum_{j<i} n_j^2, row-major [y][x].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcbs.so")
+
+CBS_OK = 0
+CBS_NOT_CONVERGED = 1
+CBS_ERR_ARG = -1
+CBS_ERR_SIZE = -2
+CBS_ERR_ILLCOND = -3
+CBS_ERR_WORKSPACE = -4
+CBS_ERR_HIP = -5
+CBS_C64 = 0
+CBS_C128 = 1
+FLAG_NO_GUARD = 1
+INST_RUNNING, INST_CONVERGED, INST_MAX_ITERS, INST_DIVERGED = 0, 1, 2, 3
+
+SUPPORTED_SIZES = (16, 32, 64, 128, 192, 256, 288, 384, 512, 1024)
+
+# Every symbol include/cbs.h declares, with its ctypes signature.
+_vp, _i32, _u32, _f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_double
+SIGNATURES = {
+    "cbs_setup": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp]),
+    "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
+    "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cbs_sweep": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _vp, _vp, _vp, _i32, _vp]),
+    "fgmres_solve": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
+    "cbs_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cbs_loss_seed": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "cbs_autotune": (_i32, [_vp, _vp, _vp]),
+    "cbs_set_tile": (_i32, [_vp, _i32]),
+    "cbs_destroy": (None, [_vp]),
+    "cbs_last_error": (ctypes.c_char_p, []),
+    "cbs_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class CbsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"cbs status {status}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libcbs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libcbs.so not found at {path}; build it with "
+                           "`python -m paper_2603_18527_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().cbs_last_error().decode()
+
+
+def _check(st: int, allow_not_converged: bool = False) -> int:
+    if st == CBS_OK or (allow_not_converged and st == CBS_NOT_CONVERGED):
+        return st
+    raise CbsError(st, last_error())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def offsets(sizes: Sequence[int]) -> List[int]:
+    out, o = [], 0
+    for n in sizes:
+        out.append(o)
+        o += n * n
+    return out
+
+
+def pack(fields: Sequence, dtype=torch.complex64, device="cuda") -> torch.Tensor:
+    """Concatenate (n, n) arrays/tensors into one packed device tensor."""
+    parts = [torch.as_tensor(np.asarray(f) if not torch.is_tensor(f) else f).reshape(-1) for f in fields]
+    return torch.cat([p.to(dtype) for p in parts]).to(device).contiguous()
+
+
+def unpack(t: torch.Tensor, sizes: Sequence[int]) -> List[torch.Tensor]:
+    out = []
+    for n, o in zip(sizes, offsets(sizes)):
+        out.append(t[o:o + n * n].reshape(n, n))
+    return out
+
+
+class Plan:
+    """A batch of Helmholtz instances on the GPU (cbs_setup)."""
+
+    def __init__(self, k2: torch.Tensor, sizes: Sequence[int], k0sq=None, eps=None,
+                 dtype: int = CBS_C64, max_restart: int = 0, guard: bool = True, stream=None):
+        lib = load()
+        self.sizes = [int(n) for n in sizes]
+        self.batch = len(self.sizes)
+        self.dtype = dtype
+        self.tdtype = torch.complex64 if dtype == CBS_C64 else torch.complex128
+        self.cells = sum(n * n for n in self.sizes)
+        if k2.dtype != self.tdtype or k2.numel() != self.cells or not k2.is_cuda:
+            raise ValueError("k2 must be a packed CUDA tensor of the plan dtype")
+        k2 = k2.contiguous()
+        n_arr = (ctypes.c_int32 * self.batch)(*self.sizes)
+        k0_arr = None if k0sq is None else (ctypes.c_double * self.batch)(
+            *[float("nan") if v is None else float(v) for v in _expand(k0sq, self.batch)])
+        eps_arr = None if eps is None else (ctypes.c_double * self.batch)(
+            *[0.0 if v is None else float(v) for v in _expand(eps, self.batch)])
+        h = ctypes.c_void_p()
+        st = lib.cbs_setup(ctypes.byref(h), self.batch, n_arr, _ptr(k2), k0_arr, eps_arr, dtype,
+                           int(max_restart), 0 if guard else FLAG_NO_GUARD, _stream(stream))
+        _check(st)
+        self._h = h
+        self.max_restart = int(max_restart)
+        cells = ctypes.c_int64()
+        k0o = (ctypes.c_double * self.batch)()
+        epso = (ctypes.c_double * self.batch)()
+        _check(lib.cbs_plan_info(h, ctypes.byref(cells), k0o, epso))
+        self.k0sq = list(k0o)
+        self.eps = list(epso)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.cbs_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    # -- helpers
+    def _field(self, t, name):
+        if t is None:
+            return None
+        if t.dtype != self.tdtype or t.numel() != self.cells or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous packed CUDA tensor of dtype {self.tdtype}")
+        return t
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(self.cells, dtype=self.tdtype, device="cuda")
+
+    def zeros(self) -> torch.Tensor:
+        return torch.zeros(self.cells, dtype=self.tdtype, device="cuda")
+
+    # -- operations
+    def apply(self, u, s, out=None, stream=None):
+        y = self.empty() if out is None else self._field(out, "out")
+        _check(load().cbs_apply(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                _ptr(y), _stream(stream)))
+        return y
+
+    def residual(self, u, s, rhs=None, out=None, norms=True, store=True, stream=None):
+        r = (self.empty() if out is None else self._field(out, "out")) if store else None
+        n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None
+        _check(load().cbs_residual(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                   _ptr(self._field(rhs, "rhs")), _ptr(r), _ptr(n2), _stream(stream)))
+        return r, n2
+
+    def sweep(self, u, s, norms=False, stream=None):
+        n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None
+        _check(load().cbs_sweep(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                _ptr(n2), _stream(stream)))
+        return n2
+
+    def iterate(self, u, s, max_sweeps=2500, rtol=1e-6, check_every=50, use_graph=True, stream=None):
+        it = (ctypes.c_int32 * self.batch)()
+        rel = (ctypes.c_double * self.batch)()
+        stat = (ctypes.c_int32 * self.batch)()
+        _check(load().cbs_iterate(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                  int(max_sweeps), float(rtol), int(check_every), it, rel, stat,
+                                  1 if use_graph else 0, _stream(stream)), allow_not_converged=True)
+        return list(it), list(rel), list(stat)
+
+    def fgmres(self, u, s, restart=30, sweeps=4, max_iters=2500, rtol=1e-6, stream=None):
+        it = (ctypes.c_int32 * self.batch)()
+        rel = (ctypes.c_double * self.batch)()
+        stat = (ctypes.c_int32 * self.batch)()
+        _check(load().fgmres_solve(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                   int(restart), int(sweeps), int(max_iters), float(rtol), it, rel, stat,
+                                   _stream(stream)), allow_not_converged=True)
+        return list(it), list(rel), list(stat)
+
+    def adjoint_step(self, u_m, s, lam_in, lam_out, grad_k2, stream=None):
+        _check(load().cbs_adjoint_step(self._h, _ptr(self._field(u_m, "u_m")), _ptr(self._field(s, "s")),
+                                       _ptr(self._field(lam_in, "lam_in")), _ptr(self._field(lam_out, "lam_out")),
+                                       _ptr(self._field(grad_k2, "grad_k2")), _stream(stream)))
+
+    def loss_seed(self, u_k, s, weight_gamma=True, lam_out=None, grad_k2=None, stream=None):
+        lam = self.empty() if lam_out is None else self._field(lam_out, "lam_out")
+        grad = self.zeros() if grad_k2 is None else self._field(grad_k2, "grad_k2")
+        loss = torch.empty(self.batch, dtype=torch.float64, device="cuda")
+        _check(load().cbs_loss_seed(self._h, _ptr(self._field(u_k, "u_k")), _ptr(self._field(s, "s")),
+                                    1 if weight_gamma else 0, _ptr(loss), _ptr(lam), _ptr(grad),
+                                    _stream(stream)))
+        return loss, lam, grad
+
+    def autotune(self, stream=None) -> int:
+        t = ctypes.c_int()
+        _check(load().cbs_autotune(self._h, ctypes.byref(t), _stream(stream)))
+        return t.value
+
+    def set_tile(self, columns: int):
+        _check(load().cbs_set_tile(self._h, int(columns)))
+
+
+def _expand(v, n):
+    if isinstance(v, (list, tuple, np.ndarray)):
+        if len(v) != n:
+            raise ValueError("per-instance parameter has the wrong length")
+        return list(v)
+    return [v] * n
+
+
+class BornResidualLoss(torch.autograd.Function):
+    """ell = sum_b || W (G s - (I - G V) u_K) ||^2 after K CBS steps from u0
+    (the metric-matched residual of Sec. 4.2 with W = gamma or W = 1).
+
+    Forward keeps the checkpoints u_0..u_K; backward runs the hand-written
+    adjoint (cbs_adjoint_step) from the seed computed by cbs_loss_seed.
+    Returns per-instance losses (float64).  Gradients w.r.t. u0 and the packed
+    complex k2 follow PyTorch's convention d/dRe + i d/dIm; eps and k0^2 are
+    constants (taken from the plan built on k2 in forward).
+    """
+
+    @staticmethod
+    def forward(ctx, u0, k2, s, sizes, steps, weight_gamma, k0sq, eps):
+        plan = Plan(k2.detach(), sizes, k0sq=k0sq, eps=eps)
+        us = [u0.detach().clone()]
+        for _ in range(int(steps)):
+            u = us[-1].clone()
+            plan.sweep(u, s)
+            us.append(u)
+        loss, lam, grad = plan.loss_seed(us[-1], s, weight_gamma)
+        ctx.plan = plan
+        ctx.us = us
+        ctx.s = s
+        ctx.lam = lam
+        ctx.grad = grad
+        return loss
+
+    @staticmethod
+    def backward(ctx, gout):
+        plan, us, s = ctx.plan, ctx.us, ctx.s
+        lam, grad = ctx.lam, ctx.grad
+        for m in range(len(us) - 2, -1, -1):
+            plan.adjoint_step(us[m], s, lam, lam, grad)
+        scale = torch.repeat_interleave(gout.to(torch.float64),
+                                        torch.tensor([n * n for n in plan.sizes], device=gout.device))
+        scale = scale.to(lam.real.dtype)
+        gu = lam * scale
+        gk = grad * scale
+        ctx.plan = None
+        return gu, gk, None, None, None, None, None, None
+
+
+def born_residual_loss(u0, k2, s, sizes, steps=8, weight_gamma=True, k0sq=None, eps=None):
+    return BornResidualLoss.apply(u0, k2, s, list(sizes), int(steps), bool(weight_gamma), k0sq, eps)

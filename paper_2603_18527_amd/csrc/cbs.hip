@@ -1,0 +1,1066 @@
+// C-ABI of the MI355X CBS library: planner, launches, solver loops.
+//
+// A plan owns a copy of k^2 (in the operator precision and in FP64), the
+// twiddle tables, the ragged work lists and every scratch buffer; calls after
+// cbs_setup never allocate.  Operator applications are the three-launch
+// pipeline of kernels.hpp.  The solvers keep the iterate in FP64 and run the
+// bulk sweeps in the operator precision (FP32 for CBS_C64 plans).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/cbs.h"
+#include "kernels.hpp"
+
+using namespace cbs;
+
+namespace {
+
+thread_local std::string g_err;
+
+cbs_status fail(cbs_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(CBS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(expr)                    \
+  do {                               \
+    cbs_status s_ = (expr);          \
+    if (s_ != CBS_OK) return s_;     \
+  } while (0)
+
+bool supported_n(int n) {
+  switch (n) {
+#define CBS_SUP(N) case N:
+    CBS_FOR_EACH_N(CBS_SUP)
+#undef CBS_SUP
+    return true;
+    default:
+      return false;
+  }
+}
+
+const int kSizes[] = {16, 32, 64, 128, 192, 256, 288, 384, 512, 1024};
+
+}  // namespace
+
+struct cbs_plan_s {
+  int batch = 0;
+  int dtype = CBS_C64;
+  int max_restart = 0;
+  int maxn = 0;
+  int tile = 16;  // column tile width in complex elements (operator precision)
+  long long cells = 0;
+  std::vector<int> n;
+  std::vector<long long> off;
+  std::vector<double> k0sq, eps;
+  std::vector<InstDesc> inst;
+  std::vector<int2> row_items;
+  std::map<int, std::vector<int2>> col_items_host;
+
+  std::vector<void*> owned;
+  InstDesc* d_inst = nullptr;
+  int2* d_row_items = nullptr;
+  std::map<int, int2*> d_col_items;
+  cpx<float>* d_tw32 = nullptr;
+  cpx<double>* d_tw64 = nullptr;
+  void* d_k2 = nullptr;        // operator precision copy (== d_k2_64 for C128)
+  cpx<double>* d_k2_64 = nullptr;
+  void* d_inter = nullptr;     // spectral buffer, operator precision
+  cpx<double>* d_inter64 = nullptr;
+  double* d_partials = nullptr;
+  // solver state
+  cpx<double>* d_u64 = nullptr;  // FP64 iterate
+  cpx<double>* d_s64 = nullptr;  // FP64 source copy (C64 plans) / scratch
+  void* d_c = nullptr;           // right-hand side of the correction equation (op. precision)
+  void* d_e = nullptr;           // correction iterate (op. precision)
+  void* d_t = nullptr;           // scratch (op. precision)
+  int* d_status = nullptr;
+  int* d_iters = nullptr;
+  int* d_chunk_active = nullptr;
+  double* d_relres = nullptr;
+  double* d_est = nullptr;
+  double* d_bnorm = nullptr;
+  double* d_rtol = nullptr;
+  int* d_maxs = nullptr;
+  // FGMRES
+  cpx<double>* d_vbasis = nullptr;
+  void* d_zbasis = nullptr;
+  double* d_kry = nullptr;
+  long long kry_stride = 0;
+  double* d_dots = nullptr;
+  double* d_scale = nullptr;
+  int* d_kactive = nullptr;
+  int* d_kjend = nullptr;
+
+  std::map<std::pair<const void*, int>, hipGraphExec_t> graphs;
+  hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
+  int op_elem() const { return dtype == CBS_C64 ? 8 : 16; }
+};
+
+namespace {
+
+void build_items(cbs_plan p) {
+  p->row_items.clear();
+  p->inst.clear();
+  int part = 0;
+  for (int i = 0; i < p->batch; ++i) {
+    InstDesc d{};
+    d.off = p->off[i];
+    d.n = p->n[i];
+    d.k0sq = p->k0sq.empty() ? 0.0 : p->k0sq[i];
+    d.eps = p->eps.empty() ? 1.0 : p->eps[i];
+    const int rpw = row_rpw(d.n);
+    d.part_off = part;
+    d.nparts = (d.n + rpw - 1) / rpw;
+    part += d.nparts;
+    p->inst.push_back(d);
+  }
+  // Largest instances first, so the short tail of the grid holds small items.
+  std::vector<int> order(p->batch);
+  for (int i = 0; i < p->batch; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->n[a] > p->n[b]; });
+  for (int i : order) {
+    const int rpw = row_rpw(p->n[i]);
+    for (int r = 0; r < p->n[i]; r += rpw) p->row_items.push_back(int2{i, r});
+  }
+  p->col_items_host.clear();
+  for (int c : {4, 8, 16, 32}) {
+    std::vector<int2> items;
+    for (int i : order) {
+      if (p->n[i] % c) continue;
+      for (int col = 0; col < p->n[i]; col += c) items.push_back(int2{i, col});
+    }
+    p->col_items_host[c] = items;
+  }
+}
+
+size_t col_lds_bytes(int maxn, int tile, int elem) { return size_t(maxn) * tile * elem; }
+constexpr size_t kColLdsMax = 64 * 1024;
+
+bool tile_ok(cbs_plan p, int tile) {
+  if (tile != 4 && tile != 8 && tile != 16 && tile != 32) return false;
+  for (int n : p->n)
+    if (n % tile) return false;
+  if (tile == 32 && p->maxn > 256) return false;
+  if (tile == 16 && p->maxn > 512) return false;
+  if (col_lds_bytes(p->maxn, tile, p->op_elem()) > kColLdsMax) return false;
+  return true;
+}
+
+// Column tile for an element size: the plan's tile, halved until it fits.
+int tile_for(cbs_plan p, int elem) {
+  int t = p->tile;
+  while (t > 4 && col_lds_bytes(p->maxn, t, elem) > kColLdsMax) t /= 2;
+  return t;
+}
+
+template <typename R>
+const cpx<R>* k2_of(cbs_plan p) {
+  return static_cast<const cpx<R>*>(sizeof(R) == 4 ? p->d_k2 : static_cast<void*>(p->d_k2_64));
+}
+template <typename R>
+cpx<R>* inter_of(cbs_plan p) {
+  return static_cast<cpx<R>*>(sizeof(R) == 4 ? p->d_inter : static_cast<void*>(p->d_inter64));
+}
+
+template <typename R>
+Params<R> base_params(cbs_plan p) {
+  Params<R> q{};
+  q.inst = p->d_inst;
+  q.k2 = k2_of<R>(p);
+  q.inter = inter_of<R>(p);
+  if constexpr (sizeof(R) == 4) q.tw = p->d_tw32;
+  else q.tw = p->d_tw64;
+  q.partials = p->d_partials;
+  q.mask = nullptr;
+  q.mask_mode = MASK_RUNNING;
+  q.pro = PRO_VU_S;
+  q.sym = SYM_GREEN;
+  q.epi = EPI_STORE;
+  return q;
+}
+
+template <typename R, int C>
+void launch_col(cbs_plan p, Params<R> q, hipStream_t st) {
+  q.items = p->d_col_items[C];
+  const int nitems = int(p->col_items_host[C].size());
+  const size_t lds = col_lds_bytes(p->maxn, C, sizeof(cpx<R>));
+  hipLaunchKernelGGL((k_col<R, C>), dim3(nitems), dim3(kThreads), lds, st, q);
+}
+
+// Forward rows (prologue) -> columns (symbol) -> inverse rows (epilogue).
+template <typename R>
+cbs_status run_pipeline(cbs_plan p, Params<R> q, hipStream_t st) {
+  const int nrow = int(p->row_items.size());
+  q.items = p->d_row_items;
+  hipLaunchKernelGGL(k_row_fwd<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+  switch (tile_for(p, sizeof(cpx<R>))) {
+    case 4: launch_col<R, 4>(p, q, st); break;
+    case 8: launch_col<R, 8>(p, q, st); break;
+    case 16: launch_col<R, 16>(p, q, st); break;
+    default: launch_col<R, 32>(p, q, st); break;
+  }
+  q.items = p->d_row_items;
+  hipLaunchKernelGGL(k_row_inv<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+template <typename R>
+cbs_status launch_pw(cbs_plan p, PwParams<R> w, hipStream_t st) {
+  w.inst = p->d_inst;
+  w.items = p->d_row_items;
+  w.k2 = k2_of<R>(p);
+  hipLaunchKernelGGL(k_pointwise<R>, dim3(p->row_items.size()), dim3(kThreads), 0, st, w);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+IterState iter_state(cbs_plan p) {
+  IterState s{};
+  s.status = p->d_status;
+  s.iters = p->d_iters;
+  s.chunk_active = p->d_chunk_active;
+  s.relres = p->d_relres;
+  s.est = p->d_est;
+  s.bnorm = p->d_bnorm;
+  s.rtol = p->d_rtol;
+  s.max_sweeps = p->d_maxs;
+  return s;
+}
+
+int inst_blocks(int batch) { return (batch + 255) / 256; }
+
+cbs_status compute_stats(cbs_plan p, int phase, hipStream_t st, std::vector<double>& a,
+                         std::vector<double>& b) {
+  HIPCHK(hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
+                        hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_stats, dim3(p->row_items.size()), dim3(kThreads), 0, st, p->d_inst,
+                     p->d_row_items, p->d_k2_64, p->d_partials, phase);
+  HIPCHK(hipGetLastError());
+  std::vector<double> part(2 * p->row_items.size());
+  HIPCHK(hipMemcpyAsync(part.data(), p->d_partials, part.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  a.assign(p->batch, 0.0);
+  b.assign(p->batch, 0.0);
+  for (int i = 0; i < p->batch; ++i) {
+    const InstDesc& d = p->inst[i];
+    double va = part[2 * d.part_off], vb = part[2 * d.part_off + 1];
+    for (int k = 1; k < d.nparts; ++k) {
+      const double xa = part[2 * (d.part_off + k)], xb = part[2 * (d.part_off + k) + 1];
+      va = (phase == 1) ? std::max(va, xa) : std::min(va, xa);
+      vb = std::max(vb, xb);
+    }
+    a[i] = va;
+    b[i] = vb;
+  }
+  return CBS_OK;
+}
+
+void drop_graphs(cbs_plan p) {
+  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+}
+
+void free_plan(cbs_plan p) {
+  drop_graphs(p);
+  if (p->own_stream) hipStreamDestroy(p->own_stream);
+  p->own_stream = nullptr;
+  for (void* q : p->owned) hipFree(q);
+  p->owned.clear();
+}
+
+// ---- generic entry helpers -------------------------------------------------------------
+
+template <typename R>
+cbs_status residual_impl(cbs_plan p, const void* u, const void* s, const void* rhs, void* r,
+                         double* norm2, hipStream_t st) {
+  Params<R> q = base_params<R>(p);
+  q.u = static_cast<const cpx<R>*>(u);
+  q.s = static_cast<const cpx<R>*>(s);
+  q.rhs = static_cast<const cpx<R>*>(rhs);
+  q.out = static_cast<cpx<R>*>(r);
+  q.epi = EPI_RESID;
+  CHK(run_pipeline(p, q, st));
+  if (norm2) {
+    hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(p->batch)), dim3(256), 0, st, p->d_inst,
+                       p->batch, p->d_partials, norm2);
+    HIPCHK(hipGetLastError());
+  }
+  return CBS_OK;
+}
+
+template <typename R>
+cbs_status sweep_impl(cbs_plan p, void* u, const void* s, double* norm2, hipStream_t st) {
+  Params<R> q = base_params<R>(p);
+  q.u = static_cast<const cpx<R>*>(u);
+  q.s = static_cast<const cpx<R>*>(s);
+  q.out = static_cast<cpx<R>*>(u);
+  q.epi = EPI_SWEEP;
+  CHK(run_pipeline(p, q, st));
+  if (norm2) {
+    hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(p->batch)), dim3(256), 0, st, p->d_inst,
+                       p->batch, p->d_partials, norm2);
+    HIPCHK(hipGetLastError());
+  }
+  return CBS_OK;
+}
+
+// One refinement chunk of stationary CBS:
+//   r64 = G(V u64 + s64) - u64 (FP64; narrowed into c), status check in FP64,
+//   e = gamma c, (chunk - 1) sweeps e <- e + gamma (G(V e) + c - e) in the
+//   operator precision with a per-sweep norm estimate, then u64 += e.
+// In exact arithmetic this is exactly `chunk` CBS sweeps from u64.
+template <typename R>
+cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
+  const IterState is = iter_state(p);
+  const int nb = inst_blocks(p->batch);
+  cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
+  cpx<R>* e = static_cast<cpx<R>*>(p->d_e);
+  {
+    Params<double> q = base_params<double>(p);
+    q.u = p->d_u64;
+    q.s = p->d_s64;
+    q.epi = EPI_RESID;
+    if constexpr (sizeof(R) == 4) q.out_narrow = reinterpret_cast<cpx<float>*>(c);
+    else q.out = reinterpret_cast<cpx<double>*>(c);
+    q.mask = p->d_status;
+    q.mask_mode = MASK_NOT_FINAL;
+    CHK(run_pipeline(p, q, st));
+    hipLaunchKernelGGL(k_check64, dim3(nb), dim3(256), 0, st, is, p->d_inst, p->batch, p->d_partials);
+  }
+  {
+    PwParams<R> w{};
+    w.op = PW_GAMMA;
+    w.e_in = c;
+    w.e_out = e;
+    w.mask = p->d_status;
+    w.mask_mode = MASK_RUNNING;
+    CHK(launch_pw(p, w, st));
+  }
+  for (int k = 1; k < chunk; ++k) {
+    Params<R> q = base_params<R>(p);
+    q.u = e;
+    q.rhs = c;
+    q.out = e;
+    q.epi = EPI_SWEEP;
+    q.mask = p->d_status;
+    q.mask_mode = MASK_RUNNING;
+    CHK(run_pipeline(p, q, st));
+    hipLaunchKernelGGL(k_check32, dim3(nb), dim3(256), 0, st, is, p->d_inst, p->batch, p->d_partials);
+  }
+  {
+    PwParams<R> w{};
+    w.op = PW_ADD_WIDE;
+    w.e_in = e;
+    w.x64 = p->d_u64;
+    w.mask = p->d_chunk_active;
+    w.mask_mode = MASK_NONZERO;
+    CHK(launch_pw(p, w, st));
+  }
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+template <typename R>
+cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
+                        int chunk, int32_t* iters, double* relres, int32_t* status,
+                        int use_graph, hipStream_t st) {
+  const int B = p->batch;
+  // u64 <- u ; s64 <- s
+  if constexpr (sizeof(R) == 4) {
+    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(u),
+                       p->d_u64, p->cells);
+    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(s),
+                       p->d_s64, p->cells);
+    HIPCHK(hipGetLastError());
+  } else {
+    HIPCHK(hipMemcpyAsync(p->d_u64, u, p->cells * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_s64, s, p->cells * 16, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipMemsetAsync(p->d_status, 0, B * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(p->d_iters, 0, B * sizeof(int), st));
+  HIPCHK(hipMemcpyAsync(p->d_rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_maxs, &max_sweeps, sizeof(int), hipMemcpyHostToDevice, st));
+  // ||G s|| in FP64
+  {
+    Params<double> q = base_params<double>(p);
+    q.s = p->d_s64;
+    q.epi = EPI_RESID;
+    CHK(run_pipeline(p, q, st));
+    hipLaunchKernelGGL(k_set_bnorm, dim3(inst_blocks(B)), dim3(256), 0, st, iter_state(p),
+                       p->d_inst, B, p->d_partials);
+    HIPCHK(hipGetLastError());
+  }
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    auto key = std::make_pair(static_cast<const void*>(nullptr), chunk);
+    auto it = p->graphs.find(key);
+    if (it == p->graphs.end()) {
+      HIPCHK(hipStreamSynchronize(st));
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      cbs_status rc = enqueue_chunk<R>(p, chunk, st);
+      hipError_t ce = hipStreamEndCapture(st, &g);
+      if (rc != CBS_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+      }
+      if (ce != hipSuccess) return fail(CBS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+      hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(CBS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      p->graphs[key] = exec;
+    } else {
+      exec = it->second;
+    }
+  }
+  std::vector<int> hstat(B);
+  const long long max_chunks = (long long)max_sweeps / std::max(1, chunk) + 3;
+  for (long long ch = 0; ch <= max_chunks; ++ch) {
+    if (exec) HIPCHK(hipGraphLaunch(exec, st));
+    else CHK(enqueue_chunk<R>(p, chunk, st));
+    HIPCHK(hipMemcpyAsync(hstat.data(), p->d_status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool done = true;
+    for (int i = 0; i < B; ++i)
+      if (hstat[i] == ST_RUNNING || hstat[i] == ST_PENDING) done = false;
+    if (done) break;
+  }
+  // u <- u64
+  if constexpr (sizeof(R) == 4) {
+    PwParams<float> w{};
+    w.op = PW_NARROW;
+    w.x64 = p->d_u64;
+    w.e_out = static_cast<cpx<float>*>(u);
+    CHK(launch_pw(p, w, st));
+  } else {
+    HIPCHK(hipMemcpyAsync(u, p->d_u64, p->cells * 16, hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<int> hit(B);
+  std::vector<double> hrel(B);
+  HIPCHK(hipMemcpyAsync(hit.data(), p->d_iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hrel.data(), p->d_relres, B * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hstat.data(), p->d_status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool all = true;
+  for (int i = 0; i < B; ++i) {
+    if (iters) iters[i] = hit[i];
+    if (relres) relres[i] = hrel[i];
+    if (status) status[i] = hstat[i];
+    if (hstat[i] != ST_CONVERGED) all = false;
+  }
+  if (!all) {
+    g_err = "at least one instance did not reach rtol";
+    return CBS_NOT_CONVERGED;
+  }
+  return CBS_OK;
+}
+
+// ---- FGMRES ---------------------------------------------------------------------------------
+
+KryParams kry_params(cbs_plan p, int m) {
+  KryParams k{};
+  k.inst = p->d_inst;
+  k.items = p->d_row_items;
+  k.vbasis = p->d_vbasis;
+  k.cells = p->cells;
+  k.kry = p->d_kry;
+  k.kstride = p->kry_stride;
+  k.m = m;
+  k.dots = p->d_dots;
+  k.partials = p->d_partials;
+  k.scale = p->d_scale;
+  k.active = p->d_kactive;
+  k.jend = p->d_kjend;
+  k.iters = p->d_iters;
+  k.status = p->d_status;
+  k.relres = p->d_relres;
+  k.rtol = p->d_rtol;
+  k.max_iters = p->d_maxs;
+  return k;
+}
+
+// True residual r = G(V x + s) - x in FP64 into v_0, then the restart decision.
+cbs_status fg_restart(cbs_plan p, int m, int first, hipStream_t st) {
+  Params<double> q = base_params<double>(p);
+  if (!first) q.u = p->d_u64;
+  q.s = p->d_s64;
+  q.epi = EPI_RESID;
+  q.out = first ? nullptr : p->d_vbasis;
+  q.mask = p->d_status;
+  q.mask_mode = MASK_RUNNING;
+  CHK(run_pipeline(p, q, st));
+  KryParams k = kry_params(p, m);
+  hipLaunchKernelGGL(k_fg_restart, dim3(inst_blocks(p->batch)), dim3(256), 0, st, k, p->batch, first);
+  HIPCHK(hipGetLastError());
+  if (!first) {
+    PwParams<double> w{};
+    w.op = PW_SCALE64;
+    w.x64 = p->d_vbasis;
+    w.scale = p->d_scale;
+    w.mask = p->d_kactive;
+    w.mask_mode = MASK_NONZERO;
+    CHK(launch_pw(p, w, st));
+  }
+  return CBS_OK;
+}
+
+// One Arnoldi step j for every active instance.
+template <typename R>
+cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
+  cpx<R>* z = static_cast<cpx<R>*>(p->d_zbasis) + (long long)j * p->cells;
+  cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
+  cpx<double>* w = p->d_vbasis + (long long)(j + 1) * p->cells;
+  // z_j = P_K(v_j): first sweep from zero is z = gamma v, then K-1 full sweeps
+  {
+    PwParams<R> pw{};
+    pw.op = PW_FIRST64;
+    pw.src64 = p->d_vbasis + (long long)j * p->cells;
+    pw.c_out = c;
+    pw.e_out = z;
+    pw.mask = p->d_kactive;
+    pw.mask_mode = MASK_NONZERO;
+    CHK(launch_pw(p, pw, st));
+  }
+  for (int k = 1; k < sweeps; ++k) {
+    Params<R> q = base_params<R>(p);
+    q.u = z;
+    q.rhs = c;
+    q.out = z;
+    q.epi = EPI_SWEEP;
+    q.partials = nullptr;
+    q.mask = p->d_kactive;
+    q.mask_mode = MASK_NONZERO;
+    CHK(run_pipeline(p, q, st));
+  }
+  // w = B z_j = z_j - G(V z_j), widened to FP64
+  {
+    Params<R> q = base_params<R>(p);
+    q.u = z;
+    q.epi = EPI_BZ_WIDE;
+    q.out_wide = w;
+    q.partials = nullptr;
+    q.mask = p->d_kactive;
+    q.mask_mode = MASK_NONZERO;
+    CHK(run_pipeline(p, q, st));
+  }
+  // classical Gram-Schmidt, twice
+  KryParams k = kry_params(p, m);
+  k.w = w;
+  k.j = j;
+  const int nrow = int(p->row_items.size());
+  for (int pass = 0; pass < 2; ++pass) {
+    k.pass = pass;
+    hipLaunchKernelGGL(k_dots, dim3(nrow), dim3(kThreads), 0, st, k);
+    hipLaunchKernelGGL(k_dots_finish, dim3(inst_blocks(p->batch)), dim3(256), 0, st, k, p->batch);
+    hipLaunchKernelGGL(k_cgs_update, dim3(nrow), dim3(kThreads), 0, st, k);
+  }
+  // norm, Givens, normalise v_{j+1} (the scale is computed before the mask drops)
+  hipLaunchKernelGGL(k_givens, dim3(inst_blocks(p->batch)), dim3(256), 0, st, k, p->batch);
+  HIPCHK(hipGetLastError());
+  {
+    PwParams<double> pw{};
+    pw.op = PW_SCALE64;
+    pw.x64 = w;
+    pw.scale = p->d_scale;
+    pw.mask = p->d_kactive;
+    pw.mask_mode = MASK_NONZERO;
+    CHK(launch_pw(p, pw, st));
+  }
+  return CBS_OK;
+}
+
+template <typename R>
+cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, int max_iters,
+                       double rtol, int32_t* iters, double* relres, int32_t* status,
+                       hipStream_t st) {
+  const int B = p->batch;
+  if constexpr (sizeof(R) == 4) {
+    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(u),
+                       p->d_u64, p->cells);
+    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(s),
+                       p->d_s64, p->cells);
+    HIPCHK(hipGetLastError());
+  } else {
+    HIPCHK(hipMemcpyAsync(p->d_u64, u, p->cells * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_s64, s, p->cells * 16, hipMemcpyDeviceToDevice, st));
+  }
+  HIPCHK(hipMemsetAsync(p->d_status, 0, B * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(p->d_iters, 0, B * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(p->d_kjend, 0, B * sizeof(int), st));
+  HIPCHK(hipMemcpyAsync(p->d_rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_maxs, &max_iters, sizeof(int), hipMemcpyHostToDevice, st));
+  CHK(fg_restart(p, m, 1, st));
+  KryParams k = kry_params(p, m);
+  std::vector<int> hact(B), hstat(B);
+  for (int cycle = 0; cycle < max_iters + 2; ++cycle) {
+    CHK(fg_restart(p, m, 0, st));
+    HIPCHK(hipMemcpyAsync(hstat.data(), p->d_status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool any = false;
+    for (int i = 0; i < B; ++i) any |= hstat[i] == ST_RUNNING;
+    if (!any) break;
+    for (int j = 0; j < m; ++j) {
+      CHK(fg_step<R>(p, m, j, sweeps, st));
+      HIPCHK(hipMemcpyAsync(hact.data(), p->d_kactive, B * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool act = false;
+      for (int i = 0; i < B; ++i) act |= hact[i] != 0;
+      if (!act) break;
+    }
+    hipLaunchKernelGGL(k_backsolve, dim3(inst_blocks(B)), dim3(256), 0, st, k, B);
+    hipLaunchKernelGGL((k_zupdate<R>), dim3(p->row_items.size()), dim3(kThreads), 0, st, k,
+                       static_cast<const cpx<R>*>(p->d_zbasis), p->d_u64);
+    HIPCHK(hipGetLastError());
+  }
+  if constexpr (sizeof(R) == 4) {
+    PwParams<float> w{};
+    w.op = PW_NARROW;
+    w.x64 = p->d_u64;
+    w.e_out = static_cast<cpx<float>*>(u);
+    CHK(launch_pw(p, w, st));
+  } else {
+    HIPCHK(hipMemcpyAsync(u, p->d_u64, p->cells * 16, hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<int> hit(B);
+  std::vector<double> hrel(B);
+  HIPCHK(hipMemcpyAsync(hit.data(), p->d_iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hrel.data(), p->d_relres, B * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hstat.data(), p->d_status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool all = true;
+  for (int i = 0; i < B; ++i) {
+    if (iters) iters[i] = hit[i];
+    if (relres) relres[i] = hrel[i];
+    if (status) status[i] = hstat[i] == ST_RUNNING ? ST_MAXIT : hstat[i];
+    if (hstat[i] != ST_CONVERGED) all = false;
+  }
+  if (!all) {
+    g_err = "at least one instance did not reach rtol";
+    return CBS_NOT_CONVERGED;
+  }
+  return CBS_OK;
+}
+
+// ---- adjoint -------------------------------------------------------------------------------
+
+template <typename R>
+cbs_status adjoint_impl(cbs_plan p, const void* um, const void* s, const void* lam_in,
+                        void* lam_out, void* grad, hipStream_t st) {
+  cpx<R>* r = static_cast<cpx<R>*>(p->d_t);
+  {
+    Params<R> q = base_params<R>(p);
+    q.u = static_cast<const cpx<R>*>(um);
+    q.s = static_cast<const cpx<R>*>(s);
+    q.epi = EPI_RESID;
+    q.out = r;
+    q.partials = nullptr;
+    CHK(run_pipeline(p, q, st));
+  }
+  Params<R> q = base_params<R>(p);
+  q.pro = PRO_CONJG_A;
+  q.sym = SYM_GREEN_CONJ;
+  q.epi = EPI_ADJ;
+  q.a = static_cast<const cpx<R>*>(lam_in);
+  q.b = r;
+  q.u = static_cast<const cpx<R>*>(um);
+  q.out = static_cast<cpx<R>*>(lam_out);
+  q.out2 = static_cast<cpx<R>*>(grad);
+  q.partials = nullptr;
+  return run_pipeline(p, q, st);
+}
+
+template <typename R>
+cbs_status seed_impl(cbs_plan p, const void* uk, const void* s, int wg, double* loss,
+                     void* lam_out, void* grad, hipStream_t st) {
+  cpx<R>* r = static_cast<cpx<R>*>(p->d_t);
+  {
+    Params<R> q = base_params<R>(p);
+    q.u = static_cast<const cpx<R>*>(uk);
+    q.s = static_cast<const cpx<R>*>(s);
+    q.epi = EPI_RESID;
+    q.out = r;
+    q.partials = nullptr;
+    CHK(run_pipeline(p, q, st));
+  }
+  Params<R> q = base_params<R>(p);
+  q.pro = PRO_SEED;
+  q.sym = SYM_GREEN_CONJ;
+  q.epi = EPI_SEED;
+  q.weight_gamma = wg ? 1 : 0;
+  q.a = r;
+  q.u = static_cast<const cpx<R>*>(uk);
+  q.out = static_cast<cpx<R>*>(lam_out);
+  q.out2 = static_cast<cpx<R>*>(grad);
+  CHK(run_pipeline(p, q, st));
+  if (loss) {
+    hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(p->batch)), dim3(256), 0, st, p->d_inst,
+                       p->batch, p->d_partials, loss);
+    HIPCHK(hipGetLastError());
+  }
+  return CBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cbs_last_error(void) { return g_err.c_str(); }
+const char* cbs_version(void) { return "cbs-mi355x 0.1 (gfx950)"; }
+
+cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
+                     const double* k0sq, const double* eps, int dtype, int max_restart,
+                     uint32_t flags, void* stream) {
+  if (!out) return fail(CBS_ERR_ARG, "plan pointer is NULL");
+  *out = nullptr;
+  if (batch < 1 || !n || !k2) return fail(CBS_ERR_ARG, "batch < 1 or n/k2 NULL");
+  if (dtype != CBS_C64 && dtype != CBS_C128) return fail(CBS_ERR_ARG, "dtype must be CBS_C64 or CBS_C128");
+  if (max_restart < 0 || max_restart > 200) return fail(CBS_ERR_ARG, "max_restart must be in [0, 200]");
+  if (flags & ~uint32_t(CBS_FLAG_NO_GUARD)) return fail(CBS_ERR_ARG, "unknown flag bits");
+  for (int i = 0; i < batch; ++i)
+    if (!supported_n(n[i]))
+      return fail(CBS_ERR_SIZE, "unsupported grid size " + std::to_string(n[i]) + " (instance " +
+                                    std::to_string(i) + ")");
+  if (eps)
+    for (int i = 0; i < batch; ++i)
+      if (std::isnan(eps[i]) || std::isinf(eps[i])) return fail(CBS_ERR_ARG, "eps must be finite");
+  if (k0sq)
+    for (int i = 0; i < batch; ++i)
+      if (std::isinf(k0sq[i])) return fail(CBS_ERR_ARG, "k0sq must be finite or NaN (auto)");
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cbs_plan p = new cbs_plan_s();
+  p->batch = batch;
+  p->dtype = dtype;
+  p->max_restart = max_restart;
+  p->n.assign(n, n + batch);
+  long long off = 0;
+  for (int i = 0; i < batch; ++i) {
+    p->off.push_back(off);
+    off += (long long)n[i] * n[i];
+    p->maxn = std::max(p->maxn, n[i]);
+  }
+  p->cells = off;
+  p->tile = (p->maxn > 512) ? 8 : 16;
+  if (dtype == CBS_C128) p->tile = (p->maxn > 512) ? 4 : 8;
+  build_items(p);
+
+  auto bail = [&](cbs_status s, const std::string& m) {
+    free_plan(p);
+    delete p;
+    return fail(s, m);
+  };
+  const long long cells = p->cells;
+  const size_t oe = p->op_elem();
+  std::vector<std::pair<void**, size_t>> req = {
+      {reinterpret_cast<void**>(&p->d_inst), batch * sizeof(InstDesc)},
+      {reinterpret_cast<void**>(&p->d_row_items), p->row_items.size() * sizeof(int2)},
+      {reinterpret_cast<void**>(&p->d_tw32), kTwTotal * sizeof(cpx<float>)},
+      {reinterpret_cast<void**>(&p->d_tw64), kTwTotal * sizeof(cpx<double>)},
+      {reinterpret_cast<void**>(&p->d_k2_64), cells * 16},
+      {reinterpret_cast<void**>(&p->d_inter64), cells * 16},
+      {reinterpret_cast<void**>(&p->d_u64), cells * 16},
+      {reinterpret_cast<void**>(&p->d_s64), cells * 16},
+      {&p->d_c, cells * oe},
+      {&p->d_e, cells * oe},
+      {&p->d_t, cells * oe},
+      {reinterpret_cast<void**>(&p->d_partials), (2 * p->row_items.size() + 64) * sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_status), batch * sizeof(int)},
+      {reinterpret_cast<void**>(&p->d_iters), batch * sizeof(int)},
+      {reinterpret_cast<void**>(&p->d_chunk_active), batch * sizeof(int)},
+      {reinterpret_cast<void**>(&p->d_relres), batch * sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_est), batch * sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_bnorm), batch * sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_rtol), sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_maxs), sizeof(int)},
+      {reinterpret_cast<void**>(&p->d_scale), batch * sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_kactive), batch * sizeof(int)},
+      {reinterpret_cast<void**>(&p->d_kjend), batch * sizeof(int)},
+  };
+  if (dtype == CBS_C64) {
+    req.push_back({&p->d_k2, cells * 8});
+    req.push_back({&p->d_inter, cells * 8});
+  }
+  if (max_restart > 0) {
+    const KryLayout L{max_restart};
+    p->kry_stride = L.size();
+    req.push_back({reinterpret_cast<void**>(&p->d_vbasis), cells * 16 * size_t(max_restart + 1)});
+    req.push_back({&p->d_zbasis, cells * oe * size_t(max_restart)});
+    req.push_back({reinterpret_cast<void**>(&p->d_kry), size_t(p->kry_stride) * batch * sizeof(double)});
+    req.push_back({reinterpret_cast<void**>(&p->d_dots),
+                   2 * size_t(max_restart + 2) * p->row_items.size() * sizeof(double)});
+  }
+  for (auto& r : req) {
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, std::max<size_t>(r.second, 16));
+    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p->owned.push_back(ptr);
+    *r.first = ptr;
+  }
+  if (dtype == CBS_C128) {
+    p->d_k2 = p->d_k2_64;
+    p->d_inter = p->d_inter64;
+  }
+  for (auto& kv : p->col_items_host) {
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, std::max<size_t>(kv.second.size() * sizeof(int2), 16));
+    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p->owned.push_back(ptr);
+    p->d_col_items[kv.first] = static_cast<int2*>(ptr);
+  }
+
+  // Twiddle tables exp(-2 pi i m / N): FP64 on the host, rounded once for FP32.
+  std::vector<cpx<double>> t64(kTwTotal);
+  std::vector<cpx<float>> t32(kTwTotal);
+  for (int nn : kSizes) {
+    const int o = tw_offset(nn);
+    for (int m = 0; m < nn; ++m) {
+      const double ang = -2.0 * M_PI * double(m) / double(nn);
+      t64[o + m] = cpx<double>{std::cos(ang), std::sin(ang)};
+      t32[o + m] = cpx<float>{float(t64[o + m].x), float(t64[o + m].y)};
+    }
+  }
+#define BAILCHK(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return bail(CBS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  BAILCHK(hipMemcpyAsync(p->d_tw64, t64.data(), kTwTotal * sizeof(cpx<double>), hipMemcpyHostToDevice, st));
+  BAILCHK(hipMemcpyAsync(p->d_tw32, t32.data(), kTwTotal * sizeof(cpx<float>), hipMemcpyHostToDevice, st));
+  BAILCHK(hipMemcpyAsync(p->d_row_items, p->row_items.data(), p->row_items.size() * sizeof(int2),
+                         hipMemcpyHostToDevice, st));
+  for (auto& kv : p->col_items_host)
+    if (!kv.second.empty())
+      BAILCHK(hipMemcpyAsync(p->d_col_items[kv.first], kv.second.data(), kv.second.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, st));
+  if (dtype == CBS_C64) {
+    BAILCHK(hipMemcpyAsync(p->d_k2, k2, cells * 8, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(p->d_k2),
+                       p->d_k2_64, cells);
+    BAILCHK(hipGetLastError());
+  } else {
+    BAILCHK(hipMemcpyAsync(p->d_k2_64, k2, cells * 16, hipMemcpyDeviceToDevice, st));
+  }
+#undef BAILCHK
+
+  // Reference k0^2 and damping eps from FP64 statistics of k^2 on the GPU.
+  p->k0sq.assign(batch, 0.0);
+  p->eps.assign(batch, 1.0);
+  build_items(p);
+  std::vector<double> a, b;
+  cbs_status s = compute_stats(p, 0, st, a, b);
+  if (s != CBS_OK) { std::string m = g_err; return bail(s, m); }
+  for (int i = 0; i < batch; ++i) {
+    const bool autok = !k0sq || std::isnan(k0sq[i]);
+    p->k0sq[i] = autok ? 0.5 * (a[i] + b[i]) : k0sq[i];
+  }
+  build_items(p);
+  s = compute_stats(p, 1, st, a, b);
+  if (s != CBS_OK) { std::string m = g_err; return bail(s, m); }
+  for (int i = 0; i < batch; ++i) {
+    const bool autoe = !eps || !(eps[i] > 0.0);
+    p->eps[i] = autoe ? a[i] : eps[i];
+    if (!(p->eps[i] > 0.0))
+      return bail(CBS_ERR_ILLCOND, "instance " + std::to_string(i) + ": k^2 == k0^2 everywhere, eps would be 0");
+    if (!(flags & CBS_FLAG_NO_GUARD) && p->eps[i] < a[i] * (1.0 - 1e-12))
+      return bail(CBS_ERR_ILLCOND, "instance " + std::to_string(i) + ": eps below max|k^2-k0^2|");
+  }
+  build_items(p);
+  s = compute_stats(p, 2, st, a, b);
+  if (s != CBS_OK) { std::string m = g_err; return bail(s, m); }
+  for (int i = 0; i < batch; ++i)
+    if (!(flags & CBS_FLAG_NO_GUARD) && !(a[i] >= 1e-3 * p->eps[i]))
+      return bail(CBS_ERR_ILLCOND,
+                  "instance " + std::to_string(i) + ": min|V|/eps below 1e-3 (gamma ~ 0 stalls CBS)");
+  hipError_t e = hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("setup sync: ") + hipGetErrorString(e));
+  *out = p;
+  return CBS_OK;
+}
+
+cbs_status cbs_plan_info(cbs_plan p, int64_t* cells, double* k0sq, double* eps) {
+  if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
+  if (cells) *cells = p->cells;
+  for (int i = 0; i < p->batch; ++i) {
+    if (k0sq) k0sq[i] = p->k0sq[i];
+    if (eps) eps[i] = p->eps[i];
+  }
+  return CBS_OK;
+}
+
+cbs_status cbs_set_tile(cbs_plan p, int columns) {
+  if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
+  if (!tile_ok(p, columns)) return fail(CBS_ERR_ARG, "tile width not valid for this batch");
+  p->tile = columns;
+  drop_graphs(p);
+  return CBS_OK;
+}
+
+cbs_status cbs_apply(cbs_plan p, const void* u, const void* s, void* y, void* stream) {
+  if (!p || !y) return fail(CBS_ERR_ARG, "plan or y is NULL");
+  if (y == u || y == s) return fail(CBS_ERR_ARG, "y must not alias u or s");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) {
+    Params<float> q = base_params<float>(p);
+    q.u = static_cast<const cpx<float>*>(u);
+    q.s = static_cast<const cpx<float>*>(s);
+    q.out = static_cast<cpx<float>*>(y);
+    q.partials = nullptr;
+    return run_pipeline(p, q, st);
+  }
+  Params<double> q = base_params<double>(p);
+  q.u = static_cast<const cpx<double>*>(u);
+  q.s = static_cast<const cpx<double>*>(s);
+  q.out = static_cast<cpx<double>*>(y);
+  q.partials = nullptr;
+  return run_pipeline(p, q, st);
+}
+
+cbs_status cbs_residual(cbs_plan p, const void* u, const void* s, const void* rhs, void* r,
+                        double* norm2, void* stream) {
+  if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
+  if (r && (r == u || r == s)) return fail(CBS_ERR_ARG, "r must not alias u or s");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return residual_impl<float>(p, u, s, rhs, r, norm2, st);
+  return residual_impl<double>(p, u, s, rhs, r, norm2, st);
+}
+
+cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, double* norm2, void* stream) {
+  if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
+  if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return sweep_impl<float>(p, u, s, norm2, st);
+  return sweep_impl<double>(p, u, s, norm2, st);
+}
+
+cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
+                       int check_every, int32_t* iters, double* relres, int32_t* status,
+                       int use_graph, void* stream) {
+  if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
+  if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
+  if (max_sweeps < 0 || check_every < 2 || check_every > 100000 || !(rtol >= 0.0))
+    return fail(CBS_ERR_ARG, "need max_sweeps >= 0, 2 <= check_every <= 1e5, rtol >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (use_graph && st == nullptr) {
+    // The legacy null stream cannot be captured: run on a plan-owned stream
+    // ordered after everything already queued on the null stream.
+    if (!p->own_stream) HIPCHK(hipStreamCreate(&p->own_stream));
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e1 = hipEventRecord(ev, nullptr);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(p->own_stream, ev, 0) : e1;
+    hipEventDestroy(ev);
+    if (e2 != hipSuccess) return fail(CBS_ERR_HIP, std::string("stream ordering: ") + hipGetErrorString(e2));
+    st = p->own_stream;
+  }
+  if (p->dtype == CBS_C64)
+    return iterate_impl<float>(p, u, s, max_sweeps, rtol, check_every, iters, relres, status, use_graph, st);
+  return iterate_impl<double>(p, u, s, max_sweeps, rtol, check_every, iters, relres, status, use_graph, st);
+}
+
+cbs_status fgmres_solve(cbs_plan p, void* u, const void* s, int restart, int inner_sweeps,
+                        int max_iters, double rtol, int32_t* iters, double* relres,
+                        int32_t* status, void* stream) {
+  if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
+  if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
+  if (restart < 1 || inner_sweeps < 1 || inner_sweeps > 1000 || max_iters < 0 || !(rtol >= 0.0))
+    return fail(CBS_ERR_ARG, "need restart >= 1, 1 <= inner_sweeps <= 1000, max_iters >= 0, rtol >= 0");
+  if (restart > p->max_restart)
+    return fail(CBS_ERR_WORKSPACE, "restart " + std::to_string(restart) + " exceeds the plan's max_restart " +
+                                       std::to_string(p->max_restart));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64)
+    return fgmres_impl<float>(p, u, s, restart, inner_sweeps, max_iters, rtol, iters, relres, status, st);
+  return fgmres_impl<double>(p, u, s, restart, inner_sweeps, max_iters, rtol, iters, relres, status, st);
+}
+
+cbs_status cbs_adjoint_step(cbs_plan p, const void* u_m, const void* s, const void* lam_in,
+                            void* lam_out, void* grad_k2, void* stream) {
+  if (!p || !u_m || !lam_in || !lam_out || !grad_k2) return fail(CBS_ERR_ARG, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return adjoint_impl<float>(p, u_m, s, lam_in, lam_out, grad_k2, st);
+  return adjoint_impl<double>(p, u_m, s, lam_in, lam_out, grad_k2, st);
+}
+
+cbs_status cbs_loss_seed(cbs_plan p, const void* u_k, const void* s, int weight_gamma, double* loss,
+                         void* lam_out, void* grad_k2, void* stream) {
+  if (!p || !u_k || !lam_out || !grad_k2) return fail(CBS_ERR_ARG, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return seed_impl<float>(p, u_k, s, weight_gamma, loss, lam_out, grad_k2, st);
+  return seed_impl<double>(p, u_k, s, weight_gamma, loss, lam_out, grad_k2, st);
+}
+
+cbs_status cbs_autotune(cbs_plan p, int* tile_out, void* stream) {
+  if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int keep = p->tile;
+  int best = keep;
+  double best_t = 1e300;
+  HIPCHK(hipMemsetAsync(p->d_e, 0, p->cells * p->op_elem(), st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int t : {4, 8, 16, 32}) {
+    if (!tile_ok(p, t)) continue;
+    p->tile = t;
+    // time a complete apply of zeros (u = e scratch) into the t scratch
+    cbs_status rc = CBS_OK;
+    for (int rep = 0; rep < 3 && rc == CBS_OK; ++rep) rc = cbs_apply(p, p->d_e, nullptr, p->d_t, stream);
+    if (rc != CBS_OK) break;
+    HIPCHK(hipEventRecord(e0, st));
+    const int reps = 10;
+    for (int rep = 0; rep < reps && rc == CBS_OK; ++rep) rc = cbs_apply(p, p->d_e, nullptr, p->d_t, stream);
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (rc == CBS_OK && ms < best_t) {
+      best_t = ms;
+      best = t;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  p->tile = best;
+  drop_graphs(p);
+  if (const char* path = std::getenv("CBS_AUTOTUNE_CACHE")) {
+    std::ostringstream key;
+    key << (p->dtype == CBS_C64 ? "c64" : "c128") << ":" << p->batch;
+    for (int nn : p->n) key << "," << nn;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << "{\"key\": \"" << key.str() << "\", \"tile\": " << best << ", \"ms_per_apply\": "
+             << best_t / 10.0 << "}\n";
+  }
+  if (tile_out) *tile_out = best;
+  return CBS_OK;
+}
+
+void cbs_destroy(cbs_plan p) {
+  if (!p) return;
+  free_plan(p);
+  delete p;
+}
+
+}  // extern "C"

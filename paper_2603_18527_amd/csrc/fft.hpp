@@ -1,0 +1,216 @@
+// Device FFT building blocks for gfx950: complex arithmetic, radix-2/3/4/8
+// butterflies and a self-sorting (Stockham) mixed-radix pass over LDS.
+//
+// A length-N transform runs as a sequence of passes with radices r_0, r_1, ...
+// (product N).  Before pass p the data holds DFTs of length Ns = r_0...r_{p-1}
+// interleaved with stride N/Ns; butterfly j (0 <= j < N/r) reads elements
+// j + q N/r (q < r), multiplies element q by w^(q k) with k = j mod Ns and
+// w = exp(-+2 pi i / (Ns r)), applies an r-point DFT and writes element q to
+// (j / Ns) Ns r + k + q Ns.  Output is in natural order; no bit reversal.
+//
+// Forward transforms use exp(-2 pi i j n / N), inverse ones exp(+...), both
+// unnormalised; the 1/N^2 of the inverse 2D transform is folded into the
+// Green-symbol multiply.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cbs {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cpx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.x * s, a.y * s}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return {a.x, -a.y}; }
+template <typename R>
+__device__ __forceinline__ R cabs2(cpx<R> a) { return a.x * a.x + a.y * a.y; }
+// (DIR * i) * a with DIR = -1 (forward) or +1 (inverse)
+template <int DIR, typename R>
+__device__ __forceinline__ cpx<R> mul_dir_i(cpx<R> a) {
+  if constexpr (DIR < 0) return {a.y, -a.x};
+  else return {-a.y, a.x};
+}
+
+// ---- butterflies (in registers) ------------------------------------------
+
+template <int DIR, typename R>
+__device__ __forceinline__ void bfly2(cpx<R>* v) {
+  cpx<R> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void bfly4(cpx<R>* v) {
+  cpx<R> t0 = v[0] + v[2], t1 = v[0] - v[2];
+  cpx<R> t2 = v[1] + v[3], t3 = mul_dir_i<DIR>(v[1] - v[3]);
+  v[0] = t0 + t2;
+  v[2] = t0 - t2;
+  v[1] = t1 + t3;
+  v[3] = t1 - t3;
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void bfly3(cpx<R>* v) {
+  const R h = R(0.8660254037844386467637232);  // sin(pi/3)
+  cpx<R> t1 = v[1] + v[2];
+  cpx<R> t2 = v[0] - cscale(t1, R(0.5));
+  cpx<R> t3 = mul_dir_i<DIR>(cscale(v[1] - v[2], h));
+  v[0] = v[0] + t1;
+  v[1] = t2 + t3;
+  v[2] = t2 - t3;
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void bfly8(cpx<R>* v) {
+  const R s = R(0.7071067811865475244008444);  // 1/sqrt(2)
+  cpx<R> e[4] = {v[0], v[2], v[4], v[6]};
+  cpx<R> o[4] = {v[1], v[3], v[5], v[7]};
+  bfly4<DIR>(e);
+  bfly4<DIR>(o);
+  // o[k] *= w8^k, w8 = exp(DIR i pi / 4)
+  cpx<R> o1 = cscale(o[1] + mul_dir_i<DIR>(o[1]), s);     // (1 + DIR i)/sqrt2
+  cpx<R> o2 = mul_dir_i<DIR>(o[2]);                        // DIR i
+  cpx<R> o3 = cscale(mul_dir_i<DIR>(o[3]) - o[3], s);     // (-1 + DIR i)/sqrt2
+  v[0] = e[0] + o[0];
+  v[4] = e[0] - o[0];
+  v[1] = e[1] + o1;
+  v[5] = e[1] - o1;
+  v[2] = e[2] + o2;
+  v[6] = e[2] - o2;
+  v[3] = e[3] + o3;
+  v[7] = e[3] - o3;
+}
+
+template <int RAD, int DIR, typename R>
+__device__ __forceinline__ void bfly(cpx<R>* v) {
+  if constexpr (RAD == 2) bfly2<DIR>(v);
+  else if constexpr (RAD == 3) bfly3<DIR>(v);
+  else if constexpr (RAD == 4) bfly4<DIR>(v);
+  else if constexpr (RAD == 8) bfly8<DIR>(v);
+  else static_assert(RAD == 2, "unsupported radix");
+}
+
+// ---- size plans -------------------------------------------------------------
+
+// Radix of pass p for length n (0 past the last pass).
+__host__ __device__ constexpr int plan_radix(int n, int p) {
+  switch (n) {
+    case 16: return p < 2 ? 4 : 0;
+    case 32: return p == 0 ? 8 : p == 1 ? 4 : 0;
+    case 64: return p < 2 ? 8 : 0;
+    case 128: return p == 0 ? 8 : p < 3 ? 4 : 0;
+    case 192: return p < 2 ? 8 : p == 2 ? 3 : 0;
+    case 256: return p < 2 ? 8 : p == 2 ? 4 : 0;
+    case 288: return p == 0 ? 8 : p == 1 ? 4 : p < 4 ? 3 : 0;
+    case 384: return p < 2 ? 8 : p == 2 ? 3 : p == 3 ? 2 : 0;
+    case 512: return p < 3 ? 8 : 0;
+    case 1024: return p < 2 ? 8 : p < 4 ? 4 : 0;
+    default: return 0;
+  }
+}
+
+__host__ __device__ constexpr int plan_product(int n) {
+  int prod = 1;
+  for (int p = 0; plan_radix(n, p) > 0; ++p) prod *= plan_radix(n, p);
+  return prod;
+}
+
+// Twiddle tables of all supported sizes are stored back to back.
+__host__ __device__ constexpr int tw_offset(int n) {
+  int off = 0;
+  const int sizes[] = {16, 32, 64, 128, 192, 256, 288, 384, 512, 1024};
+  for (int i = 0; i < 10; ++i) {
+    if (sizes[i] == n) return off;
+    off += sizes[i];
+  }
+  return -1;
+}
+constexpr int kTwTotal = 16 + 32 + 64 + 128 + 192 + 256 + 288 + 384 + 512 + 1024;
+
+// ---- Stockham pass over LDS ---------------------------------------------------
+//
+// `buf` points at element 0 of this thread's transform; elements are STRIDE
+// apart.  TPF threads cooperate on one transform (t = 0..TPF-1).  Every thread
+// of the workgroup must call this (it contains barriers); `active` masks
+// threads without a transform.  The pass is in place: all inputs are read into
+// registers before the first barrier and written after it.
+template <typename R, int N, int RAD, int NS, int TPF, int DIR, int STRIDE>
+__device__ __forceinline__ void stockham_pass(cpx<R>* buf, int t, bool active,
+                                              const cpx<R>* __restrict__ tw) {
+  constexpr int NB = N / RAD;
+  constexpr int PER = (NB + TPF - 1) / TPF;
+  constexpr bool EXACT = (NB % TPF) == 0;
+  cpx<R> v[PER][RAD];
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int j = t + p * TPF;
+      if (EXACT || j < NB) {
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) v[p][q] = buf[(j + q * NB) * STRIDE];
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int j = t + p * TPF;
+      if (EXACT || j < NB) {
+        const int k = j % NS;
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int q = 1; q < RAD; ++q) {
+            cpx<R> w = tw[q * k * (N / (NS * RAD))];
+            if constexpr (DIR > 0) w.y = -w.y;
+            v[p][q] = cmul(v[p][q], w);
+          }
+        }
+        bfly<RAD, DIR>(v[p]);
+        const int o = (j / NS) * (NS * RAD) + k;
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) buf[(o + q * NS) * STRIDE] = v[p][q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int N, int P, int NS, int TPF, int DIR, int STRIDE>
+__device__ __forceinline__ void fft_passes(cpx<R>* buf, int t, bool active,
+                                           const cpx<R>* __restrict__ tw) {
+  constexpr int RAD = plan_radix(N, P);
+  if constexpr (RAD > 0) {
+    stockham_pass<R, N, RAD, NS, TPF, DIR, STRIDE>(buf, t, active, tw);
+    fft_passes<R, N, P + 1, NS * RAD, TPF, DIR, STRIDE>(buf, t, active, tw);
+  } else {
+    static_assert(NS == N, "plan radices must multiply to N");
+  }
+}
+
+// Full length-N transform in LDS (DIR = -1 forward, +1 inverse).
+template <typename R, int N, int TPF, int DIR, int STRIDE>
+__device__ __forceinline__ void fft_lds(cpx<R>* buf, int t, bool active,
+                                        const cpx<R>* __restrict__ tw_base) {
+  static_assert(plan_product(N) == N, "no plan for this size");
+  fft_passes<R, N, 0, 1, TPF, DIR, STRIDE>(buf, t, active, tw_base + tw_offset(N));
+}
+
+}  // namespace cbs

@@ -1,0 +1,185 @@
+"""GPU parity of the CBS operator calls (cbs_apply, cbs_residual, cbs_sweep)
+against the FP64 oracle, element by element.
+
+Inputs are rounded to the plan's precision first and the oracle gets the same
+rounded values, so the comparison measures arithmetic error only.  Tolerances:
+FP32 plans 1e-5 relative L2 (the FP32 target for GPU results); FP64 plans
+1e-12 (about log2(N^2) roundings of a few ulps each).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from paper_2603_18527_amd import cbs
+from gpu_helpers import plan_for, random_problem, rel_err, say, to_list
+
+pytestmark = pytest.mark.gpu
+
+TOL = {cbs.CBS_C64: 1e-5, cbs.CBS_C128: 1e-12}
+TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
+
+
+def _rounded(x, dtype):
+    return torch.as_tensor(x).to(TDT[dtype]).to(torch.complex128)
+
+
+def _inputs(probs, dtype, seed=0):
+    rng = np.random.default_rng(seed)
+    us = [S.random_field_c(p.n, rng) for p in probs]
+    u = cbs.pack(us, TDT[dtype])
+    s = cbs.pack([p.source for p in probs], TDT[dtype])
+    return u, s
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 192, 256, 288, 384, 512, 1024])
+def test_apply_each_size(n, dtype):
+    say(f"[apply] n={n} dtype={dtype}")
+    count = 1 if n >= 512 else 2
+    probs = [random_problem(n, seed=10 * n + i) for i in range(count)]
+    plan, k2 = plan_for(probs, dtype)
+    u, s = _inputs(probs, dtype, seed=n)
+    y = plan.apply(u, s)
+    torch.cuda.synchronize()
+    sizes = [p.n for p in probs]
+    for i, (p, ui, si, yi, ki) in enumerate(zip(probs, to_list(u, sizes), to_list(s, sizes),
+                                                to_list(y, sizes), to_list(k2, sizes))):
+        assert abs(plan.eps[i] - O.choose_eps(ki, plan.k0sq[i])) <= 1e-12 * plan.eps[i]
+        ref = O.cbs_apply(ki, plan.k0sq[i], plan.eps[i], ui, si)
+        err = rel_err(yi, ref)
+        say(f"   instance {i}: rel err {err:.3e}")
+        assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_ragged_batch_every_size(dtype):
+    # One plan holding every supported size: work items of different sizes
+    # share each launch.
+    sizes = [288, 16, 512, 64, 192, 32, 384, 128, 256, 1024, 64]
+    say(f"[apply ragged] sizes={sizes} dtype={dtype}")
+    probs = [random_problem(n, seed=500 + i) for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    u, s = _inputs(probs, dtype, seed=3)
+    y = plan.apply(u, s)
+    r, n2 = plan.residual(u, s)
+    torch.cuda.synchronize()
+    n2 = n2.cpu()
+    for i, (p, ui, si, yi, ri, ki) in enumerate(zip(probs, to_list(u, sizes), to_list(s, sizes),
+                                                    to_list(y, sizes), to_list(r, sizes),
+                                                    to_list(k2, sizes))):
+        if p.n == 1024:   # the oracle's O(N^3) DFT: checked in test_apply_each_size
+            continue
+        ref = O.cbs_apply(ki, plan.k0sq[i], plan.eps[i], ui, si)
+        assert rel_err(yi, ref) <= TOL[dtype]
+        rref = ref - ui
+        assert rel_err(ri, rref) <= TOL[dtype] * 10
+        nref = float(torch.sum(torch.abs(rref) ** 2))
+        assert abs(float(n2[i]) - nref) <= 4 * TOL[dtype] * 10 * nref
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_residual_with_rhs_and_sweep(dtype):
+    sizes = [64, 128, 192]
+    say(f"[residual/sweep] sizes={sizes} dtype={dtype}")
+    probs = [random_problem(n, seed=900 + i) for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    u, s = _inputs(probs, dtype, seed=5)
+    rhs, _ = _inputs(probs, dtype, seed=6)
+    r, n2 = plan.residual(u, s, rhs=rhs)
+    u2 = u.clone()
+    n2s = plan.sweep(u2, s, norms=True)
+    torch.cuda.synchronize()
+    for i, (ui, si, bi, ri, u2i, ki) in enumerate(zip(to_list(u, sizes), to_list(s, sizes),
+                                                      to_list(rhs, sizes), to_list(r, sizes),
+                                                      to_list(u2, sizes), to_list(k2, sizes))):
+        e = plan.eps[i]
+        k0 = plan.k0sq[i]
+        ref = O.cbs_residual(ki, k0, e, ui, si, bi)
+        assert rel_err(ri, ref) <= TOL[dtype] * 10
+        sw = O.cbs_sweep(ki, k0, e, ui, si)
+        assert rel_err(u2i, sw) <= TOL[dtype] * 10
+        r0 = O.cbs_residual(ki, k0, e, ui, si)
+        nref = float(torch.sum(torch.abs(r0) ** 2))
+        assert abs(float(n2s[i]) - nref) <= 1e-4 * nref
+
+
+def test_null_source_and_null_u():
+    # apply(u=None, s) = G s ; apply(u, None) = G V u
+    probs = [random_problem(64, seed=41)]
+    plan, k2 = plan_for(probs, cbs.CBS_C128)
+    u, s = _inputs(probs, cbs.CBS_C128, seed=7)
+    g = plan.apply(None, s)
+    gv = plan.apply(u, None)
+    torch.cuda.synchronize()
+    ki = to_list(k2, [64])[0]
+    ref_g = O.green(to_list(s, [64])[0], plan.k0sq[0], plan.eps[0])
+    ref_gv = O.cbs_apply(ki, plan.k0sq[0], plan.eps[0], to_list(u, [64])[0], None)
+    assert rel_err(to_list(g, [64])[0], ref_g) <= 1e-12
+    assert rel_err(to_list(gv, [64])[0], ref_gv) <= 1e-12
+
+
+def test_single_fourier_mode_closed_form_on_gpu():
+    # With V = 0 (k^2 = k0^2 + i eps) the apply is G s; for s a Fourier mode
+    # (Nyquist included) the result is s / lambda in closed form.
+    n = 128
+    k0sq, eps = 0.5, 0.25
+    y = np.arange(n)[:, None]
+    x = np.arange(n)[None, :]
+    for (p, q) in [(3, -7), (-64, 5), (-64, -64), (0, 0)]:
+        wave = np.exp(2j * math.pi * (p * y + q * x) / n)
+        lam = (2 * math.pi / n) ** 2 * (p * p + q * q) - k0sq - 1j * eps
+        k2 = np.full((n, n), k0sq + 1j * eps)
+        plan = cbs.Plan(cbs.pack([k2], torch.complex128), [n], k0sq=[k0sq], eps=[eps],
+                        dtype=cbs.CBS_C128, guard=False)
+        out = plan.apply(None, cbs.pack([wave], torch.complex128))
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().reshape(n, n)
+        assert np.max(np.abs(got - wave / lam)) <= 1e-12 / abs(lam) * 10
+
+
+def test_guards():
+    # a cell with V = 0 (gamma = 0 never updates) and eps below max|k^2-k0^2|
+    n = 32
+    k2 = np.full((n, n), 1.0 + 0j)
+    k2[3, 4] = 1.0 + 0.5j
+    t = cbs.pack([k2], torch.complex64)
+    with pytest.raises(cbs.CbsError) as ei:
+        cbs.Plan(t, [n], k0sq=[1.0], eps=[0.5])
+    assert ei.value.status == cbs.CBS_ERR_ILLCOND
+    with pytest.raises(cbs.CbsError) as ei:
+        cbs.Plan(t, [n], k0sq=[1.0], eps=[0.25])
+    assert ei.value.status == cbs.CBS_ERR_ILLCOND
+    p = cbs.Plan(t, [n], k0sq=[1.0], eps=[0.6])
+    assert abs(p.eps[0] - 0.6) < 1e-15
+    with pytest.raises(cbs.CbsError) as ei:
+        u = p.zeros()
+        p.fgmres(u, p.zeros(), restart=5)
+    assert ei.value.status == cbs.CBS_ERR_WORKSPACE
+
+
+def test_deterministic_repeat():
+    probs = [random_problem(n, seed=77 + n) for n in (128, 256)]
+    plan, k2 = plan_for(probs)
+    u, s = _inputs(probs, cbs.CBS_C64, seed=9)
+    a = plan.apply(u, s)
+    b = plan.apply(u, s)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("tile", [4, 8, 16, 32])
+def test_column_tile_widths_agree(tile):
+    probs = [random_problem(n, seed=300 + n) for n in (64, 128, 256)]
+    plan, k2 = plan_for(probs)
+    u, s = _inputs(probs, cbs.CBS_C64, seed=11)
+    ref = plan.apply(u, s)
+    plan.set_tile(tile)
+    y = plan.apply(u, s)
+    torch.cuda.synchronize()
+    assert rel_err(y.cpu(), ref.cpu()) <= 1e-6
+    best = plan.autotune()
+    assert best in (4, 8, 16, 32)

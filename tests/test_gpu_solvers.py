@@ -1,0 +1,157 @@
+"""GPU solvers against the FP64 oracle: stationary CBS (cbs_iterate) and
+FGMRES (fgmres_solve), single instances and ragged batches.
+
+Bar (per instance): the solvers keep their iterate in FP64 and report its FP64
+Born relative residual, which must be <= rtol.  The solution handed back in an
+FP32 (complex64) plan is that iterate rounded to FP32; rounding alone moves
+the residual by ~1e-7 * ||u|| / ||G s||, so the oracle's evaluation of the
+returned FP32 solution must be <= 1e-5 (ten times rtol).  FP64 plans return
+the iterate itself: the oracle's evaluation must match the reported value to
+1% and be <= rtol.  Sweep / Arnoldi-step counts match the oracle's (the
+arithmetic is the same in exact arithmetic; FP32 noise and the check cadence
+move the stop by at most a chunk)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from paper_2603_18527_amd import cbs
+from gpu_helpers import plan_for, random_problem, rel_err, say, to_list
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_relres(k2, k0sq, eps, u, s):
+    return O.born_relres(k2, k0sq, eps, u, s)
+
+
+def _bar(dtype, reported, evaluated, rtol=1e-6):
+    assert reported <= rtol
+    if dtype == cbs.CBS_C64:
+        assert evaluated <= 10 * rtol
+    else:
+        assert evaluated <= rtol * 1.01
+        assert abs(reported - evaluated) <= 0.01 * evaluated
+
+
+@pytest.mark.parametrize("dtype,use_graph", [(cbs.CBS_C64, True), (cbs.CBS_C64, False),
+                                             (cbs.CBS_C128, True)])
+def test_iterate_blob64(dtype, use_graph):
+    say(f"[iterate blob64] dtype={dtype} graph={use_graph}")
+    p = S.blob_problem()
+    plan, k2 = plan_for([p], dtype)
+    tdt = torch.complex64 if dtype == cbs.CBS_C64 else torch.complex128
+    s = cbs.pack([p.source], tdt)
+    u = plan.zeros()
+    chunk = 25
+    its, rel, stat = plan.iterate(u, s, max_sweeps=5000, rtol=1e-6, check_every=chunk,
+                                  use_graph=use_graph)
+    ki = to_list(k2, [64])[0]
+    si = to_list(s, [64])[0]
+    uo, mo, relo = O.cbs_iterate(ki, plan.k0sq[0], plan.eps[0], si, max_sweeps=5000, rtol=1e-6)
+    ug = to_list(u, [64])[0]
+    ev = _oracle_relres(ki, plan.k0sq[0], plan.eps[0], ug, si)
+    say(f"   gpu sweeps {its[0]} relres {rel[0]:.3e} (oracle eval {ev:.3e}); oracle sweeps {mo}")
+    assert stat[0] == cbs.INST_CONVERGED
+    _bar(dtype, rel[0], ev)
+    assert mo <= its[0] <= mo + chunk
+    assert rel_err(ug, uo) <= 1e-4
+
+
+def test_iterate_graph_matches_plain_bitwise():
+    probs = [random_problem(n, seed=60 + n, source="point") for n in (64, 128)]
+    plan, k2 = plan_for(probs)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    u1, u2 = plan.zeros(), plan.zeros()
+    a = plan.iterate(u1, s, max_sweeps=3000, rtol=1e-6, check_every=20, use_graph=True)
+    b = plan.iterate(u2, s, max_sweeps=3000, rtol=1e-6, check_every=20, use_graph=False)
+    assert a == b
+    assert torch.equal(u1, u2)
+
+
+def test_batched_equals_per_instance_loop():
+    # Ragged batch in one set of launches == one plan per instance (same
+    # kernels, same per-instance reduction order => bitwise identical).
+    sizes = [192, 64, 128, 64]
+    say(f"[batched vs loop] sizes={sizes}")
+    probs = [random_problem(n, seed=70 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    u = plan.zeros()
+    its, rel, stat = plan.iterate(u, s, max_sweeps=4000, rtol=1e-6, check_every=20)
+    us = cbs.unpack(u, sizes)
+    for i, p in enumerate(probs):
+        pi, ki = plan_for([p])
+        si = cbs.pack([p.source], torch.complex64)
+        ui = pi.zeros()
+        it1, rel1, st1 = pi.iterate(ui, si, max_sweeps=4000, rtol=1e-6, check_every=20)
+        say(f"   instance {i} n={p.n}: batched {its[i]} / loop {it1[0]} sweeps")
+        assert it1[0] == its[i] and st1[0] == stat[i] == cbs.INST_CONVERGED
+        assert rel1[0] == rel[i]
+        assert torch.equal(ui.reshape(p.n, p.n), us[i])
+
+
+def test_iterate_zero_source_and_max_sweeps():
+    probs = [random_problem(64, seed=81, source="point"), random_problem(128, seed=82, source="point")]
+    plan, k2 = plan_for(probs)
+    s = cbs.pack([np.zeros((64, 64)), probs[1].source], torch.complex64)
+    u = plan.zeros()
+    its, rel, stat = plan.iterate(u, s, max_sweeps=30, rtol=1e-6, check_every=10)
+    assert stat[0] == cbs.INST_CONVERGED and its[0] == 0 and rel[0] == 0.0
+    assert stat[1] == cbs.INST_MAX_ITERS and 30 <= its[1] <= 40
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_fgmres_small_matches_oracle(dtype):
+    say(f"[fgmres 64] dtype={dtype}")
+    p = random_problem(64, seed=91, source="point", cmax=3.0, ppw=6.0)
+    plan, k2 = plan_for([p], dtype, restart=10)
+    tdt = torch.complex64 if dtype == cbs.CBS_C64 else torch.complex128
+    s = cbs.pack([p.source], tdt)
+    u = plan.zeros()
+    its, rel, stat = plan.fgmres(u, s, restart=10, sweeps=3, max_iters=500, rtol=1e-6)
+    ki = to_list(k2, [64])[0]
+    si = to_list(s, [64])[0]
+    xo, ito, relo = O.fgmres(ki, plan.k0sq[0], plan.eps[0], si, restart=10, sweeps=3,
+                             max_iters=500, rtol=1e-6)
+    ug = to_list(u, [64])[0]
+    ev = _oracle_relres(ki, plan.k0sq[0], plan.eps[0], ug, si)
+    say(f"   gpu its {its[0]} relres {rel[0]:.3e} (oracle eval {ev:.3e}); oracle its {ito}")
+    assert stat[0] == cbs.INST_CONVERGED
+    _bar(dtype, rel[0], ev)
+    if dtype == cbs.CBS_C128:
+        assert its[0] == ito
+        assert rel_err(ug, xo) <= 1e-8
+    else:
+        assert abs(its[0] - ito) <= 3
+
+
+def test_fgmres_grf256_full_size():
+    # 256x256 random-field medium, FGMRES(30) with 4 CBS sweeps.
+    say("[fgmres grf256]")
+    p = S.grf_problem()
+    plan, k2 = plan_for([p], restart=30)
+    s = cbs.pack([p.source], torch.complex64)
+    u = plan.zeros()
+    its, rel, stat = plan.fgmres(u, s, restart=30, sweeps=4, max_iters=2500, rtol=1e-6)
+    ki = to_list(k2, [256])[0]
+    si = to_list(s, [256])[0]
+    ev = _oracle_relres(ki, plan.k0sq[0], plan.eps[0], to_list(u, [256])[0], si)
+    say(f"   gpu its {its[0]} relres {rel[0]:.3e} oracle eval {ev:.3e}")
+    assert stat[0] == cbs.INST_CONVERGED
+    _bar(cbs.CBS_C64, rel[0], ev)
+
+
+def test_fgmres_ragged_batch():
+    sizes = [128, 64, 192]
+    probs = [random_problem(n, seed=95 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, restart=15)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    u = plan.zeros()
+    its, rel, stat = plan.fgmres(u, s, restart=15, sweeps=2, max_iters=1000, rtol=1e-6)
+    for i, (ui, si, ki) in enumerate(zip(to_list(u, sizes), to_list(s, sizes), to_list(k2, sizes))):
+        ev = _oracle_relres(ki, plan.k0sq[i], plan.eps[i], ui, si)
+        say(f"   instance {i}: its {its[i]} relres {rel[i]:.3e} oracle {ev:.3e}")
+        assert stat[i] == cbs.INST_CONVERGED
+        _bar(cbs.CBS_C64, rel[i], ev)
