@@ -258,7 +258,8 @@ class BornResidualLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, k2, s, sizes, steps, weight_gamma, k0sq, eps):
-        plan = Plan(k2.detach(), sizes, k0sq=k0sq, eps=eps)
+        dtype = CBS_C128 if k2.dtype == torch.complex128 else CBS_C64
+        plan = Plan(k2.detach(), sizes, k0sq=k0sq, eps=eps, dtype=dtype)
         us = [u0.detach().clone()]
         for _ in range(int(steps)):
             u = us[-1].clone()

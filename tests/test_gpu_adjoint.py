@@ -1,0 +1,163 @@
+"""GPU adjoint of the unrolled CBS residual loss (cbs_loss_seed +
+cbs_adjoint_step, and the BornResidualLoss autograd Function).
+
+* 32x32, K = 8, W = gamma and W = 1: loss, d/du0 and d/dk2 against the
+  oracle's autograd gradient.  FP64 plans: 1e-10 relative; FP32 plans: 1e-4
+  (16 FP32 operator applications in sequence, each ~2e-7 relative, with
+  cancellation in the gradient sums).
+* Full size (16 instances of 256x256, contrast 2, K = 8, W = gamma): central
+  differences (h = 1e-3, Richardson-extrapolated twice with h/2 and h/4) of the FP64 GPU
+  loss on 32 random entries (16 of u0, real and imaginary parts, and 16 of
+  Re k^2) against the FP64 GPU adjoint; and the FP32 adjoint against the
+  FP64 one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from paper_2603_18527_amd import cbs
+from gpu_helpers import rel_err, say, to_list
+
+pytestmark = pytest.mark.gpu
+
+TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
+
+
+def _unrolled(plan, u0, s, steps, weight_gamma):
+    us = [u0.clone()]
+    for _ in range(steps):
+        u = us[-1].clone()
+        plan.sweep(u, s)
+        us.append(u)
+    loss, lam, grad = plan.loss_seed(us[-1], s, weight_gamma)
+    for m in range(steps - 1, -1, -1):
+        plan.adjoint_step(us[m], s, lam, lam, grad)
+    torch.cuda.synchronize()
+    return loss.cpu(), lam, grad
+
+
+def _small_batch(n=32, layer=4, count=2, seed=0):
+    probs, u0s = [], []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        c = S.minmax_map(S.gaussian_random_field(n, 4.0, rng), 1.0, 2.0)
+        probs.append(S.velocity_problem(c, layer, 8.0, S.random_field_c(n, rng), cmin=1.0))
+        u0s.append(S.random_field_c(n, rng))
+    return probs, u0s
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+@pytest.mark.parametrize("weight_gamma", [True, False])
+def test_adjoint_matches_oracle_gradient(dtype, weight_gamma):
+    say(f"[adjoint 32x32] dtype={dtype} W=gamma:{weight_gamma}")
+    probs, u0s = _small_batch()
+    sizes = [p.n for p in probs]
+    tdt = TDT[dtype]
+    k2 = cbs.pack([p.k2 for p in probs], tdt)
+    plan = cbs.Plan(k2, sizes, k0sq=[p.k0sq for p in probs], dtype=dtype)
+    u0 = cbs.pack(u0s, tdt)
+    s = cbs.pack([p.source for p in probs], tdt)
+    loss, lam, grad = _unrolled(plan, u0, s, 8, weight_gamma)
+    tol = 1e-10 if dtype == cbs.CBS_C128 else 1e-4
+    for i, (ki, ui, si, li, gi) in enumerate(zip(to_list(k2, sizes), to_list(u0, sizes), to_list(s, sizes),
+                                                 to_list(lam, sizes), to_list(grad, sizes))):
+        val, gu, gk = O.loss_and_grad(ki, plan.k0sq[i], plan.eps[i], ui, si, 8,
+                                      "gamma" if weight_gamma else "one")
+        el, eu, ek = abs(float(loss[i]) - val) / val, rel_err(li, gu), rel_err(gi, gk)
+        say(f"   instance {i}: loss {el:.2e} du0 {eu:.2e} dk2 {ek:.2e}")
+        assert el <= tol and eu <= tol and ek <= tol
+
+
+def test_autograd_function_matches_direct_calls():
+    probs, u0s = _small_batch(seed=10)
+    sizes = [p.n for p in probs]
+    k2 = cbs.pack([p.k2 for p in probs], torch.complex128).requires_grad_(True)
+    u0 = cbs.pack(u0s, torch.complex128).requires_grad_(True)
+    s = cbs.pack([p.source for p in probs], torch.complex128)
+    loss = cbs.born_residual_loss(u0, k2, s, sizes, steps=8, weight_gamma=True,
+                                  k0sq=[p.k0sq for p in probs])
+    # weighted sum so that the per-instance grad_output scaling is exercised
+    (loss * torch.tensor([1.0, 0.5], device="cuda", dtype=torch.float64)).sum().backward()
+    for i, (ki, ui, si, gu_gpu, gk_gpu) in enumerate(zip(to_list(k2.detach(), sizes), to_list(u0.detach(), sizes),
+                                                         to_list(s, sizes), to_list(u0.grad, sizes),
+                                                         to_list(k2.grad, sizes))):
+        eps = O.choose_eps(ki, probs[i].k0sq)
+        val, gu, gk = O.loss_and_grad(ki, probs[i].k0sq, eps, ui, si, 8, "gamma")
+        w = [1.0, 0.5][i]
+        assert abs(float(loss[i]) - val) <= 1e-10 * val
+        assert rel_err(gu_gpu, w * gu) <= 1e-10
+        assert rel_err(gk_gpu, w * gk) <= 1e-10
+
+
+def _loss_only(k2_inst, n, k0sq, eps, u0_inst, s_inst, steps=8):
+    plan = cbs.Plan(k2_inst, [n], k0sq=[k0sq], eps=[eps], dtype=cbs.CBS_C128, guard=False)
+    u = u0_inst.clone()
+    for _ in range(steps):
+        plan.sweep(u, s_inst)
+    loss, lam, grad = plan.loss_seed(u, s_inst, True)
+    return float(loss.cpu()[0])
+
+
+def test_full_size_finite_differences_and_fp32_adjoint():
+    say("[adjoint 16x256^2] building")
+    probs, u0s, ss = S.diff_batch()
+    sizes = [p.n for p in probs]
+    k2 = cbs.pack([p.k2 for p in probs], torch.complex128)
+    plan = cbs.Plan(k2, sizes, k0sq=[p.k0sq for p in probs], dtype=cbs.CBS_C128)
+    u0 = cbs.pack(u0s, torch.complex128)
+    s = cbs.pack(ss, torch.complex128)
+    loss, lam, grad = _unrolled(plan, u0, s, 8, True)
+    # FP32 adjoint on the same problem against the FP64 one
+    # same k0^2 and eps as the FP64 plan (rounding k^2 to FP32 may lift
+    # max|k^2-k0^2| a few ulps above that eps, so the guard is off)
+    plan32 = cbs.Plan(k2.to(torch.complex64), sizes, k0sq=plan.k0sq, eps=plan.eps, guard=False)
+    loss32, lam32, grad32 = _unrolled(plan32, u0.to(torch.complex64), s.to(torch.complex64), 8, True)
+    e_lam = rel_err(lam32.cpu(), lam.cpu())
+    e_grad = rel_err(grad32.cpu(), grad.cpu())
+    e_loss = float(torch.max(torch.abs(loss32 - loss) / loss))
+    say(f"   FP32 vs FP64 adjoint: loss {e_loss:.2e} du0 {e_lam:.2e} dk2 {e_grad:.2e}")
+    assert e_loss <= 1e-4 and e_lam <= 1e-4 and e_grad <= 1e-4
+    rng = np.random.default_rng(2024)
+    offs = cbs.offsets(sizes)
+    lam_h = lam.cpu()
+    grad_h = grad.cpu()
+    worst = 0.0
+    for t in range(32):
+        b = int(rng.integers(0, len(probs)))
+        n = sizes[b]
+        y, x = (int(v) for v in rng.integers(0, n, size=2))
+        idx = offs[b] + y * n + x
+        k2_i = k2[offs[b]:offs[b] + n * n].clone()
+        u0_i = u0[offs[b]:offs[b] + n * n].clone()
+        s_i = s[offs[b]:offs[b] + n * n]
+        if t < 16:
+            unit = 1.0 if t % 2 == 0 else 1j
+            an = float(lam_h[idx].real if unit == 1.0 else lam_h[idx].imag)
+        else:
+            unit = 1.0
+            an = float(grad_h[idx].real)
+
+        def f(hh):
+            if t < 16:
+                up = u0_i.clone(); up[y * n + x] += unit * hh
+                um = u0_i.clone(); um[y * n + x] -= unit * hh
+                return (_loss_only(k2_i, n, plan.k0sq[b], plan.eps[b], up, s_i)
+                        - _loss_only(k2_i, n, plan.k0sq[b], plan.eps[b], um, s_i)) / (2 * hh)
+            kp = k2_i.clone(); kp[y * n + x] += hh
+            km = k2_i.clone(); km[y * n + x] -= hh
+            return (_loss_only(kp, n, plan.k0sq[b], plan.eps[b], u0_i, s_i)
+                    - _loss_only(km, n, plan.k0sq[b], plan.eps[b], u0_i, s_i)) / (2 * hh)
+
+        d1, d2, d4 = f(1e-3), f(5e-4), f(2.5e-4)
+        r1a, r1b = (4 * d2 - d1) / 3, (4 * d4 - d2) / 3   # O(h^4)
+        rich = (16 * r1b - r1a) / 15                        # O(h^6)
+        # FP64 rounding of the loss, amplified by the differencing: ~ eps L / h
+        noise = 100 * 2.2e-16 * float(loss[b]) / 2.5e-4
+        err = abs(rich - an) / (abs(an) + noise / 1e-7)
+        worst = max(worst, err)
+        assert abs(d1 - an) <= 1e-2 * abs(an) + noise, (t, d1, an)  # plain O(h^2) truncation
+        assert abs(r1a - an) <= 1e-4 * abs(an) + noise, (t, r1a, an)
+        assert abs(rich - an) <= 1e-7 * abs(an) + noise, (t, rich, an, noise)
+    say(f"   32 central differences: worst Richardson rel err {worst:.2e}")
