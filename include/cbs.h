@@ -123,11 +123,13 @@ cbs_status cbs_residual(cbs_plan plan, const void* u, const void* s, const void*
                         void* r, double* norm2, void* stream);
 
 /*
- * cbs_sweep -- one CBS step in place: u <- u + gamma (G (V u + s) - u)
- *   (Sec. 3.1, Eq. CBS).  s nullable.  norm2 as in cbs_residual (residual of
- *   the input u).
+ * cbs_sweep -- `count` CBS steps in place: u <- u + gamma (G (V u + s) - u)
+ *   (Sec. 3.1, Eq. CBS).  Consecutive sweeps are fused (the update of one
+ *   sweep and the potential multiply and forward row transforms of the next
+ *   share a pass over memory).  s nullable.  norm2 as in cbs_residual: the
+ *   residual of the input to the last sweep.  count in [1, 1e6].
  */
-cbs_status cbs_sweep(cbs_plan plan, void* u, const void* s, double* norm2, void* stream);
+cbs_status cbs_sweep(cbs_plan plan, void* u, const void* s, int count, double* norm2, void* stream);
 
 /*
  * cbs_iterate -- stationary CBS until ||G(V u + s) - u|| / ||G s|| <= rtol
@@ -194,7 +196,7 @@ cbs_status cbs_loss_seed(cbs_plan plan, const void* u_k, const void* s, int weig
  */
 cbs_status cbs_autotune(cbs_plan plan, int* tile_out, void* stream);
 
-/* Force the column tile width (4, 8, 16 or 32 columns; must fit in LDS). */
+/* Force the column tile width (2, 4, 8, 16 or 32 columns; must fit in LDS). */
 cbs_status cbs_set_tile(cbs_plan plan, int columns);
 
 void cbs_destroy(cbs_plan plan);

@@ -40,7 +40,7 @@ SIGNATURES = {
     "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "cbs_sweep": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _vp, _vp, _vp, _i32, _vp]),
     "fgmres_solve": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "cbs_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -190,10 +190,10 @@ class Plan:
                                    _ptr(self._field(rhs, "rhs")), _ptr(r), _ptr(n2), _stream(stream)))
         return r, n2
 
-    def sweep(self, u, s, norms=False, stream=None):
+    def sweep(self, u, s, count=1, norms=False, stream=None):
         n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None
         _check(load().cbs_sweep(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
-                                _ptr(n2), _stream(stream)))
+                                int(count), _ptr(n2), _stream(stream)))
         return n2
 
     def iterate(self, u, s, max_sweeps=2500, rtol=1e-6, check_every=50, use_graph=True, stream=None):

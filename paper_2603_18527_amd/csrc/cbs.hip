@@ -141,26 +141,38 @@ void build_items(cbs_plan p) {
     const int rpw = row_rpw(p->n[i]);
     for (int r = 0; r < p->n[i]; r += rpw) p->row_items.push_back(int2{i, r});
   }
+  // Column items.  Workgroups are dispatched round-robin over the 8 XCDs
+  // (workgroup w runs on XCD w mod 8), so tiles that share 128-byte lines
+  // (G = 128 B / (C * 8 B) neighbouring FP32 tiles) are placed 8 positions
+  // apart: they then run on the same XCD and hit one L2.
   p->col_items_host.clear();
-  for (int c : {4, 8, 16, 32}) {
-    std::vector<int2> items;
+  for (int c : {2, 4, 8, 16, 32}) {
+    std::vector<int2> nat;
     for (int i : order) {
       if (p->n[i] % c) continue;
-      for (int col = 0; col < p->n[i]; col += c) items.push_back(int2{i, col});
+      for (int col = 0; col < p->n[i]; col += c) nat.push_back(int2{i, col});
     }
+    const size_t g = std::max(1, 16 / c), blk = 8 * g;
+    std::vector<int2> items(nat.size());
+    size_t b = 0;
+    for (; b + blk <= nat.size(); b += blk)
+      for (size_t x = 0; x < 8; ++x)
+        for (size_t q = 0; q < g; ++q) items[b + 8 * q + x] = nat[b + x * g + q];
+    for (; b < nat.size(); ++b) items[b] = nat[b];
     p->col_items_host[c] = items;
   }
 }
 
-size_t col_lds_bytes(int maxn, int tile, int elem) { return size_t(maxn) * tile * elem; }
+size_t col_lds_bytes(int maxn, int tile, int elem) {
+  return size_t(tile) * col_stride(maxn, tile) * elem;
+}
 constexpr size_t kColLdsMax = 64 * 1024;
 
 bool tile_ok(cbs_plan p, int tile) {
-  if (tile != 4 && tile != 8 && tile != 16 && tile != 32) return false;
+  if (tile != 2 && tile != 4 && tile != 8 && tile != 16 && tile != 32) return false;
   for (int n : p->n)
     if (n % tile) return false;
   if (tile == 32 && p->maxn > 256) return false;
-  if (tile == 16 && p->maxn > 512) return false;
   if (col_lds_bytes(p->maxn, tile, p->op_elem()) > kColLdsMax) return false;
   return true;
 }
@@ -168,7 +180,7 @@ bool tile_ok(cbs_plan p, int tile) {
 // Column tile for an element size: the plan's tile, halved until it fits.
 int tile_for(cbs_plan p, int elem) {
   int t = p->tile;
-  while (t > 4 && col_lds_bytes(p->maxn, t, elem) > kColLdsMax) t /= 2;
+  while (t > 2 && col_lds_bytes(p->maxn, t, elem) > kColLdsMax) t /= 2;
   return t;
 }
 
@@ -206,20 +218,49 @@ void launch_col(cbs_plan p, Params<R> q, hipStream_t st) {
   hipLaunchKernelGGL((k_col<R, C>), dim3(nitems), dim3(kThreads), lds, st, q);
 }
 
+template <typename R>
+void launch_cols(cbs_plan p, Params<R> q, hipStream_t st) {
+  switch (tile_for(p, sizeof(cpx<R>))) {
+    case 2: launch_col<R, 2>(p, q, st); break;
+    case 4: launch_col<R, 4>(p, q, st); break;
+    case 8: launch_col<R, 8>(p, q, st); break;
+    case 16: launch_col<R, 16>(p, q, st); break;
+    default: launch_col<R, 32>(p, q, st); break;
+  }
+}
+
 // Forward rows (prologue) -> columns (symbol) -> inverse rows (epilogue).
 template <typename R>
 cbs_status run_pipeline(cbs_plan p, Params<R> q, hipStream_t st) {
   const int nrow = int(p->row_items.size());
   q.items = p->d_row_items;
   hipLaunchKernelGGL(k_row_fwd<R>, dim3(nrow), dim3(kThreads), 0, st, q);
-  switch (tile_for(p, sizeof(cpx<R>))) {
-    case 4: launch_col<R, 4>(p, q, st); break;
-    case 8: launch_col<R, 8>(p, q, st); break;
-    case 16: launch_col<R, 16>(p, q, st); break;
-    default: launch_col<R, 32>(p, q, st); break;
-  }
+  launch_cols(p, q, st);
   q.items = p->d_row_items;
   hipLaunchKernelGGL(k_row_inv<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+// `count` CBS sweeps in place on q.u (= q.out): forward rows, then
+// (count - 1) times [columns, fused inverse/forward rows], then columns and
+// inverse rows with the sweep epilogue.  The partial norms left behind are
+// those of the last sweep.
+template <typename R>
+cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
+  const int nrow = int(p->row_items.size());
+  Params<R> f = q;
+  f.items = p->d_row_items;
+  hipLaunchKernelGGL(k_row_fwd<R>, dim3(nrow), dim3(kThreads), 0, st, f);
+  for (int k = 1; k < count; ++k) {
+    launch_cols(p, q, st);
+    hipLaunchKernelGGL(k_row_sweep<R>, dim3(nrow), dim3(kThreads), 0, st, f);
+  }
+  launch_cols(p, q, st);
+  Params<R> e = q;
+  e.items = p->d_row_items;
+  e.epi = EPI_SWEEP;
+  hipLaunchKernelGGL(k_row_inv<R>, dim3(nrow), dim3(kThreads), 0, st, e);
   HIPCHK(hipGetLastError());
   return CBS_OK;
 }
@@ -310,13 +351,13 @@ cbs_status residual_impl(cbs_plan p, const void* u, const void* s, const void* r
 }
 
 template <typename R>
-cbs_status sweep_impl(cbs_plan p, void* u, const void* s, double* norm2, hipStream_t st) {
+cbs_status sweep_impl(cbs_plan p, void* u, const void* s, int count, double* norm2, hipStream_t st) {
   Params<R> q = base_params<R>(p);
   q.u = static_cast<const cpx<R>*>(u);
   q.s = static_cast<const cpx<R>*>(s);
   q.out = static_cast<cpx<R>*>(u);
   q.epi = EPI_SWEEP;
-  CHK(run_pipeline(p, q, st));
+  CHK(run_sweeps(p, q, count, st));
   if (norm2) {
     hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(p->batch)), dim3(256), 0, st, p->d_inst,
                        p->batch, p->d_partials, norm2);
@@ -357,7 +398,11 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     w.mask_mode = MASK_RUNNING;
     CHK(launch_pw(p, w, st));
   }
-  for (int k = 1; k < chunk; ++k) {
+  // (chunk - 1) sweeps e <- e + gamma (G(V e) + c - e); the status check after
+  // each sweep runs between the fused kernels (a converged instance is masked
+  // from the next launch on).
+  if (chunk > 1) {
+    const int nrow = int(p->row_items.size());
     Params<R> q = base_params<R>(p);
     q.u = e;
     q.rhs = c;
@@ -365,8 +410,17 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     q.epi = EPI_SWEEP;
     q.mask = p->d_status;
     q.mask_mode = MASK_RUNNING;
-    CHK(run_pipeline(p, q, st));
-    hipLaunchKernelGGL(k_check32, dim3(nb), dim3(256), 0, st, is, p->d_inst, p->batch, p->d_partials);
+    q.items = p->d_row_items;
+    hipLaunchKernelGGL(k_row_fwd<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+    for (int k = 1; k < chunk; ++k) {
+      launch_cols(p, q, st);
+      q.items = p->d_row_items;
+      if (k + 1 < chunk)
+        hipLaunchKernelGGL(k_row_sweep<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+      else
+        hipLaunchKernelGGL(k_row_inv<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+      hipLaunchKernelGGL(k_check32, dim3(nb), dim3(256), 0, st, is, p->d_inst, p->batch, p->d_partials);
+    }
   }
   {
     PwParams<R> w{};
@@ -542,7 +596,7 @@ cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
     pw.mask_mode = MASK_NONZERO;
     CHK(launch_pw(p, pw, st));
   }
-  for (int k = 1; k < sweeps; ++k) {
+  if (sweeps > 1) {
     Params<R> q = base_params<R>(p);
     q.u = z;
     q.rhs = c;
@@ -551,7 +605,7 @@ cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
     q.partials = nullptr;
     q.mask = p->d_kactive;
     q.mask_mode = MASK_NONZERO;
-    CHK(run_pipeline(p, q, st));
+    CHK(run_sweeps(p, q, sweeps - 1, st));
   }
   // w = B z_j = z_j - G(V z_j), widened to FP64
   {
@@ -829,15 +883,22 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
     p->d_col_items[kv.first] = static_cast<int2*>(ptr);
   }
 
-  // Twiddle tables exp(-2 pi i m / N): FP64 on the host, rounded once for FP32.
-  std::vector<cpx<double>> t64(kTwTotal);
-  std::vector<cpx<float>> t32(kTwTotal);
+  // Per-pass twiddle tables w^(q k), w = exp(-2 pi i / (Ns r)), evaluated in
+  // FP64 on the host with the exponent reduced exactly, rounded once for FP32.
+  std::vector<cpx<double>> t64(kTwTotal, cpx<double>{0.0, 0.0});
+  std::vector<cpx<float>> t32(kTwTotal, cpx<float>{0.f, 0.f});
   for (int nn : kSizes) {
-    const int o = tw_offset(nn);
-    for (int m = 0; m < nn; ++m) {
-      const double ang = -2.0 * M_PI * double(m) / double(nn);
-      t64[o + m] = cpx<double>{std::cos(ang), std::sin(ang)};
-      t32[o + m] = cpx<float>{float(t64[o + m].x), float(t64[o + m].y)};
+    for (int pass = 0; pass < plan_passes(nn); ++pass) {
+      const int ns = plan_ns(nn, pass), rad = plan_radix(nn, pass), rp = radp(rad);
+      if (ns == 1) continue;
+      const int o = tw_pass_offset(nn, pass);
+      for (int k = 0; k < ns; ++k)
+        for (int q = 0; q < rad; ++q) {
+          const long long m = ((long long)q * k) % ((long long)ns * rad);
+          const double ang = -2.0 * M_PI * double(m) / double(ns * rad);
+          t64[o + k * rp + q] = cpx<double>{std::cos(ang), std::sin(ang)};
+          t32[o + k * rp + q] = cpx<float>{float(std::cos(ang)), float(std::sin(ang))};
+        }
     }
   }
 #define BAILCHK(expr)                                                                     \
@@ -947,12 +1008,13 @@ cbs_status cbs_residual(cbs_plan p, const void* u, const void* s, const void* rh
   return residual_impl<double>(p, u, s, rhs, r, norm2, st);
 }
 
-cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, double* norm2, void* stream) {
+cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm2, void* stream) {
   if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
+  if (count < 1 || count > 1000000) return fail(CBS_ERR_ARG, "count must be in [1, 1e6]");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (p->dtype == CBS_C64) return sweep_impl<float>(p, u, s, norm2, st);
-  return sweep_impl<double>(p, u, s, norm2, st);
+  if (p->dtype == CBS_C64) return sweep_impl<float>(p, u, s, count, norm2, st);
+  return sweep_impl<double>(p, u, s, count, norm2, st);
 }
 
 cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
@@ -1022,7 +1084,7 @@ cbs_status cbs_autotune(cbs_plan p, int* tile_out, void* stream) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (int t : {4, 8, 16, 32}) {
+  for (int t : {2, 4, 8, 16, 32}) {
     if (!tile_ok(p, t)) continue;
     p->tile = t;
     // time a complete apply of zeros (u = e scratch) into the t scratch

@@ -132,43 +132,124 @@ __host__ __device__ constexpr int plan_product(int n) {
   return prod;
 }
 
-// Twiddle tables of all supported sizes are stored back to back.
+__host__ __device__ constexpr int plan_passes(int n) {
+  int p = 0;
+  while (plan_radix(n, p) > 0) ++p;
+  return p;
+}
+
+// Length of the sub-transforms already formed before pass p.
+__host__ __device__ constexpr int plan_ns(int n, int p) {
+  int ns = 1;
+  for (int i = 0; i < p; ++i) ns *= plan_radix(n, i);
+  return ns;
+}
+
+// ---- twiddle tables ----------------------------------------------------------
+//
+// For pass p (Ns = plan_ns > 1, radix r) butterfly k (0 <= k < Ns) needs
+// w^(q k), q = 1..r-1, w = exp(-2 pi i / (Ns r)).  They are stored
+// contiguously per k, padded to radp(r) entries (entry 0 = 1), so one
+// butterfly reads them with a few 16-byte loads.  Tables of all passes of all
+// supported sizes are stored back to back.
+__host__ __device__ constexpr int radp(int r) { return r == 3 ? 4 : r; }
+__host__ __device__ constexpr int tw_pass_size(int n, int p) {
+  return plan_ns(n, p) > 1 ? plan_ns(n, p) * radp(plan_radix(n, p)) : 0;
+}
+__host__ __device__ constexpr int tw_size(int n) {
+  int s = 0;
+  for (int p = 0; p < plan_passes(n); ++p) s += tw_pass_size(n, p);
+  return s;
+}
 __host__ __device__ constexpr int tw_offset(int n) {
   int off = 0;
   const int sizes[] = {16, 32, 64, 128, 192, 256, 288, 384, 512, 1024};
   for (int i = 0; i < 10; ++i) {
     if (sizes[i] == n) return off;
-    off += sizes[i];
+    off += tw_size(sizes[i]);
   }
   return -1;
 }
-constexpr int kTwTotal = 16 + 32 + 64 + 128 + 192 + 256 + 288 + 384 + 512 + 1024;
+__host__ __device__ constexpr int tw_pass_offset(int n, int p) {
+  int off = tw_offset(n);
+  for (int i = 0; i < p; ++i) off += tw_pass_size(n, i);
+  return off;
+}
+constexpr int kTwTotal = tw_offset(1024) + tw_size(1024);
 
-// ---- Stockham pass over LDS ---------------------------------------------------
+// ---- LDS layout ------------------------------------------------------------------
 //
-// `buf` points at element 0 of this thread's transform; elements are STRIDE
-// apart.  TPF threads cooperate on one transform (t = 0..TPF-1).  Every thread
-// of the workgroup must call this (it contains barriers); `active` masks
-// threads without a transform.  The pass is in place: all inputs are read into
-// registers before the first barrier and written after it.
-template <typename R, int N, int RAD, int NS, int TPF, int DIR, int STRIDE>
-__device__ __forceinline__ void stockham_pass(cpx<R>* buf, int t, bool active,
-                                              const cpx<R>* __restrict__ tw) {
+// LDS positions are skewed by one element per eight, pos(e) = e + e/8, so the
+// power-of-two strides of the Stockham writes (stride r in the first pass,
+// blocks of Ns at stride Ns r later) spread over all banks.
+__host__ __device__ constexpr int lds_pos(int e) { return e + (e >> 3); }
+__host__ __device__ constexpr int lds_len(int n) { return lds_pos(n - 1) + 1; }
+
+// pos(e + q * STEP) for q < RAD, given pos(e): a constant offset when STEP is a
+// multiple of 8, or when e is a multiple of RAD, RAD divides 8 and STEP == 1
+// (all RAD elements stay in one block of eight).
+template <int STEP, int RAD>
+__device__ __forceinline__ int lds_pos_step(int e, int pos_e, int q) {
+  if constexpr (STEP % 8 == 0) return pos_e + q * (STEP + STEP / 8);
+  else if constexpr (STEP == 1 && 8 % RAD == 0) return pos_e + q;
+  else return lds_pos(e + q * STEP);
+}
+
+template <typename R, int RADP>
+__device__ __forceinline__ void load_tw(const cpx<R>* __restrict__ p, cpx<R>* w) {
+  if constexpr (sizeof(R) == 4) {
+    const float4* p4 = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < RADP / 2; ++i) {
+      const float4 v = p4[i];
+      w[2 * i] = cpx<R>{v.x, v.y};
+      w[2 * i + 1] = cpx<R>{v.z, v.w};
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RADP; ++i) w[i] = p[i];
+  }
+}
+
+// ---- one Stockham pass ----------------------------------------------------------
+//
+// TPF threads cooperate on one transform (t = 0..TPF-1); every thread of the
+// workgroup calls this (barriers inside), `active` masks threads without a
+// transform.  The first pass reads its inputs through `ld(e)` (element e of
+// the transform, typically straight from global memory), the last pass hands
+// its outputs to `st(e, v)`; the passes in between exchange data through LDS
+// (`buf`, skewed positions).  LD_LDS / ST_LDS say that ld / st themselves touch
+// this LDS buffer, which adds the barriers an in-place pass needs.
+template <typename R, int N, int P, int TPF, int DIR, bool LD_LDS, bool ST_LDS, class LD, class ST>
+__device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
+                                         const cpx<R>* __restrict__ tw, LD& ld, ST& st) {
+  constexpr int RAD = plan_radix(N, P);
+  constexpr int NS = plan_ns(N, P);
   constexpr int NB = N / RAD;
+  constexpr bool FIRST = P == 0;
+  constexpr bool LAST = P + 1 == plan_passes(N);
   constexpr int PER = (NB + TPF - 1) / TPF;
   constexpr bool EXACT = (NB % TPF) == 0;
+  constexpr bool READS_LDS = !FIRST || LD_LDS;
+  constexpr bool WRITES_LDS = !LAST || ST_LDS;
   cpx<R> v[PER][RAD];
   if (active) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int j = t + p * TPF;
       if (EXACT || j < NB) {
+        if constexpr (FIRST) {
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) v[p][q] = buf[(j + q * NB) * STRIDE];
+          for (int q = 0; q < RAD; ++q) v[p][q] = ld(j + q * NB);
+        } else {
+          const int pj = lds_pos(j);
+#pragma unroll
+          for (int q = 0; q < RAD; ++q) v[p][q] = buf[lds_pos_step<NB, RAD>(j, pj, q)];
+        }
       }
     }
   }
-  __syncthreads();
+  if constexpr (READS_LDS && WRITES_LDS) __syncthreads();
   if (active) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
@@ -176,41 +257,39 @@ __device__ __forceinline__ void stockham_pass(cpx<R>* buf, int t, bool active,
       if (EXACT || j < NB) {
         const int k = j % NS;
         if constexpr (NS > 1) {
+          constexpr int RP = radp(RAD);
+          cpx<R> w[RP];
+          load_tw<R, RP>(tw + tw_pass_offset(N, P) + k * RP, w);
 #pragma unroll
           for (int q = 1; q < RAD; ++q) {
-            cpx<R> w = tw[q * k * (N / (NS * RAD))];
-            if constexpr (DIR > 0) w.y = -w.y;
-            v[p][q] = cmul(v[p][q], w);
+            cpx<R> wq = w[q];
+            if constexpr (DIR > 0) wq.y = -wq.y;
+            v[p][q] = cmul(v[p][q], wq);
           }
         }
         bfly<RAD, DIR>(v[p]);
         const int o = (j / NS) * (NS * RAD) + k;
+        if constexpr (LAST) {
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) buf[(o + q * NS) * STRIDE] = v[p][q];
+          for (int q = 0; q < RAD; ++q) st(o + q * NS, v[p][q]);
+        } else {
+          const int po = lds_pos(o);
+#pragma unroll
+          for (int q = 0; q < RAD; ++q) buf[lds_pos_step<NS, RAD>(o, po, q)] = v[p][q];
+        }
       }
     }
   }
-  __syncthreads();
+  if constexpr (WRITES_LDS) __syncthreads();
+  if constexpr (!LAST) fft_pass<R, N, P + 1, TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
 }
 
-template <typename R, int N, int P, int NS, int TPF, int DIR, int STRIDE>
-__device__ __forceinline__ void fft_passes(cpx<R>* buf, int t, bool active,
-                                           const cpx<R>* __restrict__ tw) {
-  constexpr int RAD = plan_radix(N, P);
-  if constexpr (RAD > 0) {
-    stockham_pass<R, N, RAD, NS, TPF, DIR, STRIDE>(buf, t, active, tw);
-    fft_passes<R, N, P + 1, NS * RAD, TPF, DIR, STRIDE>(buf, t, active, tw);
-  } else {
-    static_assert(NS == N, "plan radices must multiply to N");
-  }
-}
-
-// Full length-N transform in LDS (DIR = -1 forward, +1 inverse).
-template <typename R, int N, int TPF, int DIR, int STRIDE>
-__device__ __forceinline__ void fft_lds(cpx<R>* buf, int t, bool active,
-                                        const cpx<R>* __restrict__ tw_base) {
-  static_assert(plan_product(N) == N, "no plan for this size");
-  fft_passes<R, N, 0, 1, TPF, DIR, STRIDE>(buf, t, active, tw_base + tw_offset(N));
+// Length-N transform (DIR = -1 forward, +1 inverse, unnormalised) from ld to st.
+template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, class LD, class ST>
+__device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active,
+                                        const cpx<R>* __restrict__ tw, LD ld, ST st) {
+  static_assert(plan_product(N) == N && plan_passes(N) >= 2, "no plan for this size");
+  fft_pass<R, N, 0, TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
 }
 
 }  // namespace cbs

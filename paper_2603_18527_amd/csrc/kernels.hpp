@@ -21,7 +21,7 @@ namespace cbs {
 #define CBS_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(192) X(256) X(288) X(384) X(512) X(1024)
 
 constexpr int kThreads = 256;
-constexpr int kRowLds = 2048;  // complex elements per row-kernel workgroup
+constexpr int kRowLds = 2304;  // complex elements per row-kernel workgroup (2048 + skew)
 
 // Threads per row transform and rows per row-kernel workgroup.
 __host__ __device__ constexpr int row_tpf(int n) { return n / 8; }
@@ -86,7 +86,7 @@ __device__ __forceinline__ bool inst_enabled(const int* mask, int mode, int i) {
 }
 
 template <typename R>
-__device__ __forceinline__ cpx<R> ld(const cpx<R>* p, long long i) {
+__device__ __forceinline__ cpx<R> ld_or_zero(const cpx<R>* p, long long i) {
   return p ? p[i] : cpx<R>{R(0), R(0)};
 }
 
@@ -111,7 +111,7 @@ template <typename R>
 __device__ __forceinline__ cpx<R> prologue(const Params<R>& p, const InstDesc& d, long long i) {
   switch (p.pro) {
     case PRO_VU_S: {
-      cpx<R> q = ld(p.s, i);
+      cpx<R> q = ld_or_zero(p.s, i);
       if (p.u) {
         const Coef<R> c = coef(p, d, i);
         q = q + cmul(c.v, p.u[i]);
@@ -146,14 +146,14 @@ __device__ __forceinline__ double epilogue(const Params<R>& p, const InstDesc& d
       p.out[i] = z;
       return 0.0;
     case EPI_RESID: {
-      const cpx<R> r = z - ld(p.u, i) + ld(p.rhs, i);
+      const cpx<R> r = z - ld_or_zero(p.u, i) + ld_or_zero(p.rhs, i);
       if (p.out) p.out[i] = r;
       if (p.out_narrow) p.out_narrow[i] = cpx<float>{float(r.x), float(r.y)};
       return double(cabs2(r));
     }
     case EPI_SWEEP: {
       const cpx<R> u = p.u[i];
-      const cpx<R> r = z - u + ld(p.rhs, i);
+      const cpx<R> r = z - u + ld_or_zero(p.rhs, i);
       const Coef<R> c = coef(p, d, i);
       p.out[i] = u + cmul(c.gamma(), r);
       return double(cabs2(r));
@@ -196,7 +196,7 @@ __device__ __forceinline__ double epilogue(const Params<R>& p, const InstDesc& d
     default: {  // EPI_LAP: physical residual s - A u with A u = -Lap u - k^2 u
       const cpx<R> u = p.u[i];
       const cpx<R> au = z - cmul(p.k2[i], u);
-      const cpx<R> r = ld(p.s, i) - au;
+      const cpx<R> r = ld_or_zero(p.s, i) - au;
       if (p.out) p.out[i] = r;
       return double(cabs2(r));
     }
@@ -224,79 +224,113 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // ---- row kernels ---------------------------------------------------------------
+//
+// A row work item is (instance, first row); it covers row_rpw(N) rows (fewer at
+// the bottom edge).  Thread tid works on row tid / TPF of the tile.  The first
+// FFT pass reads straight from global memory (with the prologue) and the last
+// pass writes straight to global memory (with the epilogue); both access
+// patterns are contiguous across the threads of a row.  Only the exchanges
+// between passes go through LDS (rows at stride lds_len(N), skewed).
 
-template <typename R, int N, bool FWD>
+template <int N>
+struct RowTile {
+  static constexpr int TPF = row_tpf(N);
+  static constexpr int RPW = row_rpw(N);
+  static constexpr int RS = lds_len(N);
+  static_assert(RPW * RS <= kRowLds, "row tile does not fit");
+};
+
+// MODE 0: prologue + forward rows -> spectral buffer;
+// MODE 1: spectral buffer -> inverse rows -> epilogue (with partial norms);
+// MODE 2: spectral buffer -> inverse rows -> sweep epilogue u += gamma r
+//         (written to global) -> next sweep's prologue V u + s formed from
+//         the value just computed -> forward rows -> spectral buffer.
+template <typename R, int N, int MODE>
 __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, int row0,
                                          cpx<R>* lds, double* red) {
-  constexpr int TPF = row_tpf(N);
-  constexpr int RPW = row_rpw(N);
-  static_assert(RPW * N <= kRowLds, "row tile does not fit");
+  using T = RowTile<N>;
   const int tid = threadIdx.x;
-  const int r = tid / TPF, t = tid - r * TPF;
-  const int nrows = min(RPW, N - row0);
-  const long long base = d.off + (long long)row0 * N;
-  const int cnt = nrows * N;
-  if constexpr (FWD) {
-    for (int i = tid; i < cnt; i += kThreads) lds[i] = prologue(p, d, base + i);
-  } else {
-    for (int i = tid; i < cnt; i += kThreads) lds[i] = p.inter[base + i];
-  }
-  __syncthreads();
+  const int r = tid / T::TPF, t = tid - r * T::TPF;
+  const int nrows = min(T::RPW, N - row0);
   const bool active = r < nrows;
-  fft_lds<R, N, TPF, FWD ? -1 : 1, 1>(lds + (active ? r : 0) * N, t, active, p.tw);
-  if constexpr (FWD) {
-    for (int i = tid; i < cnt; i += kThreads) p.inter[base + i] = lds[i];
-  } else {
+  const long long rbase = d.off + (long long)(row0 + (active ? r : 0)) * N;
+  cpx<R>* mine = lds + (active ? r : 0) * T::RS;
+  if constexpr (MODE == 0) {
+    auto ld = [&](int e) { return prologue(p, d, rbase + e); };
+    auto st = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
+    fft_run<R, N, T::TPF, -1, false, false>(mine, t, active, p.tw, ld, st);
+  } else if constexpr (MODE == 1) {
     double acc = 0.0;
-    for (int i = tid; i < cnt; i += kThreads) acc += epilogue(p, d, base + i, lds[i]);
+    auto ld = [&](int e) { return p.inter[rbase + e]; };
+    auto st = [&](int e, cpx<R> v) { acc += epilogue(p, d, rbase + e, v); };
+    fft_run<R, N, T::TPF, 1, false, false>(mine, t, active, p.tw, ld, st);
     if (p.partials) {
       const double s = block_sum(acc, red);
-      if (tid == 0) p.partials[d.part_off + row0 / RPW] = s;
+      if (tid == 0) p.partials[d.part_off + row0 / T::RPW] = s;
     }
+  } else {
+    double acc = 0.0;
+    auto ld = [&](int e) { return p.inter[rbase + e]; };
+    auto st = [&](int e, cpx<R> z) {
+      const long long g = rbase + e;
+      const cpx<R> u = p.u[g];
+      const cpx<R> rres = z - u + ld_or_zero(p.rhs, g);
+      const Coef<R> c = coef(p, d, g);
+      const cpx<R> un = u + cmul(c.gamma(), rres);
+      p.out[g] = un;
+      acc += double(cabs2(rres));
+      mine[lds_pos(e)] = cmul(c.v, un) + ld_or_zero(p.s, g);
+    };
+    fft_run<R, N, T::TPF, 1, false, true>(mine, t, active, p.tw, ld, st);
+    if (p.partials) {
+      const double s = block_sum(acc, red);
+      if (tid == 0) p.partials[d.part_off + row0 / T::RPW] = s;
+    }
+    auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
+    auto st2 = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
+    fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld2, st2);
+  }
+}
+
+template <typename R, int MODE>
+__device__ __forceinline__ void row_dispatch(const Params<R>& p) {
+  __shared__ cpx<R> lds[kRowLds];
+  __shared__ double red[kThreads / 64];
+  const int2 w = p.items[blockIdx.x];
+  if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
+  const InstDesc d = p.inst[w.x];
+  switch (d.n) {
+#define CBS_ROW_CASE(N) \
+  case N:               \
+    row_body<R, N, MODE>(p, d, w.y, lds, red); \
+    break;
+    CBS_FOR_EACH_N(CBS_ROW_CASE)
+#undef CBS_ROW_CASE
+    default:
+      break;
   }
 }
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row_fwd(Params<R> p) {
-  __shared__ cpx<R> lds[kRowLds];
-  __shared__ double red[kThreads / 64];
-  const int2 w = p.items[blockIdx.x];
-  if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
-  const InstDesc d = p.inst[w.x];
-  switch (d.n) {
-#define CBS_ROW_FWD_CASE(N) \
-  case N:                   \
-    row_body<R, N, true>(p, d, w.y, lds, red); \
-    break;
-    CBS_FOR_EACH_N(CBS_ROW_FWD_CASE)
-#undef CBS_ROW_FWD_CASE
-    default:
-      break;
-  }
+  row_dispatch<R, 0>(p);
 }
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row_inv(Params<R> p) {
-  __shared__ cpx<R> lds[kRowLds];
-  __shared__ double red[kThreads / 64];
-  const int2 w = p.items[blockIdx.x];
-  if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
-  const InstDesc d = p.inst[w.x];
-  switch (d.n) {
-#define CBS_ROW_INV_CASE(N) \
-  case N:                   \
-    row_body<R, N, false>(p, d, w.y, lds, red); \
-    break;
-    CBS_FOR_EACH_N(CBS_ROW_INV_CASE)
-#undef CBS_ROW_INV_CASE
-    default:
-      break;
-  }
+  row_dispatch<R, 1>(p);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_sweep(Params<R> p) {
+  row_dispatch<R, 2>(p);
 }
 
 // ---- column kernel ---------------------------------------------------------------
 
-// Green-symbol factor for DFT bin (k1, k2), computed in FP64 and rounded once.
+// Green-symbol factor for DFT bin (k1, k2), including the 1/N^2 of the inverse
+// transform.  |xi|^2 - k0^2 is formed in FP64 (it cancels near the resonant
+// shell |xi| = k0); the remaining arithmetic runs in the precision R.
 template <typename R>
 __device__ __forceinline__ cpx<R> symbol_factor(int n, int k1, int k2, double k0sq, double eps,
                                                 int mode) {
@@ -304,37 +338,43 @@ __device__ __forceinline__ cpx<R> symbol_factor(int n, int k1, int k2, double k0
   const int m2 = k2 >= n / 2 ? k2 - n : k2;
   const double h = 6.283185307179586476925287 / double(n);
   const double xi2 = double(m1 * m1 + m2 * m2) * (h * h);
-  const double inv_n2 = 1.0 / (double(n) * double(n));
-  if (mode == SYM_LAP) return cpx<R>{R(xi2 * inv_n2), R(0)};
-  const double a = xi2 - k0sq;  // lambda = a - i eps
-  const double sc = inv_n2 / (a * a + eps * eps);
+  const R inv_n2 = R(1.0 / (double(n) * double(n)));
+  if (mode == SYM_LAP) return cpx<R>{R(xi2) * inv_n2, R(0)};
+  const R a = R(xi2 - k0sq);  // lambda = a - i eps
+  const R e = R(eps);
+  const R sc = inv_n2 / (a * a + e * e);
   // 1/lambda = (a + i eps)/|lambda|^2 ; 1/conj(lambda) = (a - i eps)/|lambda|^2
-  return cpx<R>{R(a * sc), R((mode == SYM_GREEN ? eps : -eps) * sc)};
+  return cpx<R>{a * sc, (mode == SYM_GREEN ? e : -e) * sc};
+}
+
+// Column tile: C columns of one instance.  Thread tid works on column tid % C
+// (so the C threads of a row segment read or write C neighbouring elements)
+// and butterfly slot tid / C.  Between passes column c sits in LDS at
+// c * col_stride(N, C) + pos(row); the stride is offset from a multiple of 32
+// elements by 32/C, which spreads the C columns over the banks.
+__host__ __device__ constexpr int col_stride(int n, int c) {
+  return ((lds_len(n) + 31) / 32) * 32 + 32 / c;
 }
 
 template <typename R, int N, int C>
 __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, int col0,
                                          cpx<R>* lds) {
   constexpr int TPC = kThreads / C;
+  constexpr int CS = col_stride(N, C);
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
-  const long long base = d.off + col0;
-  for (int i = tid; i < N * C; i += kThreads) {
-    const int row = i / C, cc = i - row * C;
-    lds[i] = p.inter[base + (long long)row * N + cc];
-  }
-  __syncthreads();
-  fft_lds<R, N, TPC, -1, C>(lds + c, t, true, p.tw);
-  for (int i = tid; i < N * C; i += kThreads) {
-    const int row = i / C, cc = i - row * C;
-    lds[i] = cmul(lds[i], symbol_factor<R>(N, row, col0 + cc, d.k0sq, d.eps, p.sym));
-  }
-  __syncthreads();
-  fft_lds<R, N, TPC, 1, C>(lds + c, t, true, p.tw);
-  for (int i = tid; i < N * C; i += kThreads) {
-    const int row = i / C, cc = i - row * C;
-    p.inter[base + (long long)row * N + cc] = lds[i];
-  }
+  const long long cbase = d.off + col0 + c;
+  const int kcol = col0 + c;
+  cpx<R>* mine = lds + c * CS;
+  auto ld = [&](int e) { return p.inter[cbase + (long long)e * N]; };
+  // last forward pass: multiply by the Green symbol and keep the spectrum in LDS
+  auto st = [&](int e, cpx<R> v) {
+    mine[lds_pos(e)] = cmul(v, symbol_factor<R>(N, e, kcol, d.k0sq, d.eps, p.sym));
+  };
+  fft_run<R, N, TPC, -1, false, true>(mine, t, true, p.tw, ld, st);
+  auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
+  auto st2 = [&](int e, cpx<R> v) { p.inter[cbase + (long long)e * N] = v; };
+  fft_run<R, N, TPC, 1, true, false>(mine, t, true, p.tw, ld2, st2);
 }
 
 template <typename R, int C>
@@ -631,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_dots(KryParams k) {
   long long base;
   int cnt, slot;
   item_range(d, it.y, base, cnt, slot);
-  constexpr int PER = kRowLds / kThreads;
+  constexpr int PER = 2048 / kThreads;  // row_rpw(N) * N <= 2048 for every N
   cpx<double> wv[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {

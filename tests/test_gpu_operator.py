@@ -171,9 +171,11 @@ def test_deterministic_repeat():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("tile", [4, 8, 16, 32])
+@pytest.mark.parametrize("tile", [2, 4, 8, 16, 32])
 def test_column_tile_widths_agree(tile):
-    probs = [random_problem(n, seed=300 + n) for n in (64, 128, 256)]
+    # a 32-column tile of 256-row columns would exceed the 64 KB LDS budget
+    sizes = (64, 128, 256) if tile < 32 else (32, 64, 128)
+    probs = [random_problem(n, seed=300 + n) for n in sizes]
     plan, k2 = plan_for(probs)
     u, s = _inputs(probs, cbs.CBS_C64, seed=11)
     ref = plan.apply(u, s)
@@ -182,4 +184,29 @@ def test_column_tile_widths_agree(tile):
     torch.cuda.synchronize()
     assert rel_err(y.cpu(), ref.cpu()) <= 1e-6
     best = plan.autotune()
-    assert best in (4, 8, 16, 32)
+    assert best in (2, 4, 8, 16, 32)
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_fused_sweep_chain(dtype):
+    # count sweeps in one call (inverse rows of one sweep fused with the
+    # potential multiply and forward rows of the next) == count oracle sweeps
+    sizes = [128, 64, 288, 32]
+    say(f"[fused sweeps] sizes={sizes} dtype={dtype}")
+    probs = [random_problem(n, seed=1200 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    u, s = _inputs(probs, dtype, seed=13)
+    u1 = u.clone()
+    n2 = plan.sweep(u1, s, count=5, norms=True)
+    torch.cuda.synchronize()
+    for i, (ui, si, ki, gi) in enumerate(zip(to_list(u, sizes), to_list(s, sizes), to_list(k2, sizes),
+                                             to_list(u1, sizes))):
+        ref = ui
+        for m in range(5):
+            last = O.cbs_residual(ki, plan.k0sq[i], plan.eps[i], ref, si)
+            ref = O.cbs_sweep(ki, plan.k0sq[i], plan.eps[i], ref, si)
+        err = rel_err(gi, ref)
+        say(f"   instance {i}: rel err after 5 fused sweeps {err:.2e}")
+        assert err <= TOL[dtype] * 10
+        nref = float(torch.sum(torch.abs(last) ** 2))
+        assert abs(float(n2[i]) - nref) <= 1e-4 * nref
