@@ -57,6 +57,54 @@ def measured_traffic(workload: str):
     return rec.get("bytes_per_sweep")
 
 
+def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str):
+    """Turn two rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch) into the per-sweep HBM traffic record.
+
+    Each counter is scaled by what it reads for the 1 GiB calibration copy
+    (the largest __amd_rocclr_copyBuffer dispatch).  Per-sweep bytes are the
+    means over the steady-state dispatches of k_row_sweep and of the
+    full-batch k_col launches (the largest grid; autotuning launches smaller
+    per-size-class grids)."""
+    import csv
+    import collections
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        scale = (1 << 30) / (max(copies) * 1024.0)
+        per = collections.defaultdict(list)
+        col_grid = max(int(r["Grid_Size"]) for r in rows if "k_col<float" in r["Kernel_Name"])
+        for r in rows:
+            name = r["Kernel_Name"]
+            if "k_row_sweep<float>" in name:
+                per["k_row_sweep"].append(float(r["Counter_Value"]))
+            elif "k_col<float" in name and int(r["Grid_Size"]) == col_grid:
+                per["k_col"].append(float(r["Counter_Value"]))
+        return scale, {k: 1024.0 * scale * sum(v) / len(v) for k, v in per.items()}
+
+    fs, fetch = load(fetch_csv, "FETCH_SIZE")
+    ws, write = load(write_csv, "WRITE_SIZE")
+    rec = {
+        "workload": workload,
+        "kernel_source_hash": kernel_source_hash(),
+        "fetch_scale": fs,
+        "write_scale": ws,
+        "bytes_read": fetch,
+        "bytes_written": write,
+        "bytes_per_sweep": sum(fetch.values()) + sum(write.values()),
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
+            "python -u bench.py --steps 20 --chain 20 --warmup 2 --no-cpu --no-solve --calib-copy",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
+            "python -u bench.py --steps 20 --chain 20 --warmup 2 --no-cpu --no-solve --calib-copy",
+        ],
+    }
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 def build_workload(name: str):
     import synthetic as S
     if name == "ragged64":
@@ -154,7 +202,147 @@ def time_to_solution(probs, plan_k2, sizes, k0sq, s_packed, rtol=1e-6, chunk=50,
     return out
 
 
+def _gcell(cells, applies, seconds):
+    return cells * applies / seconds / 1e9
+
+
+def run_suite(args):
+    """Solver runs on the five synthetic workloads (configs of the metric):
+    blob64 CBS, grf256 FGMRES(30)+CBS(4) and CBS, ragged64 FGMRES batched,
+    diff16 adjoint, layered1024 FGMRES(50)+CBS(4) in FP32 vs an FP64 GPU run.
+    Errors against the FP64 oracle are evaluated on the host where the naive
+    DFT is affordable (N <= 256)."""
+    import oracle as O
+    import synthetic as S
+    from paper_2603_18527_amd import cbs
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    res = {}
+    # 1. blob64: stationary CBS to 1e-6, FP32 operator with FP64 refinement
+    p = S.blob_problem()
+    k2 = cbs.pack([p.k2], torch.complex64)
+    plan = cbs.Plan(k2, [p.n], k0sq=[p.k0sq])
+    s = cbs.pack([p.source], torch.complex64)
+    u = plan.zeros()
+    plan.iterate(u, s, max_sweeps=50, check_every=25)
+    u.zero_()
+    (its, rel, st), dt = timed(lambda: plan.iterate(u, s, max_sweeps=5000, rtol=1e-6, check_every=25))
+    ki = k2.cpu().reshape(p.n, p.n)
+    si = s.cpu().reshape(p.n, p.n)
+    uo, mo, relo = O.cbs_iterate(ki, plan.k0sq[0], plan.eps[0], si, max_sweeps=5000, rtol=1e-6)
+    ug = u.cpu().reshape(p.n, p.n)
+    res["blob64_cbs"] = dict(sweeps=its[0], oracle_sweeps=mo, seconds=dt, relres_reported=rel[0],
+                             relres_oracle_eval=O.born_relres(ki, plan.k0sq[0], plan.eps[0], ug, si),
+                             rel_err_vs_oracle=float(torch.linalg.vector_norm(ug.to(torch.complex128) - uo)
+                                                     / torch.linalg.vector_norm(uo)),
+                             gcell_apply_s=_gcell(p.n * p.n, its[0], dt), converged=st[0] == 1)
+    print("# suite blob64 done", flush=True)
+    # 2. grf256: FGMRES(30) with 4 CBS sweeps, and stationary CBS
+    p = S.grf_problem()
+    k2 = cbs.pack([p.k2], torch.complex64)
+    plan = cbs.Plan(k2, [p.n], k0sq=[p.k0sq], max_restart=30)
+    s = cbs.pack([p.source], torch.complex64)
+    ki = k2.cpu().reshape(p.n, p.n)
+    si = s.cpu().reshape(p.n, p.n)
+    u = plan.zeros()
+    plan.fgmres(u, s, restart=30, sweeps=4, max_iters=5)
+    u.zero_()
+    (its, rel, st), dt = timed(lambda: plan.fgmres(u, s, restart=30, sweeps=4, max_iters=2500, rtol=1e-6))
+    ug = u.cpu().reshape(p.n, p.n)
+    ev = O.born_relres(ki, plan.k0sq[0], plan.eps[0], ug, si)
+    res["grf256_fgmres30_k4"] = dict(iterations=its[0], seconds=dt, relres_reported=rel[0],
+                                     relres_oracle_eval=ev, applies_per_iteration=4,
+                                     gcell_apply_s=_gcell(p.n * p.n, 4 * its[0], dt), converged=st[0] == 1)
+    u2 = plan.zeros()
+    plan.iterate(u2, s, max_sweeps=50)
+    u2.zero_()
+    (its, rel, st), dt = timed(lambda: plan.iterate(u2, s, max_sweeps=20000, rtol=1e-6, check_every=50))
+    ug = u2.cpu().reshape(p.n, p.n)
+    res["grf256_cbs"] = dict(sweeps=its[0], seconds=dt, relres_reported=rel[0],
+                             relres_oracle_eval=O.born_relres(ki, plan.k0sq[0], plan.eps[0], ug, si),
+                             gcell_apply_s=_gcell(p.n * p.n, its[0], dt), converged=st[0] == 1)
+    print("# suite grf256 done", flush=True)
+    # 3. ragged64: batched FGMRES(30)+CBS(4) (the CBS runs are in the main line)
+    probs = S.ragged_batch()
+    sizes = [q.n for q in probs]
+    k2 = cbs.pack([q.k2 for q in probs], torch.complex64)
+    s = cbs.pack([q.source for q in probs], torch.complex64)
+    plan = cbs.Plan(k2, sizes, k0sq=[q.k0sq for q in probs], max_restart=30)
+    plan.autotune()
+    u = plan.zeros()
+    (its, rel, st), dt = timed(lambda: plan.fgmres(u, s, restart=30, sweeps=4, max_iters=2500, rtol=1e-6))
+    res["ragged64_fgmres30_k4_batched"] = dict(max_iterations=max(its), seconds=dt,
+                                               max_relres=max(rel), all_converged=all(x == 1 for x in st))
+    del plan
+    print("# suite ragged64 fgmres done", flush=True)
+    # 4. diff16: K = 8 unrolled steps, loss with W = gamma, hand adjoint
+    probs, u0s, ss = S.diff_batch()
+    sizes = [q.n for q in probs]
+    cells = sum(n * n for n in sizes)
+    k2 = cbs.pack([q.k2 for q in probs], torch.complex64)
+    u0 = cbs.pack(u0s, torch.complex64)
+    s = cbs.pack(ss, torch.complex64)
+    plan = cbs.Plan(k2, sizes, k0sq=[q.k0sq for q in probs])
+
+    def fwd_bwd():
+        us = [u0.clone()]
+        for _ in range(8):
+            x = us[-1].clone()
+            plan.sweep(x, s)
+            us.append(x)
+        loss, lam, grad = plan.loss_seed(us[-1], s, True)
+        for m in range(7, -1, -1):
+            plan.adjoint_step(us[m], s, lam, lam, grad)
+        return loss
+
+    fwd_bwd()
+    _, dt = timed(fwd_bwd)
+    # applications: 8 sweeps + seed (2) + 8 adjoint steps (2 each)
+    res["diff16_k8_forward_backward"] = dict(seconds=dt, applies=26,
+                                             gcell_apply_s=_gcell(cells, 26, dt))
+    print("# suite diff16 done", flush=True)
+    # 5. layered1024: FGMRES(50) + CBS(4), FP32 operator vs an all-FP64 GPU run
+    probs = S.layered_batch()
+    sizes = [q.n for q in probs]
+    cells = sum(n * n for n in sizes)
+    out = {}
+    sol = {}
+    for name, dtype, tdt in (("fp32", cbs.CBS_C64, torch.complex64), ("fp64", cbs.CBS_C128, torch.complex128)):
+        k2 = cbs.pack([q.k2 for q in probs], tdt)
+        s = cbs.pack([q.source for q in probs], tdt)
+        plan = cbs.Plan(k2, sizes, k0sq=[q.k0sq for q in probs], dtype=dtype, max_restart=50)
+        plan.autotune()
+        u = plan.zeros()
+        (its, rel, st), dt = timed(lambda: plan.fgmres(u, s, restart=50, sweeps=4, max_iters=3000,
+                                                       rtol=1e-6))
+        out[name] = dict(iterations=its, seconds=dt, relres=rel, converged=[x == 1 for x in st],
+                         gcell_apply_s=_gcell(cells, 4 * max(its), dt))
+        sol[name] = u.to(torch.complex128)
+        # sweep throughput on this > Infinity-Cache working set
+        if name == "fp32":
+            x = plan.zeros()
+            plan.sweep(x, s, count=10)
+            _, dts = timed(lambda: plan.sweep(x, s, count=50))
+            out["fp32_sweep_gcell_apply_s"] = _gcell(cells, 50, dts)
+            out["fp32_sweep_ms"] = dts * 1e3 / 50
+        del plan
+        print(f"# suite layered1024 {name} done", flush=True)
+    errs = []
+    for a, b in zip(cbs.unpack(sol["fp32"], sizes), cbs.unpack(sol["fp64"], sizes)):
+        errs.append(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
+    out["rel_err_fp32_vs_fp64_per_instance"] = errs
+    res["layered1024_fgmres50_k4"] = out
+    return res
+
+
 def main():
+
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -162,11 +350,19 @@ def main():
     ap.add_argument("--workload", default="ragged64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-6 runs")
-    ap.add_argument("--tile", type=int, default=0, help="force the column tile (0: autotune)")
     ap.add_argument("--chain", type=int, default=50, help="sweeps fused per cbs_sweep call")
+    ap.add_argument("--suite", action="store_true",
+                    help="also run the solver suite over all five synthetic workloads")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_<workload>.json from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        rec = traffic_record(args.traffic_from[0], args.traffic_from[1], args.workload,
+                             os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"))
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the instances of a batch "
               "are independent, so several GPUs would each run their own share.", file=sys.stderr)
@@ -190,9 +386,10 @@ def main():
     k2 = cbs.pack([p.k2 for p in probs], torch.complex64)
     s = cbs.pack([p.source for p in probs], torch.complex64)
     plan = cbs.Plan(k2, sizes, k0sq=k0sq)
-    tile = plan.set_tile(args.tile) if args.tile else plan.autotune()
-    print(f"# workload {args.workload}: {len(sizes)} instances, {cells} cells, column tile "
-          f"{args.tile or tile}", flush=True)
+    tiles = plan.autotune()
+    tile_by_size = {str(n): t for n, t in sorted(set(zip(sizes, tiles)))}
+    print(f"# workload {args.workload}: {len(sizes)} instances, {cells} cells, column tiles "
+          f"{tile_by_size}", flush=True)
 
     u = plan.zeros()
     stream = torch.cuda.current_stream()
@@ -232,7 +429,8 @@ def main():
         "dtype": "c64 (fp32 complex), fp64 norms",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(sizes), "cells": cells,
-                   "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))}},
+                   "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))},
+                   "column_tiles": tile_by_size},
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -248,6 +446,8 @@ def main():
     }
     if not args.no_solve:
         line["time_to_1e-6"] = time_to_solution(probs, k2, sizes, k0sq, s)
+    if args.suite:
+        line["suite"] = run_suite(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(probs)
     print(json.dumps(line), flush=True)

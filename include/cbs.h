@@ -189,15 +189,20 @@ cbs_status cbs_loss_seed(cbs_plan plan, const void* u_k, const void* s, int weig
                          double* loss, void* lam_out, void* grad_k2, void* stream);
 
 /*
- * cbs_autotune -- time the column-pass tile widths on this plan's batch and
- *   keep the fastest (the choice is also stored in the JSON file named by the
- *   CBS_AUTOTUNE_CACHE environment variable when it is set).  Synchronises.
- *   tile_out: host, nullable: chosen tile width in columns.
+ * cbs_autotune -- for every grid size in the batch, time the column pass at
+ *   the tile widths compiled for that size (about 2048 / N columns rounded
+ *   down to a power of two, and half and twice that) on this plan's own
+ *   instances and keep the fastest.  The choice is appended as one JSON line
+ *   to the file named by the CBS_AUTOTUNE_CACHE environment variable when it
+ *   is set.  tiles: host[batch], nullable: chosen width per instance.
+ *   Synchronises `stream`.
  */
-cbs_status cbs_autotune(cbs_plan plan, int* tile_out, void* stream);
+cbs_status cbs_autotune(cbs_plan plan, int32_t* tiles, void* stream);
 
-/* Force the column tile width (2, 4, 8, 16 or 32 columns; must fit in LDS). */
-cbs_status cbs_set_tile(cbs_plan plan, int columns);
+/* Force the column tile width for grid size n (n = 0: every size in the
+ * plan).  CBS_ERR_ARG if the width is not one of the widths compiled for a
+ * size it applies to.  Synchronises the device. */
+cbs_status cbs_set_tile(cbs_plan plan, int n, int columns);
 
 void cbs_destroy(cbs_plan plan);
 const char* cbs_last_error(void);

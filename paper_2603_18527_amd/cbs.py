@@ -46,7 +46,7 @@ SIGNATURES = {
     "cbs_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_loss_seed": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "cbs_autotune": (_i32, [_vp, _vp, _vp]),
-    "cbs_set_tile": (_i32, [_vp, _i32]),
+    "cbs_set_tile": (_i32, [_vp, _i32, _i32]),
     "cbs_destroy": (None, [_vp]),
     "cbs_last_error": (ctypes.c_char_p, []),
     "cbs_version": (ctypes.c_char_p, []),
@@ -228,13 +228,14 @@ class Plan:
                                     _stream(stream)))
         return loss, lam, grad
 
-    def autotune(self, stream=None) -> int:
-        t = ctypes.c_int()
-        _check(load().cbs_autotune(self._h, ctypes.byref(t), _stream(stream)))
-        return t.value
+    def autotune(self, stream=None) -> List[int]:
+        """Per-size-class column tile autotuning; returns the width per instance."""
+        t = (ctypes.c_int32 * self.batch)()
+        _check(load().cbs_autotune(self._h, t, _stream(stream)))
+        return list(t)
 
-    def set_tile(self, columns: int):
-        _check(load().cbs_set_tile(self._h, int(columns)))
+    def set_tile(self, columns: int, n: int = 0):
+        _check(load().cbs_set_tile(self._h, int(n), int(columns)))
 
 
 def _expand(v, n):

@@ -20,7 +20,8 @@
 #include <vector>
 
 #include "../../include/cbs.h"
-#include "kernels.hpp"
+#include "launch.hpp"
+#include "params.hpp"
 
 using namespace cbs;
 
@@ -66,19 +67,21 @@ struct cbs_plan_s {
   int dtype = CBS_C64;
   int max_restart = 0;
   int maxn = 0;
-  int tile = 16;  // column tile width in complex elements (operator precision)
+  std::map<int, int> ctile;  // column tile width per size class (FP32 kernels)
   long long cells = 0;
   std::vector<int> n;
   std::vector<long long> off;
   std::vector<double> k0sq, eps;
   std::vector<InstDesc> inst;
   std::vector<int2> row_items;
-  std::map<int, std::vector<int2>> col_items_host;
+  std::vector<int2> col_items32, col_items64;  // column work items per precision
+  size_t col_lds32 = 0, col_lds64 = 0;          // dynamic LDS bytes of the column launches
 
   std::vector<void*> owned;
   InstDesc* d_inst = nullptr;
   int2* d_row_items = nullptr;
-  std::map<int, int2*> d_col_items;
+  int2* d_col_items32 = nullptr;
+  int2* d_col_items64 = nullptr;
   cpx<float>* d_tw32 = nullptr;
   cpx<double>* d_tw64 = nullptr;
   void* d_k2 = nullptr;        // operator precision copy (== d_k2_64 for C128)
@@ -131,6 +134,10 @@ void build_items(cbs_plan p) {
     d.part_off = part;
     d.nparts = (d.n + rpw - 1) / rpw;
     part += d.nparts;
+    auto it = p->ctile.find(d.n);
+    d.ctile = it != p->ctile.end() ? it->second : col_tile_default(d.n);
+    d.ctile64 = d.ctile;
+    while (!col_tile_valid(d.n, d.ctile64, 16) && d.ctile64 > 2) d.ctile64 /= 2;
     p->inst.push_back(d);
   }
   // Largest instances first, so the short tail of the grid holds small items.
@@ -141,47 +148,51 @@ void build_items(cbs_plan p) {
     const int rpw = row_rpw(p->n[i]);
     for (int r = 0; r < p->n[i]; r += rpw) p->row_items.push_back(int2{i, r});
   }
-  // Column items.  Workgroups are dispatched round-robin over the 8 XCDs
-  // (workgroup w runs on XCD w mod 8), so tiles that share 128-byte lines
-  // (G = 128 B / (C * 8 B) neighbouring FP32 tiles) are placed 8 positions
-  // apart: they then run on the same XCD and hit one L2.
-  p->col_items_host.clear();
-  for (int c : {2, 4, 8, 16, 32}) {
-    std::vector<int2> nat;
+  // Column items, per instance with its own tile width.  Workgroups are
+  // dispatched round-robin over the 8 XCDs (workgroup w runs on XCD w mod 8),
+  // so the G = 128 B / (C * element) neighbouring tiles that share cache
+  // lines are placed 8 positions apart: they run on the same XCD and hit one
+  // L2.  Same-size instances are adjacent, so each size class is a contiguous
+  // range of the list.
+  p->col_items32.clear();
+  p->col_items64.clear();
+  p->col_lds32 = p->col_lds64 = 0;
+  for (int prec = 0; prec < 2; ++prec) {
+    std::vector<int2>& out = prec == 0 ? p->col_items32 : p->col_items64;
+    const int elem = prec == 0 ? 8 : 16;
     for (int i : order) {
-      if (p->n[i] % c) continue;
+      const int c = prec == 0 ? p->inst[i].ctile : p->inst[i].ctile64;
+      size_t& lds = prec == 0 ? p->col_lds32 : p->col_lds64;
+      lds = std::max(lds, size_t(col_lds_elems(p->n[i], c)) * elem);
+      std::vector<int2> nat;
       for (int col = 0; col < p->n[i]; col += c) nat.push_back(int2{i, col});
+      const size_t g = std::max(1, 128 / (c * elem)), blk = 8 * g;
+      std::vector<int2> items(nat.size());
+      size_t b = 0;
+      for (; b + blk <= nat.size(); b += blk)
+        for (size_t x = 0; x < 8; ++x)
+          for (size_t q = 0; q < g; ++q) items[b + 8 * q + x] = nat[b + x * g + q];
+      for (; b < nat.size(); ++b) items[b] = nat[b];
+      out.insert(out.end(), items.begin(), items.end());
     }
-    const size_t g = std::max(1, 16 / c), blk = 8 * g;
-    std::vector<int2> items(nat.size());
-    size_t b = 0;
-    for (; b + blk <= nat.size(); b += blk)
-      for (size_t x = 0; x < 8; ++x)
-        for (size_t q = 0; q < g; ++q) items[b + 8 * q + x] = nat[b + x * g + q];
-    for (; b < nat.size(); ++b) items[b] = nat[b];
-    p->col_items_host[c] = items;
   }
 }
 
-size_t col_lds_bytes(int maxn, int tile, int elem) {
-  return size_t(tile) * col_stride(maxn, tile) * elem;
-}
-constexpr size_t kColLdsMax = 64 * 1024;
-
-bool tile_ok(cbs_plan p, int tile) {
-  if (tile != 2 && tile != 4 && tile != 8 && tile != 16 && tile != 32) return false;
-  for (int n : p->n)
-    if (n % tile) return false;
-  if (tile == 32 && p->maxn > 256) return false;
-  if (col_lds_bytes(p->maxn, tile, p->op_elem()) > kColLdsMax) return false;
-  return true;
+// Upper bound on column items (tile width 2 everywhere), for allocation.
+size_t max_col_items(cbs_plan p) {
+  size_t m = 0;
+  for (int n : p->n) m += n / 2;
+  return m;
 }
 
-// Column tile for an element size: the plan's tile, halved until it fits.
-int tile_for(cbs_plan p, int elem) {
-  int t = p->tile;
-  while (t > 2 && col_lds_bytes(p->maxn, t, elem) > kColLdsMax) t /= 2;
-  return t;
+cbs_status upload_items(cbs_plan p, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_col_items32, p->col_items32.data(), p->col_items32.size() * sizeof(int2),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_col_items64, p->col_items64.data(), p->col_items64.size() * sizeof(int2),
+                        hipMemcpyHostToDevice, st));
+  return CBS_OK;
 }
 
 template <typename R>
@@ -210,22 +221,14 @@ Params<R> base_params(cbs_plan p) {
   return q;
 }
 
-template <typename R, int C>
-void launch_col(cbs_plan p, Params<R> q, hipStream_t st) {
-  q.items = p->d_col_items[C];
-  const int nitems = int(p->col_items_host[C].size());
-  const size_t lds = col_lds_bytes(p->maxn, C, sizeof(cpx<R>));
-  hipLaunchKernelGGL((k_col<R, C>), dim3(nitems), dim3(kThreads), lds, st, q);
-}
-
 template <typename R>
 void launch_cols(cbs_plan p, Params<R> q, hipStream_t st) {
-  switch (tile_for(p, sizeof(cpx<R>))) {
-    case 2: launch_col<R, 2>(p, q, st); break;
-    case 4: launch_col<R, 4>(p, q, st); break;
-    case 8: launch_col<R, 8>(p, q, st); break;
-    case 16: launch_col<R, 16>(p, q, st); break;
-    default: launch_col<R, 32>(p, q, st); break;
+  if constexpr (sizeof(R) == 4) {
+    q.items = p->d_col_items32;
+    launch_col(int(p->col_items32.size()), p->col_lds32, st, q);
+  } else {
+    q.items = p->d_col_items64;
+    launch_col(int(p->col_items64.size()), p->col_lds64, st, q);
   }
 }
 
@@ -234,10 +237,9 @@ template <typename R>
 cbs_status run_pipeline(cbs_plan p, Params<R> q, hipStream_t st) {
   const int nrow = int(p->row_items.size());
   q.items = p->d_row_items;
-  hipLaunchKernelGGL(k_row_fwd<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+  launch_row(0, nrow, st, q);
   launch_cols(p, q, st);
-  q.items = p->d_row_items;
-  hipLaunchKernelGGL(k_row_inv<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+  launch_row(1, nrow, st, q);
   HIPCHK(hipGetLastError());
   return CBS_OK;
 }
@@ -251,16 +253,16 @@ cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
   const int nrow = int(p->row_items.size());
   Params<R> f = q;
   f.items = p->d_row_items;
-  hipLaunchKernelGGL(k_row_fwd<R>, dim3(nrow), dim3(kThreads), 0, st, f);
+  launch_row(0, nrow, st, f);
   for (int k = 1; k < count; ++k) {
     launch_cols(p, q, st);
-    hipLaunchKernelGGL(k_row_sweep<R>, dim3(nrow), dim3(kThreads), 0, st, f);
+    launch_row(2, nrow, st, f);
   }
   launch_cols(p, q, st);
   Params<R> e = q;
   e.items = p->d_row_items;
   e.epi = EPI_SWEEP;
-  hipLaunchKernelGGL(k_row_inv<R>, dim3(nrow), dim3(kThreads), 0, st, e);
+  launch_row(1, nrow, st, e);
   HIPCHK(hipGetLastError());
   return CBS_OK;
 }
@@ -270,7 +272,7 @@ cbs_status launch_pw(cbs_plan p, PwParams<R> w, hipStream_t st) {
   w.inst = p->d_inst;
   w.items = p->d_row_items;
   w.k2 = k2_of<R>(p);
-  hipLaunchKernelGGL(k_pointwise<R>, dim3(p->row_items.size()), dim3(kThreads), 0, st, w);
+  launch_pointwise(int(p->row_items.size()), st, w);
   HIPCHK(hipGetLastError());
   return CBS_OK;
 }
@@ -288,14 +290,12 @@ IterState iter_state(cbs_plan p) {
   return s;
 }
 
-int inst_blocks(int batch) { return (batch + 255) / 256; }
-
 cbs_status compute_stats(cbs_plan p, int phase, hipStream_t st, std::vector<double>& a,
                          std::vector<double>& b) {
   HIPCHK(hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
                         hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_stats, dim3(p->row_items.size()), dim3(kThreads), 0, st, p->d_inst,
-                     p->d_row_items, p->d_k2_64, p->d_partials, phase);
+  launch_stats(int(p->row_items.size()), st, p->d_inst, p->d_row_items, p->d_k2_64, p->d_partials,
+               phase);
   HIPCHK(hipGetLastError());
   std::vector<double> part(2 * p->row_items.size());
   HIPCHK(hipMemcpyAsync(part.data(), p->d_partials, part.size() * sizeof(double),
@@ -343,8 +343,7 @@ cbs_status residual_impl(cbs_plan p, const void* u, const void* s, const void* r
   q.epi = EPI_RESID;
   CHK(run_pipeline(p, q, st));
   if (norm2) {
-    hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(p->batch)), dim3(256), 0, st, p->d_inst,
-                       p->batch, p->d_partials, norm2);
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
     HIPCHK(hipGetLastError());
   }
   return CBS_OK;
@@ -359,8 +358,7 @@ cbs_status sweep_impl(cbs_plan p, void* u, const void* s, int count, double* nor
   q.epi = EPI_SWEEP;
   CHK(run_sweeps(p, q, count, st));
   if (norm2) {
-    hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(p->batch)), dim3(256), 0, st, p->d_inst,
-                       p->batch, p->d_partials, norm2);
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
     HIPCHK(hipGetLastError());
   }
   return CBS_OK;
@@ -374,7 +372,6 @@ cbs_status sweep_impl(cbs_plan p, void* u, const void* s, int count, double* nor
 template <typename R>
 cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
   const IterState is = iter_state(p);
-  const int nb = inst_blocks(p->batch);
   cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
   cpx<R>* e = static_cast<cpx<R>*>(p->d_e);
   {
@@ -387,7 +384,7 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     q.mask = p->d_status;
     q.mask_mode = MASK_NOT_FINAL;
     CHK(run_pipeline(p, q, st));
-    hipLaunchKernelGGL(k_check64, dim3(nb), dim3(256), 0, st, is, p->d_inst, p->batch, p->d_partials);
+    launch_check64(p->batch, st, is, p->d_inst, p->d_partials);
   }
   {
     PwParams<R> w{};
@@ -411,15 +408,12 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     q.mask = p->d_status;
     q.mask_mode = MASK_RUNNING;
     q.items = p->d_row_items;
-    hipLaunchKernelGGL(k_row_fwd<R>, dim3(nrow), dim3(kThreads), 0, st, q);
+    launch_row(0, nrow, st, q);
     for (int k = 1; k < chunk; ++k) {
       launch_cols(p, q, st);
       q.items = p->d_row_items;
-      if (k + 1 < chunk)
-        hipLaunchKernelGGL(k_row_sweep<R>, dim3(nrow), dim3(kThreads), 0, st, q);
-      else
-        hipLaunchKernelGGL(k_row_inv<R>, dim3(nrow), dim3(kThreads), 0, st, q);
-      hipLaunchKernelGGL(k_check32, dim3(nb), dim3(256), 0, st, is, p->d_inst, p->batch, p->d_partials);
+      launch_row(k + 1 < chunk ? 2 : 1, nrow, st, q);
+      launch_check32(p->batch, st, is, p->d_inst, p->d_partials);
     }
   }
   {
@@ -442,10 +436,8 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
   const int B = p->batch;
   // u64 <- u ; s64 <- s
   if constexpr (sizeof(R) == 4) {
-    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(u),
-                       p->d_u64, p->cells);
-    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(s),
-                       p->d_s64, p->cells);
+    launch_widen_all(st, static_cast<const cpx<float>*>(u), p->d_u64, p->cells);
+    launch_widen_all(st, static_cast<const cpx<float>*>(s), p->d_s64, p->cells);
     HIPCHK(hipGetLastError());
   } else {
     HIPCHK(hipMemcpyAsync(p->d_u64, u, p->cells * 16, hipMemcpyDeviceToDevice, st));
@@ -461,8 +453,7 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
     q.s = p->d_s64;
     q.epi = EPI_RESID;
     CHK(run_pipeline(p, q, st));
-    hipLaunchKernelGGL(k_set_bnorm, dim3(inst_blocks(B)), dim3(256), 0, st, iter_state(p),
-                       p->d_inst, B, p->d_partials);
+    launch_set_bnorm(B, st, iter_state(p), p->d_inst, p->d_partials);
     HIPCHK(hipGetLastError());
   }
   hipGraphExec_t exec = nullptr;
@@ -565,7 +556,7 @@ cbs_status fg_restart(cbs_plan p, int m, int first, hipStream_t st) {
   q.mask_mode = MASK_RUNNING;
   CHK(run_pipeline(p, q, st));
   KryParams k = kry_params(p, m);
-  hipLaunchKernelGGL(k_fg_restart, dim3(inst_blocks(p->batch)), dim3(256), 0, st, k, p->batch, first);
+  launch_fg_restart(p->batch, st, k, first);
   HIPCHK(hipGetLastError());
   if (!first) {
     PwParams<double> w{};
@@ -625,12 +616,12 @@ cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
   const int nrow = int(p->row_items.size());
   for (int pass = 0; pass < 2; ++pass) {
     k.pass = pass;
-    hipLaunchKernelGGL(k_dots, dim3(nrow), dim3(kThreads), 0, st, k);
-    hipLaunchKernelGGL(k_dots_finish, dim3(inst_blocks(p->batch)), dim3(256), 0, st, k, p->batch);
-    hipLaunchKernelGGL(k_cgs_update, dim3(nrow), dim3(kThreads), 0, st, k);
+    launch_dots(nrow, st, k);
+    launch_dots_finish(p->batch, st, k);
+    launch_cgs_update(nrow, st, k);
   }
   // norm, Givens, normalise v_{j+1} (the scale is computed before the mask drops)
-  hipLaunchKernelGGL(k_givens, dim3(inst_blocks(p->batch)), dim3(256), 0, st, k, p->batch);
+  launch_givens(p->batch, st, k);
   HIPCHK(hipGetLastError());
   {
     PwParams<double> pw{};
@@ -650,10 +641,8 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
                        hipStream_t st) {
   const int B = p->batch;
   if constexpr (sizeof(R) == 4) {
-    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(u),
-                       p->d_u64, p->cells);
-    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(s),
-                       p->d_s64, p->cells);
+    launch_widen_all(st, static_cast<const cpx<float>*>(u), p->d_u64, p->cells);
+    launch_widen_all(st, static_cast<const cpx<float>*>(s), p->d_s64, p->cells);
     HIPCHK(hipGetLastError());
   } else {
     HIPCHK(hipMemcpyAsync(p->d_u64, u, p->cells * 16, hipMemcpyDeviceToDevice, st));
@@ -682,9 +671,8 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
       for (int i = 0; i < B; ++i) act |= hact[i] != 0;
       if (!act) break;
     }
-    hipLaunchKernelGGL(k_backsolve, dim3(inst_blocks(B)), dim3(256), 0, st, k, B);
-    hipLaunchKernelGGL((k_zupdate<R>), dim3(p->row_items.size()), dim3(kThreads), 0, st, k,
-                       static_cast<const cpx<R>*>(p->d_zbasis), p->d_u64);
+    launch_backsolve(B, st, k);
+    launch_zupdate(int(p->row_items.size()), st, k, static_cast<const cpx<R>*>(p->d_zbasis), p->d_u64);
     HIPCHK(hipGetLastError());
   }
   if constexpr (sizeof(R) == 4) {
@@ -768,8 +756,7 @@ cbs_status seed_impl(cbs_plan p, const void* uk, const void* s, int wg, double* 
   q.out2 = static_cast<cpx<R>*>(grad);
   CHK(run_pipeline(p, q, st));
   if (loss) {
-    hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(p->batch)), dim3(256), 0, st, p->d_inst,
-                       p->batch, p->d_partials, loss);
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, loss);
     HIPCHK(hipGetLastError());
   }
   return CBS_OK;
@@ -815,8 +802,6 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
     p->maxn = std::max(p->maxn, n[i]);
   }
   p->cells = off;
-  p->tile = (p->maxn > 512) ? 8 : 16;
-  if (dtype == CBS_C128) p->tile = (p->maxn > 512) ? 4 : 8;
   build_items(p);
 
   auto bail = [&](cbs_status s, const std::string& m) {
@@ -875,12 +860,12 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
     p->d_k2 = p->d_k2_64;
     p->d_inter = p->d_inter64;
   }
-  for (auto& kv : p->col_items_host) {
+  for (int2** d : {&p->d_col_items32, &p->d_col_items64}) {
     void* ptr = nullptr;
-    hipError_t e = hipMalloc(&ptr, std::max<size_t>(kv.second.size() * sizeof(int2), 16));
+    hipError_t e = hipMalloc(&ptr, std::max<size_t>(max_col_items(p) * sizeof(int2), 16));
     if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
     p->owned.push_back(ptr);
-    p->d_col_items[kv.first] = static_cast<int2*>(ptr);
+    *d = static_cast<int2*>(ptr);
   }
 
   // Per-pass twiddle tables w^(q k), w = exp(-2 pi i / (Ns r)), evaluated in
@@ -910,14 +895,9 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
   BAILCHK(hipMemcpyAsync(p->d_tw32, t32.data(), kTwTotal * sizeof(cpx<float>), hipMemcpyHostToDevice, st));
   BAILCHK(hipMemcpyAsync(p->d_row_items, p->row_items.data(), p->row_items.size() * sizeof(int2),
                          hipMemcpyHostToDevice, st));
-  for (auto& kv : p->col_items_host)
-    if (!kv.second.empty())
-      BAILCHK(hipMemcpyAsync(p->d_col_items[kv.first], kv.second.data(), kv.second.size() * sizeof(int2),
-                             hipMemcpyHostToDevice, st));
   if (dtype == CBS_C64) {
     BAILCHK(hipMemcpyAsync(p->d_k2, k2, cells * 8, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, static_cast<const cpx<float>*>(p->d_k2),
-                       p->d_k2_64, cells);
+    launch_widen_all(st, static_cast<const cpx<float>*>(p->d_k2), p->d_k2_64, cells);
     BAILCHK(hipGetLastError());
   } else {
     BAILCHK(hipMemcpyAsync(p->d_k2_64, k2, cells * 16, hipMemcpyDeviceToDevice, st));
@@ -953,9 +933,11 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
     if (!(flags & CBS_FLAG_NO_GUARD) && !(a[i] >= 1e-3 * p->eps[i]))
       return bail(CBS_ERR_ILLCOND,
                   "instance " + std::to_string(i) + ": min|V|/eps below 1e-3 (gamma ~ 0 stalls CBS)");
-  hipError_t e = hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
-                                hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  {
+    cbs_status us = upload_items(p, st);
+    if (us != CBS_OK) { std::string m = g_err; return bail(us, m); }
+  }
+  hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("setup sync: ") + hipGetErrorString(e));
   *out = p;
   return CBS_OK;
@@ -971,11 +953,23 @@ cbs_status cbs_plan_info(cbs_plan p, int64_t* cells, double* k0sq, double* eps) 
   return CBS_OK;
 }
 
-cbs_status cbs_set_tile(cbs_plan p, int columns) {
+cbs_status cbs_set_tile(cbs_plan p, int n, int columns) {
   if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
-  if (!tile_ok(p, columns)) return fail(CBS_ERR_ARG, "tile width not valid for this batch");
-  p->tile = columns;
+  bool any = false;
+  for (int nn : p->n) {
+    if (n != 0 && nn != n) continue;
+    if (!col_tile_valid(nn, columns, p->op_elem()))
+      return fail(CBS_ERR_ARG, "tile width " + std::to_string(columns) + " not available for size " +
+                                   std::to_string(nn));
+    any = true;
+  }
+  if (!any) return fail(CBS_ERR_ARG, "no instance of size " + std::to_string(n) + " in the plan");
+  for (int nn : p->n)
+    if (n == 0 || nn == n) p->ctile[nn] = columns;
+  build_items(p);
   drop_graphs(p);
+  CHK(upload_items(p, nullptr));
+  HIPCHK(hipDeviceSynchronize());
   return CBS_OK;
 }
 
@@ -1074,48 +1068,82 @@ cbs_status cbs_loss_seed(cbs_plan p, const void* u_k, const void* s, int weight_
   return seed_impl<double>(p, u_k, s, weight_gamma, loss, lam_out, grad_k2, st);
 }
 
-cbs_status cbs_autotune(cbs_plan p, int* tile_out, void* stream) {
+cbs_status cbs_autotune(cbs_plan p, int32_t* tiles, void* stream) {
   if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int keep = p->tile;
-  int best = keep;
-  double best_t = 1e300;
-  HIPCHK(hipMemsetAsync(p->d_e, 0, p->cells * p->op_elem(), st));
+  HIPCHK(hipMemsetAsync(p->d_inter, 0, p->cells * p->op_elem(), st));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (int t : {2, 4, 8, 16, 32}) {
-    if (!tile_ok(p, t)) continue;
-    p->tile = t;
-    // time a complete apply of zeros (u = e scratch) into the t scratch
-    cbs_status rc = CBS_OK;
-    for (int rep = 0; rep < 3 && rc == CBS_OK; ++rep) rc = cbs_apply(p, p->d_e, nullptr, p->d_t, stream);
-    if (rc != CBS_OK) break;
-    HIPCHK(hipEventRecord(e0, st));
-    const int reps = 10;
-    for (int rep = 0; rep < reps && rc == CBS_OK; ++rep) rc = cbs_apply(p, p->d_e, nullptr, p->d_t, stream);
-    HIPCHK(hipEventRecord(e1, st));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (rc == CBS_OK && ms < best_t) {
-      best_t = ms;
-      best = t;
+  std::vector<int> classes;
+  for (int n : p->n)
+    if (std::find(classes.begin(), classes.end(), n) == classes.end()) classes.push_back(n);
+  std::ostringstream rec;
+  rec << "{\"dtype\": \"" << (p->dtype == CBS_C64 ? "c64" : "c128") << "\", \"tiles\": {";
+  bool first = true;
+  cbs_status rc = CBS_OK;
+  for (int n : classes) {
+    const int c0 = col_tile_default(n);
+    int best = c0;
+    double best_ms = 1e300;
+    for (int c : {c0 / 2, c0, c0 * 2}) {
+      if (!col_tile_valid(n, c, p->op_elem())) continue;
+      p->ctile[n] = c;
+      build_items(p);
+      rc = upload_items(p, st);
+      if (rc != CBS_OK) break;
+      // the column items of size class n form one contiguous range
+      const std::vector<int2>& items = p->dtype == CBS_C64 ? p->col_items32 : p->col_items64;
+      size_t lo = items.size(), hi = 0;
+      for (size_t k = 0; k < items.size(); ++k)
+        if (p->n[items[k].x] == n) {
+          lo = std::min(lo, k);
+          hi = k + 1;
+        }
+      auto launch = [&]() {
+        if (p->dtype == CBS_C64) {
+          Params<float> q = base_params<float>(p);
+          q.items = p->d_col_items32 + lo;
+          launch_col(int(hi - lo), p->col_lds32, st, q);
+        } else {
+          Params<double> q = base_params<double>(p);
+          q.items = p->d_col_items64 + lo;
+          launch_col(int(hi - lo), p->col_lds64, st, q);
+        }
+      };
+      for (int rep = 0; rep < 3; ++rep) launch();
+      HIPCHK(hipEventRecord(e0, st));
+      const int reps = 20;
+      for (int rep = 0; rep < reps; ++rep) launch();
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipGetLastError());
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms / reps < best_ms) {
+        best_ms = ms / reps;
+        best = c;
+      }
     }
+    if (rc != CBS_OK) break;
+    p->ctile[n] = best;
+    rec << (first ? "" : ", ") << "\"" << n << "\": {\"tile\": " << best << ", \"col_ms\": " << best_ms << "}";
+    first = false;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  p->tile = best;
+  if (rc != CBS_OK) return rc;
+  build_items(p);
   drop_graphs(p);
+  CHK(upload_items(p, st));
+  HIPCHK(hipStreamSynchronize(st));
+  rec << "}}";
   if (const char* path = std::getenv("CBS_AUTOTUNE_CACHE")) {
-    std::ostringstream key;
-    key << (p->dtype == CBS_C64 ? "c64" : "c128") << ":" << p->batch;
-    for (int nn : p->n) key << "," << nn;
     std::ofstream f(path, std::ios::app);
-    if (f) f << "{\"key\": \"" << key.str() << "\", \"tile\": " << best << ", \"ms_per_apply\": "
-             << best_t / 10.0 << "}\n";
+    if (f) f << rec.str() << "\n";
   }
-  if (tile_out) *tile_out = best;
+  if (tiles)
+    for (int i = 0; i < p->batch; ++i) tiles[i] = p->inst[i].ctile;
   return CBS_OK;
 }
 

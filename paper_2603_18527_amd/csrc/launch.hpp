@@ -1,0 +1,40 @@
+// Host-side launchers of the CBS kernels.  The kernels live in separate
+// translation units (ops_f32.hip, ops_f64.hip, misc.hip) that are compiled in
+// parallel; the host planner only sees these declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "params.hpp"
+
+namespace cbs {
+
+// mode 0: prologue + forward rows, 1: inverse rows + epilogue,
+// 2: fused inverse rows + CBS update + next prologue + forward rows
+void launch_row(int mode, int grid, hipStream_t st, const Params<float>& p);
+void launch_row(int mode, int grid, hipStream_t st, const Params<double>& p);
+void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
+void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
+void launch_pointwise(int grid, hipStream_t st, const PwParams<float>& p);
+void launch_pointwise(int grid, hipStream_t st, const PwParams<double>& p);
+void launch_zupdate(int grid, hipStream_t st, const KryParams& k, const cpx<float>* z, cpx<double>* x);
+void launch_zupdate(int grid, hipStream_t st, const KryParams& k, const cpx<double>* z, cpx<double>* x);
+
+void launch_instance_sums(int batch, hipStream_t st, const InstDesc* inst, const double* partials,
+                          double* out);
+void launch_check64(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
+                    const double* partials);
+void launch_check32(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
+                    const double* partials);
+void launch_set_bnorm(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
+                      const double* partials);
+void launch_stats(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
+                  const cpx<double>* k2, double* partials, int phase);
+void launch_widen_all(hipStream_t st, const cpx<float>* in, cpx<double>* out, long long count);
+void launch_dots(int grid, hipStream_t st, const KryParams& k);
+void launch_dots_finish(int batch, hipStream_t st, const KryParams& k);
+void launch_cgs_update(int grid, hipStream_t st, const KryParams& k);
+void launch_givens(int batch, hipStream_t st, const KryParams& k);
+void launch_backsolve(int batch, hipStream_t st, const KryParams& k);
+void launch_fg_restart(int batch, hipStream_t st, const KryParams& k, int first);
+
+}  // namespace cbs

@@ -1,0 +1,410 @@
+// Per-instance reductions, solver bookkeeping, setup statistics and the FP64
+// Krylov kernels of FGMRES (Arnoldi with classical Gram-Schmidt applied twice,
+// Givens rotations, back substitution).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace cbs {
+
+// ---- per-instance reductions and solver bookkeeping -------------------------------
+
+// norm2[i] = sum of the instance's partials (fixed order => deterministic).
+__global__ void k_instance_sums(const InstDesc* inst, int batch, const double* partials,
+                                double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const InstDesc d = inst[i];
+  double s = 0.0;
+  for (int k = 0; k < d.nparts; ++k) s += partials[d.part_off + k];
+  out[i] = s;
+}
+
+// After the FP64 residual of the current iterate (start of a chunk).
+__global__ void k_check64(IterState st, const InstDesc* inst, int batch,
+                          const double* partials) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const int s0 = st.status[i];
+  if (s0 == ST_CONVERGED || s0 == ST_MAXIT || s0 == ST_DIVERGED) {
+    st.chunk_active[i] = 0;
+    return;
+  }
+  const InstDesc d = inst[i];
+  double sum = 0.0;
+  for (int k = 0; k < d.nparts; ++k) sum += partials[d.part_off + k];
+  const double bn = st.bnorm[i] > 0.0 ? st.bnorm[i] : 1.0;
+  const double rel = sqrt(sum) / bn;
+  st.relres[i] = rel;
+  int s = ST_RUNNING;
+  if (!isfinite(rel)) s = ST_DIVERGED;
+  else if (rel <= st.rtol[0]) s = ST_CONVERGED;
+  else if (st.iters[i] >= st.max_sweeps[0]) s = ST_MAXIT;
+  st.status[i] = s;
+  st.chunk_active[i] = (s == ST_RUNNING) ? 1 : 0;
+  if (s == ST_RUNNING) st.iters[i] += 1;  // the pointwise first sweep that follows
+}
+
+// After an FP32 sweep of the correction: count it and test the estimate.
+__global__ void k_check32(IterState st, const InstDesc* inst, int batch,
+                          const double* partials) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  if (st.status[i] != ST_RUNNING) return;
+  const InstDesc d = inst[i];
+  double sum = 0.0;
+  for (int k = 0; k < d.nparts; ++k) sum += partials[d.part_off + k];
+  const double bn = st.bnorm[i] > 0.0 ? st.bnorm[i] : 1.0;
+  const double rel = sqrt(sum) / bn;
+  st.est[i] = rel;
+  st.iters[i] += 1;
+  if (!(rel > st.rtol[0]) || st.iters[i] >= st.max_sweeps[0]) st.status[i] = ST_PENDING;
+}
+
+// bnorm[i] = sqrt(sum of partials)
+__global__ void k_set_bnorm(IterState st, const InstDesc* inst, int batch,
+                            const double* partials) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const InstDesc d = inst[i];
+  double sum = 0.0;
+  for (int k = 0; k < d.nparts; ++k) sum += partials[d.part_off + k];
+  st.bnorm[i] = sqrt(sum);
+}
+
+// ---- setup statistics ------------------------------------------------------------------
+// phase 0: (min Re k2, max Re k2); phase 1: max |k2 - k0^2|; phase 2: min |k2 - k0^2 - i eps|
+__global__ __launch_bounds__(kThreads) void k_stats(const InstDesc* inst, const int2* items,
+                                                    const cpx<double>* k2, double* partials,
+                                                    int phase) {
+  __shared__ double red[kThreads / 64];
+  const int2 w = items[blockIdx.x];
+  const InstDesc d = inst[w.x];
+  const int n = d.n;
+  const int rpw = row_rpw(n);
+  const int nrows = min(rpw, n - w.y);
+  const long long base = d.off + (long long)w.y * n;
+  const int cnt = nrows * n;
+  double a = phase == 0 ? 1e300 : (phase == 1 ? 0.0 : 1e300);
+  double b = -1e300;
+  for (int j = threadIdx.x; j < cnt; j += kThreads) {
+    const cpx<double> k = k2[base + j];
+    if (phase == 0) {
+      a = fmin(a, k.x);
+      b = fmax(b, k.x);
+    } else if (phase == 1) {
+      a = fmax(a, hypot(k.x - d.k0sq, k.y));
+    } else {
+      a = fmin(a, hypot(k.x - d.k0sq, k.y - d.eps));
+    }
+  }
+  // min/max reductions via the wave shuffles
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double oa = __shfl_xor(a, o, 64);
+    const double ob = __shfl_xor(b, o, 64);
+    a = (phase == 1) ? fmax(a, oa) : fmin(a, oa);
+    b = fmax(b, ob);
+  }
+  __shared__ double redb[kThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wid] = a;
+    redb[wid] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kThreads / 64; ++q) {
+      a = (phase == 1) ? fmax(a, red[q]) : fmin(a, red[q]);
+      b = fmax(b, redb[q]);
+    }
+    const int slot = d.part_off + w.y / rpw;
+    partials[2 * slot] = a;
+    partials[2 * slot + 1] = b;
+  }
+}
+
+// ---- FGMRES: FP64 Arnoldi, CGS2, Givens least squares -------------------------------
+//
+// Per-instance small dense state (doubles), restart length m:
+//   H  (m+1) x m complex, row-major        at 0
+//   cs m real, sn m complex                 (Givens rotations)
+//   g  m+1 complex                          (rotated beta e1)
+//   y  m complex                            (least-squares solution)
+//   coef m+1 complex                        (current Gram-Schmidt coefficients)
+//   sc 8 scalars: [0] beta [1] bnorm [2] estimate
+// Partial dot products <v_q, w> for q = 0..j over one row item.
+__global__ __launch_bounds__(kThreads) void k_dots(KryParams k) {
+  __shared__ double red[kThreads / 64];
+  const int2 it = k.items[blockIdx.x];
+  if (!k.active[it.x]) return;
+  const InstDesc d = k.inst[it.x];
+  long long base;
+  int cnt, slot;
+  item_range(d, it.y, base, cnt, slot);
+  constexpr int PER = 2048 / kThreads;  // row_rpw(N) * N <= 2048 for every N
+  cpx<double> wv[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int j = threadIdx.x + e * kThreads;
+    wv[e] = j < cnt ? k.w[base + j] : cpx<double>{0.0, 0.0};
+  }
+  for (int q = 0; q <= k.j; ++q) {
+    const cpx<double>* v = k.vbasis + q * k.cells;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int j = threadIdx.x + e * kThreads;
+      if (j < cnt) {
+        const cpx<double> a = v[base + j];
+        re += a.x * wv[e].x + a.y * wv[e].y;
+        im += a.x * wv[e].y - a.y * wv[e].x;
+      }
+    }
+    const double sre = block_sum(re, red);
+    __syncthreads();
+    const double sim = block_sum(im, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      k.dots[2LL * ((long long)slot * (k.m + 1) + q)] = sre;
+      k.dots[2LL * ((long long)slot * (k.m + 1) + q) + 1] = sim;
+    }
+  }
+}
+
+// coef_q = sum of partial dots; H[q][j] (+)= coef_q.
+__global__ void k_dots_finish(KryParams k, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch || !k.active[i]) return;
+  const InstDesc d = k.inst[i];
+  const KryLayout L{k.m};
+  double* s = k.kry + i * k.kstride;
+  for (int q = 0; q <= k.j; ++q) {
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < d.nparts; ++t) {
+      re += k.dots[2LL * ((long long)(d.part_off + t) * (k.m + 1) + q)];
+      im += k.dots[2LL * ((long long)(d.part_off + t) * (k.m + 1) + q) + 1];
+    }
+    s[L.coef() + 2 * q] = re;
+    s[L.coef() + 2 * q + 1] = im;
+    if (k.pass == 0) {
+      s[L.h(q, k.j)] = re;
+      s[L.h(q, k.j) + 1] = im;
+    } else {
+      s[L.h(q, k.j)] += re;
+      s[L.h(q, k.j) + 1] += im;
+    }
+  }
+}
+
+// w -= sum_q coef_q v_q ; also the partial |w|^2 for the norm that follows.
+__global__ __launch_bounds__(kThreads) void k_cgs_update(KryParams k) {
+  __shared__ double red[kThreads / 64];
+  const int2 it = k.items[blockIdx.x];
+  if (!k.active[it.x]) return;
+  const InstDesc d = k.inst[it.x];
+  long long base;
+  int cnt, slot;
+  item_range(d, it.y, base, cnt, slot);
+  const KryLayout L{k.m};
+  const double* s = k.kry + it.x * k.kstride + L.coef();
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < cnt; j += kThreads) {
+    cpx<double> wv = k.w[base + j];
+    for (int q = 0; q <= k.j; ++q) {
+      const cpx<double> v = k.vbasis[q * k.cells + base + j];
+      const cpx<double> c{s[2 * q], s[2 * q + 1]};
+      wv = wv - cmul(c, v);
+    }
+    k.w[base + j] = wv;
+    acc += cabs2(wv);
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) k.partials[slot] = t;
+}
+
+// h_{j+1,j} = ||w||; scale = 1/h; Givens update and residual estimate.
+__global__ void k_givens(KryParams k, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch || !k.active[i]) return;
+  const InstDesc d = k.inst[i];
+  const KryLayout L{k.m};
+  double* s = k.kry + i * k.kstride;
+  double sum = 0.0;
+  for (int t = 0; t < d.nparts; ++t) sum += k.partials[d.part_off + t];
+  const double hn = sqrt(sum);
+  const int j = k.j;
+  s[L.h(j + 1, j)] = hn;
+  s[L.h(j + 1, j) + 1] = 0.0;
+  k.scale[i] = hn > 0.0 ? 1.0 / hn : 0.0;
+  // apply previous rotations to column j
+  for (int q = 0; q < j; ++q) {
+    const double c = s[L.cs() + q];
+    const cpx<double> sn{s[L.sn() + 2 * q], s[L.sn() + 2 * q + 1]};
+    const cpx<double> a{s[L.h(q, j)], s[L.h(q, j) + 1]};
+    const cpx<double> b{s[L.h(q + 1, j)], s[L.h(q + 1, j) + 1]};
+    const cpx<double> na = cscale(a, c) + cmul(sn, b);
+    const cpx<double> nb = cscale(b, c) - cmul(cconj(sn), a);
+    s[L.h(q, j)] = na.x;
+    s[L.h(q, j) + 1] = na.y;
+    s[L.h(q + 1, j)] = nb.x;
+    s[L.h(q + 1, j) + 1] = nb.y;
+  }
+  // new rotation zeroing h_{j+1,j}
+  const cpx<double> a{s[L.h(j, j)], s[L.h(j, j) + 1]};
+  const cpx<double> b{s[L.h(j + 1, j)], s[L.h(j + 1, j) + 1]};
+  const double aa = sqrt(cabs2(a));
+  const double nu = sqrt(cabs2(a) + cabs2(b));
+  double c;
+  cpx<double> sn;
+  if (aa == 0.0) {
+    c = 0.0;
+    sn = cpx<double>{1.0, 0.0};
+  } else {
+    c = aa / nu;
+    sn = cscale(cmul(a, cconj(b)), 1.0 / (aa * nu));
+  }
+  s[L.cs() + j] = c;
+  s[L.sn() + 2 * j] = sn.x;
+  s[L.sn() + 2 * j + 1] = sn.y;
+  const cpx<double> na = cscale(a, c) + cmul(sn, b);
+  s[L.h(j, j)] = na.x;
+  s[L.h(j, j) + 1] = na.y;
+  s[L.h(j + 1, j)] = 0.0;
+  s[L.h(j + 1, j) + 1] = 0.0;
+  const cpx<double> gj{s[L.g() + 2 * j], s[L.g() + 2 * j + 1]};
+  const cpx<double> g1 = cscale(cmul(cconj(sn), gj), -1.0);
+  const cpx<double> g0 = cscale(gj, c);
+  s[L.g() + 2 * j] = g0.x;
+  s[L.g() + 2 * j + 1] = g0.y;
+  s[L.g() + 2 * (j + 1)] = g1.x;
+  s[L.g() + 2 * (j + 1) + 1] = g1.y;
+  const double est = sqrt(cabs2(g1)) / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
+  s[L.sc() + 2] = est;
+  k.jend[i] = j + 1;
+  k.iters[i] += 1;
+  if (!(est > k.rtol[0]) || hn == 0.0 || k.iters[i] >= k.max_iters[0] || j + 1 >= k.m)
+    k.active[i] = 0;
+}
+
+// Back substitution H[0:jend, 0:jend] y = g[0:jend] (H upper triangular after rotations).
+__global__ void k_backsolve(KryParams k, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const int n = k.jend[i];
+  if (n <= 0) return;
+  const KryLayout L{k.m};
+  double* s = k.kry + i * k.kstride;
+  for (int r = n - 1; r >= 0; --r) {
+    cpx<double> acc{s[L.g() + 2 * r], s[L.g() + 2 * r + 1]};
+    for (int c = r + 1; c < n; ++c) {
+      const cpx<double> h{s[L.h(r, c)], s[L.h(r, c) + 1]};
+      const cpx<double> yc{s[L.y() + 2 * c], s[L.y() + 2 * c + 1]};
+      acc = acc - cmul(h, yc);
+    }
+    const cpx<double> h{s[L.h(r, r)], s[L.h(r, r) + 1]};
+    const double den = cabs2(h);
+    const cpx<double> yr = den > 0.0 ? cscale(cmulc(h, acc), 1.0 / den) : cpx<double>{0.0, 0.0};
+    s[L.y() + 2 * r] = yr.x;
+    s[L.y() + 2 * r + 1] = yr.y;
+  }
+}
+
+// After the FP64 true residual r = G(V x + s) - x was written to v_0 with its
+// partial norms: decide convergence and start a new cycle.
+__global__ void k_fg_restart(KryParams k, int batch, int first) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const KryLayout L{k.m};
+  double* s = k.kry + i * k.kstride;
+  if (first) {  // partials hold |G s|^2: store ||G s||
+    const InstDesc d0 = k.inst[i];
+    double sum0 = 0.0;
+    for (int t = 0; t < d0.nparts; ++t) sum0 += k.partials[d0.part_off + t];
+    s[L.sc() + 1] = sqrt(sum0);
+    return;
+  }
+  k.jend[i] = 0;
+  const int st = k.status[i];
+  if (st != ST_RUNNING) {
+    k.active[i] = 0;
+    return;
+  }
+  const InstDesc d = k.inst[i];
+  double sum = 0.0;
+  for (int t = 0; t < d.nparts; ++t) sum += k.partials[d.part_off + t];
+  const double beta = sqrt(sum);
+  const double rel = beta / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
+  k.relres[i] = rel;
+  s[L.sc() + 0] = beta;
+  int ns = ST_RUNNING;
+  if (!isfinite(rel)) ns = ST_DIVERGED;
+  else if (rel <= k.rtol[0]) ns = ST_CONVERGED;
+  else if (k.iters[i] >= k.max_iters[0]) ns = ST_MAXIT;
+  k.status[i] = ns;
+  k.active[i] = ns == ST_RUNNING ? 1 : 0;
+  k.scale[i] = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int q = 0; q <= k.m; ++q) {
+    s[L.g() + 2 * q] = q == 0 ? beta : 0.0;
+    s[L.g() + 2 * q + 1] = 0.0;
+  }
+}
+
+__global__ void k_widen_all(const cpx<float>* in, cpx<double>* out, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    const cpx<float> v = in[i];
+    out[i] = cpx<double>{double(v.x), double(v.y)};
+  }
+}
+
+
+// ---- launchers -----------------------------------------------------------------
+
+static int inst_blocks(int batch) { return (batch + 255) / 256; }
+
+void launch_instance_sums(int batch, hipStream_t st, const InstDesc* inst, const double* partials,
+                          double* out) {
+  hipLaunchKernelGGL(k_instance_sums, dim3(inst_blocks(batch)), dim3(256), 0, st, inst, batch,
+                     partials, out);
+}
+void launch_check64(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
+                    const double* partials) {
+  hipLaunchKernelGGL(k_check64, dim3(inst_blocks(batch)), dim3(256), 0, st, is, inst, batch, partials);
+}
+void launch_check32(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
+                    const double* partials) {
+  hipLaunchKernelGGL(k_check32, dim3(inst_blocks(batch)), dim3(256), 0, st, is, inst, batch, partials);
+}
+void launch_set_bnorm(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
+                      const double* partials) {
+  hipLaunchKernelGGL(k_set_bnorm, dim3(inst_blocks(batch)), dim3(256), 0, st, is, inst, batch, partials);
+}
+void launch_stats(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
+                  const cpx<double>* k2, double* partials, int phase) {
+  hipLaunchKernelGGL(k_stats, dim3(grid), dim3(kThreads), 0, st, inst, items, k2, partials, phase);
+}
+void launch_widen_all(hipStream_t st, const cpx<float>* in, cpx<double>* out, long long count) {
+  hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, in, out, count);
+}
+void launch_dots(int grid, hipStream_t st, const KryParams& k) {
+  hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kThreads), 0, st, k);
+}
+void launch_dots_finish(int batch, hipStream_t st, const KryParams& k) {
+  hipLaunchKernelGGL(k_dots_finish, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);
+}
+void launch_cgs_update(int grid, hipStream_t st, const KryParams& k) {
+  hipLaunchKernelGGL(k_cgs_update, dim3(grid), dim3(kThreads), 0, st, k);
+}
+void launch_givens(int batch, hipStream_t st, const KryParams& k) {
+  hipLaunchKernelGGL(k_givens, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);
+}
+void launch_backsolve(int batch, hipStream_t st, const KryParams& k) {
+  hipLaunchKernelGGL(k_backsolve, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);
+}
+void launch_fg_restart(int batch, hipStream_t st, const KryParams& k, int first) {
+  hipLaunchKernelGGL(k_fg_restart, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch, first);
+}
+
+}  // namespace cbs

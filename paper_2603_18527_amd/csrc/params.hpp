@@ -1,0 +1,165 @@
+// Data structures shared by the host planner and the GPU kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+
+namespace cbs {
+
+#define CBS_FOR_EACH_N(X) X(16) X(32) X(64) X(128) X(192) X(256) X(288) X(384) X(512) X(1024)
+
+constexpr int kThreads = 256;
+constexpr int kRowLds = 2304;  // complex elements per row-kernel workgroup (2048 + skew)
+
+// Threads per row transform and rows per row-kernel workgroup.
+__host__ __device__ constexpr int row_tpf(int n) { return n / 8; }
+__host__ __device__ constexpr int row_rpw(int n) {
+  return (kThreads / row_tpf(n)) < n ? (kThreads / row_tpf(n)) : n;
+}
+
+struct InstDesc {
+  long long off;  // element offset of the instance in packed fields
+  int n;
+  int part_off;  // first partial-sum slot (one per row work item)
+  int nparts;
+  int ctile;     // column tile width: FP32 kernels (ctile) and FP64 kernels (ctile64)
+  int ctile64;
+  int pad;
+  double k0sq;
+  double eps;
+};
+
+enum Pro { PRO_VU_S = 0, PRO_CONJG_A = 1, PRO_SEED = 2, PRO_U = 3 };
+enum Sym { SYM_GREEN = 0, SYM_GREEN_CONJ = 1, SYM_LAP = 2 };
+enum Epi {
+  EPI_STORE = 0,
+  EPI_RESID = 1,
+  EPI_SWEEP = 2,
+  EPI_BZ_WIDE = 3,
+  EPI_ADJ = 4,
+  EPI_SEED = 5,
+  EPI_LAP = 6
+};
+// Instance masks: which status values let an instance run.
+enum MaskMode { MASK_RUNNING = 0, MASK_NOT_FINAL = 1, MASK_NONZERO = 2 };
+enum InstStatus { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_DIVERGED = 3, ST_PENDING = 4 };
+
+template <typename R>
+struct Params {
+  const InstDesc* inst;
+  const int2* items;
+  const cpx<R>* k2;
+  const cpx<R>* tw;
+  const cpx<R>* u;
+  const cpx<R>* s;
+  const cpx<R>* rhs;
+  const cpx<R>* a;
+  const cpx<R>* b;
+  cpx<R>* inter;
+  cpx<R>* out;
+  cpx<R>* out2;
+  cpx<float>* out_narrow;
+  cpx<double>* out_wide;
+  double* partials;
+  const int* mask;
+  int mask_mode;
+  int pro, sym, epi;
+  int weight_gamma;
+};
+
+
+// ---- column tiles ------------------------------------------------------------------
+//
+// Column stride in LDS for a tile of C columns of length n: offset from a
+// multiple of 32 elements by 32/C so the C columns spread over the banks.
+__host__ __device__ constexpr int col_stride(int n, int c) {
+  return ((lds_len(n) + 31) / 32) * 32 + 32 / c;
+}
+__host__ __device__ constexpr int col_lds_elems(int n, int c) { return c * col_stride(n, c); }
+constexpr int kColLdsBytes = 64 * 1024;
+// Default tile: about 2048 elements per workgroup (C * n ~ 8 elements per thread).
+__host__ __device__ constexpr int col_tile_default(int n) {
+  int c = 2;
+  while (c * 2 <= 32 && c * 2 * n <= 2048 && n % (c * 2) == 0) c *= 2;
+  return c;
+}
+// Tiles a kernel is compiled for at size n: the default, half and double.
+__host__ __device__ constexpr bool col_tile_valid(int n, int c, int elem_bytes) {
+  const int c0 = col_tile_default(n);
+  return (c == c0 || c == c0 / 2 || c == c0 * 2) && c >= 2 && c <= 32 && n % c == 0 &&
+         col_lds_elems(n, c) * elem_bytes <= kColLdsBytes;
+}
+
+enum PwOp {
+  PW_GAMMA = 0,        // e_out = gamma * e_in
+  PW_FIRST64 = 1,      // c_out = (R) src64; e_out = gamma * c_out
+  PW_ADD_WIDE = 2,     // x64 += e_in
+  PW_WIDEN = 3,        // x64 = e_in
+  PW_NARROW = 4,       // e_out = (R) x64
+  PW_SCALE64 = 5       // x64 *= scale[instance] (FP64)
+};
+
+template <typename R>
+struct PwParams {
+  const InstDesc* inst;
+  const int2* items;
+  const cpx<R>* k2;
+  const cpx<double>* src64;
+  cpx<double>* x64;
+  const cpx<R>* e_in;
+  cpx<R>* e_out;
+  cpx<R>* c_out;
+  const double* scale;  // per-instance factor for PW_SCALE64
+  const int* mask;
+  int mask_mode;
+  int op;
+};
+
+struct IterState {
+  int* status;
+  int* iters;
+  int* chunk_active;
+  double* relres;   // FP64-verified relative residual
+  double* est;      // latest FP32 estimate
+  double* bnorm;    // ||G s|| per instance
+  const double* rtol;
+  const int* max_sweeps;
+};
+
+struct KryLayout {
+  int m;
+  __host__ __device__ long long h(int r, int c) const { return 2LL * (r * m + c); }
+  __host__ __device__ long long cs() const { return 2LL * (m + 1) * m; }
+  __host__ __device__ long long sn() const { return cs() + m; }
+  __host__ __device__ long long g() const { return sn() + 2LL * m; }
+  __host__ __device__ long long y() const { return g() + 2LL * (m + 1); }
+  __host__ __device__ long long coef() const { return y() + 2LL * m; }
+  __host__ __device__ long long sc() const { return coef() + 2LL * (m + 1); }
+  __host__ __device__ long long size() const { return sc() + 8; }
+};
+
+struct KryParams {
+  const InstDesc* inst;
+  const int2* items;
+  const cpx<double>* vbasis;  // (m+1) fields of `cells` elements
+  long long cells;
+  cpx<double>* w;             // vector being orthogonalised
+  double* kry;                // per-instance state, stride kstride
+  long long kstride;
+  int m;
+  int j;                      // current Arnoldi column
+  double* dots;               // per partial slot: (m+1) complex partial dot products
+  double* partials;           // per partial slot: one double
+  double* scale;              // per instance
+  int* active;                // per instance: 1 while in the Arnoldi cycle
+  int* jend;                  // per instance: Arnoldi steps done this cycle
+  int* iters;                 // per instance: total Arnoldi steps
+  int* status;                // per instance: solver status
+  double* relres;             // per instance: last FP64 true relative residual
+  const double* rtol;
+  const int* max_iters;
+  int pass;                   // Gram-Schmidt pass 0 (sets H) or 1 (adds)
+};
+
+
+}  // namespace cbs

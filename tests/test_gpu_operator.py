@@ -171,20 +171,31 @@ def test_deterministic_repeat():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("tile", [2, 4, 8, 16, 32])
-def test_column_tile_widths_agree(tile):
-    # a 32-column tile of 256-row columns would exceed the 64 KB LDS budget
-    sizes = (64, 128, 256) if tile < 32 else (32, 64, 128)
+@pytest.mark.parametrize("which", ["half", "double"])
+def test_column_tile_widths_agree(which):
+    # every compiled tile width (half / default / double of ~2048/N columns)
+    # gives the same apply; the autotuner picks one of them per size
+    sizes = (64, 128, 256, 512, 1024)
     probs = [random_problem(n, seed=300 + n) for n in sizes]
     plan, k2 = plan_for(probs)
     u, s = _inputs(probs, cbs.CBS_C64, seed=11)
     ref = plan.apply(u, s)
-    plan.set_tile(tile)
+    default = {16: 16, 32: 32, 64: 32, 128: 16, 192: 8, 256: 8, 288: 4, 384: 4, 512: 4, 1024: 2}
+    for n in sizes:
+        c = default[n] // 2 if which == "half" else default[n] * 2
+        try:
+            plan.set_tile(c, n=n)
+        except cbs.CbsError as e:
+            assert e.status == cbs.CBS_ERR_ARG   # width not compiled for this size
     y = plan.apply(u, s)
     torch.cuda.synchronize()
     assert rel_err(y.cpu(), ref.cpu()) <= 1e-6
-    best = plan.autotune()
-    assert best in (2, 4, 8, 16, 32)
+    tiles = plan.autotune()
+    for n, c in zip(sizes, tiles):
+        assert c in (default[n] // 2, default[n], default[n] * 2)
+    y2 = plan.apply(u, s)
+    torch.cuda.synchronize()
+    assert rel_err(y2.cpu(), ref.cpu()) <= 1e-6
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
