@@ -132,6 +132,17 @@ cbs_status cbs_residual(cbs_plan plan, const void* u, const void* s, const void*
 cbs_status cbs_sweep(cbs_plan plan, void* u, const void* s, int count, double* norm2, void* stream);
 
 /*
+ * cbs_helmholtz_residual -- physical residual r = s - A u with the Fourier
+ *   pseudospectral A u = F^-1(|xi|^2 F u) - k^2 u (App. E, relation to A;
+ *   Sec. 5 stops on ||s - A u|| / ||s||).  One transform pair per call.
+ *   u required; s nullable (zero); r nullable (not stored); norm2 nullable
+ *   DEVICE double[batch]: per-instance sum |r|^2 in FP64.  r must not alias
+ *   u or s.
+ */
+cbs_status cbs_helmholtz_residual(cbs_plan plan, const void* u, const void* s, void* r,
+                                  double* norm2, void* stream);
+
+/*
  * cbs_iterate -- stationary CBS until ||G(V u + s) - u|| / ||G s|| <= rtol
  *   per instance (Sec. 3.1, Eq. CBS; the paper's stopping rule, Sec. 5, is
  *   measured in these preconditioned coordinates).

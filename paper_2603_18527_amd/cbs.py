@@ -41,6 +41,7 @@ SIGNATURES = {
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "cbs_helmholtz_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _vp, _vp, _vp, _i32, _vp]),
     "fgmres_solve": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "cbs_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -189,6 +190,21 @@ class Plan:
         _check(load().cbs_residual(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
                                    _ptr(self._field(rhs, "rhs")), _ptr(r), _ptr(n2), _stream(stream)))
         return r, n2
+
+    def helmholtz_residual(self, u, s, out=None, norms=True, store=True, stream=None):
+        """r = s - A u (physical residual) and per-instance sums |r|^2."""
+        r = (self.empty() if out is None else self._field(out, "out")) if store else None
+        n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None
+        _check(load().cbs_helmholtz_residual(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                             _ptr(r), _ptr(n2), _stream(stream)))
+        return r, n2
+
+    def physical_relres(self, u, s, stream=None):
+        """The paper's rTol = ||s - A u|| / ||s|| per instance (FP64 sums)."""
+        _, n2 = self.helmholtz_residual(u, s, norms=True, store=False, stream=stream)
+        sn = torch.stack([torch.linalg.vector_norm(x.to(torch.complex128))
+                          for x in unpack(s, self.sizes)])
+        return (torch.sqrt(n2) / sn).cpu().tolist()
 
     def sweep(self, u, s, count=1, norms=False, stream=None):
         n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None

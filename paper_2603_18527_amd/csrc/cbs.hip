@@ -1002,6 +1002,37 @@ cbs_status cbs_residual(cbs_plan p, const void* u, const void* s, const void* rh
   return residual_impl<double>(p, u, s, rhs, r, norm2, st);
 }
 
+cbs_status cbs_helmholtz_residual(cbs_plan p, const void* u, const void* s, void* r, double* norm2,
+                                  void* stream) {
+  if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
+  if (r && (r == u || r == s)) return fail(CBS_ERR_ARG, "r must not alias u or s");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) {
+    Params<float> q = base_params<float>(p);
+    q.u = static_cast<const cpx<float>*>(u);
+    q.s = static_cast<const cpx<float>*>(s);
+    q.out = static_cast<cpx<float>*>(r);
+    q.pro = PRO_U;
+    q.sym = SYM_LAP;
+    q.epi = EPI_LAP;
+    CHK(run_pipeline(p, q, st));
+  } else {
+    Params<double> q = base_params<double>(p);
+    q.u = static_cast<const cpx<double>*>(u);
+    q.s = static_cast<const cpx<double>*>(s);
+    q.out = static_cast<cpx<double>*>(r);
+    q.pro = PRO_U;
+    q.sym = SYM_LAP;
+    q.epi = EPI_LAP;
+    CHK(run_pipeline(p, q, st));
+  }
+  if (norm2) {
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
+    HIPCHK(hipGetLastError());
+  }
+  return CBS_OK;
+}
+
 cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm2, void* stream) {
   if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");

@@ -9,31 +9,44 @@
 namespace cbs {
 
 // ---- per-instance reductions and solver bookkeeping -------------------------------
+//
+// One wavefront per instance: lane l sums partial slots l, l+64, ... and the
+// wave is reduced by a fixed shuffle tree, so every sum is deterministic.
+// Lane 0 then does the instance's bookkeeping.
+
+__device__ __forceinline__ int wave_instance() {
+  return int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+}
+
+__device__ __forceinline__ double instance_sum(const double* partials, const InstDesc& d) {
+  double s = 0.0;
+  for (int k = threadIdx.x & 63; k < d.nparts; k += 64) s += partials[d.part_off + k];
+  return wave_sum(s);
+}
 
 // norm2[i] = sum of the instance's partials (fixed order => deterministic).
 __global__ void k_instance_sums(const InstDesc* inst, int batch, const double* partials,
                                 double* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = wave_instance();
   if (i >= batch) return;
   const InstDesc d = inst[i];
-  double s = 0.0;
-  for (int k = 0; k < d.nparts; ++k) s += partials[d.part_off + k];
-  out[i] = s;
+  const double s = instance_sum(partials, d);
+  if ((threadIdx.x & 63) == 0) out[i] = s;
 }
 
 // After the FP64 residual of the current iterate (start of a chunk).
 __global__ void k_check64(IterState st, const InstDesc* inst, int batch,
                           const double* partials) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = wave_instance();
   if (i >= batch) return;
   const int s0 = st.status[i];
   if (s0 == ST_CONVERGED || s0 == ST_MAXIT || s0 == ST_DIVERGED) {
-    st.chunk_active[i] = 0;
+    if ((threadIdx.x & 63) == 0) st.chunk_active[i] = 0;
     return;
   }
   const InstDesc d = inst[i];
-  double sum = 0.0;
-  for (int k = 0; k < d.nparts; ++k) sum += partials[d.part_off + k];
+  const double sum = instance_sum(partials, d);
+  if ((threadIdx.x & 63) != 0) return;
   const double bn = st.bnorm[i] > 0.0 ? st.bnorm[i] : 1.0;
   const double rel = sqrt(sum) / bn;
   st.relres[i] = rel;
@@ -49,12 +62,12 @@ __global__ void k_check64(IterState st, const InstDesc* inst, int batch,
 // After an FP32 sweep of the correction: count it and test the estimate.
 __global__ void k_check32(IterState st, const InstDesc* inst, int batch,
                           const double* partials) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = wave_instance();
   if (i >= batch) return;
   if (st.status[i] != ST_RUNNING) return;
   const InstDesc d = inst[i];
-  double sum = 0.0;
-  for (int k = 0; k < d.nparts; ++k) sum += partials[d.part_off + k];
+  const double sum = instance_sum(partials, d);
+  if ((threadIdx.x & 63) != 0) return;
   const double bn = st.bnorm[i] > 0.0 ? st.bnorm[i] : 1.0;
   const double rel = sqrt(sum) / bn;
   st.est[i] = rel;
@@ -65,12 +78,11 @@ __global__ void k_check32(IterState st, const InstDesc* inst, int batch,
 // bnorm[i] = sqrt(sum of partials)
 __global__ void k_set_bnorm(IterState st, const InstDesc* inst, int batch,
                             const double* partials) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = wave_instance();
   if (i >= batch) return;
   const InstDesc d = inst[i];
-  double sum = 0.0;
-  for (int k = 0; k < d.nparts; ++k) sum += partials[d.part_off + k];
-  st.bnorm[i] = sqrt(sum);
+  const double sum = instance_sum(partials, d);
+  if ((threadIdx.x & 63) == 0) st.bnorm[i] = sqrt(sum);
 }
 
 // ---- setup statistics ------------------------------------------------------------------
@@ -134,9 +146,11 @@ __global__ __launch_bounds__(kThreads) void k_stats(const InstDesc* inst, const 
 //   y  m complex                            (least-squares solution)
 //   coef m+1 complex                        (current Gram-Schmidt coefficients)
 //   sc 8 scalars: [0] beta [1] bnorm [2] estimate
-// Partial dot products <v_q, w> for q = 0..j over one row item.
+// Partial dot products <v_q, w> for q = 0..j over one row item, eight
+// vectors per workgroup reduction.
 __global__ __launch_bounds__(kThreads) void k_dots(KryParams k) {
-  __shared__ double red[kThreads / 64];
+  constexpr int QB = 8;
+  __shared__ double red[QB][2][kThreads / 64];
   const int2 it = k.items[blockIdx.x];
   if (!k.active[it.x]) return;
   const InstDesc d = k.inst[it.x];
@@ -150,42 +164,68 @@ __global__ __launch_bounds__(kThreads) void k_dots(KryParams k) {
     const int j = threadIdx.x + e * kThreads;
     wv[e] = j < cnt ? k.w[base + j] : cpx<double>{0.0, 0.0};
   }
-  for (int q = 0; q <= k.j; ++q) {
-    const cpx<double>* v = k.vbasis + q * k.cells;
-    double re = 0.0, im = 0.0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int q0 = 0; q0 <= k.j; q0 += QB) {
+    double re[QB], im[QB];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int j = threadIdx.x + e * kThreads;
-      if (j < cnt) {
-        const cpx<double> a = v[base + j];
-        re += a.x * wv[e].x + a.y * wv[e].y;
-        im += a.x * wv[e].y - a.y * wv[e].x;
+    for (int qq = 0; qq < QB; ++qq) {
+      re[qq] = 0.0;
+      im[qq] = 0.0;
+      const int q = q0 + qq;
+      if (q <= k.j) {
+        const cpx<double>* v = k.vbasis + q * k.cells + base;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+          const int j = threadIdx.x + e * kThreads;
+          if (j < cnt) {
+            const cpx<double> a = v[j];
+            re[qq] += a.x * wv[e].x + a.y * wv[e].y;
+            im[qq] += a.x * wv[e].y - a.y * wv[e].x;
+          }
+        }
+      }
+      re[qq] = wave_sum(re[qq]);
+      im[qq] = wave_sum(im[qq]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int qq = 0; qq < QB; ++qq) {
+        red[qq][0][wid] = re[qq];
+        red[qq][1][wid] = im[qq];
       }
     }
-    const double sre = block_sum(re, red);
     __syncthreads();
-    const double sim = block_sum(im, red);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      k.dots[2LL * ((long long)slot * (k.m + 1) + q)] = sre;
-      k.dots[2LL * ((long long)slot * (k.m + 1) + q) + 1] = sim;
+    if (threadIdx.x < 2 * QB) {
+      const int qq = threadIdx.x >> 1, c = threadIdx.x & 1;
+      const int q = q0 + qq;
+      if (q <= k.j) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) t += red[qq][c][w];
+        k.dots[2LL * ((long long)slot * (k.m + 1) + q) + c] = t;
+      }
     }
+    __syncthreads();
   }
 }
 
 // coef_q = sum of partial dots; H[q][j] (+)= coef_q.
 __global__ void k_dots_finish(KryParams k, int batch) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = wave_instance();
   if (i >= batch || !k.active[i]) return;
   const InstDesc d = k.inst[i];
   const KryLayout L{k.m};
   double* s = k.kry + i * k.kstride;
+  const int lane = threadIdx.x & 63;
   for (int q = 0; q <= k.j; ++q) {
     double re = 0.0, im = 0.0;
-    for (int t = 0; t < d.nparts; ++t) {
+    for (int t = lane; t < d.nparts; t += 64) {
       re += k.dots[2LL * ((long long)(d.part_off + t) * (k.m + 1) + q)];
       im += k.dots[2LL * ((long long)(d.part_off + t) * (k.m + 1) + q) + 1];
     }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane != 0) continue;
     s[L.coef() + 2 * q] = re;
     s[L.coef() + 2 * q + 1] = im;
     if (k.pass == 0) {
@@ -209,16 +249,30 @@ __global__ __launch_bounds__(kThreads) void k_cgs_update(KryParams k) {
   item_range(d, it.y, base, cnt, slot);
   const KryLayout L{k.m};
   const double* s = k.kry + it.x * k.kstride + L.coef();
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < cnt; j += kThreads) {
-    cpx<double> wv = k.w[base + j];
-    for (int q = 0; q <= k.j; ++q) {
-      const cpx<double> v = k.vbasis[q * k.cells + base + j];
-      const cpx<double> c{s[2 * q], s[2 * q + 1]};
-      wv = wv - cmul(c, v);
+  constexpr int PER = 2048 / kThreads;  // row_rpw(N) * N <= 2048 for every N
+  cpx<double> wv[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int j = threadIdx.x + e * kThreads;
+    wv[e] = j < cnt ? k.w[base + j] : cpx<double>{0.0, 0.0};
+  }
+  for (int q = 0; q <= k.j; ++q) {
+    const cpx<double> c{s[2 * q], s[2 * q + 1]};
+    const cpx<double>* v = k.vbasis + q * k.cells + base;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int j = threadIdx.x + e * kThreads;
+      if (j < cnt) wv[e] = wv[e] - cmul(c, v[j]);
     }
-    k.w[base + j] = wv;
-    acc += cabs2(wv);
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int j = threadIdx.x + e * kThreads;
+    if (j < cnt) {
+      k.w[base + j] = wv[e];
+      acc += cabs2(wv[e]);
+    }
   }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) k.partials[slot] = t;
@@ -226,13 +280,13 @@ __global__ __launch_bounds__(kThreads) void k_cgs_update(KryParams k) {
 
 // h_{j+1,j} = ||w||; scale = 1/h; Givens update and residual estimate.
 __global__ void k_givens(KryParams k, int batch) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = wave_instance();
   if (i >= batch || !k.active[i]) return;
   const InstDesc d = k.inst[i];
   const KryLayout L{k.m};
   double* s = k.kry + i * k.kstride;
-  double sum = 0.0;
-  for (int t = 0; t < d.nparts; ++t) sum += k.partials[d.part_off + t];
+  const double sum = instance_sum(k.partials, d);
+  if ((threadIdx.x & 63) != 0) return;
   const double hn = sqrt(sum);
   const int j = k.j;
   s[L.h(j + 1, j)] = hn;
@@ -290,8 +344,8 @@ __global__ void k_givens(KryParams k, int batch) {
 
 // Back substitution H[0:jend, 0:jend] y = g[0:jend] (H upper triangular after rotations).
 __global__ void k_backsolve(KryParams k, int batch) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= batch) return;
+  const int i = wave_instance();
+  if (i >= batch || (threadIdx.x & 63) != 0) return;
   const int n = k.jend[i];
   if (n <= 0) return;
   const KryLayout L{k.m};
@@ -314,26 +368,28 @@ __global__ void k_backsolve(KryParams k, int batch) {
 // After the FP64 true residual r = G(V x + s) - x was written to v_0 with its
 // partial norms: decide convergence and start a new cycle.
 __global__ void k_fg_restart(KryParams k, int batch, int first) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = wave_instance();
   if (i >= batch) return;
   const KryLayout L{k.m};
   double* s = k.kry + i * k.kstride;
+  const InstDesc d = k.inst[i];
+  const int lane = threadIdx.x & 63;
   if (first) {  // partials hold |G s|^2: store ||G s||
-    const InstDesc d0 = k.inst[i];
-    double sum0 = 0.0;
-    for (int t = 0; t < d0.nparts; ++t) sum0 += k.partials[d0.part_off + t];
-    s[L.sc() + 1] = sqrt(sum0);
+    const double sum0 = instance_sum(k.partials, d);
+    if (lane == 0) s[L.sc() + 1] = sqrt(sum0);
     return;
   }
-  k.jend[i] = 0;
   const int st = k.status[i];
   if (st != ST_RUNNING) {
-    k.active[i] = 0;
+    if (lane == 0) {
+      k.jend[i] = 0;
+      k.active[i] = 0;
+    }
     return;
   }
-  const InstDesc d = k.inst[i];
-  double sum = 0.0;
-  for (int t = 0; t < d.nparts; ++t) sum += k.partials[d.part_off + t];
+  const double sum = instance_sum(k.partials, d);
+  if (lane != 0) return;
+  k.jend[i] = 0;
   const double beta = sqrt(sum);
   const double rel = beta / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
   k.relres[i] = rel;
@@ -362,7 +418,8 @@ __global__ void k_widen_all(const cpx<float>* in, cpx<double>* out, long long co
 
 // ---- launchers -----------------------------------------------------------------
 
-static int inst_blocks(int batch) { return (batch + 255) / 256; }
+// one wavefront per instance, four per 256-thread block
+static int inst_blocks(int batch) { return (batch + 3) / 4; }
 
 void launch_instance_sums(int batch, hipStream_t st, const InstDesc* inst, const double* partials,
                           double* out) {

@@ -221,3 +221,38 @@ def test_fused_sweep_chain(dtype):
         assert err <= TOL[dtype] * 10
         nref = float(torch.sum(torch.abs(last) ** 2))
         assert abs(float(n2[i]) - nref) <= 1e-4 * nref
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_helmholtz_residual(dtype):
+    # r = s - A u with the pseudospectral A; the paper's rTol on a converged
+    # CBS solution agrees with the oracle's physical residual
+    sizes = [64, 192, 32]
+    say(f"[helmholtz residual] sizes={sizes} dtype={dtype}")
+    probs = [random_problem(n, seed=1300 + i) for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    u, s = _inputs(probs, dtype, seed=17)
+    r, n2 = plan.helmholtz_residual(u, s)
+    torch.cuda.synchronize()
+    for i, (ui, si, ki, ri) in enumerate(zip(to_list(u, sizes), to_list(s, sizes), to_list(k2, sizes),
+                                             to_list(r, sizes))):
+        ref = si - O.helmholtz(ki, ui)
+        assert rel_err(ri, ref) <= TOL[dtype] * 10
+        nref = float(torch.sum(torch.abs(ref) ** 2))
+        assert abs(float(n2[i]) - nref) <= 1e-4 * nref
+    # on a converged solution
+    p = S.blob_problem()
+    plan, k2 = plan_for([p], dtype)
+    tdt = TDT[dtype]
+    s = cbs.pack([p.source], tdt)
+    u = plan.zeros()
+    plan.iterate(u, s, max_sweeps=5000, rtol=1e-6, check_every=25)
+    got = plan.physical_relres(u, s)[0]
+    ki, ui, si = to_list(k2, [64])[0], to_list(u, [64])[0], to_list(s, [64])[0]
+    ref = O.physical_relres(ki, ui, si)
+    # s - A u cancels on a converged u: its rounding error is bounded by a few
+    # ulps of the terms, not of the (small) result
+    unit = 6e-8 if dtype == cbs.CBS_C64 else 1.2e-16
+    terms = (O.norm(O.laplacian(ui)) + O.norm(ki * ui) + O.norm(si)) / O.norm(si)
+    say(f"   blob64 rTol gpu {got:.3e} oracle {ref:.3e} (rounding scale {unit * terms:.1e})")
+    assert abs(got - ref) <= 16 * unit * terms
