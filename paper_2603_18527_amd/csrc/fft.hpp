@@ -115,13 +115,13 @@ __host__ __device__ constexpr int plan_radix(int n, int p) {
     case 16: return p < 2 ? 4 : 0;
     case 32: return p == 0 ? 8 : p == 1 ? 4 : 0;
     case 64: return p < 2 ? 8 : 0;
-    case 128: return p == 0 ? 8 : p < 3 ? 4 : 0;
-    case 192: return p < 2 ? 8 : p == 2 ? 3 : 0;
-    case 256: return p < 2 ? 8 : p == 2 ? 4 : 0;
+    case 128: return p == 0 ? 8 : p == 1 ? 2 : p == 2 ? 8 : 0;
+    case 192: return p == 0 ? 8 : p == 1 ? 3 : p == 2 ? 8 : 0;
+    case 256: return p == 0 ? 8 : p == 1 ? 4 : p == 2 ? 8 : 0;
     case 288: return p == 0 ? 8 : p == 1 ? 4 : p < 4 ? 3 : 0;
-    case 384: return p < 2 ? 8 : p == 2 ? 3 : p == 3 ? 2 : 0;
+    case 384: return p == 0 ? 8 : p == 1 ? 2 : p == 2 ? 3 : p == 3 ? 8 : 0;
     case 512: return p < 3 ? 8 : 0;
-    case 1024: return p < 2 ? 8 : p < 4 ? 4 : 0;
+    case 1024: return p == 0 ? 8 : p < 3 ? 4 : p == 3 ? 8 : 0;
     default: return 0;
   }
 }
@@ -211,6 +211,18 @@ __device__ __forceinline__ void load_tw(const cpx<R>* __restrict__ p, cpx<R>* w)
   }
 }
 
+// Twiddle multiply of butterfly k of pass P: v[q] *= w^(q k) (forward) or
+// conj(w)^(q k) (inverse).
+template <typename R, int N, int P, int DIR>
+__device__ __forceinline__ void twiddle(cpx<R>* v, int k, const cpx<R>* __restrict__ tw) {
+  constexpr int RAD = plan_radix(N, P);
+  constexpr int RP = radp(RAD);
+  cpx<R> w[RP];
+  load_tw<R, RP>(tw + tw_pass_offset(N, P) + k * RP, w);
+#pragma unroll
+  for (int q = 1; q < RAD; ++q) v[q] = DIR < 0 ? cmul(w[q], v[q]) : cmulc(w[q], v[q]);
+}
+
 // ---- one Stockham pass ----------------------------------------------------------
 //
 // TPF threads cooperate on one transform (t = 0..TPF-1); every thread of the
@@ -220,7 +232,8 @@ __device__ __forceinline__ void load_tw(const cpx<R>* __restrict__ p, cpx<R>* w)
 // its outputs to `st(e, v)`; the passes in between exchange data through LDS
 // (`buf`, skewed positions).  LD_LDS / ST_LDS say that ld / st themselves touch
 // this LDS buffer, which adds the barriers an in-place pass needs.
-template <typename R, int N, int P, int TPF, int DIR, bool LD_LDS, bool ST_LDS, class LD, class ST>
+template <typename R, int N, int P, int PEND, int TPF, int DIR, bool LD_LDS, bool ST_LDS, class LD,
+          class ST>
 __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
                                          const cpx<R>* __restrict__ tw, LD& ld, ST& st) {
   constexpr int RAD = plan_radix(N, P);
@@ -256,17 +269,7 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
       const int j = t + p * TPF;
       if (EXACT || j < NB) {
         const int k = j % NS;
-        if constexpr (NS > 1) {
-          constexpr int RP = radp(RAD);
-          cpx<R> w[RP];
-          load_tw<R, RP>(tw + tw_pass_offset(N, P) + k * RP, w);
-#pragma unroll
-          for (int q = 1; q < RAD; ++q) {
-            cpx<R> wq = w[q];
-            if constexpr (DIR > 0) wq.y = -wq.y;
-            v[p][q] = cmul(v[p][q], wq);
-          }
-        }
+        if constexpr (NS > 1) twiddle<R, N, P, DIR>(v[p], k, tw);
         bfly<RAD, DIR>(v[p]);
         const int o = (j / NS) * (NS * RAD) + k;
         if constexpr (LAST) {
@@ -281,7 +284,8 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
     }
   }
   if constexpr (WRITES_LDS) __syncthreads();
-  if constexpr (!LAST) fft_pass<R, N, P + 1, TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
+  if constexpr (P + 1 < PEND)
+    fft_pass<R, N, P + 1, PEND, TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
 }
 
 // Length-N transform (DIR = -1 forward, +1 inverse, unnormalised) from ld to st.
@@ -289,7 +293,68 @@ template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, class L
 __device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active,
                                         const cpx<R>* __restrict__ tw, LD ld, ST st) {
   static_assert(plan_product(N) == N && plan_passes(N) >= 2, "no plan for this size");
-  fft_pass<R, N, 0, TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
+  fft_pass<R, N, 0, plan_passes(N), TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
+}
+
+// Two transforms back to back with an elementwise map between them, where the
+// plan's first and last radix are equal: the last pass of the first transform
+// and the first pass of the second act on the same elements in each thread,
+// so they run in registers with `mid(e, v)` applied in between (no LDS round
+// trip).  ld feeds the first pass of transform 1 (direction D1), st takes the
+// last pass of transform 2 (direction D2).
+__host__ __device__ constexpr bool plan_bridgeable(int n) {
+  return plan_passes(n) >= 3 && plan_radix(n, 0) == plan_radix(n, plan_passes(n) - 1);
+}
+
+template <typename R, int N, int TPF, int D1, int D2, class LD, class MID, class ST>
+__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
+                                         const cpx<R>* __restrict__ tw, LD ld, MID mid, ST st) {
+  static_assert(plan_bridgeable(N), "first and last radix differ");
+  constexpr int PL = plan_passes(N) - 1;  // last pass index
+  constexpr int RAD = plan_radix(N, PL);
+  constexpr int NS = plan_ns(N, PL);      // = N / RAD
+  constexpr int NB = N / RAD;
+  constexpr int PER = (NB + TPF - 1) / TPF;
+  constexpr bool EXACT = (NB % TPF) == 0;
+  auto none = [](int, cpx<R>) {};
+  // transform 1, passes 0 .. PL-1 (the last of them writes LDS)
+  fft_pass<R, N, 0, PL, TPF, D1, false, false>(buf, t, active, tw, ld, none);
+  cpx<R> v[PER][RAD];
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int j = t + p * TPF;
+      if (EXACT || j < NB) {
+        const int pj = lds_pos(j);
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) v[p][q] = buf[lds_pos_step<NB, RAD>(j, pj, q)];
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int j = t + p * TPF;
+      if (EXACT || j < NB) {
+        // last pass of transform 1: k = j (j < NS), outputs at j + q NS
+        twiddle<R, N, PL, D1>(v[p], j, tw);
+        bfly<RAD, D1>(v[p]);
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) v[p][q] = mid(j + q * NS, v[p][q]);
+        // first pass of transform 2 reads the same elements j + q N/RAD
+        bfly<RAD, D2>(v[p]);
+        const int o = j * RAD;
+        const int po = lds_pos(o);
+#pragma unroll
+        for (int q = 0; q < RAD; ++q) buf[lds_pos_step<1, RAD>(o, po, q)] = v[p][q];
+      }
+    }
+  }
+  __syncthreads();
+  // transform 2, passes 1 .. PL
+  auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
+  fft_pass<R, N, 1, PL + 1, TPF, D2, false, false>(buf, t, active, tw, noload, st);
 }
 
 }  // namespace cbs

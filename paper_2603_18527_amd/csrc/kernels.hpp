@@ -213,7 +213,8 @@ __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, 
   } else {
     double acc = 0.0;
     auto ld = [&](int e) { return p.inter[rbase + e]; };
-    auto st = [&](int e, cpx<R> z) {
+    // u_new = u + gamma (z - u + rhs), written out; returns V u_new + s
+    auto update = [&](int e, cpx<R> z) {
       const long long g = rbase + e;
       const cpx<R> u = p.u[g];
       const cpx<R> rres = z - u + ld_or_zero(p.rhs, g);
@@ -221,16 +222,21 @@ __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, 
       const cpx<R> un = u + cmul(c.gamma(), rres);
       p.out[g] = un;
       acc += double(cabs2(rres));
-      mine[lds_pos(e)] = cmul(c.v, un) + ld_or_zero(p.s, g);
+      return cmul(c.v, un) + ld_or_zero(p.s, g);
     };
-    fft_run<R, N, T::TPF, 1, false, true>(mine, t, active, p.tw, ld, st);
+    auto st2 = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
+    if constexpr (plan_bridgeable(N)) {
+      fft_run2<R, N, T::TPF, 1, -1>(mine, t, active, p.tw, ld, update, st2);
+    } else {
+      auto st = [&](int e, cpx<R> z) { mine[lds_pos(e)] = update(e, z); };
+      fft_run<R, N, T::TPF, 1, false, true>(mine, t, active, p.tw, ld, st);
+      auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
+      fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld2, st2);
+    }
     if (p.partials) {
       const double s = block_sum(acc, red);
       if (tid == 0) p.partials[d.part_off + row0 / T::RPW] = s;
     }
-    auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
-    auto st2 = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
-    fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld2, st2);
   }
 }
 
@@ -284,7 +290,9 @@ __device__ __forceinline__ cpx<R> symbol_factor(int n, int k1, int k2, double k0
   if (mode == SYM_LAP) return cpx<R>{R(xi2) * inv_n2, R(0)};
   const R a = R(xi2 - k0sq);  // lambda = a - i eps
   const R e = R(eps);
-  const R sc = inv_n2 / (a * a + e * e);
+  R sc;
+  if constexpr (sizeof(R) == 4) sc = inv_n2 * __builtin_amdgcn_rcpf(a * a + e * e);  // 1 ulp
+  else sc = inv_n2 / (a * a + e * e);
   // 1/lambda = (a + i eps)/|lambda|^2 ; 1/conj(lambda) = (a - i eps)/|lambda|^2
   return cpx<R>{a * sc, (mode == SYM_GREEN ? e : -e) * sc};
 }
@@ -304,14 +312,20 @@ __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, 
   const int kcol = col0 + c;
   cpx<R>* mine = lds + c * CS;
   auto ld = [&](int e) { return p.inter[cbase + (long long)e * N]; };
-  // last forward pass: multiply by the Green symbol and keep the spectrum in LDS
-  auto st = [&](int e, cpx<R> v) {
-    mine[lds_pos(e)] = cmul(v, symbol_factor<R>(N, e, kcol, d.k0sq, d.eps, p.sym));
+  auto sym = [&](int e, cpx<R> v) {
+    return cmul(v, symbol_factor<R>(N, e, kcol, d.k0sq, d.eps, p.sym));
   };
-  fft_run<R, N, TPC, -1, false, true>(mine, t, true, p.tw, ld, st);
-  auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
   auto st2 = [&](int e, cpx<R> v) { p.inter[cbase + (long long)e * N] = v; };
-  fft_run<R, N, TPC, 1, true, false>(mine, t, true, p.tw, ld2, st2);
+  if constexpr (plan_bridgeable(N)) {
+    // forward column transform, symbol, inverse transform; the last forward
+    // and first inverse passes share registers
+    fft_run2<R, N, TPC, -1, 1>(mine, t, true, p.tw, ld, sym, st2);
+  } else {
+    auto st = [&](int e, cpx<R> v) { mine[lds_pos(e)] = sym(e, v); };
+    fft_run<R, N, TPC, -1, false, true>(mine, t, true, p.tw, ld, st);
+    auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
+    fft_run<R, N, TPC, 1, true, false>(mine, t, true, p.tw, ld2, st2);
+  }
 }
 
 template <typename R, int N>
