@@ -173,6 +173,12 @@ def time_to_solution(probs, plan_k2, sizes, k0sq, s_packed, rtol=1e-6, chunk=50,
     t_batch = time.perf_counter() - t0
     out["batched_graph_s"] = t_batch
     out["batched_sweeps_max"] = int(max(its))
+    by = {}
+    for n, k in zip(sizes, its):
+        lo, hi = by.get(str(n), (k, k))
+        by[str(n)] = (min(lo, k), max(hi, k))
+    out["sweeps_min_max_by_size"] = by
+    out["sweeps_sorted_top8"] = sorted((int(k) for k in its), reverse=True)[:8]
     out["batched_all_converged"] = all(s == cbs.INST_CONVERGED for s in stat)
     out["batched_max_relres"] = float(max(rel))
     # plain: a per-instance loop of plans with ordinary launches

@@ -113,7 +113,22 @@ struct cbs_plan_s {
   int* d_kactive = nullptr;
   int* d_kjend = nullptr;
 
-  std::map<std::pair<const void*, int>, hipGraphExec_t> graphs;
+  // Work lists the launches use: the whole batch, or a compacted view holding
+  // only the instances still iterating (cbs_iterate switches to it once the
+  // running instances cover at most half of the current view's cells).
+  struct View {
+    int2* rows = nullptr;
+    int nrows = 0;
+    int2* cols32 = nullptr;
+    int ncols32 = 0;
+    int2* cols64 = nullptr;
+    int ncols64 = 0;
+    long long cells = 0;
+    int gen = 0;
+  };
+  View full, compact;
+  View* view = &full;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (view generation, chunk)
   hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
   int op_elem() const { return dtype == CBS_C64 ? 8 : 16; }
 };
@@ -185,7 +200,55 @@ size_t max_col_items(cbs_plan p) {
   return m;
 }
 
+void set_full_view(cbs_plan p) {
+  cbs_plan_s::View& v = p->full;
+  v.rows = p->d_row_items;
+  v.nrows = int(p->row_items.size());
+  v.cols32 = p->d_col_items32;
+  v.ncols32 = int(p->col_items32.size());
+  v.cols64 = p->d_col_items64;
+  v.ncols64 = int(p->col_items64.size());
+  v.cells = p->cells;
+  v.gen = 0;
+}
+
+// Compacted view over the instances flagged in `keep` (whole instances, so
+// the per-instance XCD grouping of the column tiles is preserved).
+cbs_status build_compact_view(cbs_plan p, const std::vector<char>& keep, hipStream_t st) {
+  std::vector<int2> rows, c32, c64;
+  for (const int2& it : p->row_items)
+    if (keep[it.x]) rows.push_back(it);
+  for (const int2& it : p->col_items32)
+    if (keep[it.x]) c32.push_back(it);
+  for (const int2& it : p->col_items64)
+    if (keep[it.x]) c64.push_back(it);
+  cbs_plan_s::View& v = p->compact;
+  HIPCHK(hipMemcpyAsync(v.rows, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(v.cols32, c32.data(), c32.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(v.cols64, c64.data(), c64.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  v.nrows = int(rows.size());
+  v.ncols32 = int(c32.size());
+  v.ncols64 = int(c64.size());
+  v.cells = 0;
+  for (int i = 0; i < p->batch; ++i)
+    if (keep[i]) v.cells += (long long)p->n[i] * p->n[i];
+  // graphs captured on the previous compacted lists are stale
+  for (auto it = p->graphs.begin(); it != p->graphs.end();) {
+    if (it->first.first == v.gen) {
+      hipGraphExecDestroy(it->second);
+      it = p->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  v.gen += 1;
+  p->view = &v;
+  return CBS_OK;
+}
+
 cbs_status upload_items(cbs_plan p, hipStream_t st) {
+  set_full_view(p);
   HIPCHK(hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
                         hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->d_col_items32, p->col_items32.data(), p->col_items32.size() * sizeof(int2),
@@ -224,19 +287,19 @@ Params<R> base_params(cbs_plan p) {
 template <typename R>
 void launch_cols(cbs_plan p, Params<R> q, hipStream_t st) {
   if constexpr (sizeof(R) == 4) {
-    q.items = p->d_col_items32;
-    launch_col(int(p->col_items32.size()), p->col_lds32, st, q);
+    q.items = p->view->cols32;
+    launch_col(p->view->ncols32, p->col_lds32, st, q);
   } else {
-    q.items = p->d_col_items64;
-    launch_col(int(p->col_items64.size()), p->col_lds64, st, q);
+    q.items = p->view->cols64;
+    launch_col(p->view->ncols64, p->col_lds64, st, q);
   }
 }
 
 // Forward rows (prologue) -> columns (symbol) -> inverse rows (epilogue).
 template <typename R>
 cbs_status run_pipeline(cbs_plan p, Params<R> q, hipStream_t st) {
-  const int nrow = int(p->row_items.size());
-  q.items = p->d_row_items;
+  const int nrow = p->view->nrows;
+  q.items = p->view->rows;
   launch_row(0, nrow, st, q);
   launch_cols(p, q, st);
   launch_row(1, nrow, st, q);
@@ -250,9 +313,9 @@ cbs_status run_pipeline(cbs_plan p, Params<R> q, hipStream_t st) {
 // those of the last sweep.
 template <typename R>
 cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
-  const int nrow = int(p->row_items.size());
+  const int nrow = p->view->nrows;
   Params<R> f = q;
-  f.items = p->d_row_items;
+  f.items = p->view->rows;
   launch_row(0, nrow, st, f);
   for (int k = 1; k < count; ++k) {
     launch_cols(p, q, st);
@@ -260,7 +323,7 @@ cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
   }
   launch_cols(p, q, st);
   Params<R> e = q;
-  e.items = p->d_row_items;
+  e.items = p->view->rows;
   e.epi = EPI_SWEEP;
   launch_row(1, nrow, st, e);
   HIPCHK(hipGetLastError());
@@ -270,9 +333,9 @@ cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
 template <typename R>
 cbs_status launch_pw(cbs_plan p, PwParams<R> w, hipStream_t st) {
   w.inst = p->d_inst;
-  w.items = p->d_row_items;
+  w.items = p->view->rows;
   w.k2 = k2_of<R>(p);
-  launch_pointwise(int(p->row_items.size()), st, w);
+  launch_pointwise(p->view->nrows, st, w);
   HIPCHK(hipGetLastError());
   return CBS_OK;
 }
@@ -399,7 +462,7 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
   // each sweep runs between the fused kernels (a converged instance is masked
   // from the next launch on).
   if (chunk > 1) {
-    const int nrow = int(p->row_items.size());
+    const int nrow = p->view->nrows;
     Params<R> q = base_params<R>(p);
     q.u = e;
     q.rhs = c;
@@ -407,11 +470,11 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     q.epi = EPI_SWEEP;
     q.mask = p->d_status;
     q.mask_mode = MASK_RUNNING;
-    q.items = p->d_row_items;
+    q.items = p->view->rows;
     launch_row(0, nrow, st, q);
     for (int k = 1; k < chunk; ++k) {
       launch_cols(p, q, st);
-      q.items = p->d_row_items;
+      q.items = p->view->rows;
       launch_row(k + 1 < chunk ? 2 : 1, nrow, st, q);
       launch_check32(p->batch, st, is, p->d_inst, p->d_partials);
     }
@@ -429,11 +492,18 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
   return CBS_OK;
 }
 
+struct FullViewOnExit {
+  cbs_plan p;
+  ~FullViewOnExit() { p->view = &p->full; }
+};
+
 template <typename R>
 cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
                         int chunk, int32_t* iters, double* relres, int32_t* status,
                         int use_graph, hipStream_t st) {
   const int B = p->batch;
+  p->view = &p->full;
+  FullViewOnExit restore{p};
   // u64 <- u ; s64 <- s
   if constexpr (sizeof(R) == 4) {
     launch_widen_all(st, static_cast<const cpx<float>*>(u), p->d_u64, p->cells);
@@ -456,41 +526,56 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
     launch_set_bnorm(B, st, iter_state(p), p->d_inst, p->d_partials);
     HIPCHK(hipGetLastError());
   }
-  hipGraphExec_t exec = nullptr;
-  if (use_graph) {
-    auto key = std::make_pair(static_cast<const void*>(nullptr), chunk);
+  // Capture (once per view and chunk length) and replay.
+  auto get_graph = [&](hipGraphExec_t* exec) -> cbs_status {
+    *exec = nullptr;
+    if (!use_graph) return CBS_OK;
+    const auto key = std::make_pair(p->view->gen, chunk);
     auto it = p->graphs.find(key);
-    if (it == p->graphs.end()) {
-      HIPCHK(hipStreamSynchronize(st));
-      hipGraph_t g = nullptr;
-      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      cbs_status rc = enqueue_chunk<R>(p, chunk, st);
-      hipError_t ce = hipStreamEndCapture(st, &g);
-      if (rc != CBS_OK) {
-        if (g) hipGraphDestroy(g);
-        return rc;
-      }
-      if (ce != hipSuccess) return fail(CBS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
-      hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
-      if (ie != hipSuccess) return fail(CBS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-      p->graphs[key] = exec;
-    } else {
-      exec = it->second;
+    if (it != p->graphs.end()) {
+      *exec = it->second;
+      return CBS_OK;
     }
-  }
+    HIPCHK(hipStreamSynchronize(st));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    cbs_status rc = enqueue_chunk<R>(p, chunk, st);
+    hipError_t ce = hipStreamEndCapture(st, &g);
+    if (rc != CBS_OK) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (ce != hipSuccess) return fail(CBS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(CBS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    p->graphs[key] = *exec;
+    return CBS_OK;
+  };
+  hipGraphExec_t exec = nullptr;
+  CHK(get_graph(&exec));
   std::vector<int> hstat(B);
+  std::vector<char> keep(B);
   const long long max_chunks = (long long)max_sweeps / std::max(1, chunk) + 3;
   for (long long ch = 0; ch <= max_chunks; ++ch) {
     if (exec) HIPCHK(hipGraphLaunch(exec, st));
     else CHK(enqueue_chunk<R>(p, chunk, st));
     HIPCHK(hipMemcpyAsync(hstat.data(), p->d_status, B * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    bool done = true;
-    for (int i = 0; i < B; ++i)
-      if (hstat[i] == ST_RUNNING || hstat[i] == ST_PENDING) done = false;
-    if (done) break;
+    long long active_cells = 0;
+    for (int i = 0; i < B; ++i) {
+      keep[i] = hstat[i] == ST_RUNNING || hstat[i] == ST_PENDING;
+      if (keep[i]) active_cells += (long long)p->n[i] * p->n[i];
+    }
+    if (active_cells == 0) break;
+    // Compact the work lists once the running instances cover at most half
+    // of the current view: later launches then dispatch only their items.
+    if (2 * active_cells <= p->view->cells) {
+      CHK(build_compact_view(p, keep, st));
+      CHK(get_graph(&exec));
+    }
   }
+  p->view = &p->full;
   // u <- u64
   if constexpr (sizeof(R) == 4) {
     PwParams<float> w{};
@@ -860,9 +945,12 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
     p->d_k2 = p->d_k2_64;
     p->d_inter = p->d_inter64;
   }
-  for (int2** d : {&p->d_col_items32, &p->d_col_items64}) {
+  p->compact.gen = 1;
+  for (int2** d : {&p->d_col_items32, &p->d_col_items64, &p->compact.rows, &p->compact.cols32,
+                   &p->compact.cols64}) {
     void* ptr = nullptr;
-    hipError_t e = hipMalloc(&ptr, std::max<size_t>(max_col_items(p) * sizeof(int2), 16));
+    const size_t cap = std::max(max_col_items(p), p->row_items.size());
+    hipError_t e = hipMalloc(&ptr, std::max<size_t>(cap * sizeof(int2), 16));
     if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
     p->owned.push_back(ptr);
     *d = static_cast<int2*>(ptr);
