@@ -155,3 +155,71 @@ def test_fgmres_ragged_batch():
         say(f"   instance {i}: its {its[i]} relres {rel[i]:.3e} oracle {ev:.3e}")
         assert stat[i] == cbs.INST_CONVERGED
         _bar(cbs.CBS_C64, rel[i], ev)
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_iterate_and_fgmres_from_nonzero_initial_guess(dtype):
+    # Sec. 3.1 Eq. CBS from u0 != 0: same sweep count as the oracle from the
+    # same u0; FGMRES restarts from the true residual of u0.
+    sizes = [64, 128]
+    say(f"[nonzero u0] dtype={dtype}")
+    probs = [random_problem(n, seed=140 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype, restart=12)
+    tdt = torch.complex64 if dtype == cbs.CBS_C64 else torch.complex128
+    rng = np.random.default_rng(5)
+    u0 = cbs.pack([0.01 * S.random_field_c(n, rng) for n in sizes], tdt)
+    s = cbs.pack([p.source for p in probs], tdt)
+    u = u0.clone()
+    its, rel, stat = plan.iterate(u, s, max_sweeps=5000, rtol=1e-6, check_every=20)
+    v = u0.clone()
+    fits, frel, fstat = plan.fgmres(v, s, restart=12, sweeps=2, max_iters=2000, rtol=1e-6)
+    for i, (ki, si, u0i, ui, vi) in enumerate(zip(to_list(k2, sizes), to_list(s, sizes), to_list(u0, sizes),
+                                                  to_list(u, sizes), to_list(v, sizes))):
+        uo, mo, relo = O.cbs_iterate(ki, plan.k0sq[i], plan.eps[i], si, u0=u0i, max_sweeps=5000, rtol=1e-6)
+        say(f"   instance {i}: gpu {its[i]} oracle {mo} sweeps; fgmres {fits[i]} its")
+        assert stat[i] == cbs.INST_CONVERGED and mo <= its[i] <= mo + 20
+        _bar(dtype, rel[i], _oracle_relres(ki, plan.k0sq[i], plan.eps[i], ui, si))
+        assert fstat[i] == cbs.INST_CONVERGED
+        _bar(dtype, frel[i], _oracle_relres(ki, plan.k0sq[i], plan.eps[i], vi, si))
+
+
+def test_iterate_degenerate_cases():
+    probs = [random_problem(64, seed=150, source="point"), random_problem(32, seed=151, source="point")]
+    plan, k2 = plan_for(probs)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    # no sweeps allowed: status MAX_ITERS, u unchanged
+    u = plan.zeros()
+    its, rel, stat = plan.iterate(u, s, max_sweeps=0, rtol=1e-6, check_every=5)
+    assert its == [0, 0] and stat == [cbs.INST_MAX_ITERS] * 2 and float(torch.abs(u).max()) == 0.0
+    assert abs(rel[0] - 1.0) < 1e-6 and abs(rel[1] - 1.0) < 1e-6   # r(0) = G s
+    # a NaN in the source of instance 1: that instance diverges, instance 0 converges
+    s2 = s.clone()
+    s2[64 * 64 + 5] = float("nan")
+    u = plan.zeros()
+    its, rel, stat = plan.iterate(u, s2, max_sweeps=2000, rtol=1e-6, check_every=10)
+    assert stat[0] == cbs.INST_CONVERGED and stat[1] == cbs.INST_DIVERGED
+    # FGMRES with restart 1 (steepest-descent-like) still reaches the tolerance
+    plan2, _ = plan_for(probs[:1], restart=1)
+    u = plan2.zeros()
+    its, rel, stat = plan2.fgmres(u, cbs.pack([probs[0].source], torch.complex64), restart=1, sweeps=3,
+                                  max_iters=5000, rtol=1e-6)
+    assert stat[0] == cbs.INST_CONVERGED and rel[0] <= 1e-6
+
+
+def test_aliasing_and_argument_errors():
+    probs = [random_problem(32, seed=160)]
+    plan, k2 = plan_for(probs)
+    u = plan.zeros()
+    lib = cbs.load()
+    ptr = lambda t: cbs._ptr(t)
+    assert lib.cbs_apply(plan._h, ptr(u), None, ptr(u), None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_residual(plan._h, ptr(u), None, None, ptr(u), None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_sweep(plan._h, ptr(u), ptr(u), 1, None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_sweep(plan._h, ptr(u), None, 0, None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_iterate(plan._h, ptr(u), ptr(u), 10, 1e-6, 10, None, None, None, 0, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_iterate(plan._h, ptr(u), ptr(plan.zeros()), 10, 1e-6, 1, None, None, None, 0, None) \
+        == cbs.CBS_ERR_ARG
+    assert lib.cbs_set_tile(plan._h, 32, 3) == cbs.CBS_ERR_ARG
+    assert lib.cbs_set_tile(plan._h, 48, 16) == cbs.CBS_ERR_ARG
+    with pytest.raises(ValueError):
+        plan.apply(torch.zeros(10, dtype=torch.complex64, device="cuda"), None)
