@@ -76,7 +76,8 @@ enum {
 
 /* Setup flags. */
 enum {
-  CBS_FLAG_NO_GUARD = 1u   /* skip the eps / min|V| conditioning guard */
+  CBS_FLAG_NO_GUARD = 1u,   /* skip the eps / min|V| conditioning guard */
+  CBS_FLAG_ONE_STREAM = 2u  /* enqueue every kernel on the caller's stream (no lanes) */
 };
 
 /*
@@ -97,6 +98,14 @@ enum {
  * Guard: unless CBS_FLAG_NO_GUARD, rejects eps < max|k^2 - k0^2| (1e-12
  * relative slack) and min|V|/eps < 1e-3 with CBS_ERR_ILLCOND (a cell with
  * V = 0 has gamma = 0 and never updates).  Synchronises `stream`.
+ * Lanes: a batch of at least two instances and 2^21 cells is split into two
+ * lanes of about equal cell count.  Sweep chains (cbs_sweep, the sweeps of
+ * cbs_iterate and of the FGMRES preconditioner) run each lane on a
+ * plan-owned non-blocking stream, forked from and joined back into the
+ * caller's stream with events, so one lane's memory-bound row transforms
+ * overlap the other lane's compute-bound column transforms.  Results are
+ * bitwise the same as with CBS_FLAG_ONE_STREAM; calls stay ordered on the
+ * caller's stream.
  */
 cbs_status cbs_setup(cbs_plan* plan, int batch, const int32_t* n, const void* k2,
                      const double* k0sq, const double* eps, int dtype, int max_restart,

@@ -29,6 +29,7 @@ CBS_ERR_HIP = -5
 CBS_C64 = 0
 CBS_C128 = 1
 FLAG_NO_GUARD = 1
+FLAG_ONE_STREAM = 2
 INST_RUNNING, INST_CONVERGED, INST_MAX_ITERS, INST_DIVERGED = 0, 1, 2, 3
 
 SUPPORTED_SIZES = (16, 32, 64, 128, 192, 256, 288, 384, 512, 1024)
@@ -126,7 +127,8 @@ class Plan:
     """A batch of Helmholtz instances on the GPU (cbs_setup)."""
 
     def __init__(self, k2: torch.Tensor, sizes: Sequence[int], k0sq=None, eps=None,
-                 dtype: int = CBS_C64, max_restart: int = 0, guard: bool = True, stream=None):
+                 dtype: int = CBS_C64, max_restart: int = 0, guard: bool = True, stream=None,
+                 lanes: bool = True):
         lib = load()
         self.sizes = [int(n) for n in sizes]
         self.batch = len(self.sizes)
@@ -143,7 +145,9 @@ class Plan:
             *[0.0 if v is None else float(v) for v in _expand(eps, self.batch)])
         h = ctypes.c_void_p()
         st = lib.cbs_setup(ctypes.byref(h), self.batch, n_arr, _ptr(k2), k0_arr, eps_arr, dtype,
-                           int(max_restart), 0 if guard else FLAG_NO_GUARD, _stream(stream))
+                           int(max_restart),
+                           (0 if guard else FLAG_NO_GUARD) | (0 if lanes else FLAG_ONE_STREAM),
+                           _stream(stream))
         _check(st)
         self._h = h
         self.max_restart = int(max_restart)

@@ -116,6 +116,18 @@ struct cbs_plan_s {
   // Work lists the launches use: the whole batch, or a compacted view holding
   // only the instances still iterating (cbs_iterate switches to it once the
   // running instances cover at most half of the current view's cells).
+  // A work list: row items, column items per precision and (for a lane) the
+  // instances it covers.
+  struct Items {
+    const int2* rows = nullptr;
+    int nrows = 0;
+    const int2* cols32 = nullptr;
+    int ncols32 = 0;
+    const int2* cols64 = nullptr;
+    int ncols64 = 0;
+    const int* ids = nullptr;
+    int nids = 0;
+  };
   struct View {
     int2* rows = nullptr;
     int nrows = 0;
@@ -125,11 +137,26 @@ struct cbs_plan_s {
     int ncols64 = 0;
     long long cells = 0;
     int gen = 0;
+    // Two lanes of about equal cell count (nlanes == 0: no split).  Their
+    // lists live back to back in lrows / lcols32 / lcols64 / lids; the host
+    // copies stay alive while the uploads are in flight.
+    int nlanes = 0;
+    Items lane[2];
+    int2* lrows = nullptr;
+    int2* lcols32 = nullptr;
+    int2* lcols64 = nullptr;
+    int* lids = nullptr;
+    std::vector<int2> h_rows, h_c32, h_c64;
+    std::vector<int> h_ids;
+    Items all() const { return Items{rows, nrows, cols32, ncols32, cols64, ncols64, nullptr, 0}; }
   };
   View full, compact;
   View* view = &full;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (view generation, chunk)
   hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
+  bool one_stream = false;           // CBS_FLAG_ONE_STREAM
+  hipStream_t lane_st[2] = {nullptr, nullptr};  // non-blocking lane streams
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int op_elem() const { return dtype == CBS_C64 ? 8 : 16; }
 };
 
@@ -212,6 +239,71 @@ void set_full_view(cbs_plan p) {
   v.gen = 0;
 }
 
+// Batches smaller than this (or of one instance) run on the caller's stream.
+constexpr long long kLaneMinCells = 1LL << 21;
+
+bool lanes_wanted(cbs_plan p, const std::vector<char>& keep) {
+  if (p->one_stream) return false;
+  int count = 0;
+  long long cells = 0;
+  for (int i = 0; i < p->batch; ++i)
+    if (keep[i]) {
+      ++count;
+      cells += (long long)p->n[i] * p->n[i];
+    }
+  return count >= 2 && cells >= kLaneMinCells;
+}
+
+// Split the instances flagged in `keep` into two lanes (largest first, each
+// to the lane with fewer cells so far) and upload the lanes' lists.  Each
+// lane keeps the order of the full lists, so an instance's column tiles stay
+// contiguous and tiles that share cache lines stay 8 launch positions apart.
+cbs_status build_lanes(cbs_plan p, cbs_plan_s::View& v, const std::vector<char>& keep,
+                       hipStream_t st) {
+  v.nlanes = 0;
+  if (!lanes_wanted(p, keep) || !p->lane_st[0]) return CBS_OK;
+  std::vector<int> order;
+  for (int i = 0; i < p->batch; ++i)
+    if (keep[i]) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->n[a] > p->n[b]; });
+  std::vector<int> lane_of(p->batch, -1);
+  long long load[2] = {0, 0};
+  for (int i : order) {
+    const int l = load[1] < load[0] ? 1 : 0;
+    lane_of[i] = l;
+    load[l] += (long long)p->n[i] * p->n[i];
+  }
+  const std::vector<int2>& c32 = p->col_items32;
+  const std::vector<int2>& c64 = p->col_items64;
+  v.h_rows.clear();
+  v.h_c32.clear();
+  v.h_c64.clear();
+  v.h_ids.clear();
+  int cnt[2][4] = {};
+  for (int l = 0; l < 2; ++l) {
+    for (const int2& it : p->row_items)
+      if (lane_of[it.x] == l) { v.h_rows.push_back(it); ++cnt[l][0]; }
+    for (const int2& it : c32)
+      if (lane_of[it.x] == l) { v.h_c32.push_back(it); ++cnt[l][1]; }
+    for (const int2& it : c64)
+      if (lane_of[it.x] == l) { v.h_c64.push_back(it); ++cnt[l][2]; }
+    for (int i = 0; i < p->batch; ++i)
+      if (lane_of[i] == l) { v.h_ids.push_back(i); ++cnt[l][3]; }
+  }
+  HIPCHK(hipMemcpyAsync(v.lrows, v.h_rows.data(), v.h_rows.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(v.lcols32, v.h_c32.data(), v.h_c32.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(v.lcols64, v.h_c64.data(), v.h_c64.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(v.lids, v.h_ids.data(), v.h_ids.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  for (int l = 0; l < 2; ++l) {
+    const int o0 = l ? cnt[0][0] : 0, o1 = l ? cnt[0][1] : 0, o2 = l ? cnt[0][2] : 0,
+              o3 = l ? cnt[0][3] : 0;
+    v.lane[l] = cbs_plan_s::Items{v.lrows + o0, cnt[l][0], v.lcols32 + o1, cnt[l][1],
+                                  v.lcols64 + o2, cnt[l][2], v.lids + o3, cnt[l][3]};
+  }
+  v.nlanes = 2;
+  return CBS_OK;
+}
+
 // Compacted view over the instances flagged in `keep` (whole instances, so
 // the per-instance XCD grouping of the column tiles is preserved).
 cbs_status build_compact_view(cbs_plan p, const std::vector<char>& keep, hipStream_t st) {
@@ -226,6 +318,7 @@ cbs_status build_compact_view(cbs_plan p, const std::vector<char>& keep, hipStre
   HIPCHK(hipMemcpyAsync(v.rows, rows.data(), rows.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(v.cols32, c32.data(), c32.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(v.cols64, c64.data(), c64.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+  CHK(build_lanes(p, v, keep, st));
   HIPCHK(hipStreamSynchronize(st));
   v.nrows = int(rows.size());
   v.ncols32 = int(c32.size());
@@ -249,6 +342,7 @@ cbs_status build_compact_view(cbs_plan p, const std::vector<char>& keep, hipStre
 
 cbs_status upload_items(cbs_plan p, hipStream_t st) {
   set_full_view(p);
+  CHK(build_lanes(p, p->full, std::vector<char>(p->batch, 1), st));
   HIPCHK(hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
                         hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->d_col_items32, p->col_items32.data(), p->col_items32.size() * sizeof(int2),
@@ -285,14 +379,33 @@ Params<R> base_params(cbs_plan p) {
 }
 
 template <typename R>
-void launch_cols(cbs_plan p, Params<R> q, hipStream_t st) {
+void launch_cols(cbs_plan p, Params<R> q, hipStream_t st, const cbs_plan_s::Items& it) {
   if constexpr (sizeof(R) == 4) {
-    q.items = p->view->cols32;
-    launch_col(p->view->ncols32, p->col_lds32, st, q);
+    q.items = it.cols32;
+    launch_col(it.ncols32, p->col_lds32, st, q);
   } else {
-    q.items = p->view->cols64;
-    launch_col(p->view->ncols64, p->col_lds64, st, q);
+    q.items = it.cols64;
+    launch_col(it.ncols64, p->col_lds64, st, q);
   }
+}
+template <typename R>
+void launch_cols(cbs_plan p, Params<R> q, hipStream_t st) {
+  launch_cols(p, q, st, p->view->all());
+}
+
+// Fork the two lane streams off `st` / join them back into it (stream
+// ordered, also under graph capture).
+cbs_status lanes_fork(cbs_plan p, hipStream_t st) {
+  HIPCHK(hipEventRecord(p->ev_fork, st));
+  for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(p->lane_st[l], p->ev_fork, 0));
+  return CBS_OK;
+}
+cbs_status lanes_join(cbs_plan p, hipStream_t st) {
+  for (int l = 0; l < 2; ++l) {
+    HIPCHK(hipEventRecord(p->ev_join[l], p->lane_st[l]));
+    HIPCHK(hipStreamWaitEvent(st, p->ev_join[l], 0));
+  }
+  return CBS_OK;
 }
 
 // Forward rows (prologue) -> columns (symbol) -> inverse rows (epilogue).
@@ -312,20 +425,32 @@ cbs_status run_pipeline(cbs_plan p, Params<R> q, hipStream_t st) {
 // inverse rows with the sweep epilogue.  The partial norms left behind are
 // those of the last sweep.
 template <typename R>
-cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
-  const int nrow = p->view->nrows;
+void sweep_chain(cbs_plan p, const Params<R>& q, int count, hipStream_t st,
+                 const cbs_plan_s::Items& it) {
   Params<R> f = q;
-  f.items = p->view->rows;
-  launch_row(0, nrow, st, f);
+  f.items = it.rows;
+  launch_row(0, it.nrows, st, f);
   for (int k = 1; k < count; ++k) {
-    launch_cols(p, q, st);
-    launch_row(2, nrow, st, f);
+    launch_cols(p, q, st, it);
+    launch_row(2, it.nrows, st, f);
   }
-  launch_cols(p, q, st);
+  launch_cols(p, q, st, it);
   Params<R> e = q;
-  e.items = p->view->rows;
+  e.items = it.rows;
   e.epi = EPI_SWEEP;
-  launch_row(1, nrow, st, e);
+  launch_row(1, it.nrows, st, e);
+}
+
+template <typename R>
+cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
+  const cbs_plan_s::View& v = *p->view;
+  if (v.nlanes) {
+    CHK(lanes_fork(p, st));
+    for (int l = 0; l < v.nlanes; ++l) sweep_chain(p, q, count, p->lane_st[l], v.lane[l]);
+    HIPCHK(hipGetLastError());
+    return lanes_join(p, st);
+  }
+  sweep_chain(p, q, count, st, v.all());
   HIPCHK(hipGetLastError());
   return CBS_OK;
 }
@@ -389,6 +514,14 @@ void free_plan(cbs_plan p) {
   drop_graphs(p);
   if (p->own_stream) hipStreamDestroy(p->own_stream);
   p->own_stream = nullptr;
+  for (int l = 0; l < 2; ++l) {
+    if (p->lane_st[l]) hipStreamDestroy(p->lane_st[l]);
+    if (p->ev_join[l]) hipEventDestroy(p->ev_join[l]);
+    p->lane_st[l] = nullptr;
+    p->ev_join[l] = nullptr;
+  }
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  p->ev_fork = nullptr;
   for (void* q : p->owned) hipFree(q);
   p->owned.clear();
 }
@@ -462,7 +595,6 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
   // each sweep runs between the fused kernels (a converged instance is masked
   // from the next launch on).
   if (chunk > 1) {
-    const int nrow = p->view->nrows;
     Params<R> q = base_params<R>(p);
     q.u = e;
     q.rhs = c;
@@ -470,13 +602,26 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     q.epi = EPI_SWEEP;
     q.mask = p->d_status;
     q.mask_mode = MASK_RUNNING;
-    q.items = p->view->rows;
-    launch_row(0, nrow, st, q);
-    for (int k = 1; k < chunk; ++k) {
-      launch_cols(p, q, st);
-      q.items = p->view->rows;
-      launch_row(k + 1 < chunk ? 2 : 1, nrow, st, q);
-      launch_check32(p->batch, st, is, p->d_inst, p->d_partials);
+    // Each lane checks only its own instances, so the lanes never wait on
+    // each other inside the chunk.
+    auto chain = [&](hipStream_t ls, const cbs_plan_s::Items& it, int ncheck, const int* ids) {
+      q.items = it.rows;
+      launch_row(0, it.nrows, ls, q);
+      for (int k = 1; k < chunk; ++k) {
+        launch_cols(p, q, ls, it);
+        q.items = it.rows;
+        launch_row(k + 1 < chunk ? 2 : 1, it.nrows, ls, q);
+        launch_check32(ncheck, ids, ls, is, p->d_inst, p->d_partials);
+      }
+    };
+    const cbs_plan_s::View& v = *p->view;
+    if (v.nlanes) {
+      CHK(lanes_fork(p, st));
+      for (int l = 0; l < v.nlanes; ++l) chain(p->lane_st[l], v.lane[l], v.lane[l].nids, v.lane[l].ids);
+      HIPCHK(hipGetLastError());
+      CHK(lanes_join(p, st));
+    } else {
+      chain(st, v.all(), p->batch, nullptr);
     }
   }
   {
@@ -862,7 +1007,8 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
   if (batch < 1 || !n || !k2) return fail(CBS_ERR_ARG, "batch < 1 or n/k2 NULL");
   if (dtype != CBS_C64 && dtype != CBS_C128) return fail(CBS_ERR_ARG, "dtype must be CBS_C64 or CBS_C128");
   if (max_restart < 0 || max_restart > 200) return fail(CBS_ERR_ARG, "max_restart must be in [0, 200]");
-  if (flags & ~uint32_t(CBS_FLAG_NO_GUARD)) return fail(CBS_ERR_ARG, "unknown flag bits");
+  if (flags & ~uint32_t(CBS_FLAG_NO_GUARD | CBS_FLAG_ONE_STREAM))
+    return fail(CBS_ERR_ARG, "unknown flag bits");
   for (int i = 0; i < batch; ++i)
     if (!supported_n(n[i]))
       return fail(CBS_ERR_SIZE, "unsupported grid size " + std::to_string(n[i]) + " (instance " +
@@ -879,6 +1025,7 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
   p->batch = batch;
   p->dtype = dtype;
   p->max_restart = max_restart;
+  p->one_stream = (flags & CBS_FLAG_ONE_STREAM) != 0;
   p->n.assign(n, n + batch);
   long long off = 0;
   for (int i = 0; i < batch; ++i) {
@@ -947,13 +1094,30 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
   }
   p->compact.gen = 1;
   for (int2** d : {&p->d_col_items32, &p->d_col_items64, &p->compact.rows, &p->compact.cols32,
-                   &p->compact.cols64}) {
+                   &p->compact.cols64, &p->full.lrows, &p->full.lcols32, &p->full.lcols64,
+                   &p->compact.lrows, &p->compact.lcols32, &p->compact.lcols64}) {
     void* ptr = nullptr;
     const size_t cap = std::max(max_col_items(p), p->row_items.size());
     hipError_t e = hipMalloc(&ptr, std::max<size_t>(cap * sizeof(int2), 16));
     if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
     p->owned.push_back(ptr);
     *d = static_cast<int2*>(ptr);
+  }
+  for (int** d : {&p->full.lids, &p->compact.lids}) {
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, std::max<size_t>(batch * sizeof(int), 16));
+    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p->owned.push_back(ptr);
+    *d = static_cast<int*>(ptr);
+  }
+  if (lanes_wanted(p, std::vector<char>(batch, 1))) {
+    for (int l = 0; l < 2; ++l) {
+      hipError_t e = hipStreamCreateWithFlags(&p->lane_st[l], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join[l], hipEventDisableTiming);
+      if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("lane stream: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("lane event: ") + hipGetErrorString(e));
   }
 
   // Per-pass twiddle tables w^(q k), w = exp(-2 pi i / (Ns r)), evaluated in

@@ -23,8 +23,8 @@ void launch_instance_sums(int batch, hipStream_t st, const InstDesc* inst, const
                           double* out);
 void launch_check64(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
                     const double* partials);
-void launch_check32(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
-                    const double* partials);
+void launch_check32(int count, const int* ids, hipStream_t st, const IterState& is,
+                    const InstDesc* inst, const double* partials);
 void launch_set_bnorm(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
                       const double* partials);
 void launch_stats(int grid, hipStream_t st, const InstDesc* inst, const int2* items,

@@ -60,10 +60,13 @@ __global__ void k_check64(IterState st, const InstDesc* inst, int batch,
 }
 
 // After an FP32 sweep of the correction: count it and test the estimate.
-__global__ void k_check32(IterState st, const InstDesc* inst, int batch,
+// ids (nullable) lists the instances to check; count is its length (or the
+// batch size when ids is NULL).
+__global__ void k_check32(IterState st, const InstDesc* inst, const int* ids, int count,
                           const double* partials) {
-  const int i = wave_instance();
-  if (i >= batch) return;
+  const int w = wave_instance();
+  if (w >= count) return;
+  const int i = ids ? ids[w] : w;
   if (st.status[i] != ST_RUNNING) return;
   const InstDesc d = inst[i];
   const double sum = instance_sum(partials, d);
@@ -430,9 +433,10 @@ void launch_check64(int batch, hipStream_t st, const IterState& is, const InstDe
                     const double* partials) {
   hipLaunchKernelGGL(k_check64, dim3(inst_blocks(batch)), dim3(256), 0, st, is, inst, batch, partials);
 }
-void launch_check32(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
-                    const double* partials) {
-  hipLaunchKernelGGL(k_check32, dim3(inst_blocks(batch)), dim3(256), 0, st, is, inst, batch, partials);
+void launch_check32(int count, const int* ids, hipStream_t st, const IterState& is,
+                    const InstDesc* inst, const double* partials) {
+  hipLaunchKernelGGL(k_check32, dim3(inst_blocks(count)), dim3(256), 0, st, is, inst, ids, count,
+                     partials);
 }
 void launch_set_bnorm(int batch, hipStream_t st, const IterState& is, const InstDesc* inst,
                       const double* partials) {
