@@ -195,6 +195,21 @@ __device__ __forceinline__ int lds_pos_step(int e, int pos_e, int q) {
   else return lds_pos(e + q * STEP);
 }
 
+// One element from LDS.  FP32 elements are read by single 8-byte accesses
+// (volatile, so the compiler does not pair neighbouring reads into
+// ds_read2_b64: on gfx950 a paired read occupies the LDS for as many cycles
+// as four single 8-byte reads of the same lanes).
+template <typename R>
+__device__ __forceinline__ cpx<R> lds_ld(const cpx<R>* p) {
+  if constexpr (sizeof(R) == 4) {
+    using lds_u64 = __attribute__((address_space(3))) const volatile unsigned long long;
+    const unsigned long long b = *(lds_u64*)(p);
+    return __builtin_bit_cast(cpx<R>, b);
+  } else {
+    return *p;
+  }
+}
+
 template <typename R, int RADP>
 __device__ __forceinline__ void load_tw(const cpx<R>* __restrict__ p, cpx<R>* w) {
   if constexpr (sizeof(R) == 4) {
@@ -230,10 +245,12 @@ __device__ __forceinline__ void twiddle(cpx<R>* v, int k, const cpx<R>* __restri
 // transform.  The first pass reads its inputs through `ld(e)` (element e of
 // the transform, typically straight from global memory), the last pass hands
 // its outputs to `st(e, v)`; the passes in between exchange data through LDS
-// (`buf`, skewed positions).  LD_LDS / ST_LDS say that ld / st themselves touch
-// this LDS buffer, which adds the barriers an in-place pass needs.
-template <typename R, int N, int P, int PEND, int TPF, int DIR, bool LD_LDS, bool ST_LDS, class LD,
-          class ST>
+// (`buf`, skewed positions, ES elements apart: position x of the transform is
+// buf[ES * x], so ES transforms can share one buffer element-interleaved).
+// LD_LDS / ST_LDS say that ld / st themselves touch this LDS buffer, which
+// adds the barriers an in-place pass needs.
+template <typename R, int N, int P, int PEND, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES,
+          class LD, class ST>
 __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
                                          const cpx<R>* __restrict__ tw, LD& ld, ST& st) {
   constexpr int RAD = plan_radix(N, P);
@@ -257,7 +274,7 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
         } else {
           const int pj = lds_pos(j);
 #pragma unroll
-          for (int q = 0; q < RAD; ++q) v[p][q] = buf[lds_pos_step<NB, RAD>(j, pj, q)];
+          for (int q = 0; q < RAD; ++q) v[p][q] = lds_ld(buf + ES * lds_pos_step<NB, RAD>(j, pj, q));
         }
       }
     }
@@ -278,22 +295,23 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
         } else {
           const int po = lds_pos(o);
 #pragma unroll
-          for (int q = 0; q < RAD; ++q) buf[lds_pos_step<NS, RAD>(o, po, q)] = v[p][q];
+          for (int q = 0; q < RAD; ++q) buf[ES * lds_pos_step<NS, RAD>(o, po, q)] = v[p][q];
         }
       }
     }
   }
   if constexpr (WRITES_LDS) __syncthreads();
   if constexpr (P + 1 < PEND)
-    fft_pass<R, N, P + 1, PEND, TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
+    fft_pass<R, N, P + 1, PEND, TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
 }
 
 // Length-N transform (DIR = -1 forward, +1 inverse, unnormalised) from ld to st.
-template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, class LD, class ST>
+template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES = 1, class LD,
+          class ST>
 __device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active,
                                         const cpx<R>* __restrict__ tw, LD ld, ST st) {
   static_assert(plan_product(N) == N && plan_passes(N) >= 2, "no plan for this size");
-  fft_pass<R, N, 0, plan_passes(N), TPF, DIR, LD_LDS, ST_LDS>(buf, t, active, tw, ld, st);
+  fft_pass<R, N, 0, plan_passes(N), TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
 }
 
 // Two transforms back to back with an elementwise map between them, where the
@@ -306,7 +324,7 @@ __host__ __device__ constexpr bool plan_bridgeable(int n) {
   return plan_passes(n) >= 3 && plan_radix(n, 0) == plan_radix(n, plan_passes(n) - 1);
 }
 
-template <typename R, int N, int TPF, int D1, int D2, class LD, class MID, class ST>
+template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class LD, class MID, class ST>
 __device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
                                          const cpx<R>* __restrict__ tw, LD ld, MID mid, ST st) {
   static_assert(plan_bridgeable(N), "first and last radix differ");
@@ -318,7 +336,7 @@ __device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
   constexpr bool EXACT = (NB % TPF) == 0;
   auto none = [](int, cpx<R>) {};
   // transform 1, passes 0 .. PL-1 (the last of them writes LDS)
-  fft_pass<R, N, 0, PL, TPF, D1, false, false>(buf, t, active, tw, ld, none);
+  fft_pass<R, N, 0, PL, TPF, D1, false, false, ES>(buf, t, active, tw, ld, none);
   cpx<R> v[PER][RAD];
   if (active) {
 #pragma unroll
@@ -327,7 +345,7 @@ __device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
       if (EXACT || j < NB) {
         const int pj = lds_pos(j);
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) v[p][q] = buf[lds_pos_step<NB, RAD>(j, pj, q)];
+        for (int q = 0; q < RAD; ++q) v[p][q] = lds_ld(buf + ES * lds_pos_step<NB, RAD>(j, pj, q));
       }
     }
   }
@@ -347,14 +365,14 @@ __device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
         const int o = j * RAD;
         const int po = lds_pos(o);
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) buf[lds_pos_step<1, RAD>(o, po, q)] = v[p][q];
+        for (int q = 0; q < RAD; ++q) buf[ES * lds_pos_step<1, RAD>(o, po, q)] = v[p][q];
       }
     }
   }
   __syncthreads();
   // transform 2, passes 1 .. PL
   auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
-  fft_pass<R, N, 1, PL + 1, TPF, D2, false, false>(buf, t, active, tw, noload, st);
+  fft_pass<R, N, 1, PL + 1, TPF, D2, false, false, ES>(buf, t, active, tw, noload, st);
 }
 
 }  // namespace cbs

@@ -230,7 +230,7 @@ __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, 
     } else {
       auto st = [&](int e, cpx<R> z) { mine[lds_pos(e)] = update(e, z); };
       fft_run<R, N, T::TPF, 1, false, true>(mine, t, active, p.tw, ld, st);
-      auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
+      auto ld2 = [&](int e) { return lds_ld(mine + lds_pos(e)); };
       fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld2, st2);
     }
     if (p.partials) {
@@ -299,18 +299,18 @@ __device__ __forceinline__ cpx<R> symbol_factor(int n, int k1, int k2, double k0
 
 // Column tile: C columns of one instance.  Thread tid works on column tid % C
 // (so the C threads of a row segment read or write C neighbouring elements)
-// and butterfly slot tid / C.  Between passes column c sits in LDS at
-// c * col_stride(N, C) + pos(row).
+// and butterfly slot tid / C.  Between passes the tile sits in LDS
+// element-interleaved (position x of column c at C * pos(x) + c), which keeps
+// every pass's LDS reads and writes free of bank conflicts on gfx950.
 template <typename R, int N, int C>
 __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, int col0,
                                          cpx<R>* lds) {
   constexpr int TPC = kThreads / C;
-  constexpr int CS = col_stride(N, C);
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
   const long long cbase = d.off + col0 + c;
   const int kcol = col0 + c;
-  cpx<R>* mine = lds + c * CS;
+  cpx<R>* mine = lds + c;
   auto ld = [&](int e) { return p.inter[cbase + (long long)e * N]; };
   auto sym = [&](int e, cpx<R> v) {
     return cmul(v, symbol_factor<R>(N, e, kcol, d.k0sq, d.eps, p.sym));
@@ -319,12 +319,12 @@ __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, 
   if constexpr (plan_bridgeable(N)) {
     // forward column transform, symbol, inverse transform; the last forward
     // and first inverse passes share registers
-    fft_run2<R, N, TPC, -1, 1>(mine, t, true, p.tw, ld, sym, st2);
+    fft_run2<R, N, TPC, -1, 1, C>(mine, t, true, p.tw, ld, sym, st2);
   } else {
-    auto st = [&](int e, cpx<R> v) { mine[lds_pos(e)] = sym(e, v); };
-    fft_run<R, N, TPC, -1, false, true>(mine, t, true, p.tw, ld, st);
-    auto ld2 = [&](int e) { return mine[lds_pos(e)]; };
-    fft_run<R, N, TPC, 1, true, false>(mine, t, true, p.tw, ld2, st2);
+    auto st = [&](int e, cpx<R> v) { mine[C * lds_pos(e)] = sym(e, v); };
+    fft_run<R, N, TPC, -1, false, true, C>(mine, t, true, p.tw, ld, st);
+    auto ld2 = [&](int e) { return lds_ld(mine + C * lds_pos(e)); };
+    fft_run<R, N, TPC, 1, true, false, C>(mine, t, true, p.tw, ld2, st2);
   }
 }
 

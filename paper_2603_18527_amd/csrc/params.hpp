@@ -72,10 +72,9 @@ struct Params {
 //
 // Column stride in LDS for a tile of C columns of length n: offset from a
 // multiple of 32 elements by 32/C so the C columns spread over the banks.
-__host__ __device__ constexpr int col_stride(int n, int c) {
-  return ((lds_len(n) + 31) / 32) * 32 + 32 / c;
-}
-__host__ __device__ constexpr int col_lds_elems(int n, int c) { return c * col_stride(n, c); }
+// Column tile of c columns in LDS: element-interleaved, position x of column
+// k at c * pos(x) + k.
+__host__ __device__ constexpr int col_lds_elems(int n, int c) { return c * lds_len(n); }
 constexpr int kColLdsBytes = 64 * 1024;
 // Default tile: about 2048 elements per workgroup (C * n ~ 8 elements per thread).
 __host__ __device__ constexpr int col_tile_default(int n) {
