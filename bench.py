@@ -201,8 +201,28 @@ def time_to_solution(probs, plan_k2, sizes, k0sq, s_packed, rtol=1e-6, chunk=50,
     out["plain_loop_s"] = t_plain
     out["speedup_batched_vs_plain"] = t_plain / t_batch
     if t_512:
-        out["plain_512_each_s_mean"] = float(np.mean(t_512))
+        # the 512^2 instances alone: one batched plan (graph replay) against
+        # the per-instance loop over the same instances timed above
+        idx = [i for i, n in enumerate(sizes) if n == 512]
+        k2_512 = torch.cat([plan_k2[offs[i]:offs[i] + n * n] for i, n in enumerate(sizes) if n == 512])
+        s_512 = torch.cat([s_packed[offs[i]:offs[i] + n * n] for i, n in enumerate(sizes) if n == 512])
+        pb = cbs.Plan(k2_512.contiguous(), [512] * len(idx), k0sq=[k0sq[i] for i in idx])
+        ub = pb.zeros()
+        pb.iterate(ub, s_512, max_sweeps=60, rtol=rtol, check_every=chunk, use_graph=True)
+        ub.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its5, rel5, st5 = pb.iterate(ub, s_512, max_sweeps=max_sweeps, rtol=rtol, check_every=chunk,
+                                     use_graph=True)
+        t_b512 = time.perf_counter() - t0
+        pb.close()
         out["n_512_instances"] = len(t_512)
+        out["batched_512_s"] = t_b512
+        out["batched_512_sweeps_max"] = int(max(its5))
+        out["batched_512_all_converged"] = all(x == cbs.INST_CONVERGED for x in st5)
+        out["plain_512_loop_s"] = float(np.sum(t_512))
+        out["plain_512_each_s_mean"] = float(np.mean(t_512))
+        out["speedup_512_batched_vs_plain"] = float(np.sum(t_512)) / t_b512
     out["chunk"] = chunk
     out["rtol"] = rtol
     return out

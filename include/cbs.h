@@ -111,6 +111,31 @@ cbs_status cbs_setup(cbs_plan* plan, int batch, const int32_t* n, const void* k2
                      const double* k0sq, const double* eps, int dtype, int max_restart,
                      uint32_t flags, void* stream);
 
+/*
+ * cbs_workspace_size -- device bytes a plan of these sizes needs when the
+ * caller provides its memory (cbs_setup_ws).  Host-only; touches no device.
+ *   batch, n, dtype, max_restart as in cbs_setup; bytes out.
+ * The plan's buffers: FP64 copies of k^2, the spectral buffer, the FP64
+ * iterate and source, three operator-precision fields, per-row partial sums,
+ * per-instance solver state, twiddle tables, work lists, and for
+ * max_restart m > 0 the FGMRES bases (m + 1 FP64 fields and m
+ * operator-precision fields) with the Hessenberg/Givens storage.
+ */
+cbs_status cbs_workspace_size(int batch, const int32_t* n, int dtype, int max_restart,
+                              size_t* bytes);
+
+/*
+ * cbs_setup_ws -- cbs_setup with caller-owned device memory: every device
+ * buffer of the plan is carved from `workspace` (device pointer, 256-byte
+ * aligned, at least cbs_workspace_size bytes; owned by the caller and kept
+ * alive, unused by anything else, until cbs_destroy).  The plan then
+ * allocates no device memory of its own.  CBS_ERR_WORKSPACE if the
+ * workspace is too small or misaligned, CBS_ERR_ARG if it is NULL.
+ */
+cbs_status cbs_setup_ws(cbs_plan* plan, int batch, const int32_t* n, const void* k2,
+                        const double* k0sq, const double* eps, int dtype, int max_restart,
+                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Total packed cells (sum n[i]^2) and the per-instance k0^2 and eps in use
  * (host arrays of length batch, may be NULL). */
 cbs_status cbs_plan_info(cbs_plan plan, int64_t* cells, double* k0sq, double* eps);

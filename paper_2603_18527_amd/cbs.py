@@ -38,6 +38,9 @@ SUPPORTED_SIZES = (16, 32, 64, 128, 192, 256, 288, 384, 512, 1024)
 _vp, _i32, _u32, _f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_double
 SIGNATURES = {
     "cbs_setup": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp]),
+    "cbs_setup_ws": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp,
+                            ctypes.c_size_t, _vp]),
+    "cbs_workspace_size": (_i32, [_i32, _vp, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -102,6 +105,14 @@ def _stream(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def workspace_size(sizes: Sequence[int], dtype: int = CBS_C64, max_restart: int = 0) -> int:
+    """Device bytes of a plan's workspace (cbs_workspace_size; host only)."""
+    n_arr = (ctypes.c_int32 * len(sizes))(*[int(n) for n in sizes])
+    out = ctypes.c_size_t()
+    _check(load().cbs_workspace_size(len(sizes), n_arr, int(dtype), int(max_restart), ctypes.byref(out)))
+    return int(out.value)
+
+
 def offsets(sizes: Sequence[int]) -> List[int]:
     out, o = [], 0
     for n in sizes:
@@ -128,7 +139,9 @@ class Plan:
 
     def __init__(self, k2: torch.Tensor, sizes: Sequence[int], k0sq=None, eps=None,
                  dtype: int = CBS_C64, max_restart: int = 0, guard: bool = True, stream=None,
-                 lanes: bool = True):
+                 lanes: bool = True, torch_workspace: bool = True):
+        """torch_workspace: the plan's device memory is one torch tensor
+        (cbs_setup_ws); False lets the library allocate it (cbs_setup)."""
         lib = load()
         self.sizes = [int(n) for n in sizes]
         self.batch = len(self.sizes)
@@ -144,10 +157,17 @@ class Plan:
         eps_arr = None if eps is None else (ctypes.c_double * self.batch)(
             *[0.0 if v is None else float(v) for v in _expand(eps, self.batch)])
         h = ctypes.c_void_p()
-        st = lib.cbs_setup(ctypes.byref(h), self.batch, n_arr, _ptr(k2), k0_arr, eps_arr, dtype,
-                           int(max_restart),
-                           (0 if guard else FLAG_NO_GUARD) | (0 if lanes else FLAG_ONE_STREAM),
-                           _stream(stream))
+        flags = (0 if guard else FLAG_NO_GUARD) | (0 if lanes else FLAG_ONE_STREAM)
+        self._ws = None
+        if torch_workspace:
+            self._ws = torch.empty(workspace_size(self.sizes, dtype, max_restart), dtype=torch.uint8,
+                                   device="cuda")
+            st = lib.cbs_setup_ws(ctypes.byref(h), self.batch, n_arr, _ptr(k2), k0_arr, eps_arr, dtype,
+                                  int(max_restart), flags, _ptr(self._ws), self._ws.numel(),
+                                  _stream(stream))
+        else:
+            st = lib.cbs_setup(ctypes.byref(h), self.batch, n_arr, _ptr(k2), k0_arr, eps_arr, dtype,
+                               int(max_restart), flags, _stream(stream))
         _check(st)
         self._h = h
         self.max_restart = int(max_restart)
@@ -161,8 +181,16 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
+            if getattr(self, "_ws", None) is not None:
+                # queued work of the plan (also on its lane streams) must end
+                # before torch may hand the workspace to someone else
+                try:
+                    torch.cuda.synchronize()
+                except Exception:
+                    pass
             _lib.cbs_destroy(h)
             self._h = None
+        self._ws = None
 
     def close(self):
         self.__del__()

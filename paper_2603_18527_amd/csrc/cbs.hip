@@ -992,19 +992,8 @@ cbs_status seed_impl(cbs_plan p, const void* uk, const void* s, int wg, double* 
   return CBS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* cbs_last_error(void) { return g_err.c_str(); }
-const char* cbs_version(void) { return "cbs-mi355x 0.1 (gfx950)"; }
-
-cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
-                     const double* k0sq, const double* eps, int dtype, int max_restart,
-                     uint32_t flags, void* stream) {
-  if (!out) return fail(CBS_ERR_ARG, "plan pointer is NULL");
-  *out = nullptr;
-  if (batch < 1 || !n || !k2) return fail(CBS_ERR_ARG, "batch < 1 or n/k2 NULL");
+cbs_status check_setup_args(int batch, const int32_t* n, int dtype, int max_restart, uint32_t flags) {
+  if (batch < 1 || !n) return fail(CBS_ERR_ARG, "batch < 1 or n NULL");
   if (dtype != CBS_C64 && dtype != CBS_C128) return fail(CBS_ERR_ARG, "dtype must be CBS_C64 or CBS_C128");
   if (max_restart < 0 || max_restart > 200) return fail(CBS_ERR_ARG, "max_restart must be in [0, 200]");
   if (flags & ~uint32_t(CBS_FLAG_NO_GUARD | CBS_FLAG_ONE_STREAM))
@@ -1013,15 +1002,11 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
     if (!supported_n(n[i]))
       return fail(CBS_ERR_SIZE, "unsupported grid size " + std::to_string(n[i]) + " (instance " +
                                     std::to_string(i) + ")");
-  if (eps)
-    for (int i = 0; i < batch; ++i)
-      if (std::isnan(eps[i]) || std::isinf(eps[i])) return fail(CBS_ERR_ARG, "eps must be finite");
-  if (k0sq)
-    for (int i = 0; i < batch; ++i)
-      if (std::isinf(k0sq[i])) return fail(CBS_ERR_ARG, "k0sq must be finite or NaN (auto)");
+  return CBS_OK;
+}
 
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  cbs_plan p = new cbs_plan_s();
+// Host-side layout of a plan: sizes, packed offsets, work items.
+void init_layout(cbs_plan p, int batch, const int32_t* n, int dtype, int max_restart, uint32_t flags) {
   p->batch = batch;
   p->dtype = dtype;
   p->max_restart = max_restart;
@@ -1034,18 +1019,19 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
     p->maxn = std::max(p->maxn, n[i]);
   }
   p->cells = off;
+  if (max_restart > 0) p->kry_stride = KryLayout{max_restart}.size();
   build_items(p);
+}
 
-  auto bail = [&](cbs_status s, const std::string& m) {
-    free_plan(p);
-    delete p;
-    return fail(s, m);
-  };
+// Every device buffer of a plan (pointer to set, bytes).
+std::vector<std::pair<void**, size_t>> buffer_requests(cbs_plan p) {
   const long long cells = p->cells;
   const size_t oe = p->op_elem();
+  const size_t batch = size_t(p->batch);
+  const size_t nrow = p->row_items.size();
   std::vector<std::pair<void**, size_t>> req = {
       {reinterpret_cast<void**>(&p->d_inst), batch * sizeof(InstDesc)},
-      {reinterpret_cast<void**>(&p->d_row_items), p->row_items.size() * sizeof(int2)},
+      {reinterpret_cast<void**>(&p->d_row_items), nrow * sizeof(int2)},
       {reinterpret_cast<void**>(&p->d_tw32), kTwTotal * sizeof(cpx<float>)},
       {reinterpret_cast<void**>(&p->d_tw64), kTwTotal * sizeof(cpx<double>)},
       {reinterpret_cast<void**>(&p->d_k2_64), cells * 16},
@@ -1055,7 +1041,7 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
       {&p->d_c, cells * oe},
       {&p->d_e, cells * oe},
       {&p->d_t, cells * oe},
-      {reinterpret_cast<void**>(&p->d_partials), (2 * p->row_items.size() + 64) * sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_partials), (2 * nrow + 64) * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_status), batch * sizeof(int)},
       {reinterpret_cast<void**>(&p->d_iters), batch * sizeof(int)},
       {reinterpret_cast<void**>(&p->d_chunk_active), batch * sizeof(int)},
@@ -1067,49 +1053,132 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
       {reinterpret_cast<void**>(&p->d_scale), batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_kactive), batch * sizeof(int)},
       {reinterpret_cast<void**>(&p->d_kjend), batch * sizeof(int)},
+      {reinterpret_cast<void**>(&p->full.lids), batch * sizeof(int)},
+      {reinterpret_cast<void**>(&p->compact.lids), batch * sizeof(int)},
   };
-  if (dtype == CBS_C64) {
+  if (p->dtype == CBS_C64) {
     req.push_back({&p->d_k2, cells * 8});
     req.push_back({&p->d_inter, cells * 8});
   }
-  if (max_restart > 0) {
-    const KryLayout L{max_restart};
-    p->kry_stride = L.size();
-    req.push_back({reinterpret_cast<void**>(&p->d_vbasis), cells * 16 * size_t(max_restart + 1)});
-    req.push_back({&p->d_zbasis, cells * oe * size_t(max_restart)});
+  if (p->max_restart > 0) {
+    const size_t m = size_t(p->max_restart);
+    req.push_back({reinterpret_cast<void**>(&p->d_vbasis), cells * 16 * (m + 1)});
+    req.push_back({&p->d_zbasis, cells * oe * m});
     req.push_back({reinterpret_cast<void**>(&p->d_kry), size_t(p->kry_stride) * batch * sizeof(double)});
-    req.push_back({reinterpret_cast<void**>(&p->d_dots),
-                   2 * size_t(max_restart + 2) * p->row_items.size() * sizeof(double)});
+    req.push_back({reinterpret_cast<void**>(&p->d_dots), 2 * (m + 2) * nrow * sizeof(double)});
   }
-  for (auto& r : req) {
-    void* ptr = nullptr;
-    hipError_t e = hipMalloc(&ptr, std::max<size_t>(r.second, 16));
-    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
-    p->owned.push_back(ptr);
-    *r.first = ptr;
+  // work lists (capacity: tile width 2 everywhere)
+  const size_t cap = std::max(max_col_items(p), nrow) * sizeof(int2);
+  for (int2** d : {&p->d_col_items32, &p->d_col_items64, &p->compact.rows, &p->compact.cols32,
+                   &p->compact.cols64, &p->full.lrows, &p->full.lcols32, &p->full.lcols64,
+                   &p->compact.lrows, &p->compact.lcols32, &p->compact.lcols64})
+    req.push_back({reinterpret_cast<void**>(d), cap});
+  return req;
+}
+
+size_t padded(size_t bytes) { return (std::max<size_t>(bytes, 16) + 255) / 256 * 256; }
+
+size_t request_bytes(const std::vector<std::pair<void**, size_t>>& req) {
+  size_t total = 0;
+  for (const auto& r : req) total += padded(r.second);
+  return total;
+}
+
+cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2,
+                      const double* k0sq, const double* eps, int dtype, int max_restart,
+                      uint32_t flags, void* ws, size_t ws_bytes, void* stream);
+
+}  // namespace
+
+extern "C" {
+
+const char* cbs_last_error(void) { return g_err.c_str(); }
+const char* cbs_version(void) { return "cbs-mi355x 0.1 (gfx950)"; }
+
+cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
+                     const double* k0sq, const double* eps, int dtype, int max_restart,
+                     uint32_t flags, void* stream) {
+  return setup_impl(out, batch, n, k2, k0sq, eps, dtype, max_restart, flags, nullptr, 0, stream);
+}
+
+cbs_status cbs_setup_ws(cbs_plan* out, int batch, const int32_t* n, const void* k2,
+                        const double* k0sq, const double* eps, int dtype, int max_restart,
+                        uint32_t flags, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!workspace) {
+    if (out) *out = nullptr;
+    return fail(CBS_ERR_ARG, "workspace is NULL");
+  }
+  return setup_impl(out, batch, n, k2, k0sq, eps, dtype, max_restart, flags, workspace,
+                    workspace_bytes, stream);
+}
+
+cbs_status cbs_workspace_size(int batch, const int32_t* n, int dtype, int max_restart,
+                              size_t* bytes) {
+  if (!bytes) return fail(CBS_ERR_ARG, "bytes is NULL");
+  *bytes = 0;
+  CHK(check_setup_args(batch, n, dtype, max_restart, 0));
+  cbs_plan_s p;
+  init_layout(&p, batch, n, dtype, max_restart, 0);
+  *bytes = request_bytes(buffer_requests(&p));
+  return CBS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2,
+                      const double* k0sq, const double* eps, int dtype, int max_restart,
+                      uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
+  if (!out) return fail(CBS_ERR_ARG, "plan pointer is NULL");
+  *out = nullptr;
+  if (!k2) return fail(CBS_ERR_ARG, "k2 is NULL");
+  CHK(check_setup_args(batch, n, dtype, max_restart, flags));
+  if (eps)
+    for (int i = 0; i < batch; ++i)
+      if (std::isnan(eps[i]) || std::isinf(eps[i])) return fail(CBS_ERR_ARG, "eps must be finite");
+  if (k0sq)
+    for (int i = 0; i < batch; ++i)
+      if (std::isinf(k0sq[i])) return fail(CBS_ERR_ARG, "k0sq must be finite or NaN (auto)");
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  cbs_plan p = new cbs_plan_s();
+  init_layout(p, batch, n, dtype, max_restart, flags);
+
+  auto bail = [&](cbs_status s, const std::string& m) {
+    free_plan(p);
+    delete p;
+    return fail(s, m);
+  };
+  const long long cells = p->cells;
+  const std::vector<std::pair<void**, size_t>> req = buffer_requests(p);
+  if (ws) {
+    // Every buffer is carved from the caller's workspace (256-byte aligned).
+    const size_t need = request_bytes(req);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+      return bail(CBS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+      return bail(CBS_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                                         std::to_string(need));
+    char* cur = static_cast<char*>(ws);
+    for (auto& r : req) {
+      *r.first = cur;
+      cur += padded(r.second);
+    }
+  } else {
+    for (auto& r : req) {
+      void* ptr = nullptr;
+      hipError_t e = hipMalloc(&ptr, padded(r.second));
+      if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+      p->owned.push_back(ptr);
+      *r.first = ptr;
+    }
   }
   if (dtype == CBS_C128) {
     p->d_k2 = p->d_k2_64;
     p->d_inter = p->d_inter64;
   }
   p->compact.gen = 1;
-  for (int2** d : {&p->d_col_items32, &p->d_col_items64, &p->compact.rows, &p->compact.cols32,
-                   &p->compact.cols64, &p->full.lrows, &p->full.lcols32, &p->full.lcols64,
-                   &p->compact.lrows, &p->compact.lcols32, &p->compact.lcols64}) {
-    void* ptr = nullptr;
-    const size_t cap = std::max(max_col_items(p), p->row_items.size());
-    hipError_t e = hipMalloc(&ptr, std::max<size_t>(cap * sizeof(int2), 16));
-    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
-    p->owned.push_back(ptr);
-    *d = static_cast<int2*>(ptr);
-  }
-  for (int** d : {&p->full.lids, &p->compact.lids}) {
-    void* ptr = nullptr;
-    hipError_t e = hipMalloc(&ptr, std::max<size_t>(batch * sizeof(int), 16));
-    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
-    p->owned.push_back(ptr);
-    *d = static_cast<int*>(ptr);
-  }
   if (lanes_wanted(p, std::vector<char>(batch, 1))) {
     for (int l = 0; l < 2; ++l) {
       hipError_t e = hipStreamCreateWithFlags(&p->lane_st[l], hipStreamNonBlocking);
@@ -1194,6 +1263,10 @@ cbs_status cbs_setup(cbs_plan* out, int batch, const int32_t* n, const void* k2,
   *out = p;
   return CBS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 cbs_status cbs_plan_info(cbs_plan p, int64_t* cells, double* k0sq, double* eps) {
   if (!p) return fail(CBS_ERR_ARG, "plan is NULL");

@@ -70,3 +70,43 @@ def test_calls_with_null_plan_fail_cleanly():
 
 def test_packing_offsets():
     assert cbs.offsets([16, 32, 64]) == [0, 256, 256 + 1024]
+
+
+def test_workspace_size_without_gpu():
+    small = cbs.workspace_size([64])
+    assert small > 0 and small % 256 == 0
+    assert cbs.workspace_size([64], cbs.CBS_C64, 0) == small
+    assert cbs.workspace_size([64], cbs.CBS_C64, 10) > small        # FGMRES bases
+    assert cbs.workspace_size([64], cbs.CBS_C128) > small           # complex128 fields
+    assert cbs.workspace_size([64, 128]) > cbs.workspace_size([128])
+    # at least the packed fields the plan keeps: 4 FP64 copies + 2 FP32 + 3 operator fields
+    cells = 128 * 128 + 192 * 192
+    assert cbs.workspace_size([128, 192]) >= cells * (4 * 16 + 2 * 8 + 3 * 8)
+    lib = cbs.load()
+    out = ctypes.c_size_t()
+    n = (ctypes.c_int32 * 1)(100)
+    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, 0, ctypes.byref(out)) == cbs.CBS_ERR_SIZE
+    n = (ctypes.c_int32 * 1)(64)
+    assert lib.cbs_workspace_size(0, n, cbs.CBS_C64, 0, ctypes.byref(out)) == cbs.CBS_ERR_ARG
+    assert lib.cbs_workspace_size(1, n, 5, 0, ctypes.byref(out)) == cbs.CBS_ERR_ARG
+    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, -1, ctypes.byref(out)) == cbs.CBS_ERR_ARG
+    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, 0, None) == cbs.CBS_ERR_ARG
+
+
+def test_setup_ws_rejects_bad_workspace_without_gpu():
+    # every check below fails before the library touches the device
+    lib = cbs.load()
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int32 * 1)(64)
+    need = cbs.workspace_size([64])
+    fake_k2 = ctypes.c_void_p(1 << 20)
+
+    def setup(ws, nbytes):
+        return lib.cbs_setup_ws(ctypes.byref(h), 1, n, fake_k2, None, None, cbs.CBS_C64, 0, 0,
+                                ws, nbytes, None)
+    assert setup(None, need) == cbs.CBS_ERR_ARG
+    assert setup(ctypes.c_void_p((1 << 20) + 8), need) == cbs.CBS_ERR_WORKSPACE
+    assert "aligned" in cbs.last_error()
+    assert setup(ctypes.c_void_p(1 << 20), need - 256) == cbs.CBS_ERR_WORKSPACE
+    assert "need" in cbs.last_error()
+    assert h.value is None
