@@ -58,46 +58,55 @@ def measured_traffic(workload: str):
 
 
 def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str):
-    """Turn two rocprofv3 --pmc runs of `bench.py --calib-copy` (FETCH_SIZE,
-    WRITE_SIZE; KiB per dispatch) into the per-sweep HBM traffic record.
+    """Turn two rocprofv3 --pmc runs of `bench.py --steps 60 --chain 60
+    --warmup 2 --calib-copy` (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into
+    the per-sweep HBM traffic record.
 
     Each counter is scaled by what it reads for the 1 GiB calibration copy
-    (the largest __amd_rocclr_copyBuffer dispatch).  Per-sweep bytes are the
-    means over the steady-state dispatches of k_row_sweep and of the
-    full-batch k_col launches (the largest grid; autotuning launches smaller
-    per-size-class grids)."""
+    (the largest __amd_rocclr_copyBuffer dispatch).  That run makes, per lane
+    (two lanes, or one when the batch is not split), 62 k_col and 60
+    k_row_sweep dispatches of the lane's grid (warm-up call of 2 sweeps, one
+    chain of 60); the autotuner's per-size-class k_col launches come 23 per
+    grid.  Per-sweep bytes: the bytes of every dispatch of a grid launched at
+    least that often, divided by the number of sweeps."""
     import csv
     import collections
+    sweeps = {"k_row_sweep": 60, "k_col": 62}
 
     def load(path, counter):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         scale = (1 << 30) / (max(copies) * 1024.0)
-        per = collections.defaultdict(list)
-        col_grid = max(int(r["Grid_Size"]) for r in rows if "k_col<float" in r["Kernel_Name"])
-        for r in rows:
-            name = r["Kernel_Name"]
-            if "k_row_sweep<float>" in name:
-                per["k_row_sweep"].append(float(r["Counter_Value"]))
-            elif "k_col<float" in name and int(r["Grid_Size"]) == col_grid:
-                per["k_col"].append(float(r["Counter_Value"]))
-        return scale, {k: 1024.0 * scale * sum(v) / len(v) for k, v in per.items()}
+        out, grids = {}, {}
+        for kern, tag in (("k_row_sweep", "k_row_sweep<float>"), ("k_col", "k_col<float")):
+            by_grid = collections.defaultdict(list)
+            for r in rows:
+                if tag in r["Kernel_Name"]:
+                    by_grid[int(r["Grid_Size"])].append(float(r["Counter_Value"]))
+            lanes = sorted(g for g, v in by_grid.items() if len(v) >= sweeps[kern])
+            for g in lanes:
+                if len(by_grid[g]) % sweeps[kern]:
+                    raise ValueError(f"{kern} grid {g}: {len(by_grid[g])} dispatches, not a whole "
+                                     f"number of lanes x {sweeps[kern]} sweeps")
+            out[kern] = 1024.0 * scale * sum(sum(by_grid[g]) for g in lanes) / sweeps[kern]
+            grids[kern] = lanes
+        return scale, out, grids
 
-    fs, fetch = load(fetch_csv, "FETCH_SIZE")
-    ws, write = load(write_csv, "WRITE_SIZE")
+    fs, fetch, grids = load(fetch_csv, "FETCH_SIZE")
+    ws, write, _ = load(write_csv, "WRITE_SIZE")
+    cmd = ("python -u bench.py --steps 60 --chain 60 --warmup 2 --no-cpu --no-solve --calib-copy")
     rec = {
         "workload": workload,
         "kernel_source_hash": kernel_source_hash(),
         "fetch_scale": fs,
         "write_scale": ws,
+        "lane_grids": grids,
         "bytes_read": fetch,
         "bytes_written": write,
         "bytes_per_sweep": sum(fetch.values()) + sum(write.values()),
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- "
-            "python -u bench.py --steps 20 --chain 20 --warmup 2 --no-cpu --no-solve --calib-copy",
-            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- "
-            "python -u bench.py --steps 20 --chain 20 --warmup 2 --no-cpu --no-solve --calib-copy",
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- " + cmd,
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- " + cmd,
         ],
     }
     with open(out_path, "w") as f:

@@ -602,17 +602,22 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     q.epi = EPI_SWEEP;
     q.mask = p->d_status;
     q.mask_mode = MASK_RUNNING;
+    // The check of each sweep runs in the next column launch (its first
+    // tiles' workgroups); the last sweep's check is a launch of its own.
     // Each lane checks only its own instances, so the lanes never wait on
     // each other inside the chunk.
+    q.chk = is;
     auto chain = [&](hipStream_t ls, const cbs_plan_s::Items& it, int ncheck, const int* ids) {
       q.items = it.rows;
       launch_row(0, it.nrows, ls, q);
       for (int k = 1; k < chunk; ++k) {
+        q.check = k >= 2 ? 1 : 0;
         launch_cols(p, q, ls, it);
+        q.check = 0;
         q.items = it.rows;
         launch_row(k + 1 < chunk ? 2 : 1, it.nrows, ls, q);
-        launch_check32(ncheck, ids, ls, is, p->d_inst, p->d_partials);
       }
+      launch_check32(ncheck, ids, ls, is, p->d_inst, p->d_partials);
     };
     const cbs_plan_s::View& v = *p->view;
     if (v.nlanes) {

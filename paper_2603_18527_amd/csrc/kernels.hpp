@@ -21,7 +21,9 @@ namespace cbs {
 
 __device__ __forceinline__ bool inst_enabled(const int* mask, int mode, int i) {
   if (!mask) return true;
-  const int m = mask[i];
+  // atomic: a column launch may update an instance's status while other
+  // workgroups of the same launch read it (k_col's folded check)
+  const int m = __hip_atomic_load(mask + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (mode == MASK_RUNNING) return m == ST_RUNNING;
   if (mode == MASK_NOT_FINAL) return m == ST_RUNNING || m == ST_PENDING;
   return m != 0;
@@ -152,6 +154,32 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Workgroup sum of one double per thread (all threads must call).
+// Sum of an instance's partial slots by one full wavefront: lane l adds
+// slots l, l+64, ..., then a fixed shuffle tree (deterministic).
+__device__ __forceinline__ double instance_sum(const double* partials, const InstDesc& d) {
+  double s = 0.0;
+  for (int k = threadIdx.x & 63; k < d.nparts; k += 64) s += partials[d.part_off + k];
+  return wave_sum(s);
+}
+
+// FP32 convergence check of instance i after a correction sweep (one full
+// wavefront): count the sweep, record the estimate ||r|| / ||G s|| and flag
+// the instance ST_PENDING once it is at or below rtol or out of sweeps.
+__device__ __forceinline__ void check32_instance(const IterState& st, const InstDesc* inst,
+                                                 const double* partials, int i) {
+  if (__hip_atomic_load(st.status + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ST_RUNNING)
+    return;
+  const InstDesc d = inst[i];
+  const double sum = instance_sum(partials, d);
+  if ((threadIdx.x & 63) != 0) return;
+  const double bn = st.bnorm[i] > 0.0 ? st.bnorm[i] : 1.0;
+  const double rel = sqrt(sum) / bn;
+  st.est[i] = rel;
+  st.iters[i] += 1;
+  if (!(rel > st.rtol[0]) || st.iters[i] >= st.max_sweeps[0])
+    __hip_atomic_store(st.status + i, int(ST_PENDING), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -347,6 +375,10 @@ __global__ __launch_bounds__(kThreads) void k_col(Params<R> p) {
   extern __shared__ float4 smem_raw[];
   cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
   const int2 w = p.items[blockIdx.x];
+  // the first tile's workgroup checks the sweep the previous launch finished
+  // (the instance's next row launch sees the result; whether the other tiles
+  // of this launch see it only decides whether they do work nobody reads)
+  if (p.check && w.y == 0 && threadIdx.x < 64) check32_instance(p.chk, p.inst, p.partials, w.x);
   if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
   const InstDesc d = p.inst[w.x];
   switch (d.n) {

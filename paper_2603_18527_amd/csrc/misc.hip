@@ -18,12 +18,6 @@ __device__ __forceinline__ int wave_instance() {
   return int((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
-__device__ __forceinline__ double instance_sum(const double* partials, const InstDesc& d) {
-  double s = 0.0;
-  for (int k = threadIdx.x & 63; k < d.nparts; k += 64) s += partials[d.part_off + k];
-  return wave_sum(s);
-}
-
 // norm2[i] = sum of the instance's partials (fixed order => deterministic).
 __global__ void k_instance_sums(const InstDesc* inst, int batch, const double* partials,
                                 double* out) {
@@ -66,16 +60,7 @@ __global__ void k_check32(IterState st, const InstDesc* inst, const int* ids, in
                           const double* partials) {
   const int w = wave_instance();
   if (w >= count) return;
-  const int i = ids ? ids[w] : w;
-  if (st.status[i] != ST_RUNNING) return;
-  const InstDesc d = inst[i];
-  const double sum = instance_sum(partials, d);
-  if ((threadIdx.x & 63) != 0) return;
-  const double bn = st.bnorm[i] > 0.0 ? st.bnorm[i] : 1.0;
-  const double rel = sqrt(sum) / bn;
-  st.est[i] = rel;
-  st.iters[i] += 1;
-  if (!(rel > st.rtol[0]) || st.iters[i] >= st.max_sweeps[0]) st.status[i] = ST_PENDING;
+  check32_instance(st, inst, partials, ids ? ids[w] : w);
 }
 
 // bnorm[i] = sqrt(sum of partials)

@@ -44,6 +44,17 @@ enum Epi {
 enum MaskMode { MASK_RUNNING = 0, MASK_NOT_FINAL = 1, MASK_NONZERO = 2 };
 enum InstStatus { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_DIVERGED = 3, ST_PENDING = 4 };
 
+struct IterState {
+  int* status;
+  int* iters;
+  int* chunk_active;
+  double* relres;   // FP64-verified relative residual
+  double* est;      // latest FP32 estimate
+  double* bnorm;    // ||G s|| per instance
+  const double* rtol;
+  const int* max_sweeps;
+};
+
 template <typename R>
 struct Params {
   const InstDesc* inst;
@@ -65,13 +76,16 @@ struct Params {
   int mask_mode;
   int pro, sym, epi;
   int weight_gamma;
+  // check != 0: the workgroup of each instance's first column tile also
+  // runs the FP32 convergence check of the sweep that the previous row
+  // launch finished (k_col only)
+  IterState chk;
+  int check;
 };
 
 
 // ---- column tiles ------------------------------------------------------------------
 //
-// Column stride in LDS for a tile of C columns of length n: offset from a
-// multiple of 32 elements by 32/C so the C columns spread over the banks.
 // Column tile of c columns in LDS: element-interleaved, position x of column
 // k at c * pos(x) + k.
 __host__ __device__ constexpr int col_lds_elems(int n, int c) { return c * lds_len(n); }
@@ -114,16 +128,6 @@ struct PwParams {
   int op;
 };
 
-struct IterState {
-  int* status;
-  int* iters;
-  int* chunk_active;
-  double* relres;   // FP64-verified relative residual
-  double* est;      // latest FP32 estimate
-  double* bnorm;    // ||G s|| per instance
-  const double* rtol;
-  const int* max_sweeps;
-};
 
 struct KryLayout {
   int m;
