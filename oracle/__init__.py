@@ -298,22 +298,29 @@ def unrolled_loss(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma",
                   normalise: bool = False) -> torch.Tensor:
     """ell = || W * (G s - (I - G V) u_K) ||^2 with u_{m+1} = u_m + gamma r(u_m).
 
-    weight "gamma" uses W = gamma; "one" uses W = 1.  With normalise=True the
-    squared norm is divided by ||G s||^2 (the ratio form of L_bs^{R_eta} with
-    the probe r = s).  eps and k0^2 are constants; k2 and u0 may require grad.
+    weight "gamma" uses W = gamma; "one" uses W = 1 (the residual of the
+    metric-matched loss L_bs^{R_eta}, Sec. 4.2); "physical" measures the
+    unpreconditioned residual instead, ell = || s - A u_K ||^2 (the residual
+    of L_dir, Sec. 4, and of L_bs^{l2}, Sec. 4.2).  With normalise=True the
+    squared norm is divided by ||G s||^2 (W residuals) or ||s||^2
+    (physical).  eps and k0^2 are constants; k2 and u0 may require grad.
     """
     u = as_c(u0) if not torch.is_tensor(u0) else u0
     for _ in range(steps):
         u = cbs_sweep(k2, k0sq, eps, u, s)
-    r = cbs_residual(k2, k0sq, eps, u, s)
-    if weight == "gamma":
-        r = gamma(k2, k0sq, eps) * r
-    elif weight != "one":
-        raise ValueError(weight)
+    if weight == "physical":
+        r = as_c(s) - helmholtz(k2, u)
+        den = as_c(s)
+    else:
+        r = cbs_residual(k2, k0sq, eps, u, s)
+        if weight == "gamma":
+            r = gamma(k2, k0sq, eps) * r
+        elif weight != "one":
+            raise ValueError(weight)
+        den = green(as_c(s), k0sq, eps)
     val = torch.sum(r.real ** 2 + r.imag ** 2)
     if normalise:
-        g = green(as_c(s), k0sq, eps)
-        val = val / torch.sum(g.real ** 2 + g.imag ** 2)
+        val = val / torch.sum(den.real ** 2 + den.imag ** 2)
     return val
 
 

@@ -20,7 +20,7 @@ def _problem(n=8, layer=2, seed=0):
     return p, u0
 
 
-@pytest.mark.parametrize("weight", ["gamma", "one"])
+@pytest.mark.parametrize("weight", ["gamma", "one", "physical"])
 def test_loss_gradient_central_differences(weight):
     # P11: central differences with h = 1e-3 on Re/Im u0 and Re/Im k^2.  The
     # loss is a high-degree polynomial in k^2, so the plain O(h^2) truncation
@@ -70,21 +70,29 @@ def adjoint_recursion(k2, k0sq, eps, u0, s, steps, weight="gamma"):
     lam_m = lam_{m+1} + conj(V) G^H(conj(g) lam_{m+1}) - conj(g) lam_{m+1};
     dk2 += (-i/eps) lam_{m+1} conj(r_m) + G^H(conj(g) lam_{m+1}) conj(u_m),
     plus (-i/eps) mu conj(r_K) + G^H(conj(g) mu) conj(u_K) for W = gamma.
+    For the physical loss |s - A u_K|^2 only the seed differs (see below).
     """
     v = O.potential(k2, k0sq, eps)
     g = O.gamma(k2, k0sq, eps)
     us = [O.as_c(u0)]
     for _ in range(steps):
         us.append(O.cbs_sweep(k2, k0sq, eps, us[-1], s))
-    rk = O.cbs_residual(k2, k0sq, eps, us[-1], s)
-    w = g if weight == "gamma" else torch.ones_like(g)
-    mu = 2 * w * rk
-    gr = w.conj() * mu
-    lam = v.conj() * O.green_adjoint(gr, k0sq, eps) - gr
-    dk = (v.conj() * 0)
-    dk = dk + O.green_adjoint(gr, k0sq, eps) * us[-1].conj()
-    if weight == "gamma":
-        dk = dk + (-1j / eps) * mu * rk.conj()
+    if weight == "physical":
+        # loss |e|^2, e = s - A u_K: lam_K = -2 A^H e with A^H e = -Lap e -
+        # conj(k^2) e, and dk2 = 2 conj(u_K) e (A depends on k^2 through -k^2 u)
+        e = O.as_c(s) - O.helmholtz(k2, us[-1])
+        lam = -2 * (O.laplacian(e) - O.as_c(k2).conj() * e)
+        dk = 2 * us[-1].conj() * e
+    else:
+        rk = O.cbs_residual(k2, k0sq, eps, us[-1], s)
+        w = g if weight == "gamma" else torch.ones_like(g)
+        mu = 2 * w * rk
+        gr = w.conj() * mu
+        lam = v.conj() * O.green_adjoint(gr, k0sq, eps) - gr
+        dk = (v.conj() * 0)
+        dk = dk + O.green_adjoint(gr, k0sq, eps) * us[-1].conj()
+        if weight == "gamma":
+            dk = dk + (-1j / eps) * mu * rk.conj()
     for m in range(steps - 1, -1, -1):
         rm = O.cbs_residual(k2, k0sq, eps, us[m], s)
         t = O.green_adjoint(g.conj() * lam, k0sq, eps)
@@ -93,7 +101,7 @@ def adjoint_recursion(k2, k0sq, eps, u0, s, steps, weight="gamma"):
     return lam, dk
 
 
-@pytest.mark.parametrize("weight", ["gamma", "one"])
+@pytest.mark.parametrize("weight", ["gamma", "one", "physical"])
 def test_adjoint_recursion_matches_autograd(weight):
     # The hand-written reverse recursion (implemented by the GPU adjoint) equals
     # the oracle's autograd gradient at 32x32, K = 8.
