@@ -25,8 +25,10 @@
  *    complex128 for CBS_C128 plans, row-major [y][x] per instance, and the
  *    instances are packed back to back in instance order: instance i starts at
  *    element sum_{j<i} n[j]^2.  Packed totals are returned by cbs_plan_cells.
- *  * The plan owns a copy of k^2 and all scratch memory; it is allocated in
- *    cbs_setup and freed in cbs_destroy.  No other call allocates.
+ *  * The plan keeps a copy of k^2 and all scratch memory in device memory
+ *    that cbs_setup allocates (freed by cbs_destroy), or that the caller
+ *    provides to cbs_setup_ws (cbs_workspace_size bytes).  No other call
+ *    allocates device memory.
  *  * `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    cbs_apply, cbs_residual, cbs_adjoint_step and cbs_loss_seed are
  *    stream-ordered and return without synchronising.  cbs_iterate and
@@ -223,14 +225,20 @@ cbs_status cbs_adjoint_step(cbs_plan plan, const void* u_m, const void* s, const
                             void* lam_out, void* grad_k2, void* stream);
 
 /*
- * cbs_loss_seed -- loss l = sum |W r_K|^2 with r_K = G(V u_K + s) - u_K and
- *   W = gamma (weight_gamma != 0) or W = 1, its adjoint seed
+ * cbs_loss_seed -- a residual loss of the iterate u_K, its adjoint seed
+ *   lam_K = dl/du_K and its direct k^2 term (Sec. 4 and 4.2).
+ *   weight 0 or 1: l = sum |W r_K|^2 with the Born residual
+ *     r_K = G(V u_K + s) - u_K and W = 1 (weight 0; the residual of the
+ *     metric-matched loss L_bs^{R_eta}) or W = gamma (weight 1):
  *     lam_K = conj(V) G^H(conj(W) mu) - conj(W) mu,  mu = 2 W r_K,
- *   and the direct k^2 term grad_k2 += G^H(conj(W) mu) conj(u_K)
- *   (+ (-i/eps) mu conj(r_K) when W = gamma).  loss: DEVICE double[batch]
- *   (per-instance FP64 sums), nullable.  grad_k2 is accumulated.
+ *     grad_k2 += G^H(conj(W) mu) conj(u_K)  (+ (-i/eps) mu conj(r_K) for W = gamma).
+ *   weight 2: l = sum |e|^2 with the physical residual e = s - A u_K,
+ *     A u = -Lap u - k^2 u (App. E; the residual of L_dir and L_bs^{l2}):
+ *     lam_K = -2 A^H e = -2 (-Lap e - conj(k^2) e),  grad_k2 += 2 conj(u_K) e.
+ *   Other weights: CBS_ERR_ARG.  loss: DEVICE double[batch] (per-instance
+ *   FP64 sums), nullable.  grad_k2 is accumulated.  Two transform pairs.
  */
-cbs_status cbs_loss_seed(cbs_plan plan, const void* u_k, const void* s, int weight_gamma,
+cbs_status cbs_loss_seed(cbs_plan plan, const void* u_k, const void* s, int weight,
                          double* loss, void* lam_out, void* grad_k2, void* stream);
 
 /*

@@ -267,12 +267,14 @@ class Plan:
                                        _ptr(self._field(lam_in, "lam_in")), _ptr(self._field(lam_out, "lam_out")),
                                        _ptr(self._field(grad_k2, "grad_k2")), _stream(stream)))
 
-    def loss_seed(self, u_k, s, weight_gamma=True, lam_out=None, grad_k2=None, stream=None):
+    def loss_seed(self, u_k, s, weight="gamma", lam_out=None, grad_k2=None, stream=None):
+        """weight: "gamma" (W = gamma), "one" (W = 1) or "physical" (s - A u_K);
+        True / False stand for "gamma" / "one"."""
         lam = self.empty() if lam_out is None else self._field(lam_out, "lam_out")
         grad = self.zeros() if grad_k2 is None else self._field(grad_k2, "grad_k2")
         loss = torch.empty(self.batch, dtype=torch.float64, device="cuda")
         _check(load().cbs_loss_seed(self._h, _ptr(self._field(u_k, "u_k")), _ptr(self._field(s, "s")),
-                                    1 if weight_gamma else 0, _ptr(loss), _ptr(lam), _ptr(grad),
+                                    _weight_code(weight), _ptr(loss), _ptr(lam), _ptr(grad),
                                     _stream(stream)))
         return loss, lam, grad
 
@@ -286,6 +288,17 @@ class Plan:
         _check(load().cbs_set_tile(self._h, int(n), int(columns)))
 
 
+_WEIGHTS = {"one": 0, "gamma": 1, "physical": 2}
+
+
+def _weight_code(weight) -> int:
+    if isinstance(weight, bool):
+        return 1 if weight else 0
+    if weight not in _WEIGHTS:
+        raise ValueError(f"weight must be one of {sorted(_WEIGHTS)}")
+    return _WEIGHTS[weight]
+
+
 def _expand(v, n):
     if isinstance(v, (list, tuple, np.ndarray)):
         if len(v) != n:
@@ -296,7 +309,9 @@ def _expand(v, n):
 
 class BornResidualLoss(torch.autograd.Function):
     """ell = sum_b || W (G s - (I - G V) u_K) ||^2 after K CBS steps from u0
-    (the metric-matched residual of Sec. 4.2 with W = gamma or W = 1).
+    (the metric-matched residual of Sec. 4.2 with W = gamma or W = 1), or
+    ell = sum_b || s - A u_K ||^2 with weight "physical" (the residual that
+    L_dir, Sec. 4, and L_bs^{l2}, Sec. 4.2, measure).
 
     Forward keeps the checkpoints u_0..u_K; backward runs the hand-written
     adjoint (cbs_adjoint_step) from the seed computed by cbs_loss_seed.
@@ -306,7 +321,7 @@ class BornResidualLoss(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, u0, k2, s, sizes, steps, weight_gamma, k0sq, eps):
+    def forward(ctx, u0, k2, s, sizes, steps, weight, k0sq, eps):
         dtype = CBS_C128 if k2.dtype == torch.complex128 else CBS_C64
         plan = Plan(k2.detach(), sizes, k0sq=k0sq, eps=eps, dtype=dtype)
         us = [u0.detach().clone()]
@@ -314,7 +329,7 @@ class BornResidualLoss(torch.autograd.Function):
             u = us[-1].clone()
             plan.sweep(u, s)
             us.append(u)
-        loss, lam, grad = plan.loss_seed(us[-1], s, weight_gamma)
+        loss, lam, grad = plan.loss_seed(us[-1], s, weight)
         ctx.plan = plan
         ctx.us = us
         ctx.s = s
@@ -337,5 +352,7 @@ class BornResidualLoss(torch.autograd.Function):
         return gu, gk, None, None, None, None, None, None
 
 
-def born_residual_loss(u0, k2, s, sizes, steps=8, weight_gamma=True, k0sq=None, eps=None):
-    return BornResidualLoss.apply(u0, k2, s, list(sizes), int(steps), bool(weight_gamma), k0sq, eps)
+def born_residual_loss(u0, k2, s, sizes, steps=8, weight="gamma", k0sq=None, eps=None):
+    """weight: "gamma", "one" or "physical" (see BornResidualLoss)."""
+    _weight_code(weight)
+    return BornResidualLoss.apply(u0, k2, s, list(sizes), int(steps), weight, k0sq, eps)

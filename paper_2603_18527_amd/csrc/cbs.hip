@@ -971,25 +971,47 @@ template <typename R>
 cbs_status seed_impl(cbs_plan p, const void* uk, const void* s, int wg, double* loss,
                      void* lam_out, void* grad, hipStream_t st) {
   cpx<R>* r = static_cast<cpx<R>*>(p->d_t);
-  {
+  if (wg == 2) {
+    // physical residual e = s - A u_K, then lam_K = -2 A^H e (symbol |xi|^2)
     Params<R> q = base_params<R>(p);
     q.u = static_cast<const cpx<R>*>(uk);
     q.s = static_cast<const cpx<R>*>(s);
-    q.epi = EPI_RESID;
+    q.pro = PRO_U;
+    q.sym = SYM_LAP;
+    q.epi = EPI_LAP;
     q.out = r;
     q.partials = nullptr;
     CHK(run_pipeline(p, q, st));
+    Params<R> a = base_params<R>(p);
+    a.pro = PRO_A;
+    a.sym = SYM_LAP;
+    a.epi = EPI_PHYS_SEED;
+    a.a = r;
+    a.u = static_cast<const cpx<R>*>(uk);
+    a.out = static_cast<cpx<R>*>(lam_out);
+    a.out2 = static_cast<cpx<R>*>(grad);
+    CHK(run_pipeline(p, a, st));
+  } else {
+    {
+      Params<R> q = base_params<R>(p);
+      q.u = static_cast<const cpx<R>*>(uk);
+      q.s = static_cast<const cpx<R>*>(s);
+      q.epi = EPI_RESID;
+      q.out = r;
+      q.partials = nullptr;
+      CHK(run_pipeline(p, q, st));
+    }
+    Params<R> q = base_params<R>(p);
+    q.pro = PRO_SEED;
+    q.sym = SYM_GREEN_CONJ;
+    q.epi = EPI_SEED;
+    q.weight_gamma = wg ? 1 : 0;
+    q.a = r;
+    q.u = static_cast<const cpx<R>*>(uk);
+    q.out = static_cast<cpx<R>*>(lam_out);
+    q.out2 = static_cast<cpx<R>*>(grad);
+    CHK(run_pipeline(p, q, st));
   }
-  Params<R> q = base_params<R>(p);
-  q.pro = PRO_SEED;
-  q.sym = SYM_GREEN_CONJ;
-  q.epi = EPI_SEED;
-  q.weight_gamma = wg ? 1 : 0;
-  q.a = r;
-  q.u = static_cast<const cpx<R>*>(uk);
-  q.out = static_cast<cpx<R>*>(lam_out);
-  q.out2 = static_cast<cpx<R>*>(grad);
-  CHK(run_pipeline(p, q, st));
   if (loss) {
     launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, loss);
     HIPCHK(hipGetLastError());
@@ -1424,6 +1446,8 @@ cbs_status cbs_adjoint_step(cbs_plan p, const void* u_m, const void* s, const vo
 cbs_status cbs_loss_seed(cbs_plan p, const void* u_k, const void* s, int weight_gamma, double* loss,
                          void* lam_out, void* grad_k2, void* stream) {
   if (!p || !u_k || !lam_out || !grad_k2) return fail(CBS_ERR_ARG, "NULL argument");
+  if (weight_gamma < 0 || weight_gamma > 2)
+    return fail(CBS_ERR_ARG, "weight must be 0 (W = 1), 1 (W = gamma) or 2 (physical residual)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == CBS_C64) return seed_impl<float>(p, u_k, s, weight_gamma, loss, lam_out, grad_k2, st);
   return seed_impl<double>(p, u_k, s, weight_gamma, loss, lam_out, grad_k2, st);

@@ -75,6 +75,8 @@ __device__ __forceinline__ cpx<R> prologue(const Params<R>& p, const InstDesc& d
       }
       return cscale(p.a[i], R(2) * w2);
     }
+    case PRO_A:
+      return p.a[i];
     default:  // PRO_U
       return p.u[i];
   }
@@ -136,6 +138,15 @@ __device__ __forceinline__ double epilogue(const Params<R>& p, const InstDesc& d
       if (p.weight_gamma) g = g + cscale(c.v, R(2) * c.inv_eps * c.inv_eps * r2);
       p.out2[i] = p.out2[i] + g;
       return double(w2) * double(r2);
+    }
+    case EPI_PHYS_SEED: {
+      // e = a = s - A u_K, z = -Lap e; loss term |e|^2;
+      // lam_K = -2 A^H e = -2 (z - conj(k^2) e); grad += 2 conj(u_K) e
+      const cpx<R> e = p.a[i];
+      const cpx<R> k = p.k2[i];
+      p.out[i] = cscale(z - cmulc(k, e), R(-2));
+      p.out2[i] = p.out2[i] + cscale(cmulc(p.u[i], e), R(2));
+      return double(cabs2(e));
     }
     default: {  // EPI_LAP: physical residual s - A u with A u = -Lap u - k^2 u
       const cpx<R> u = p.u[i];

@@ -29,7 +29,7 @@ struct InstDesc {
   double eps;
 };
 
-enum Pro { PRO_VU_S = 0, PRO_CONJG_A = 1, PRO_SEED = 2, PRO_U = 3 };
+enum Pro { PRO_VU_S = 0, PRO_CONJG_A = 1, PRO_SEED = 2, PRO_U = 3, PRO_A = 4 };
 enum Sym { SYM_GREEN = 0, SYM_GREEN_CONJ = 1, SYM_LAP = 2 };
 enum Epi {
   EPI_STORE = 0,
@@ -38,7 +38,8 @@ enum Epi {
   EPI_BZ_WIDE = 3,
   EPI_ADJ = 4,
   EPI_SEED = 5,
-  EPI_LAP = 6
+  EPI_LAP = 6,
+  EPI_PHYS_SEED = 7
 };
 // Instance masks: which status values let an instance run.
 enum MaskMode { MASK_RUNNING = 0, MASK_NOT_FINAL = 1, MASK_NONZERO = 2 };

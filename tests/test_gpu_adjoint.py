@@ -25,13 +25,13 @@ pytestmark = pytest.mark.gpu
 TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
 
 
-def _unrolled(plan, u0, s, steps, weight_gamma):
+def _unrolled(plan, u0, s, steps, weight):
     us = [u0.clone()]
     for _ in range(steps):
         u = us[-1].clone()
         plan.sweep(u, s)
         us.append(u)
-    loss, lam, grad = plan.loss_seed(us[-1], s, weight_gamma)
+    loss, lam, grad = plan.loss_seed(us[-1], s, weight)
     for m in range(steps - 1, -1, -1):
         plan.adjoint_step(us[m], s, lam, lam, grad)
     torch.cuda.synchronize()
@@ -49,9 +49,9 @@ def _small_batch(n=32, layer=4, count=2, seed=0):
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
-@pytest.mark.parametrize("weight_gamma", [True, False])
-def test_adjoint_matches_oracle_gradient(dtype, weight_gamma):
-    say(f"[adjoint 32x32] dtype={dtype} W=gamma:{weight_gamma}")
+@pytest.mark.parametrize("weight", ["gamma", "one", "physical"])
+def test_adjoint_matches_oracle_gradient(dtype, weight):
+    say(f"[adjoint 32x32] dtype={dtype} weight={weight}")
     probs, u0s = _small_batch()
     sizes = [p.n for p in probs]
     tdt = TDT[dtype]
@@ -59,24 +59,24 @@ def test_adjoint_matches_oracle_gradient(dtype, weight_gamma):
     plan = cbs.Plan(k2, sizes, k0sq=[p.k0sq for p in probs], dtype=dtype)
     u0 = cbs.pack(u0s, tdt)
     s = cbs.pack([p.source for p in probs], tdt)
-    loss, lam, grad = _unrolled(plan, u0, s, 8, weight_gamma)
+    loss, lam, grad = _unrolled(plan, u0, s, 8, weight)
     tol = 1e-10 if dtype == cbs.CBS_C128 else 1e-4
     for i, (ki, ui, si, li, gi) in enumerate(zip(to_list(k2, sizes), to_list(u0, sizes), to_list(s, sizes),
                                                  to_list(lam, sizes), to_list(grad, sizes))):
-        val, gu, gk = O.loss_and_grad(ki, plan.k0sq[i], plan.eps[i], ui, si, 8,
-                                      "gamma" if weight_gamma else "one")
+        val, gu, gk = O.loss_and_grad(ki, plan.k0sq[i], plan.eps[i], ui, si, 8, weight)
         el, eu, ek = abs(float(loss[i]) - val) / val, rel_err(li, gu), rel_err(gi, gk)
         say(f"   instance {i}: loss {el:.2e} du0 {eu:.2e} dk2 {ek:.2e}")
         assert el <= tol and eu <= tol and ek <= tol
 
 
-def test_autograd_function_matches_direct_calls():
+@pytest.mark.parametrize("weight", ["gamma", "physical"])
+def test_autograd_function_matches_direct_calls(weight):
     probs, u0s = _small_batch(seed=10)
     sizes = [p.n for p in probs]
     k2 = cbs.pack([p.k2 for p in probs], torch.complex128).requires_grad_(True)
     u0 = cbs.pack(u0s, torch.complex128).requires_grad_(True)
     s = cbs.pack([p.source for p in probs], torch.complex128)
-    loss = cbs.born_residual_loss(u0, k2, s, sizes, steps=8, weight_gamma=True,
+    loss = cbs.born_residual_loss(u0, k2, s, sizes, steps=8, weight=weight,
                                   k0sq=[p.k0sq for p in probs])
     # weighted sum so that the per-instance grad_output scaling is exercised
     (loss * torch.tensor([1.0, 0.5], device="cuda", dtype=torch.float64)).sum().backward()
@@ -84,7 +84,7 @@ def test_autograd_function_matches_direct_calls():
                                                          to_list(s, sizes), to_list(u0.grad, sizes),
                                                          to_list(k2.grad, sizes))):
         eps = O.choose_eps(ki, probs[i].k0sq)
-        val, gu, gk = O.loss_and_grad(ki, probs[i].k0sq, eps, ui, si, 8, "gamma")
+        val, gu, gk = O.loss_and_grad(ki, probs[i].k0sq, eps, ui, si, 8, weight)
         w = [1.0, 0.5][i]
         assert abs(float(loss[i]) - val) <= 1e-10 * val
         assert rel_err(gu_gpu, w * gu) <= 1e-10
@@ -161,3 +161,19 @@ def test_full_size_finite_differences_and_fp32_adjoint():
         assert abs(r1a - an) <= 1e-4 * abs(an) + noise, (t, r1a, an)
         assert abs(rich - an) <= 1e-7 * abs(an) + noise, (t, rich, an, noise)
     say(f"   32 central differences: worst Richardson rel err {worst:.2e}")
+
+
+def test_loss_seed_rejects_unknown_weight():
+    import ctypes
+    probs, u0s = _small_batch(count=1, seed=30)
+    k2 = cbs.pack([probs[0].k2], torch.complex64)
+    plan = cbs.Plan(k2, [probs[0].n], k0sq=[probs[0].k0sq])
+    u = cbs.pack(u0s, torch.complex64)
+    lam, grad = plan.empty(), plan.zeros()
+    lib = cbs.load()
+    for bad in (-1, 3):
+        st = lib.cbs_loss_seed(plan._h, ctypes.c_void_p(u.data_ptr()), None, bad, None,
+                               ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(grad.data_ptr()), None)
+        assert st == cbs.CBS_ERR_ARG and "weight" in cbs.last_error()
+    with pytest.raises(ValueError):
+        plan.loss_seed(u, None, weight="l2")
