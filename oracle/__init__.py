@@ -174,19 +174,27 @@ def born_relres(k2, k0sq, eps, u, s) -> float:
 # ---------------------------------------------------------------------------
 
 def cbs_iterate(k2, k0sq, eps, s, u0=None, max_sweeps: int = 2500, rtol: float = 1e-6,
-                history: bool = False):
-    """Run u <- u + gamma r(u) from u0 (zeros by default) until
-    ||r(u_m)|| / ||G s|| <= rtol.  Returns (u, sweeps, relres[, history]).
-    `sweeps` is the number of updates applied; relres is that of the returned u."""
+                history: bool = False, stop: str = "born"):
+    """Run u <- u + gamma r(u) from u0 (zeros by default) until the relative
+    residual is at most rtol: stop="born" measures ||r(u_m)|| / ||G s||, the
+    Born (preconditioned) residual; stop="physical" the paper's unified rule
+    rTol = ||s - A u_m|| / ||s|| (Sec. 5).  Returns (u, sweeps, relres[,
+    history]).  `sweeps` is the number of updates applied; relres is that of
+    the returned u."""
     s = as_c(s)
     u = torch.zeros_like(s) if u0 is None else as_c(u0).clone()
     g = gamma(k2, k0sq, eps)
-    bnorm = norm(green(s, k0sq, eps))
+    if stop not in ("born", "physical"):
+        raise ValueError(stop)
+    bnorm = norm(green(s, k0sq, eps)) if stop == "born" else norm(s)
     hist = []
     m = 0
     while True:
         r = cbs_residual(k2, k0sq, eps, u, s)
-        rel = norm(r) / bnorm
+        if stop == "born":
+            rel = norm(r) / bnorm
+        else:
+            rel = norm(s - helmholtz(k2, u)) / bnorm
         hist.append(rel)
         if rel <= rtol or m >= max_sweeps or not math.isfinite(rel):
             break

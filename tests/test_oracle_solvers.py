@@ -56,6 +56,30 @@ def test_cbs_matches_dense_solve():
     assert O.physical_relres(p.k2, u, p.source) < 1e-10
 
 
+def test_physical_stop_rule():
+    # The paper's unified stopping rule rTol = ||s - A u|| / ||s|| (Sec. 5).
+    # Pins: (i) the physical residual is L_eta applied to the Born residual,
+    # s - A u = L_eta (G (V u + s) - u) (Prop. 3.1 key identity), here with
+    # the Laplacian and k^2 on one side and the symbol lambda on the other;
+    # (ii) the loop stops at the first sweep whose residual is <= rtol, with
+    # the numpy-built dense A as the judge of the returned iterate.
+    p = _problem16(seed=3)
+    eps = O.choose_eps(p.k2, p.k0sq)
+    u, m, rel, hist = O.cbs_iterate(p.k2, p.k0sq, eps, p.source, max_sweeps=5000, rtol=1e-8,
+                                    history=True, stop="physical")
+    a = _dense_helmholtz_numpy(p.k2)
+    e_dense = p.source.reshape(-1) - a @ u.numpy().reshape(-1)
+    assert np.linalg.norm(e_dense) / np.linalg.norm(p.source) == pytest.approx(rel, rel=1e-9)
+    assert rel <= 1e-8 < hist[-2] and len(hist) == m + 1
+    r = O.cbs_residual(p.k2, p.k0sq, eps, u, p.source)
+    l_eta_r = O.idft2(O.dft2(r) * O.symbol(16, p.k0sq, eps))
+    e = O.as_c(p.source) - O.helmholtz(p.k2, u)
+    assert torch.max(torch.abs(l_eta_r - e)) <= 1e-12 * torch.max(torch.abs(O.as_c(p.source)))
+    # the Born rule on the same problem stops at a different sweep
+    _, m_born, _ = O.cbs_iterate(p.k2, p.k0sq, eps, p.source, max_sweeps=5000, rtol=1e-8)
+    assert m_born != m
+
+
 @pytest.mark.parametrize("restart,sweeps", [(5, 1), (10, 4), (300, 2)])
 def test_fgmres_matches_dense_solve(restart, sweeps):
     # P6 for FGMRES(m) with P_K: same solution as LAPACK.
