@@ -68,6 +68,12 @@ typedef enum {
 
 enum { CBS_C64 = 0, CBS_C128 = 1 };
 
+/* Stopping rules of cbs_iterate. */
+enum {
+  CBS_STOP_BORN = 0,     /* ||G(V u + s) - u|| / ||G s|| (preconditioned residual) */
+  CBS_STOP_PHYSICAL = 1  /* rTol = ||s - A u|| / ||s||, the paper's unified rule (Sec. 5) */
+};
+
 /* Per-instance solver status codes written by cbs_iterate / fgmres_solve. */
 enum {
   CBS_INST_RUNNING = 0,
@@ -179,23 +185,31 @@ cbs_status cbs_helmholtz_residual(cbs_plan plan, const void* u, const void* s, v
                                   double* norm2, void* stream);
 
 /*
- * cbs_iterate -- stationary CBS until ||G(V u + s) - u|| / ||G s|| <= rtol
- *   per instance (Sec. 3.1, Eq. CBS; the paper's stopping rule, Sec. 5, is
- *   measured in these preconditioned coordinates).
+ * cbs_iterate -- stationary CBS (Sec. 3.1, Eq. CBS) per instance until its
+ *   relative residual is at most rtol.
  *   u          device, in/out: initial guess and result
  *   s          device: source
  *   max_sweeps per-instance cap on applied sweeps
- *   check_every  sweeps per refinement chunk (>= 2): for CBS_C64 plans the
- *              iterate is kept in FP64 and the residual recomputed in FP64
- *              every check_every sweeps; FP32 sweeps advance the correction
+ *   check_every  sweeps per refinement chunk (>= 2): the iterate is kept in
+ *              FP64 and its residual recomputed in FP64 every check_every
+ *              sweeps; sweeps in the plan's dtype advance the correction
+ *   stop       CBS_STOP_BORN: ||G(V u + s) - u|| / ||G s||, tested in FP64
+ *              at each chunk start and estimated after every sweep (an
+ *              instance stops at the first sweep whose estimate is <= rtol
+ *              and is confirmed at the next chunk start);
+ *              CBS_STOP_PHYSICAL: the paper's rTol = ||s - A u|| / ||s||
+ *              (Sec. 5; A u = -Lap u - k^2 u, App. E), tested in FP64 at each
+ *              chunk start only (one more transform pair per chunk), so the
+ *              sweep count is a multiple of check_every
  *   iters, relres, status  host[batch] outputs (sweeps applied, FP64-verified
- *              relative residual of the returned u, CBS_INST_* code); nullable
+ *              relative residual of the returned u under the chosen rule,
+ *              CBS_INST_* code); nullable
  *   use_graph  nonzero: replay each chunk from a captured hipGraph
  * Returns CBS_NOT_CONVERGED if any instance stopped without reaching rtol.
  */
 cbs_status cbs_iterate(cbs_plan plan, void* u, const void* s, int max_sweeps, double rtol,
-                       int check_every, int32_t* iters, double* relres, int32_t* status,
-                       int use_graph, void* stream);
+                       int check_every, int stop, int32_t* iters, double* relres,
+                       int32_t* status, int use_graph, void* stream);
 
 /*
  * fgmres_solve -- flexible GMRES(restart) on B u = G s with B = I - G V = G A

@@ -46,7 +46,7 @@ SIGNATURES = {
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "cbs_helmholtz_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
-    "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _vp, _vp, _vp, _i32, _vp]),
+    "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
     "fgmres_solve": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "cbs_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_loss_seed": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
@@ -244,12 +244,17 @@ class Plan:
                                 int(count), _ptr(n2), _stream(stream)))
         return n2
 
-    def iterate(self, u, s, max_sweeps=2500, rtol=1e-6, check_every=50, use_graph=True, stream=None):
+    def iterate(self, u, s, max_sweeps=2500, rtol=1e-6, check_every=50, use_graph=True, stream=None,
+                stop="born"):
+        """stop: "born" (preconditioned residual) or "physical" (rTol = ||s - A u|| / ||s||)."""
+        if stop not in _STOPS:
+            raise ValueError(f"stop must be one of {sorted(_STOPS)}")
         it = (ctypes.c_int32 * self.batch)()
         rel = (ctypes.c_double * self.batch)()
         stat = (ctypes.c_int32 * self.batch)()
         _check(load().cbs_iterate(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
-                                  int(max_sweeps), float(rtol), int(check_every), it, rel, stat,
+                                  int(max_sweeps), float(rtol), int(check_every), _STOPS[stop],
+                                  it, rel, stat,
                                   1 if use_graph else 0, _stream(stream)), allow_not_converged=True)
         return list(it), list(rel), list(stat)
 
@@ -289,6 +294,7 @@ class Plan:
 
 
 _WEIGHTS = {"one": 0, "gamma": 1, "physical": 2}
+_STOPS = {"born": 0, "physical": 1}
 
 
 def _weight_code(weight) -> int:

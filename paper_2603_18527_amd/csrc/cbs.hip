@@ -101,7 +101,9 @@ struct cbs_plan_s {
   double* d_relres = nullptr;
   double* d_est = nullptr;
   double* d_bnorm = nullptr;
+  double* d_bnorm_phys = nullptr;  // ||s|| per instance (physical stop rule)
   double* d_rtol = nullptr;
+  double* d_rtol32 = nullptr;      // rtol of the FP32 per-sweep estimate
   int* d_maxs = nullptr;
   // FGMRES
   cpx<double>* d_vbasis = nullptr;
@@ -152,7 +154,7 @@ struct cbs_plan_s {
   };
   View full, compact;
   View* view = &full;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (view generation, chunk)
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (view generation, 2 chunk + stop rule)
   hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
   bool one_stream = false;           // CBS_FLAG_ONE_STREAM
   hipStream_t lane_st[2] = {nullptr, nullptr};  // non-blocking lane streams
@@ -566,8 +568,8 @@ cbs_status sweep_impl(cbs_plan p, void* u, const void* s, int count, double* nor
 //   operator precision with a per-sweep norm estimate, then u64 += e.
 // In exact arithmetic this is exactly `chunk` CBS sweeps from u64.
 template <typename R>
-cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
-  const IterState is = iter_state(p);
+cbs_status enqueue_chunk(cbs_plan p, int chunk, int stop, hipStream_t st) {
+  IterState is = iter_state(p);
   cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
   cpx<R>* e = static_cast<cpx<R>*>(p->d_e);
   {
@@ -580,8 +582,27 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, hipStream_t st) {
     q.mask = p->d_status;
     q.mask_mode = MASK_NOT_FINAL;
     CHK(run_pipeline(p, q, st));
-    launch_check64(p->batch, st, is, p->d_inst, p->d_partials);
+    if (stop == CBS_STOP_PHYSICAL) {
+      // the decision uses the physical residual s - A u64 instead
+      Params<double> h = base_params<double>(p);
+      h.u = p->d_u64;
+      h.s = p->d_s64;
+      h.pro = PRO_U;
+      h.sym = SYM_LAP;
+      h.epi = EPI_LAP;
+      h.mask = p->d_status;
+      h.mask_mode = MASK_NOT_FINAL;
+      CHK(run_pipeline(p, h, st));
+      IterState ip = is;
+      ip.bnorm = p->d_bnorm_phys;
+      launch_check64(p->batch, st, ip, p->d_inst, p->d_partials);
+    } else {
+      launch_check64(p->batch, st, is, p->d_inst, p->d_partials);
+    }
   }
+  // The FP32 estimate of each sweep stops an instance early only under the
+  // Born rule (it estimates the Born residual); it always counts the sweep.
+  is.rtol = p->d_rtol32;
   {
     PwParams<R> w{};
     w.op = PW_GAMMA;
@@ -649,7 +670,7 @@ struct FullViewOnExit {
 
 template <typename R>
 cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
-                        int chunk, int32_t* iters, double* relres, int32_t* status,
+                        int chunk, int stop, int32_t* iters, double* relres, int32_t* status,
                         int use_graph, hipStream_t st) {
   const int B = p->batch;
   p->view = &p->full;
@@ -666,6 +687,8 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
   HIPCHK(hipMemsetAsync(p->d_status, 0, B * sizeof(int), st));
   HIPCHK(hipMemsetAsync(p->d_iters, 0, B * sizeof(int), st));
   HIPCHK(hipMemcpyAsync(p->d_rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, st));
+  const double rtol32 = stop == CBS_STOP_PHYSICAL ? 0.0 : rtol;
+  HIPCHK(hipMemcpyAsync(p->d_rtol32, &rtol32, sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->d_maxs, &max_sweeps, sizeof(int), hipMemcpyHostToDevice, st));
   // ||G s|| in FP64
   {
@@ -676,11 +699,24 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
     launch_set_bnorm(B, st, iter_state(p), p->d_inst, p->d_partials);
     HIPCHK(hipGetLastError());
   }
+  // ||s|| in FP64 (s - A 0 through the physical-residual pipeline)
+  if (stop == CBS_STOP_PHYSICAL) {
+    Params<double> q = base_params<double>(p);
+    q.s = p->d_s64;
+    q.pro = PRO_U;
+    q.sym = SYM_LAP;
+    q.epi = EPI_LAP;
+    CHK(run_pipeline(p, q, st));
+    IterState ip = iter_state(p);
+    ip.bnorm = p->d_bnorm_phys;
+    launch_set_bnorm(B, st, ip, p->d_inst, p->d_partials);
+    HIPCHK(hipGetLastError());
+  }
   // Capture (once per view and chunk length) and replay.
   auto get_graph = [&](hipGraphExec_t* exec) -> cbs_status {
     *exec = nullptr;
     if (!use_graph) return CBS_OK;
-    const auto key = std::make_pair(p->view->gen, chunk);
+    const auto key = std::make_pair(p->view->gen, 2 * chunk + stop);
     auto it = p->graphs.find(key);
     if (it != p->graphs.end()) {
       *exec = it->second;
@@ -689,7 +725,7 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
     HIPCHK(hipStreamSynchronize(st));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    cbs_status rc = enqueue_chunk<R>(p, chunk, st);
+    cbs_status rc = enqueue_chunk<R>(p, chunk, stop, st);
     hipError_t ce = hipStreamEndCapture(st, &g);
     if (rc != CBS_OK) {
       if (g) hipGraphDestroy(g);
@@ -709,7 +745,7 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
   const long long max_chunks = (long long)max_sweeps / std::max(1, chunk) + 3;
   for (long long ch = 0; ch <= max_chunks; ++ch) {
     if (exec) HIPCHK(hipGraphLaunch(exec, st));
-    else CHK(enqueue_chunk<R>(p, chunk, st));
+    else CHK(enqueue_chunk<R>(p, chunk, stop, st));
     HIPCHK(hipMemcpyAsync(hstat.data(), p->d_status, B * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     long long active_cells = 0;
@@ -1076,6 +1112,8 @@ std::vector<std::pair<void**, size_t>> buffer_requests(cbs_plan p) {
       {reinterpret_cast<void**>(&p->d_est), batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_bnorm), batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_rtol), sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_rtol32), sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_bnorm_phys), batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_maxs), sizeof(int)},
       {reinterpret_cast<void**>(&p->d_scale), batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_kactive), batch * sizeof(int)},
@@ -1395,9 +1433,11 @@ cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm
 }
 
 cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
-                       int check_every, int32_t* iters, double* relres, int32_t* status,
+                       int check_every, int stop, int32_t* iters, double* relres, int32_t* status,
                        int use_graph, void* stream) {
   if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
+  if (stop != CBS_STOP_BORN && stop != CBS_STOP_PHYSICAL)
+    return fail(CBS_ERR_ARG, "stop must be CBS_STOP_BORN or CBS_STOP_PHYSICAL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
   if (max_sweeps < 0 || check_every < 2 || check_every > 100000 || !(rtol >= 0.0))
     return fail(CBS_ERR_ARG, "need max_sweeps >= 0, 2 <= check_every <= 1e5, rtol >= 0");
@@ -1415,8 +1455,10 @@ cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, doubl
     st = p->own_stream;
   }
   if (p->dtype == CBS_C64)
-    return iterate_impl<float>(p, u, s, max_sweeps, rtol, check_every, iters, relres, status, use_graph, st);
-  return iterate_impl<double>(p, u, s, max_sweeps, rtol, check_every, iters, relres, status, use_graph, st);
+    return iterate_impl<float>(p, u, s, max_sweeps, rtol, check_every, stop, iters, relres, status,
+                               use_graph, st);
+  return iterate_impl<double>(p, u, s, max_sweeps, rtol, check_every, stop, iters, relres, status,
+                              use_graph, st);
 }
 
 cbs_status fgmres_solve(cbs_plan p, void* u, const void* s, int restart, int inner_sweeps,

@@ -78,7 +78,7 @@ __device__ __forceinline__ cpx<R> prologue(const Params<R>& p, const InstDesc& d
     case PRO_A:
       return p.a[i];
     default:  // PRO_U
-      return p.u[i];
+      return ld_or_zero(p.u, i);
   }
 }
 
@@ -149,7 +149,7 @@ __device__ __forceinline__ double epilogue(const Params<R>& p, const InstDesc& d
       return double(cabs2(e));
     }
     default: {  // EPI_LAP: physical residual s - A u with A u = -Lap u - k^2 u
-      const cpx<R> u = p.u[i];
+      const cpx<R> u = ld_or_zero(p.u, i);
       const cpx<R> au = z - cmul(p.k2[i], u);
       const cpx<R> r = ld_or_zero(p.s, i) - au;
       if (p.out) p.out[i] = r;

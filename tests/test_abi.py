@@ -61,7 +61,7 @@ def test_calls_with_null_plan_fail_cleanly():
     lib = cbs.load()
     assert lib.cbs_apply(None, None, None, None, None) == cbs.CBS_ERR_ARG
     assert lib.cbs_residual(None, None, None, None, None, None, None) == cbs.CBS_ERR_ARG
-    assert lib.cbs_iterate(None, None, None, 10, 1e-6, 10, None, None, None, 0, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_iterate(None, None, None, 10, 1e-6, 10, 0, None, None, None, 0, None) == cbs.CBS_ERR_ARG
     assert lib.fgmres_solve(None, None, None, 10, 4, 10, 1e-6, None, None, None, None) == cbs.CBS_ERR_ARG
     assert lib.cbs_adjoint_step(None, None, None, None, None, None, None) == cbs.CBS_ERR_ARG
     assert lib.cbs_set_tile(None, 0, 16) == cbs.CBS_ERR_ARG

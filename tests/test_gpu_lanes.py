@@ -53,15 +53,15 @@ def test_sweep_chain_lanes_bitwise(plans):
         assert torch.equal(na, nb)
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_iterate_lanes_bitwise(plans, use_graph):
+@pytest.mark.parametrize("use_graph,stop", [(True, "born"), (False, "born"), (True, "physical")])
+def test_iterate_lanes_bitwise(plans, use_graph, stop):
     # Instances converge at different sweep counts, so the work lists are
     # compacted (and the lanes rebuilt) along the way.
     lanes, single, s = plans
-    say(f"[lanes iterate] graph={use_graph}")
+    say(f"[lanes iterate] graph={use_graph} stop={stop}")
     ua, ub = lanes.zeros(), single.zeros()
-    a = lanes.iterate(ua, s, max_sweeps=900, rtol=1e-5, check_every=25, use_graph=use_graph)
-    b = single.iterate(ub, s, max_sweeps=900, rtol=1e-5, check_every=25, use_graph=use_graph)
+    a = lanes.iterate(ua, s, max_sweeps=900, rtol=1e-5, check_every=25, use_graph=use_graph, stop=stop)
+    b = single.iterate(ub, s, max_sweeps=900, rtol=1e-5, check_every=25, use_graph=use_graph, stop=stop)
     its = np.array(a[0])
     say(f"   sweeps min {its.min()} max {its.max()}, status {a[2]}")
     assert a == b

@@ -92,6 +92,66 @@ def test_batched_equals_per_instance_loop():
         assert torch.equal(ui.reshape(p.n, p.n), us[i])
 
 
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_iterate_physical_stop_rule(dtype):
+    # rTol = ||s - A u|| / ||s|| (the paper's unified rule) tested in FP64 at
+    # every chunk start: the GPU stops at the first multiple of check_every at
+    # or after the oracle's first sweep with rTol <= rtol.
+    k, rtol = 10, 1e-6
+    p = S.blob_problem()
+    tdt = torch.complex64 if dtype == cbs.CBS_C64 else torch.complex128
+    plan, k2 = plan_for([p], dtype)
+    s = cbs.pack([p.source], tdt)
+    u = plan.zeros()
+    its, rel, stat = plan.iterate(u, s, max_sweeps=5000, rtol=rtol, check_every=k, stop="physical")
+    ki, si = to_list(k2, [p.n])[0], to_list(s, [p.n])[0]
+    _, m, relo, hist = O.cbs_iterate(ki, plan.k0sq[0], plan.eps[0], si, max_sweeps=5000, rtol=rtol,
+                                     history=True, stop="physical")
+    expect = k * -(-m // k)
+    ug = to_list(u, [p.n])[0]
+    ev = O.physical_relres(ki, ug, si)
+    say(f"[physical stop] dtype={dtype}: gpu {its[0]} sweeps rTol {rel[0]:.3e} (oracle eval {ev:.3e}); "
+        f"oracle first <= rtol at {m}")
+    assert stat[0] == cbs.INST_CONVERGED and rel[0] <= rtol
+    assert its[0] % k == 0 and hist[m] <= rtol < hist[m - 1]
+    if dtype == cbs.CBS_C128:
+        assert its[0] == expect
+        assert ev <= rtol and abs(ev - rel[0]) <= 0.01 * ev
+    else:
+        assert abs(its[0] - expect) <= k
+        # rounding the FP64 iterate to FP32 moves A u by ~ unit * (|Lap u| + |k^2 u|)
+        lap, ku = O.laplacian(ug), ki * ug
+        bound = 16 * 2.0 ** -24 * float((torch.linalg.vector_norm(lap) + torch.linalg.vector_norm(ku))
+                                        / torch.linalg.vector_norm(si))
+        assert ev <= rtol + bound
+    # the Born rule on the same problem is a different criterion
+    u2 = plan.zeros()
+    its_b, rel_b, _ = plan.iterate(u2, s, max_sweeps=5000, rtol=rtol, check_every=k)
+    say(f"   Born rule: {its_b[0]} sweeps")
+    assert its_b[0] != its[0]
+
+
+def test_physical_stop_graph_plain_and_batched_bitwise():
+    sizes = [128, 64, 192]
+    probs = [random_problem(n, seed=610 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs)
+    s = cbs.pack([q.source for q in probs], torch.complex64)
+    ua, ub = plan.zeros(), plan.zeros()
+    a = plan.iterate(ua, s, max_sweeps=3000, rtol=1e-6, check_every=20, stop="physical")
+    b = plan.iterate(ub, s, max_sweeps=3000, rtol=1e-6, check_every=20, stop="physical",
+                     use_graph=False)
+    assert a == b and torch.equal(ua, ub)
+    for i, q in enumerate(probs):
+        pi, _ = plan_for([q])
+        ui = pi.zeros()
+        r = pi.iterate(ui, cbs.pack([q.source], torch.complex64), max_sweeps=3000, rtol=1e-6,
+                       check_every=20, stop="physical")
+        assert r[0][0] == a[0][i] and r[1][0] == a[1][i] and r[2][0] == a[2][i]
+        assert torch.equal(ui, cbs.unpack(ua, sizes)[i].reshape(-1))
+    with pytest.raises(ValueError):
+        plan.iterate(ua, s, stop="l2")
+
+
 def test_iterate_zero_source_and_max_sweeps():
     probs = [random_problem(64, seed=81, source="point"), random_problem(128, seed=82, source="point")]
     plan, k2 = plan_for(probs)
@@ -216,9 +276,13 @@ def test_aliasing_and_argument_errors():
     assert lib.cbs_residual(plan._h, ptr(u), None, None, ptr(u), None, None) == cbs.CBS_ERR_ARG
     assert lib.cbs_sweep(plan._h, ptr(u), ptr(u), 1, None, None) == cbs.CBS_ERR_ARG
     assert lib.cbs_sweep(plan._h, ptr(u), None, 0, None, None) == cbs.CBS_ERR_ARG
-    assert lib.cbs_iterate(plan._h, ptr(u), ptr(u), 10, 1e-6, 10, None, None, None, 0, None) == cbs.CBS_ERR_ARG
-    assert lib.cbs_iterate(plan._h, ptr(u), ptr(plan.zeros()), 10, 1e-6, 1, None, None, None, 0, None) \
+    assert lib.cbs_iterate(plan._h, ptr(u), ptr(u), 10, 1e-6, 10, 0, None, None, None, 0, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_iterate(plan._h, ptr(u), ptr(plan.zeros()), 10, 1e-6, 1, 0, None, None, None, 0, None) \
         == cbs.CBS_ERR_ARG
+    for bad_stop in (-1, 2):
+        assert lib.cbs_iterate(plan._h, ptr(u), ptr(plan.zeros()), 10, 1e-6, 10, bad_stop, None, None, None,
+                               0, None) == cbs.CBS_ERR_ARG
+        assert "stop" in cbs.last_error()
     assert lib.cbs_set_tile(plan._h, 32, 3) == cbs.CBS_ERR_ARG
     assert lib.cbs_set_tile(plan._h, 48, 16) == cbs.CBS_ERR_ARG
     with pytest.raises(ValueError):
