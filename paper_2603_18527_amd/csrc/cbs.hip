@@ -179,7 +179,7 @@ void build_items(cbs_plan p) {
     d.nparts = (d.n + rpw - 1) / rpw;
     part += d.nparts;
     auto it = p->ctile.find(d.n);
-    d.ctile = it != p->ctile.end() ? it->second : col_tile_default(d.n);
+    d.ctile = it != p->ctile.end() ? it->second : col_tile_start(d.n);
     d.ctile64 = d.ctile;
     while (!col_tile_valid(d.n, d.ctile64, 16) && d.ctile64 > 2) d.ctile64 /= 2;
     p->inst.push_back(d);

@@ -97,6 +97,14 @@ __host__ __device__ constexpr int col_tile_default(int n) {
   while (c * 2 <= 32 && c * 2 * n <= 2048 && n % (c * 2) == 0) c *= 2;
   return c;
 }
+// Width a plan starts with before any cbs_autotune: the width the autotuner
+// settles on for that size on MI355X (ragged 128..512 batch, 8 x 1024^2), the
+// default elsewhere.  Always one of the compiled widths.
+__host__ __device__ constexpr int col_tile_start(int n) {
+  return (n == 128 || n == 192 || n == 256 || n == 512) ? 8
+         : (n == 384 || n == 1024)                      ? 4
+                                                         : col_tile_default(n);
+}
 // Tiles a kernel is compiled for at size n: the default, half and double.
 __host__ __device__ constexpr bool col_tile_valid(int n, int c, int elem_bytes) {
   const int c0 = col_tile_default(n);

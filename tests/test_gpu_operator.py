@@ -171,10 +171,11 @@ def test_deterministic_repeat():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("which", ["half", "double"])
+@pytest.mark.parametrize("which", ["half", "default", "double"])
 def test_column_tile_widths_agree(which):
     # every compiled tile width (half / default / double of ~2048/N columns)
-    # gives the same apply; the autotuner picks one of them per size
+    # gives the same apply as the width a plan starts with; the autotuner
+    # picks one of them per size
     sizes = (64, 128, 256, 512, 1024)
     probs = [random_problem(n, seed=300 + n) for n in sizes]
     plan, k2 = plan_for(probs)
@@ -182,7 +183,7 @@ def test_column_tile_widths_agree(which):
     ref = plan.apply(u, s)
     default = {16: 16, 32: 32, 64: 32, 128: 16, 192: 8, 256: 8, 288: 4, 384: 4, 512: 4, 1024: 2}
     for n in sizes:
-        c = default[n] // 2 if which == "half" else default[n] * 2
+        c = {"half": default[n] // 2, "default": default[n], "double": default[n] * 2}[which]
         try:
             plan.set_tile(c, n=n)
         except cbs.CbsError as e:
