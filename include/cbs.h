@@ -3,13 +3,13 @@
  *
  * The library applies, on one GPU, the Born-series operator of the heterogeneous
  * Helmholtz problem A u = s with A = -Laplacian - k(x)^2 on periodic N x N grids
- * (Sec. 3.1, Eq. helm and the discrete split A = L_eta - V_eta; App. E, Fourier
+ * (Sec. 3.1, Eq. helm and the discrete split A = L_eta - V_eta; App. D, Fourier
  * pseudospectral discretisation):
  *
  *   reference   L_eta = -Laplacian - (k0^2 + i eps),  eps > 0           (Sec. 3.1)
  *   symbol      lambda_n = |xi_n|^2 - k0^2 - i eps, xi = 2 pi n / N,
- *               n in {-N/2, ..., N/2-1}                                  (App. E)
- *   Green op.   G q = F^-1 (F q / lambda)                               (App. D, App. E)
+ *               n in {-N/2, ..., N/2-1}                                  (App. D)
+ *   Green op.   G q = F^-1 (F q / lambda)                               (App. C, App. D)
  *   potential   V = k^2 - k0^2 - i eps  (pointwise)                      (Sec. 3.1)
  *   CBS step    u <- u + gamma (G (V u + s) - u),  gamma = i V / eps     (Sec. 3.1, Eq. CBS)
  *   Born resid. r = G (V u + s) - u = G (s - A u)                        (Sec. 4.1, Eq. npbs_iter)
@@ -90,7 +90,7 @@ enum {
 
 /*
  * cbs_setup -- build a plan for a batch of instances (step: setup; Sec. 3.1
- * defines V and gamma from k^2, k0 and eps; App. E the grid and symbol).
+ * defines V and gamma from k^2, k0 and eps; App. D the grid and symbol).
  *   plan       out: new plan handle (NULL on error)
  *   batch      number of instances, >= 1
  *   n          host[batch]: grid size of each instance
@@ -175,7 +175,7 @@ cbs_status cbs_sweep(cbs_plan plan, void* u, const void* s, int count, double* n
 
 /*
  * cbs_helmholtz_residual -- physical residual r = s - A u with the Fourier
- *   pseudospectral A u = F^-1(|xi|^2 F u) - k^2 u (App. E, relation to A;
+ *   pseudospectral A u = F^-1(|xi|^2 F u) - k^2 u (App. D, relation to A;
  *   Sec. 5 stops on ||s - A u|| / ||s||).  One transform pair per call.
  *   u required; s nullable (zero); r nullable (not stored); norm2 nullable
  *   DEVICE double[batch]: per-instance sum |r|^2 in FP64.  r must not alias
@@ -198,7 +198,7 @@ cbs_status cbs_helmholtz_residual(cbs_plan plan, const void* u, const void* s, v
  *              instance stops at the first sweep whose estimate is <= rtol
  *              and is confirmed at the next chunk start);
  *              CBS_STOP_PHYSICAL: the paper's rTol = ||s - A u|| / ||s||
- *              (Sec. 5; A u = -Lap u - k^2 u, App. E), tested in FP64 at each
+ *              (Sec. 5; A u = -Lap u - k^2 u, App. D), tested in FP64 at each
  *              chunk start only (one more transform pair per chunk), so the
  *              sweep count is a multiple of check_every
  *   iters, relres, status  host[batch] outputs (sweeps applied, FP64-verified
@@ -247,7 +247,7 @@ cbs_status cbs_adjoint_step(cbs_plan plan, const void* u_m, const void* s, const
  *     lam_K = conj(V) G^H(conj(W) mu) - conj(W) mu,  mu = 2 W r_K,
  *     grad_k2 += G^H(conj(W) mu) conj(u_K)  (+ (-i/eps) mu conj(r_K) for W = gamma).
  *   weight 2: l = sum |e|^2 with the physical residual e = s - A u_K,
- *     A u = -Lap u - k^2 u (App. E; the residual of L_dir and L_bs^{l2}):
+ *     A u = -Lap u - k^2 u (App. D; the residual of L_dir and L_bs^{l2}):
  *     lam_K = -2 A^H e = -2 (-Lap e - conj(k^2) e),  grad_k2 += 2 conj(u_K) e.
  *   Other weights: CBS_ERR_ARG.  loss: DEVICE double[batch] (per-instance
  *   FP64 sums), nullable.  grad_k2 is accumulated.  Two transform pairs.

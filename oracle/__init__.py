@@ -11,10 +11,10 @@ against the paper:
     in exact integer arithmetic (no FFT library);
   * Fourier pseudospectral reference operator L_eta = -Laplacian - (k0^2 + i eta),
     symbol lambda_n = |xi_n|^2 - k0^2 - i eta, xi = 2 pi n / N,
-    n in {-N/2, ..., N/2 - 1} (App. E, "Periodic grid and Fourier modes" and
-    "Discrete symbol"; App. D, Helmholtz case);
-  * Green operator G q = F^-1 (F q / lambda) (App. E, the three-step recipe);
-  * potential V = k^2 - k0^2 - i eta (Sec. 3.1 coefficient-only split; App. E);
+    n in {-N/2, ..., N/2 - 1} (App. D, "Periodic grid and Fourier modes" and
+    "Discrete symbol"; App. C, Helmholtz case);
+  * Green operator G q = F^-1 (F q / lambda) (App. D, the three-step recipe);
+  * potential V = k^2 - k0^2 - i eta (Sec. 3.1 coefficient-only split; App. D);
   * CBS fixed-point step u <- u + gamma (G (V u + s) - u)  (Sec. 3.1, Eq. CBS)
     with gamma = i V / eta (the paper only says gamma is derived from V;
     this is the Osnabrugge et al. 2016 choice cited there);
@@ -48,7 +48,7 @@ def as_c(x) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------------------
-# Grid, DFT and symbol (App. E)
+# Grid, DFT and symbol (App. D)
 # ---------------------------------------------------------------------------
 
 @functools.lru_cache(maxsize=32)
@@ -76,7 +76,7 @@ def idft2(x: torch.Tensor) -> torch.Tensor:
 
 def mode_index(n: int) -> torch.Tensor:
     """Signed Fourier index for DFT bin k: k for k < N/2, k - N otherwise, so
-    the Nyquist bin maps to -N/2 (App. E)."""
+    the Nyquist bin maps to -N/2 (App. D)."""
     k = torch.arange(n, dtype=torch.int64)
     return torch.where(k >= n // 2, k - n, k)
 
@@ -99,12 +99,12 @@ def green(q: torch.Tensor, k0sq: float, eps: float) -> torch.Tensor:
 
 
 def green_adjoint(q: torch.Tensor, k0sq: float, eps: float) -> torch.Tensor:
-    """G^H q = F^-1 (F q / conj(lambda))  (App. D: G = F^-1 Lambda^-1 F)."""
+    """G^H q = F^-1 (F q / conj(lambda))  (App. C: G = F^-1 Lambda^-1 F)."""
     return idft2(dft2(q) / symbol(q.shape[-1], k0sq, eps).conj())
 
 
 def laplacian(u: torch.Tensor) -> torch.Tensor:
-    """-Laplacian u = F^-1 (|xi|^2 F u)  (App. E, relation to A)."""
+    """-Laplacian u = F^-1 (|xi|^2 F u)  (App. D, relation to A)."""
     return idft2(dft2(u) * xi_squared(u.shape[-1]).to(CDT))
 
 
@@ -203,6 +203,26 @@ def cbs_iterate(k2, k0sq, eps, s, u0=None, max_sweeps: int = 2500, rtol: float =
     if history:
         return u, m, rel, hist
     return u, m, rel
+
+
+# ---------------------------------------------------------------------------
+# NPBS step with a linear Fourier-layer preconditioner (Sec. 4.1; App. E)
+# ---------------------------------------------------------------------------
+
+def linear_fourier_layer(x, wf, wloc) -> torch.Tensor:
+    """M(x) = F^-1 (W^F * F x) + W^loc * x: the linear Fourier layer LFL of
+    App. E (Eq. lfl) on one complex channel, with spectral weights wf on the
+    (N, N) grid of DFT bins and local weights wloc (a scalar or an (N, N)
+    field; per cell it also stands for the fixed coefficient-branch factor
+    that multiplies the residual branch in Eq. fno_impl)."""
+    x = as_c(x)
+    return idft2(as_c(wf) * dft2(x)) + as_c(wloc) * x
+
+
+def npbs_step(k2, k0sq, eps, u, s, wf, wloc) -> torch.Tensor:
+    """u + M(G (V u + s) - u) with M the linear Fourier layer (Sec. 4.1,
+    Eq. npbs_integral)."""
+    return as_c(u) + linear_fourier_layer(cbs_residual(k2, k0sq, eps, u, s), wf, wloc)
 
 
 # ---------------------------------------------------------------------------

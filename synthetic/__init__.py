@@ -12,7 +12,7 @@ available, so the generators below produce stand-ins with the same shapes and
 value ranges: Gaussian random-field velocities, layered media, Gaussian blobs.
 Velocities are in km/s-like units (1.5-4.5) and the grid spacing is one cell.
 
-Conventions (Sec. 3.1, App. E):
+Conventions (Sec. 3.1, App. D):
   * the grid is the full periodic FFT grid of N x N cells, rows = y, cols = x;
   * the outer L cells on every side form the absorbing layer, the interior is
     (N - 2L)^2 cells;

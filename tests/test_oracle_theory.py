@@ -97,3 +97,34 @@ def test_npbs_reductions():
     u1 = u0 + (m_exact @ r.reshape(-1)).reshape(p.n, p.n)
     ref = np.linalg.solve(_dense_helmholtz_numpy(p.k2), p.source.reshape(-1)).reshape(p.n, p.n)
     assert np.max(np.abs(u1.numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_npbs_linear_fourier_layer_reductions():
+    # Sec. 4.1 with the linear Fourier layer of App. E as M:
+    # (i) W^F = 0, W^loc = gamma is the CBS step;
+    # (ii) in a homogeneous lossy medium V = v is constant, (I - G V)^{-1} is
+    #     diagonal in Fourier space with entries lambda / (lambda - v), so that
+    #     W^F (W^loc = 0) solves in one step from any u; the solution is the
+    #     closed form F^-1(F s / (|xi|^2 - k^2)) evaluated with numpy.fft;
+    # (iii) W^F = 1, W^loc = 0 gives M = identity: u + r = G (V u + s).
+    p = _small_problem(seed=6)
+    eps = O.choose_eps(p.k2, p.k0sq)
+    rng = np.random.default_rng(9)
+    u0 = O.as_c(S.random_field_c(p.n, rng))
+    zero = torch.zeros(p.n, p.n, dtype=O.CDT)
+    got = O.npbs_step(p.k2, p.k0sq, eps, u0, p.source, zero, O.gamma(p.k2, p.k0sq, eps))
+    assert torch.equal(got, O.cbs_sweep(p.k2, p.k0sq, eps, u0, p.source))
+    one = torch.ones(p.n, p.n, dtype=O.CDT)
+    got = O.npbs_step(p.k2, p.k0sq, eps, u0, p.source, one, 0.0)
+    assert torch.max(torch.abs(got - O.cbs_apply(p.k2, p.k0sq, eps, u0, p.source))) <= 1e-12
+    n, k0sq, kappa = 24, 0.7, 0.25
+    s = S.random_field_c(n, rng)
+    h = S.homogeneous_lossy(n, k0sq, kappa, s)
+    e = 1.5 * kappa
+    lam = O.symbol(n, k0sq, e)
+    v = complex(0.0, kappa - e)              # V = k^2 - k0^2 - i eps = i (kappa - eps)
+    wf = lam / (lam - v)
+    u1 = O.npbs_step(h.k2, k0sq, e, S.random_field_c(n, rng), s, wf, 0.0)
+    xi = 2 * np.pi * np.fft.fftfreq(n)
+    exact = np.fft.ifft2(np.fft.fft2(s) / (xi[:, None] ** 2 + xi[None, :] ** 2 - k0sq - 1j * kappa))
+    assert np.max(np.abs(u1.numpy() - exact)) <= 1e-12 * np.max(np.abs(exact))

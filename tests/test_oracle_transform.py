@@ -1,6 +1,6 @@
 """Pins of the oracle's DFT, symbol and Green operator against things other
 than itself: numpy.fft (an independent library), closed forms for single
-Fourier modes (App. E), and operator invariants (App. D)."""
+Fourier modes (App. D), and operator invariants (App. C)."""
 import math
 
 import numpy as np
@@ -22,7 +22,7 @@ def test_dft_matches_numpy_fft(n):
 
 
 def test_mode_index_keeps_nyquist_negative():
-    # App. E: n in {-N/2, ..., N/2 - 1}.
+    # App. D: n in {-N/2, ..., N/2 - 1}.
     m = O.mode_index(8).tolist()
     assert m == [0, 1, 2, 3, -4, -3, -2, -1]
 
