@@ -237,6 +237,29 @@ def time_to_solution(probs, plan_k2, sizes, k0sq, s_packed, rtol=1e-6, chunk=50,
     return out
 
 
+def npbs_throughput(plan, sizes, s, steps=20):
+    """NPBS steps with a linear Fourier layer of seeded random weights (the
+    learned preconditioner's residual branch; two transform pairs per step)
+    over the same batch: Gcell * NPBS-step / s."""
+    g = torch.Generator(device="cpu").manual_seed(2026)
+    cells = sum(n * n for n in sizes)
+
+    def field(scale):
+        x = torch.complex(torch.randn(cells, generator=g), torch.randn(cells, generator=g))
+        return (scale * x).to(torch.complex64).cuda()
+    wf, wl = field(0.3), field(0.3)
+    u = plan.zeros()
+    plan.npbs_step(u, s, wf, wl, count=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.npbs_step(u, s, wf, wl, count=steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"unit": "Gcell*NPBS-step/s", "value": cells / dt / 1e9, "ms_per_step": dt * 1e3,
+            "steps": steps, "transform_pairs_per_step": 2,
+            "weights": "seeded random spectral and local weights, 0.3 * CN(0, 1)"}
+
+
 def _gcell(cells, applies, seconds):
     return cells * applies / seconds / 1e9
 
@@ -489,6 +512,7 @@ def main():
             "event_ms_per_sweep": ev_ms,
         },
     }
+    line["npbs_step"] = npbs_throughput(plan, sizes, s)
     if not args.no_solve:
         line["time_to_1e-6"] = time_to_solution(probs, k2, sizes, k0sq, s)
     if args.suite:

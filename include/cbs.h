@@ -174,6 +174,23 @@ cbs_status cbs_residual(cbs_plan plan, const void* u, const void* s, const void*
 cbs_status cbs_sweep(cbs_plan plan, void* u, const void* s, int count, double* norm2, void* stream);
 
 /*
+ * cbs_npbs_step -- `count` NPBS steps in place (Sec. 4.1, Eq. npbs_integral)
+ *   with the linear Fourier layer of App. E (Eq. lfl) as the preconditioner:
+ *     r = G(V u + s) - u,   u <- u + F^-1(wf * F r) + wloc * r
+ *   (F the unnormalised forward DFT, F^-1 its inverse with the 1/N^2).
+ *   wf    device, packed like the fields: per instance the N x N spectral
+ *         weights on the DFT bins in FFT order (bin (k1, k2), k = 0..N-1 with
+ *         k >= N/2 standing for k - N, at offset_i + k1 N + k2); required
+ *   wloc  device, packed field of per-cell local weights (the 1 x 1 channel
+ *         weight, or any fixed per-cell factor); NULL = 0
+ *   s nullable; u must not alias s, wf or wloc.  count in [1, 1e6].
+ *   wf = 0, wloc = gamma gives cbs_sweep's step.  Two transform pairs per
+ *   step; uses the plan's scratch field, so calls on one plan serialise.
+ */
+cbs_status cbs_npbs_step(cbs_plan plan, void* u, const void* s, const void* wf, const void* wloc,
+                         int count, void* stream);
+
+/*
  * cbs_helmholtz_residual -- physical residual r = s - A u with the Fourier
  *   pseudospectral A u = F^-1(|xi|^2 F u) - k^2 u (App. D, relation to A;
  *   Sec. 5 stops on ||s - A u|| / ||s||).  One transform pair per call.

@@ -45,6 +45,7 @@ SIGNATURES = {
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "cbs_npbs_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "cbs_helmholtz_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
     "fgmres_solve": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
@@ -243,6 +244,14 @@ class Plan:
         _check(load().cbs_sweep(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
                                 int(count), _ptr(n2), _stream(stream)))
         return n2
+
+    def npbs_step(self, u, s, wf, wloc=None, count=1, stream=None):
+        """count NPBS steps in place with the linear Fourier layer
+        M(r) = F^-1(wf * F r) + wloc * r (wf packed per instance on the DFT bins)."""
+        _check(load().cbs_npbs_step(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                    _ptr(self._field(wf, "wf")), _ptr(self._field(wloc, "wloc")),
+                                    int(count), _stream(stream)))
+        return u
 
     def iterate(self, u, s, max_sweeps=2500, rtol=1e-6, check_every=50, use_graph=True, stream=None,
                 stop="born"):

@@ -975,6 +975,38 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
   return CBS_OK;
 }
 
+// ---- NPBS step with a linear Fourier layer ------------------------------------------------
+
+// count steps u <- u + F^-1(wf F r) + wloc r, r = G(V u + s) - u: the residual
+// pipeline (r kept in the scratch field), then the layer's pipeline with the
+// tabulated spectral weights and the update in its epilogue (in place).
+template <typename R>
+cbs_status npbs_impl(cbs_plan p, void* u, const void* s, const void* wf, const void* wloc,
+                     int count, hipStream_t st) {
+  cpx<R>* r = static_cast<cpx<R>*>(p->d_t);
+  for (int k = 0; k < count; ++k) {
+    Params<R> q = base_params<R>(p);
+    q.u = static_cast<const cpx<R>*>(u);
+    q.s = static_cast<const cpx<R>*>(s);
+    q.epi = EPI_RESID;
+    q.out = r;
+    q.partials = nullptr;
+    CHK(run_pipeline(p, q, st));
+    Params<R> m = base_params<R>(p);
+    m.pro = PRO_A;
+    m.a = r;
+    m.sym = SYM_TABLE;
+    m.table = static_cast<const cpx<R>*>(wf);
+    m.epi = EPI_NPBS;
+    m.u = static_cast<const cpx<R>*>(u);
+    m.b = static_cast<const cpx<R>*>(wloc);
+    m.out = static_cast<cpx<R>*>(u);
+    m.partials = nullptr;
+    CHK(run_pipeline(p, m, st));
+  }
+  return CBS_OK;
+}
+
 // ---- adjoint -------------------------------------------------------------------------------
 
 template <typename R>
@@ -1421,6 +1453,16 @@ cbs_status cbs_helmholtz_residual(cbs_plan p, const void* u, const void* s, void
     HIPCHK(hipGetLastError());
   }
   return CBS_OK;
+}
+
+cbs_status cbs_npbs_step(cbs_plan p, void* u, const void* s, const void* wf, const void* wloc,
+                         int count, void* stream) {
+  if (!p || !u || !wf) return fail(CBS_ERR_ARG, "plan, u or wf is NULL");
+  if (u == s || u == wf || u == wloc) return fail(CBS_ERR_ARG, "u must not alias s, wf or wloc");
+  if (count < 1 || count > 1000000) return fail(CBS_ERR_ARG, "count must be in [1, 1e6]");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return npbs_impl<float>(p, u, s, wf, wloc, count, st);
+  return npbs_impl<double>(p, u, s, wf, wloc, count, st);
 }
 
 cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm2, void* stream) {

@@ -148,6 +148,12 @@ __device__ __forceinline__ double epilogue(const Params<R>& p, const InstDesc& d
       p.out2[i] = p.out2[i] + cscale(cmulc(p.u[i], e), R(2));
       return double(cabs2(e));
     }
+    case EPI_NPBS: {
+      // linear Fourier layer applied to r = a: u += F^-1(W^F F r) + W^loc r
+      const cpx<R> r = p.a[i];
+      p.out[i] = p.u[i] + z + cmul(ld_or_zero(p.b, i), r);
+      return 0.0;
+    }
     default: {  // EPI_LAP: physical residual s - A u with A u = -Lap u - k^2 u
       const cpx<R> u = ld_or_zero(p.u, i);
       const cpx<R> au = z - cmul(p.k2[i], u);
@@ -352,6 +358,8 @@ __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, 
   cpx<R>* mine = lds + c;
   auto ld = [&](int e) { return p.inter[cbase + (long long)e * N]; };
   auto sym = [&](int e, cpx<R> v) {
+    if (p.sym == SYM_TABLE)  // tabulated weights; 1/N^2 of the inverse transform
+      return cscale(cmul(v, p.table[cbase + (long long)e * N]), R(1.0 / (double(N) * double(N))));
     return cmul(v, symbol_factor<R>(N, e, kcol, d.k0sq, d.eps, p.sym));
   };
   auto st2 = [&](int e, cpx<R> v) { p.inter[cbase + (long long)e * N] = v; };

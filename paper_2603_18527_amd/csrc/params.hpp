@@ -30,7 +30,7 @@ struct InstDesc {
 };
 
 enum Pro { PRO_VU_S = 0, PRO_CONJG_A = 1, PRO_SEED = 2, PRO_U = 3, PRO_A = 4 };
-enum Sym { SYM_GREEN = 0, SYM_GREEN_CONJ = 1, SYM_LAP = 2 };
+enum Sym { SYM_GREEN = 0, SYM_GREEN_CONJ = 1, SYM_LAP = 2, SYM_TABLE = 3 };
 enum Epi {
   EPI_STORE = 0,
   EPI_RESID = 1,
@@ -39,7 +39,8 @@ enum Epi {
   EPI_ADJ = 4,
   EPI_SEED = 5,
   EPI_LAP = 6,
-  EPI_PHYS_SEED = 7
+  EPI_PHYS_SEED = 7,
+  EPI_NPBS = 8
 };
 // Instance masks: which status values let an instance run.
 enum MaskMode { MASK_RUNNING = 0, MASK_NOT_FINAL = 1, MASK_NONZERO = 2 };
@@ -67,6 +68,7 @@ struct Params {
   const cpx<R>* rhs;
   const cpx<R>* a;
   const cpx<R>* b;
+  const cpx<R>* table;  // SYM_TABLE: spectral weights on the DFT bins (packed like fields)
   cpx<R>* inter;
   cpx<R>* out;
   cpx<R>* out2;
