@@ -206,6 +206,91 @@ def cbs_iterate(k2, k0sq, eps, s, u0=None, max_sweeps: int = 2500, rtol: float =
 
 
 # ---------------------------------------------------------------------------
+# Dirichlet problems: five-point FD on the unit square, DST-I reference
+# (App. C "Newton linear systems for nonlinear PDEs"; App. B, Newton-Born)
+# ---------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=32)
+def dst1_matrix(n: int) -> torch.Tensor:
+    """S[j, k] = sin(pi (j+1)(k+1) / (n+1)), j, k = 0..n-1 (the DST-I; S is
+    symmetric and S^-1 = 2/(n+1) S)."""
+    j = torch.arange(1, n + 1, dtype=torch.int64)
+    e = (j[:, None] * j[None, :]) % (2 * (n + 1))
+    return torch.sin(math.pi * e.to(RDT) / (n + 1)).to(CDT)
+
+
+def dst2(x: torch.Tensor) -> torch.Tensor:
+    """2D DST-I along both axes: S x S."""
+    s = dst1_matrix(x.shape[-1])
+    return s @ x @ s
+
+
+def idst2(x: torch.Tensor) -> torch.Tensor:
+    """Inverse 2D DST-I: (2/(n+1))^2 S x S."""
+    n = x.shape[-1]
+    return (2.0 / (n + 1)) ** 2 * dst2(x)
+
+
+def dirichlet_eigs(n: int) -> torch.Tensor:
+    """Eigenvalues of the five-point negative Laplacian with h = 1/(n+1) on
+    DST bins (p, q) = 1..n: 4/h^2 (sin^2(p pi h/2) + sin^2(q pi h/2))."""
+    h = 1.0 / (n + 1)
+    p = torch.arange(1, n + 1, dtype=RDT)
+    m = 4.0 / h ** 2 * torch.sin(p * math.pi * h / 2) ** 2
+    return m[:, None] + m[None, :]
+
+
+def green_dirichlet(q, k0sq: float, eps: float) -> torch.Tensor:
+    """G q = S^-1 (S q / lambda), lambda = eigs - k0^2 - i eps."""
+    q = as_c(q)
+    lam = dirichlet_eigs(q.shape[-1]).to(CDT) - complex(k0sq, eps)
+    return idst2(dst2(q) / lam)
+
+
+def laplacian_dirichlet(u) -> torch.Tensor:
+    """Five-point negative Laplacian with zero boundary values, h = 1/(n+1):
+    (4 u_ij - u_i-1,j - u_i+1,j - u_i,j-1 - u_i,j+1) / h^2."""
+    u = as_c(u)
+    n = u.shape[-1]
+    z = torch.zeros(n + 2, n + 2, dtype=CDT)
+    z[1:-1, 1:-1] = u
+    return (4 * u - z[:-2, 1:-1] - z[2:, 1:-1] - z[1:-1, :-2] - z[1:-1, 2:]) * (n + 1) ** 2
+
+
+def cbs_residual_dirichlet(k2, k0sq, eps, u, s=None) -> torch.Tensor:
+    """Born residual G (V u + s) - u with the Dirichlet G (V as in Sec. 3.1)."""
+    q = potential(k2, k0sq, eps) * as_c(u)
+    if s is not None:
+        q = q + as_c(s)
+    return green_dirichlet(q, k0sq, eps) - as_c(u)
+
+
+def cbs_sweep_dirichlet(k2, k0sq, eps, u, s=None) -> torch.Tensor:
+    return as_c(u) + gamma(k2, k0sq, eps) * cbs_residual_dirichlet(k2, k0sq, eps, u, s)
+
+
+def helmholtz_dirichlet(k2, u) -> torch.Tensor:
+    """A u = L_D u - k^2 u (a Newton Jacobian J = L_D - 2 diag(u_m) is k^2 = 2 u_m)."""
+    return laplacian_dirichlet(u) - as_c(k2) * as_c(u)
+
+
+def cbs_iterate_dirichlet(k2, k0sq, eps, s, max_sweeps: int = 2500, rtol: float = 1e-6):
+    """Stationary CBS with the Dirichlet G until ||r|| / ||G s|| <= rtol."""
+    s = as_c(s)
+    u = torch.zeros_like(s)
+    g = gamma(k2, k0sq, eps)
+    bnorm = norm(green_dirichlet(s, k0sq, eps))
+    m = 0
+    while True:
+        r = cbs_residual_dirichlet(k2, k0sq, eps, u, s)
+        rel = norm(r) / bnorm
+        if rel <= rtol or m >= max_sweeps or not math.isfinite(rel):
+            return u, m, rel
+        u = u + g * r
+        m += 1
+
+
+# ---------------------------------------------------------------------------
 # NPBS step with a linear Fourier-layer preconditioner (Sec. 4.1; App. E)
 # ---------------------------------------------------------------------------
 
