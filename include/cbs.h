@@ -85,7 +85,8 @@ enum {
 /* Setup flags. */
 enum {
   CBS_FLAG_NO_GUARD = 1u,   /* skip the eps / min|V| conditioning guard */
-  CBS_FLAG_ONE_STREAM = 2u  /* enqueue every kernel on the caller's stream (no lanes) */
+  CBS_FLAG_ONE_STREAM = 2u, /* enqueue every kernel on the caller's stream (no lanes) */
+  CBS_FLAG_DIRICHLET = 4u   /* Dirichlet instances: DST-I reference (see cbs_setup) */
 };
 
 /*
@@ -106,6 +107,16 @@ enum {
  * Guard: unless CBS_FLAG_NO_GUARD, rejects eps < max|k^2 - k0^2| (1e-12
  * relative slack) and min|V|/eps < 1e-3 with CBS_ERR_ILLCOND (a cell with
  * V = 0 has gamma = 0 and never updates).  Synchronises `stream`.
+ * Dirichlet plans (CBS_FLAG_DIRICHLET; App. C "Newton linear systems"): every
+ * instance is the n x n interior of the unit square, h = 1/(n+1), with
+ * homogeneous Dirichlet boundaries and the five-point negative Laplacian L_D;
+ * the operator is A u = L_D u - k^2 u, the reference L_eta = L_D - (k0^2 +
+ * i eps), and G = S^-1 diag(1/lambda) S with S the 2D DST-I and lambda_pq =
+ * 4/h^2 (sin^2(p pi h/2) + sin^2(q pi h/2)) - k0^2 - i eps.  Every call then
+ * uses that G and L_D in place of the periodic ones.  n must satisfy
+ * 2(n+1) in {16, ..., 1024} above: n in {7, 15, 31, 63, 95, 127, 143, 191,
+ * 255, 511}.  (A Newton step J du = r with J = L_D - 2 diag(u) is the case
+ * k^2 = 2u; k0^2 = 2 mean(u) - alpha gives the paper's reference Jacobian.)
  * Lanes: a batch of at least two instances and 2^21 cells is split into two
  * lanes of about equal cell count.  Sweep chains (cbs_sweep, the sweeps of
  * cbs_iterate and of the FGMRES preconditioner) run each lane on a
@@ -122,7 +133,7 @@ cbs_status cbs_setup(cbs_plan* plan, int batch, const int32_t* n, const void* k2
 /*
  * cbs_workspace_size -- device bytes a plan of these sizes needs when the
  * caller provides its memory (cbs_setup_ws).  Host-only; touches no device.
- *   batch, n, dtype, max_restart as in cbs_setup; bytes out.
+ *   batch, n, dtype, max_restart, flags as in cbs_setup; bytes out.
  * The plan's buffers: FP64 copies of k^2, the spectral buffer, the FP64
  * iterate and source, three operator-precision fields, per-row partial sums,
  * per-instance solver state, twiddle tables, work lists, and for
@@ -130,7 +141,7 @@ cbs_status cbs_setup(cbs_plan* plan, int batch, const int32_t* n, const void* k2
  * operator-precision fields) with the Hessenberg/Givens storage.
  */
 cbs_status cbs_workspace_size(int batch, const int32_t* n, int dtype, int max_restart,
-                              size_t* bytes);
+                              uint32_t flags, size_t* bytes);
 
 /*
  * cbs_setup_ws -- cbs_setup with caller-owned device memory: every device

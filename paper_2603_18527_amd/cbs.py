@@ -30,9 +30,12 @@ CBS_C64 = 0
 CBS_C128 = 1
 FLAG_NO_GUARD = 1
 FLAG_ONE_STREAM = 2
+FLAG_DIRICHLET = 4
 INST_RUNNING, INST_CONVERGED, INST_MAX_ITERS, INST_DIVERGED = 0, 1, 2, 3
 
 SUPPORTED_SIZES = (16, 32, 64, 128, 192, 256, 288, 384, 512, 1024)
+# Dirichlet instance sizes n (interior points): 2(n + 1) is a supported FFT length
+SUPPORTED_DIRICHLET = tuple(m // 2 - 1 for m in SUPPORTED_SIZES)
 
 # Every symbol include/cbs.h declares, with its ctypes signature.
 _vp, _i32, _u32, _f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_double
@@ -40,7 +43,7 @@ SIGNATURES = {
     "cbs_setup": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp]),
     "cbs_setup_ws": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp,
                             ctypes.c_size_t, _vp]),
-    "cbs_workspace_size": (_i32, [_i32, _vp, _i32, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "cbs_workspace_size": (_i32, [_i32, _vp, _i32, _i32, _u32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -106,11 +109,13 @@ def _stream(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def workspace_size(sizes: Sequence[int], dtype: int = CBS_C64, max_restart: int = 0) -> int:
+def workspace_size(sizes: Sequence[int], dtype: int = CBS_C64, max_restart: int = 0,
+                   dirichlet: bool = False) -> int:
     """Device bytes of a plan's workspace (cbs_workspace_size; host only)."""
     n_arr = (ctypes.c_int32 * len(sizes))(*[int(n) for n in sizes])
     out = ctypes.c_size_t()
-    _check(load().cbs_workspace_size(len(sizes), n_arr, int(dtype), int(max_restart), ctypes.byref(out)))
+    _check(load().cbs_workspace_size(len(sizes), n_arr, int(dtype), int(max_restart),
+                                     FLAG_DIRICHLET if dirichlet else 0, ctypes.byref(out)))
     return int(out.value)
 
 
@@ -140,9 +145,11 @@ class Plan:
 
     def __init__(self, k2: torch.Tensor, sizes: Sequence[int], k0sq=None, eps=None,
                  dtype: int = CBS_C64, max_restart: int = 0, guard: bool = True, stream=None,
-                 lanes: bool = True, torch_workspace: bool = True):
+                 lanes: bool = True, torch_workspace: bool = True, dirichlet: bool = False):
         """torch_workspace: the plan's device memory is one torch tensor
-        (cbs_setup_ws); False lets the library allocate it (cbs_setup)."""
+        (cbs_setup_ws); False lets the library allocate it (cbs_setup).
+        dirichlet: instances are n x n interiors of the unit square with
+        homogeneous Dirichlet boundaries (five-point FD, DST-I reference)."""
         lib = load()
         self.sizes = [int(n) for n in sizes]
         self.batch = len(self.sizes)
@@ -158,10 +165,12 @@ class Plan:
         eps_arr = None if eps is None else (ctypes.c_double * self.batch)(
             *[0.0 if v is None else float(v) for v in _expand(eps, self.batch)])
         h = ctypes.c_void_p()
-        flags = (0 if guard else FLAG_NO_GUARD) | (0 if lanes else FLAG_ONE_STREAM)
+        flags = ((0 if guard else FLAG_NO_GUARD) | (0 if lanes else FLAG_ONE_STREAM)
+                 | (FLAG_DIRICHLET if dirichlet else 0))
+        self.dirichlet = bool(dirichlet)
         self._ws = None
         if torch_workspace:
-            self._ws = torch.empty(workspace_size(self.sizes, dtype, max_restart), dtype=torch.uint8,
+            self._ws = torch.empty(workspace_size(self.sizes, dtype, max_restart, dirichlet), dtype=torch.uint8,
                                    device="cuda")
             st = lib.cbs_setup_ws(ctypes.byref(h), self.batch, n_arr, _ptr(k2), k0_arr, eps_arr, dtype,
                                   int(max_restart), flags, _ptr(self._ws), self._ws.numel(),

@@ -157,6 +157,10 @@ struct cbs_plan_s {
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (view generation, 2 chunk + stop rule)
   hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
   bool one_stream = false;           // CBS_FLAG_ONE_STREAM
+  bool dirichlet = false;            // CBS_FLAG_DIRICHLET: DST-I instances
+  double* d_mu = nullptr;            // Dirichlet eigenvalue table (all transform lengths)
+  // FFT length that carries an instance of size n
+  int tlen(int n) const { return dirichlet ? dst_len(n) : n; }
   hipStream_t lane_st[2] = {nullptr, nullptr};  // non-blocking lane streams
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int op_elem() const { return dtype == CBS_C64 ? 8 : 16; }
@@ -174,14 +178,17 @@ void build_items(cbs_plan p) {
     d.n = p->n[i];
     d.k0sq = p->k0sq.empty() ? 0.0 : p->k0sq[i];
     d.eps = p->eps.empty() ? 1.0 : p->eps[i];
-    const int rpw = row_rpw(d.n);
+    d.kind = p->dirichlet ? KIND_DIRICHLET : KIND_PERIODIC;
+    const int m = p->tlen(d.n);
+    const int rpw = row_rpw(m);
+    d.rpw = rpw;
     d.part_off = part;
     d.nparts = (d.n + rpw - 1) / rpw;
     part += d.nparts;
     auto it = p->ctile.find(d.n);
-    d.ctile = it != p->ctile.end() ? it->second : col_tile_start(d.n);
+    d.ctile = it != p->ctile.end() ? it->second : col_tile_start(m);
     d.ctile64 = d.ctile;
-    while (!col_tile_valid(d.n, d.ctile64, 16) && d.ctile64 > 2) d.ctile64 /= 2;
+    while (!col_tile_valid(m, d.ctile64, 16) && d.ctile64 > 2) d.ctile64 /= 2;
     p->inst.push_back(d);
   }
   // Largest instances first, so the short tail of the grid holds small items.
@@ -189,7 +196,7 @@ void build_items(cbs_plan p) {
   for (int i = 0; i < p->batch; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->n[a] > p->n[b]; });
   for (int i : order) {
-    const int rpw = row_rpw(p->n[i]);
+    const int rpw = p->inst[i].rpw;
     for (int r = 0; r < p->n[i]; r += rpw) p->row_items.push_back(int2{i, r});
   }
   // Column items, per instance with its own tile width.  Workgroups are
@@ -207,7 +214,7 @@ void build_items(cbs_plan p) {
     for (int i : order) {
       const int c = prec == 0 ? p->inst[i].ctile : p->inst[i].ctile64;
       size_t& lds = prec == 0 ? p->col_lds32 : p->col_lds64;
-      lds = std::max(lds, size_t(col_lds_elems(p->n[i], c)) * elem);
+      lds = std::max(lds, size_t(col_lds_elems(p->tlen(p->n[i]), c)) * elem);
       std::vector<int2> nat;
       for (int col = 0; col < p->n[i]; col += c) nat.push_back(int2{i, col});
       const size_t g = std::max(1, 128 / (c * elem)), blk = 8 * g;
@@ -377,6 +384,8 @@ Params<R> base_params(cbs_plan p) {
   q.pro = PRO_VU_S;
   q.sym = SYM_GREEN;
   q.epi = EPI_STORE;
+  q.dst = p->dirichlet ? 1 : 0;
+  q.mu = p->d_mu;
   return q;
 }
 
@@ -1091,12 +1100,13 @@ cbs_status check_setup_args(int batch, const int32_t* n, int dtype, int max_rest
   if (batch < 1 || !n) return fail(CBS_ERR_ARG, "batch < 1 or n NULL");
   if (dtype != CBS_C64 && dtype != CBS_C128) return fail(CBS_ERR_ARG, "dtype must be CBS_C64 or CBS_C128");
   if (max_restart < 0 || max_restart > 200) return fail(CBS_ERR_ARG, "max_restart must be in [0, 200]");
-  if (flags & ~uint32_t(CBS_FLAG_NO_GUARD | CBS_FLAG_ONE_STREAM))
+  if (flags & ~uint32_t(CBS_FLAG_NO_GUARD | CBS_FLAG_ONE_STREAM | CBS_FLAG_DIRICHLET))
     return fail(CBS_ERR_ARG, "unknown flag bits");
+  const bool dir = (flags & CBS_FLAG_DIRICHLET) != 0;
   for (int i = 0; i < batch; ++i)
-    if (!supported_n(n[i]))
-      return fail(CBS_ERR_SIZE, "unsupported grid size " + std::to_string(n[i]) + " (instance " +
-                                    std::to_string(i) + ")");
+    if (n[i] < 1 || !supported_n(dir ? dst_len(n[i]) : n[i]))
+      return fail(CBS_ERR_SIZE, std::string(dir ? "unsupported Dirichlet size " : "unsupported grid size ") +
+                                    std::to_string(n[i]) + " (instance " + std::to_string(i) + ")");
   return CBS_OK;
 }
 
@@ -1106,6 +1116,7 @@ void init_layout(cbs_plan p, int batch, const int32_t* n, int dtype, int max_res
   p->dtype = dtype;
   p->max_restart = max_restart;
   p->one_stream = (flags & CBS_FLAG_ONE_STREAM) != 0;
+  p->dirichlet = (flags & CBS_FLAG_DIRICHLET) != 0;
   p->n.assign(n, n + batch);
   long long off = 0;
   for (int i = 0; i < batch; ++i) {
@@ -1129,6 +1140,7 @@ std::vector<std::pair<void**, size_t>> buffer_requests(cbs_plan p) {
       {reinterpret_cast<void**>(&p->d_row_items), nrow * sizeof(int2)},
       {reinterpret_cast<void**>(&p->d_tw32), kTwTotal * sizeof(cpx<float>)},
       {reinterpret_cast<void**>(&p->d_tw64), kTwTotal * sizeof(cpx<double>)},
+      {reinterpret_cast<void**>(&p->d_mu), kMuTotal * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_k2_64), cells * 16},
       {reinterpret_cast<void**>(&p->d_inter64), cells * 16},
       {reinterpret_cast<void**>(&p->d_u64), cells * 16},
@@ -1210,12 +1222,12 @@ cbs_status cbs_setup_ws(cbs_plan* out, int batch, const int32_t* n, const void* 
 }
 
 cbs_status cbs_workspace_size(int batch, const int32_t* n, int dtype, int max_restart,
-                              size_t* bytes) {
+                              uint32_t flags, size_t* bytes) {
   if (!bytes) return fail(CBS_ERR_ARG, "bytes is NULL");
   *bytes = 0;
-  CHK(check_setup_args(batch, n, dtype, max_restart, 0));
+  CHK(check_setup_args(batch, n, dtype, max_restart, flags));
   cbs_plan_s p;
-  init_layout(&p, batch, n, dtype, max_restart, 0);
+  init_layout(&p, batch, n, dtype, max_restart, flags);
   *bytes = request_bytes(buffer_requests(&p));
   return CBS_OK;
 }
@@ -1310,6 +1322,15 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
     if (e_ != hipSuccess) return bail(CBS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
   BAILCHK(hipMemcpyAsync(p->d_tw64, t64.data(), kTwTotal * sizeof(cpx<double>), hipMemcpyHostToDevice, st));
+  // Dirichlet eigenvalue table mu_p = M^2 sin^2(pi p / M) (5-point FD Laplacian
+  // on the unit square, h = 1/(n+1) = 2/M), FP64 on the host
+  std::vector<double> mu(kMuTotal, 0.0);
+  for (int mm : kSizes)
+    for (int q = 0; q < mm; ++q) {
+      const double sn = std::sin(M_PI * double(q) / double(mm));
+      mu[mu_offset(mm) + q] = double(mm) * double(mm) * sn * sn;
+    }
+  BAILCHK(hipMemcpyAsync(p->d_mu, mu.data(), kMuTotal * sizeof(double), hipMemcpyHostToDevice, st));
   BAILCHK(hipMemcpyAsync(p->d_tw32, t32.data(), kTwTotal * sizeof(cpx<float>), hipMemcpyHostToDevice, st));
   BAILCHK(hipMemcpyAsync(p->d_row_items, p->row_items.data(), p->row_items.size() * sizeof(int2),
                          hipMemcpyHostToDevice, st));
@@ -1380,7 +1401,7 @@ cbs_status cbs_set_tile(cbs_plan p, int n, int columns) {
   bool any = false;
   for (int nn : p->n) {
     if (n != 0 && nn != n) continue;
-    if (!col_tile_valid(nn, columns, p->op_elem()))
+    if (!col_tile_valid(p->tlen(nn), columns, p->op_elem()))
       return fail(CBS_ERR_ARG, "tile width " + std::to_string(columns) + " not available for size " +
                                    std::to_string(nn));
     any = true;
@@ -1552,11 +1573,11 @@ cbs_status cbs_autotune(cbs_plan p, int32_t* tiles, void* stream) {
   bool first = true;
   cbs_status rc = CBS_OK;
   for (int n : classes) {
-    const int c0 = col_tile_default(n);
+    const int c0 = col_tile_default(p->tlen(n));
     int best = c0;
     double best_ms = 1e300;
     for (int c : {c0 / 2, c0, c0 * 2}) {
-      if (!col_tile_valid(n, c, p->op_elem())) continue;
+      if (!col_tile_valid(p->tlen(n), c, p->op_elem())) continue;
       p->ctile[n] = c;
       build_items(p);
       rc = upload_items(p, st);

@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
   if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
   const InstDesc d = p.inst[w.x];
   const int n = d.n;
-  const int rpw = row_rpw(n);
+  const int rpw = d.rpw;
   const int nrows = min(rpw, n - w.y);
   const long long base = d.off + (long long)w.y * n;
   const int cnt = nrows * n;
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
 
 __device__ __forceinline__ void item_range(const InstDesc& d, int row0, long long& base, int& cnt,
                                            int& slot) {
-  const int rpw = row_rpw(d.n);
+  const int rpw = d.rpw;
   const int nrows = min(rpw, d.n - row0);
   base = d.off + (long long)row0 * d.n;
   cnt = nrows * d.n;

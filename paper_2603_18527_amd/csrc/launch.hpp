@@ -14,6 +14,11 @@ void launch_row(int mode, int grid, hipStream_t st, const Params<float>& p);
 void launch_row(int mode, int grid, hipStream_t st, const Params<double>& p);
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
+// the same for Dirichlet plans (DST-I kernels; called by launch_row / launch_col)
+void launch_row_dst(int mode, int grid, hipStream_t st, const Params<float>& p);
+void launch_row_dst(int mode, int grid, hipStream_t st, const Params<double>& p);
+void launch_col_dst(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
+void launch_col_dst(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
 void launch_pointwise(int grid, hipStream_t st, const PwParams<float>& p);
 void launch_pointwise(int grid, hipStream_t st, const PwParams<double>& p);
 void launch_zupdate(int grid, hipStream_t st, const KryParams& k, const cpx<float>* z, cpx<double>* x);

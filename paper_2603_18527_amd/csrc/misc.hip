@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_stats(const InstDesc* inst, const 
   const int2 w = items[blockIdx.x];
   const InstDesc d = inst[w.x];
   const int n = d.n;
-  const int rpw = row_rpw(n);
+  const int rpw = d.rpw;
   const int nrows = min(rpw, n - w.y);
   const long long base = d.off + (long long)w.y * n;
   const int cnt = nrows * n;

@@ -8,6 +8,10 @@
 namespace cbs {
 
 void launch_row(int mode, int grid, hipStream_t st, const Params<float>& p) {
+  if (p.dst) {
+    launch_row_dst(mode, grid, st, p);
+    return;
+  }
   if (mode == 0)
     hipLaunchKernelGGL(k_row_fwd<float>, dim3(grid), dim3(kThreads), 0, st, p);
   else if (mode == 1)
@@ -17,6 +21,10 @@ void launch_row(int mode, int grid, hipStream_t st, const Params<float>& p) {
 }
 
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p) {
+  if (p.dst) {
+    launch_col_dst(grid, lds_bytes, st, p);
+    return;
+  }
   hipLaunchKernelGGL(k_col<float>, dim3(grid), dim3(kThreads), lds_bytes, st, p);
 }
 

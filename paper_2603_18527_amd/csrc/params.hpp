@@ -17,14 +17,23 @@ __host__ __device__ constexpr int row_rpw(int n) {
   return (kThreads / row_tpf(n)) < n ? (kThreads / row_tpf(n)) : n;
 }
 
+// Instance kinds: periodic N x N grid (FFT, App. D) or the n x n interior of
+// a unit square with homogeneous Dirichlet boundaries (five-point FD, DST-I,
+// App. C "Newton linear systems").
+enum InstKind { KIND_PERIODIC = 0, KIND_DIRICHLET = 1 };
+
+// Length of the FFT that carries a DST-I of length n (odd extension).
+__host__ __device__ constexpr int dst_len(int n) { return 2 * (n + 1); }
+
 struct InstDesc {
   long long off;  // element offset of the instance in packed fields
-  int n;
-  int part_off;  // first partial-sum slot (one per row work item)
+  int n;          // field size n x n
+  int part_off;   // first partial-sum slot (one per row work item)
   int nparts;
-  int ctile;     // column tile width: FP32 kernels (ctile) and FP64 kernels (ctile64)
+  int ctile;      // column tile width: FP32 kernels (ctile) and FP64 kernels (ctile64)
   int ctile64;
-  int pad;
+  int kind;       // InstKind
+  int rpw;        // rows per row work item
   double k0sq;
   double eps;
 };
@@ -69,6 +78,7 @@ struct Params {
   const cpx<R>* a;
   const cpx<R>* b;
   const cpx<R>* table;  // SYM_TABLE: spectral weights on the DFT bins (packed like fields)
+  const double* mu;     // Dirichlet plans: M^2 sin^2(pi p / M) per transform length M
   cpx<R>* inter;
   cpx<R>* out;
   cpx<R>* out2;
@@ -84,6 +94,7 @@ struct Params {
   // launch finished (k_col only)
   IterState chk;
   int check;
+  int dst;  // nonzero: Dirichlet plan (DST-I kernels)
 };
 
 
@@ -113,6 +124,19 @@ __host__ __device__ constexpr bool col_tile_valid(int n, int c, int elem_bytes) 
   return (c == c0 || c == c0 / 2 || c == c0 * 2) && c >= 2 && c <= 32 && n % c == 0 &&
          col_lds_elems(n, c) * elem_bytes <= kColLdsBytes;
 }
+
+// Dirichlet eigenvalue table: for each supported transform length M the
+// values M^2 sin^2(pi p / M), p = 0..M-1, back to back.
+__host__ __device__ constexpr int mu_offset(int m) {
+  int off = 0;
+  const int sizes[] = {16, 32, 64, 128, 192, 256, 288, 384, 512, 1024};
+  for (int i = 0; i < 10; ++i) {
+    if (sizes[i] == m) return off;
+    off += sizes[i];
+  }
+  return -1;
+}
+constexpr int kMuTotal = mu_offset(1024) + 1024;
 
 enum PwOp {
   PW_GAMMA = 0,        // e_out = gamma * e_in

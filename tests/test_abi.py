@@ -85,12 +85,12 @@ def test_workspace_size_without_gpu():
     lib = cbs.load()
     out = ctypes.c_size_t()
     n = (ctypes.c_int32 * 1)(100)
-    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, 0, ctypes.byref(out)) == cbs.CBS_ERR_SIZE
+    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, 0, 0, ctypes.byref(out)) == cbs.CBS_ERR_SIZE
     n = (ctypes.c_int32 * 1)(64)
-    assert lib.cbs_workspace_size(0, n, cbs.CBS_C64, 0, ctypes.byref(out)) == cbs.CBS_ERR_ARG
-    assert lib.cbs_workspace_size(1, n, 5, 0, ctypes.byref(out)) == cbs.CBS_ERR_ARG
-    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, -1, ctypes.byref(out)) == cbs.CBS_ERR_ARG
-    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, 0, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_workspace_size(0, n, cbs.CBS_C64, 0, 0, ctypes.byref(out)) == cbs.CBS_ERR_ARG
+    assert lib.cbs_workspace_size(1, n, 5, 0, 0, ctypes.byref(out)) == cbs.CBS_ERR_ARG
+    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, -1, 0, ctypes.byref(out)) == cbs.CBS_ERR_ARG
+    assert lib.cbs_workspace_size(1, n, cbs.CBS_C64, 0, 0, None) == cbs.CBS_ERR_ARG
 
 
 def test_setup_ws_rejects_bad_workspace_without_gpu():

@@ -1,0 +1,160 @@
+"""GPU Dirichlet plans (five-point FD on the unit square, DST-I reference;
+App. C "Newton linear systems") against the FP64 oracle: apply, residual,
+physical residual, fused sweeps, stationary CBS, FGMRES and the NPBS step.
+Bars as elsewhere: FP32 plans 1e-5 relative (FP32 rounding of transforms of
+length 2(n+1)), FP64 plans 1e-12."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from paper_2603_18527_amd import cbs
+from gpu_helpers import rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
+TOL = {cbs.CBS_C64: 1e-5, cbs.CBS_C128: 1e-12}
+ALL_N = [63, 7, 127, 31, 15, 255, 95, 143, 191, 511]
+
+
+def _media(sizes, seed, base=100.0, amp=60.0):
+    rng = np.random.default_rng(seed)
+    k2 = [base + amp * S.gaussian_random_field(n, max(2.0, n / 8), rng) for n in sizes]
+    src = [S.random_field_c(n, rng) for n in sizes]
+    u0 = [S.random_field_c(n, rng) for n in sizes]
+    return k2, src, u0
+
+
+def _plan(k2, sizes, dtype, **kw):
+    return cbs.Plan(cbs.pack(k2, TDT[dtype]), sizes, dtype=dtype, dirichlet=True, **kw)
+
+
+def _unpack(t, sizes):
+    return [x.cpu().to(torch.complex128) for x in cbs.unpack(t, sizes)]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_dirichlet_apply_and_residual_all_sizes(dtype):
+    k2, src, u0 = _media(ALL_N, 800)
+    plan = _plan(k2, ALL_N, dtype)
+    u = cbs.pack(u0, TDT[dtype])
+    s = cbs.pack(src, TDT[dtype])
+    y = plan.apply(u, s)
+    r, n2 = plan.residual(u, s)
+    h, hn2 = plan.helmholtz_residual(u, s)
+    torch.cuda.synchronize()
+    for i, n in enumerate(ALL_N):
+        v = O.potential(k2[i], plan.k0sq[i], plan.eps[i]) * O.as_c(u0[i]) + O.as_c(src[i])
+        ref = O.green_dirichlet(v, plan.k0sq[i], plan.eps[i])
+        e_apply = rel_err(_unpack(y, ALL_N)[i], ref)
+        e_res = rel_err(_unpack(r, ALL_N)[i], ref - O.as_c(u0[i]))
+        phys = O.as_c(src[i]) - O.helmholtz_dirichlet(k2[i], u0[i])
+        e_phys = rel_err(_unpack(h, ALL_N)[i], phys)
+        e_n2 = abs(float(n2[i]) - float(torch.sum(torch.abs(ref - O.as_c(u0[i])) ** 2))) / float(n2[i])
+        say(f"[dirichlet] dtype={dtype} n={n}: apply {e_apply:.1e} resid {e_res:.1e} "
+            f"physical {e_phys:.1e} norm {e_n2:.1e}")
+        assert e_apply <= TOL[dtype] and e_res <= TOL[dtype] and e_n2 <= TOL[dtype]
+        assert e_phys <= TOL[dtype] * 10
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_dirichlet_fused_sweeps(dtype):
+    sizes = [63, 31, 127, 15]
+    k2, src, u0 = _media(sizes, 810)
+    plan = _plan(k2, sizes, dtype)
+    u = cbs.pack(u0, TDT[dtype])
+    plan.sweep(u, cbs.pack(src, TDT[dtype]), count=5)
+    torch.cuda.synchronize()
+    for i, n in enumerate(sizes):
+        x = O.as_c(u0[i])
+        for _ in range(5):
+            x = O.cbs_sweep_dirichlet(k2[i], plan.k0sq[i], plan.eps[i], x, src[i])
+        e = rel_err(_unpack(u, sizes)[i], x)
+        say(f"[dirichlet sweeps] dtype={dtype} n={n}: {e:.1e}")
+        assert e <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_dirichlet_iterate_matches_oracle_and_dense_solve(dtype):
+    sizes = [15, 31]
+    k2, src, _ = _media(sizes, 4)
+    plan = _plan(k2, sizes, dtype)
+    u = plan.zeros()
+    its, rel, stat = plan.iterate(u, cbs.pack(src, TDT[dtype]), max_sweeps=20000, rtol=1e-6,
+                                  check_every=20)
+    for i, n in enumerate(sizes):
+        uo, mo, relo = O.cbs_iterate_dirichlet(k2[i], plan.k0sq[i], plan.eps[i], src[i],
+                                               max_sweeps=20000, rtol=1e-6)
+        ug = _unpack(u, sizes)[i]
+        ev = O.norm(O.cbs_residual_dirichlet(k2[i], plan.k0sq[i], plan.eps[i], ug, src[i])) \
+            / O.norm(O.green_dirichlet(src[i], plan.k0sq[i], plan.eps[i]))
+        say(f"[dirichlet iterate] dtype={dtype} n={n}: gpu {its[0 + i]} sweeps rel {rel[i]:.2e} "
+            f"(oracle eval {ev:.2e}); oracle {mo}")
+        assert stat[i] == cbs.INST_CONVERGED and rel[i] <= 1e-6
+        assert abs(its[i] - mo) <= 20
+        assert ev <= (1e-5 if dtype == cbs.CBS_C64 else 1.01e-6)
+    # n = 15 against the dense solve of (L_D - k^2) u = s
+    eye = np.eye(15 * 15).reshape(-1, 15, 15)
+    a = np.stack([O.laplacian_dirichlet(e).numpy().reshape(-1) for e in eye], axis=1) \
+        - np.diag(k2[0].reshape(-1))
+    ref = np.linalg.solve(a, src[0].reshape(-1)).reshape(15, 15)
+    assert rel_err(_unpack(u, sizes)[0], torch.from_numpy(ref)) <= 1e-4
+
+
+def test_dirichlet_fgmres_on_newton_jacobians():
+    # J du = r with J = L_D - 2 diag(u_m): k^2 = 2 u_m, u_m a smooth state
+    # built like the paper's initial guesses (sum of low sine modes)
+    n, batch = 63, 4
+    rng = np.random.default_rng(820)
+    x = np.arange(1, n + 1) / (n + 1)
+    k2, rhs = [], []
+    for b in range(batch):
+        c = rng.normal(0.0, 0.1, size=(4, 4))
+        um = 40.0 + 4.0 * sum(c[i, j] * np.outer(np.sin((i + 1) * math.pi * x), np.sin((j + 1) * math.pi * x))
+                              for i in range(4) for j in range(4))
+        k2.append(2.0 * um)
+        rhs.append(S.random_field_c(n, rng))
+    plan = _plan(k2, [n] * batch, cbs.CBS_C64, max_restart=20)
+    u = plan.zeros()
+    s = cbs.pack(rhs, torch.complex64)
+    its, rel, stat = plan.fgmres(u, s, restart=20, sweeps=3, max_iters=500, rtol=1e-6)
+    say(f"[dirichlet fgmres] its {its} rel {[f'{r:.1e}' for r in rel]}")
+    for i in range(batch):
+        ug = _unpack(u, [n] * batch)[i]
+        ev = O.norm(O.cbs_residual_dirichlet(k2[i], plan.k0sq[i], plan.eps[i], ug, rhs[i])) \
+            / O.norm(O.green_dirichlet(rhs[i], plan.k0sq[i], plan.eps[i]))
+        assert stat[i] == cbs.INST_CONVERGED and rel[i] <= 1e-6 and ev <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_dirichlet_npbs_step(dtype):
+    # spectral weights on DST bins: M(r) = S^-1 (W * S r) + w r
+    sizes = [31, 63]
+    k2, src, u0 = _media(sizes, 830)
+    rng = np.random.default_rng(831)
+    wf = [0.3 * S.random_field_c(n, rng) for n in sizes]
+    wl = [0.3 * S.random_field_c(n, rng) for n in sizes]
+    plan = _plan(k2, sizes, dtype)
+    u = cbs.pack(u0, TDT[dtype])
+    plan.npbs_step(u, cbs.pack(src, TDT[dtype]), cbs.pack(wf, TDT[dtype]), cbs.pack(wl, TDT[dtype]),
+                   count=2)
+    torch.cuda.synchronize()
+    for i, n in enumerate(sizes):
+        x = O.as_c(u0[i])
+        for _ in range(2):
+            r = O.cbs_residual_dirichlet(k2[i], plan.k0sq[i], plan.eps[i], x, src[i])
+            x = x + O.idst2(O.as_c(wf[i]) * O.dst2(r)) + O.as_c(wl[i]) * r
+        e = rel_err(_unpack(u, sizes)[i], x)
+        say(f"[dirichlet npbs] dtype={dtype} n={n}: {e:.1e}")
+        assert e <= TOL[dtype]
+
+
+def test_dirichlet_sizes_checked():
+    with pytest.raises(cbs.CbsError) as e:
+        _plan([np.ones((64, 64))], [64], cbs.CBS_C64)
+    assert e.value.status == cbs.CBS_ERR_SIZE
+    assert cbs.SUPPORTED_DIRICHLET == (7, 15, 31, 63, 95, 127, 143, 191, 255, 511)
