@@ -267,7 +267,8 @@ def _gcell(cells, applies, seconds):
 def run_suite(args):
     """Solver runs on the five synthetic workloads (configs of the metric):
     blob64 CBS, grf256 FGMRES(30)+CBS(4) and CBS, ragged64 FGMRES batched,
-    diff16 adjoint, layered1024 FGMRES(50)+CBS(4) in FP32 vs an FP64 GPU run.
+    diff16 adjoint, layered1024 FGMRES(50)+CBS(4) in FP32 vs an FP64 GPU run;
+    and the Dirichlet (DST-I) Newton-system batch newton63.
     Errors against the FP64 oracle are evaluated on the host where the naive
     DFT is affordable (N <= 256)."""
     import oracle as O
@@ -406,6 +407,32 @@ def run_suite(args):
         errs.append(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
     out["rel_err_fp32_vs_fp64_per_instance"] = errs
     res["layered1024_fgmres50_k4"] = out
+    # 6. newton63: Dirichlet (DST-I reference) Newton Jacobians J = L_D - 2 diag(u_m),
+    #    100 instances of 63^2 interior points; FGMRES(20) + 3 CBS sweeps to 1e-6
+    probs = S.newton_batch()
+    sizes = [q.n for q in probs]
+    cells = sum(n * n for n in sizes)
+    k2 = cbs.pack([q.k2 for q in probs], torch.complex64)
+    s = cbs.pack([q.source for q in probs], torch.complex64)
+    plan = cbs.Plan(k2, sizes, dirichlet=True, max_restart=20)
+    x = plan.zeros()
+    plan.apply(x, s)
+    dta = min(timed(lambda: [plan.apply(x, s) for _ in range(20)])[1] for _ in range(3)) / 20
+    plan.sweep(x, s, count=10)
+    dts = min(timed(lambda: plan.sweep(x, s, count=50))[1] for _ in range(3)) / 50
+    u = plan.zeros()
+    (its, rel, st), dt = timed(lambda: plan.fgmres(u, s, restart=20, sweeps=3, max_iters=2000, rtol=1e-6))
+    ug = u.cpu()[:sizes[0] ** 2].reshape(sizes[0], sizes[0])
+    k20 = k2.cpu()[:sizes[0] ** 2].reshape(sizes[0], sizes[0])
+    s0 = s.cpu()[:sizes[0] ** 2].reshape(sizes[0], sizes[0])
+    ev = O.norm(O.cbs_residual_dirichlet(k20, plan.k0sq[0], plan.eps[0], ug, s0)) / \
+        O.norm(O.green_dirichlet(s0, plan.k0sq[0], plan.eps[0]))
+    res["newton63_dirichlet"] = dict(
+        instances=len(sizes), cells=cells, apply_ms=dta * 1e3, apply_gcell_s=_gcell(cells, 1, dta),
+        sweep_ms=dts * 1e3, sweep_gcell_s=_gcell(cells, 1, dts),
+        fgmres20_k3=dict(seconds=dt, max_iterations=max(its), max_relres=max(rel),
+                         all_converged=all(x == 1 for x in st), instance0_relres_oracle_eval=ev))
+    print("# suite newton63 done", flush=True)
     return res
 
 
