@@ -986,13 +986,61 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
 
 // ---- NPBS step with a linear Fourier layer ------------------------------------------------
 
-// count steps u <- u + F^-1(wf F r) + wloc r, r = G(V u + s) - u: the residual
-// pipeline (r kept in the scratch field), then the layer's pipeline with the
-// tabulated spectral weights and the update in its epilogue (in place).
+// count steps u <- u + F^-1(wf F r) + wloc r, r = G(V u + s) - u.  Periodic
+// plans run them as one chain per lane: forward rows of V u + s, then per
+// step [Green columns, rows r = z - u -> forward rows of r, layer columns
+// (tabulated weights), rows u += z + wloc r -> forward rows of V u + s];
+// the last step ends with inverse rows and the update.  Dirichlet plans run
+// the residual pipeline and the layer's pipeline one after the other.
+template <typename R>
+void npbs_chain(cbs_plan p, const Params<R>& base, int count, hipStream_t st,
+                const cbs_plan_s::Items& it) {
+  Params<R> g = base;
+  g.items = it.rows;
+  launch_row(0, it.nrows, st, g);            // V u + s -> forward rows
+  Params<R> m = base;
+  m.sym = SYM_TABLE;
+  for (int k = 0; k < count; ++k) {
+    launch_cols(p, base, st, it);            // Green
+    g.items = it.rows;
+    launch_row(3, it.nrows, st, g);          // r = z - u -> forward rows of r
+    launch_cols(p, m, st, it);               // layer's spectral weights
+    m.items = it.rows;
+    if (k + 1 < count) {
+      launch_row(4, it.nrows, st, m);        // u += z + wloc r -> forward rows of V u + s
+    } else {
+      Params<R> e = m;
+      e.epi = EPI_NPBS;
+      launch_row(1, it.nrows, st, e);        // u += z + wloc r
+    }
+  }
+}
+
 template <typename R>
 cbs_status npbs_impl(cbs_plan p, void* u, const void* s, const void* wf, const void* wloc,
                      int count, hipStream_t st) {
   cpx<R>* r = static_cast<cpx<R>*>(p->d_t);
+  if (!p->dirichlet) {
+    Params<R> q = base_params<R>(p);
+    q.u = static_cast<const cpx<R>*>(u);
+    q.s = static_cast<const cpx<R>*>(s);
+    q.out = static_cast<cpx<R>*>(u);
+    q.out2 = r;
+    q.a = r;
+    q.b = static_cast<const cpx<R>*>(wloc);
+    q.table = static_cast<const cpx<R>*>(wf);
+    q.partials = nullptr;
+    const cbs_plan_s::View& v = *p->view;
+    if (v.nlanes) {
+      CHK(lanes_fork(p, st));
+      for (int l = 0; l < v.nlanes; ++l) npbs_chain(p, q, count, p->lane_st[l], v.lane[l]);
+      HIPCHK(hipGetLastError());
+      return lanes_join(p, st);
+    }
+    npbs_chain(p, q, count, st, v.all());
+    HIPCHK(hipGetLastError());
+    return CBS_OK;
+  }
   for (int k = 0; k < count; ++k) {
     Params<R> q = base_params<R>(p);
     q.u = static_cast<const cpx<R>*>(u);

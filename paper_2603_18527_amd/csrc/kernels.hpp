@@ -232,6 +232,10 @@ struct RowTile {
 // MODE 2: spectral buffer -> inverse rows -> sweep epilogue u += gamma r
 //         (written to global) -> next sweep's prologue V u + s formed from
 //         the value just computed -> forward rows -> spectral buffer.
+// MODE 3 / 4: the two halves of a fused NPBS step with a linear Fourier
+//         layer: after the Green pass r = z - u (kept in out2) -> forward rows
+//         of r; after the layer's spectral pass u += z + W^loc r (written) ->
+//         forward rows of the next step's V u + s.
 template <typename R, int N, int MODE>
 __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, int row0,
                                          cpx<R>* lds, double* red) {
@@ -254,6 +258,31 @@ __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, 
     if (p.partials) {
       const double s = block_sum(acc, red);
       if (tid == 0) p.partials[d.part_off + row0 / T::RPW] = s;
+    }
+  } else if constexpr (MODE == 3 || MODE == 4) {
+    auto ld = [&](int e) { return p.inter[rbase + e]; };
+    auto mid = [&](int e, cpx<R> z) {
+      const long long g = rbase + e;
+      const cpx<R> u = p.u[g];
+      if constexpr (MODE == 3) {
+        const cpx<R> rr = z - u;
+        p.out2[g] = rr;
+        return rr;
+      } else {
+        const cpx<R> un = u + z + cmul(ld_or_zero(p.b, g), p.a[g]);
+        p.out[g] = un;
+        const Coef<R> c = coef(p, d, g);
+        return cmul(c.v, un) + ld_or_zero(p.s, g);
+      }
+    };
+    auto st2 = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
+    if constexpr (plan_bridgeable(N)) {
+      fft_run2<R, N, T::TPF, 1, -1>(mine, t, active, p.tw, ld, mid, st2);
+    } else {
+      auto st = [&](int e, cpx<R> z) { mine[lds_pos(e)] = mid(e, z); };
+      fft_run<R, N, T::TPF, 1, false, true>(mine, t, active, p.tw, ld, st);
+      auto ld2 = [&](int e) { return lds_ld(mine + lds_pos(e)); };
+      fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld2, st2);
     }
   } else {
     double acc = 0.0;
@@ -317,6 +346,16 @@ __global__ __launch_bounds__(kThreads) void k_row_inv(Params<R> p) {
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row_sweep(Params<R> p) {
   row_dispatch<R, 2>(p);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_npbs_a(Params<R> p) {
+  row_dispatch<R, 3>(p);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_npbs_b(Params<R> p) {
+  row_dispatch<R, 4>(p);
 }
 
 // ---- column kernel ---------------------------------------------------------------

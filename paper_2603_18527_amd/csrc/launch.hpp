@@ -9,7 +9,8 @@
 namespace cbs {
 
 // mode 0: prologue + forward rows, 1: inverse rows + epilogue,
-// 2: fused inverse rows + CBS update + next prologue + forward rows
+// 2: fused inverse rows + CBS update + next prologue + forward rows,
+// 3 / 4: the two fused halves of an NPBS step (periodic plans only)
 void launch_row(int mode, int grid, hipStream_t st, const Params<float>& p);
 void launch_row(int mode, int grid, hipStream_t st, const Params<double>& p);
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);

@@ -16,8 +16,12 @@ void launch_row(int mode, int grid, hipStream_t st, const Params<float>& p) {
     hipLaunchKernelGGL(k_row_fwd<float>, dim3(grid), dim3(kThreads), 0, st, p);
   else if (mode == 1)
     hipLaunchKernelGGL(k_row_inv<float>, dim3(grid), dim3(kThreads), 0, st, p);
-  else
+  else if (mode == 2)
     hipLaunchKernelGGL(k_row_sweep<float>, dim3(grid), dim3(kThreads), 0, st, p);
+  else if (mode == 3)
+    hipLaunchKernelGGL(k_row_npbs_a<float>, dim3(grid), dim3(kThreads), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_row_npbs_b<float>, dim3(grid), dim3(kThreads), 0, st, p);
 }
 
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p) {

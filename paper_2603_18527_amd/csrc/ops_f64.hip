@@ -16,8 +16,12 @@ void launch_row(int mode, int grid, hipStream_t st, const Params<double>& p) {
     hipLaunchKernelGGL(k_row_fwd<double>, dim3(grid), dim3(kThreads), 0, st, p);
   else if (mode == 1)
     hipLaunchKernelGGL(k_row_inv<double>, dim3(grid), dim3(kThreads), 0, st, p);
-  else
+  else if (mode == 2)
     hipLaunchKernelGGL(k_row_sweep<double>, dim3(grid), dim3(kThreads), 0, st, p);
+  else if (mode == 3)
+    hipLaunchKernelGGL(k_row_npbs_a<double>, dim3(grid), dim3(kThreads), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_row_npbs_b<double>, dim3(grid), dim3(kThreads), 0, st, p);
 }
 
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p) {

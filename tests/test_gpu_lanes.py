@@ -102,3 +102,20 @@ def test_lanes_follow_caller_stream(plans):
     single.sweep(ub, s, count=3)
     torch.cuda.synchronize()
     assert torch.equal(out, ub * 2)
+
+
+def test_npbs_chain_lanes_bitwise(plans):
+    lanes, single, s = plans
+    g = torch.Generator(device="cpu").manual_seed(9)
+    cells = sum(n * n for n in SIZES)
+
+    def field(scale):
+        return (scale * torch.complex(torch.randn(cells, generator=g),
+                                      torch.randn(cells, generator=g))).to(torch.complex64).cuda()
+    u0, wf, wl = field(1.0), field(0.3), field(0.3)
+    for count in (1, 3):
+        ua, ub = u0.clone(), u0.clone()
+        lanes.npbs_step(ua, s, wf, wl, count=count)
+        single.npbs_step(ub, s, wf, wl, count=count)
+        torch.cuda.synchronize()
+        assert torch.equal(ua, ub)
