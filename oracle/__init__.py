@@ -247,6 +247,13 @@ def green_dirichlet(q, k0sq: float, eps: float) -> torch.Tensor:
     return idst2(dst2(q) / lam)
 
 
+def green_adjoint_dirichlet(q, k0sq: float, eps: float) -> torch.Tensor:
+    """G^H q = S^-1 (S q / conj(lambda)) (S^-1 S real symmetric up to scale)."""
+    q = as_c(q)
+    lam = dirichlet_eigs(q.shape[-1]).to(CDT) - complex(k0sq, eps)
+    return idst2(dst2(q) / lam.conj())
+
+
 def laplacian_dirichlet(u) -> torch.Tensor:
     """Five-point negative Laplacian with zero boundary values, h = 1/(n+1):
     (4 u_ij - u_i-1,j - u_i+1,j - u_i,j-1 - u_i,j+1) / h^2."""
@@ -408,7 +415,7 @@ def fgmres(k2, k0sq, eps, s, x0=None, restart: int = 30, sweeps: int = 4,
 # ---------------------------------------------------------------------------
 
 def unrolled_loss(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma",
-                  normalise: bool = False) -> torch.Tensor:
+                  normalise: bool = False, bc: str = "periodic") -> torch.Tensor:
     """ell = || W * (G s - (I - G V) u_K) ||^2 with u_{m+1} = u_m + gamma r(u_m).
 
     weight "gamma" uses W = gamma; "one" uses W = 1 (the residual of the
@@ -417,31 +424,41 @@ def unrolled_loss(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma",
     of L_dir, Sec. 4, and of L_bs^{l2}, Sec. 4.2).  With normalise=True the
     squared norm is divided by ||G s||^2 (W residuals) or ||s||^2
     (physical).  eps and k0^2 are constants; k2 and u0 may require grad.
+    bc="dirichlet" uses the five-point Dirichlet operators instead (the
+    Newton-state instance of the metric-matched loss, App. B Eq. nl_bs_loss,
+    with k^2 = 2 u_m).
     """
+    if bc == "periodic":
+        sweep, resid, grn, hel = cbs_sweep, cbs_residual, green, helmholtz
+    elif bc == "dirichlet":
+        sweep, resid, grn, hel = (cbs_sweep_dirichlet, cbs_residual_dirichlet, green_dirichlet,
+                                  helmholtz_dirichlet)
+    else:
+        raise ValueError(bc)
     u = as_c(u0) if not torch.is_tensor(u0) else u0
     for _ in range(steps):
-        u = cbs_sweep(k2, k0sq, eps, u, s)
+        u = sweep(k2, k0sq, eps, u, s)
     if weight == "physical":
-        r = as_c(s) - helmholtz(k2, u)
+        r = as_c(s) - hel(k2, u)
         den = as_c(s)
     else:
-        r = cbs_residual(k2, k0sq, eps, u, s)
+        r = resid(k2, k0sq, eps, u, s)
         if weight == "gamma":
             r = gamma(k2, k0sq, eps) * r
         elif weight != "one":
             raise ValueError(weight)
-        den = green(as_c(s), k0sq, eps)
+        den = grn(as_c(s), k0sq, eps)
     val = torch.sum(r.real ** 2 + r.imag ** 2)
     if normalise:
         val = val / torch.sum(den.real ** 2 + den.imag ** 2)
     return val
 
 
-def loss_and_grad(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma"):
+def loss_and_grad(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma", bc: str = "periodic"):
     """Returns (loss, dl/du0, dl/dk2) with PyTorch's complex-gradient
     convention dl/dRe + i dl/dIm, computed by autograd through the oracle."""
     k2t = as_c(k2).clone().requires_grad_(True)
     u0t = as_c(u0).clone().requires_grad_(True)
-    val = unrolled_loss(k2t, k0sq, eps, u0t, as_c(s), steps, weight)
+    val = unrolled_loss(k2t, k0sq, eps, u0t, as_c(s), steps, weight, bc=bc)
     gu, gk = torch.autograd.grad(val, (u0t, k2t))
     return float(val.detach()), gu, gk

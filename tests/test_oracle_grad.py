@@ -20,16 +20,27 @@ def _problem(n=8, layer=2, seed=0):
     return p, u0
 
 
-@pytest.mark.parametrize("weight", ["gamma", "one", "physical"])
-def test_loss_gradient_central_differences(weight):
+def _dirichlet_problem(n=7, seed=0):
+    # Newton-type Jacobian J = L_D - 2 diag(u_m): k^2 = 2 u_m real and smooth
+    rng = np.random.default_rng(seed)
+    k2 = (100.0 + 60.0 * S.gaussian_random_field(n, 2.0, rng)).astype(np.complex128)
+    p = S.Problem(n=n, layer=0, k2=k2, k0sq=float(0.5 * (k2.real.min() + k2.real.max())),
+                  source=S.random_field_c(n, rng))
+    return p, S.random_field_c(n, rng)
+
+
+@pytest.mark.parametrize("weight,bc", [("gamma", "periodic"), ("one", "periodic"),
+                                       ("physical", "periodic"), ("one", "dirichlet"),
+                                       ("physical", "dirichlet")])
+def test_loss_gradient_central_differences(weight, bc):
     # P11: central differences with h = 1e-3 on Re/Im u0 and Re/Im k^2.  The
     # loss is a high-degree polynomial in k^2, so the plain O(h^2) truncation
     # is ~1e-5 relative; Richardson extrapolation of D(h) and D(h/2) removes it
     # and the two then agree to ~1e-9.
-    p, u0 = _problem()
+    p, u0 = _problem() if bc == "periodic" else _dirichlet_problem()
     eps = O.choose_eps(p.k2, p.k0sq)
     steps = 3
-    val, gu, gk = O.loss_and_grad(p.k2, p.k0sq, eps, u0, p.source, steps, weight)
+    val, gu, gk = O.loss_and_grad(p.k2, p.k0sq, eps, u0, p.source, steps, weight, bc)
     h = 1e-3
     rng = np.random.default_rng(1)
 
@@ -38,8 +49,8 @@ def test_loss_gradient_central_differences(weight):
         d[y, x] = unit * hh
         return (float(fn(base + d)) - float(fn(base - d))) / (2 * hh)
 
-    f_u = lambda u: O.unrolled_loss(p.k2, p.k0sq, eps, u, p.source, steps, weight)
-    f_k = lambda k: O.unrolled_loss(k, p.k0sq, eps, u0, p.source, steps, weight)
+    f_u = lambda u: O.unrolled_loss(p.k2, p.k0sq, eps, u, p.source, steps, weight, bc=bc)
+    f_k = lambda k: O.unrolled_loss(k, p.k0sq, eps, u0, p.source, steps, weight, bc=bc)
     for _ in range(6):
         y, x = rng.integers(0, p.n, size=2)
         for unit in (1.0, 1j):
