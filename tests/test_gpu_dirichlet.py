@@ -1,6 +1,7 @@
 """GPU Dirichlet plans (five-point FD on the unit square, DST-I reference;
 App. C "Newton linear systems") against the FP64 oracle: apply, residual,
-physical residual, fused sweeps, stationary CBS, FGMRES and the NPBS step.
+physical residual, fused sweeps, stationary CBS, FGMRES, the NPBS step and the
+unrolled losses with their adjoint (the Newton-state metric-matched loss).
 Bars as elsewhere: FP32 plans 1e-5 relative (FP32 rounding of transforms of
 length 2(n+1)), FP64 plans 1e-12."""
 import math
@@ -158,3 +159,33 @@ def test_dirichlet_sizes_checked():
         _plan([np.ones((64, 64))], [64], cbs.CBS_C64)
     assert e.value.status == cbs.CBS_ERR_SIZE
     assert cbs.SUPPORTED_DIRICHLET == (7, 15, 31, 63, 95, 127, 143, 191, 255, 511)
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+@pytest.mark.parametrize("weight", ["one", "gamma", "physical"])
+def test_dirichlet_loss_and_adjoint_match_oracle(dtype, weight):
+    # Newton-state metric-matched loss (App. B, Eq. nl_bs_loss) and the
+    # physical one, K = 6 unrolled steps, gradients w.r.t. u0 and k^2
+    sizes = [31, 15]
+    k2, src, u0 = _media(sizes, 840)
+    plan = _plan(k2, sizes, dtype)
+    tdt = TDT[dtype]
+    us = [cbs.pack(u0, tdt)]
+    s = cbs.pack(src, tdt)
+    for _ in range(6):
+        x = us[-1].clone()
+        plan.sweep(x, s)
+        us.append(x)
+    loss, lam, grad = plan.loss_seed(us[-1], s, weight)
+    for m in range(5, -1, -1):
+        plan.adjoint_step(us[m], s, lam, lam, grad)
+    torch.cuda.synchronize()
+    tol = 1e-10 if dtype == cbs.CBS_C128 else 1e-4
+    for i, n in enumerate(sizes):
+        val, gu, gk = O.loss_and_grad(k2[i], plan.k0sq[i], plan.eps[i], u0[i], src[i], 6, weight,
+                                      bc="dirichlet")
+        el = abs(float(loss[i]) - val) / val
+        eu = rel_err(_unpack(lam, sizes)[i], gu)
+        ek = rel_err(_unpack(grad, sizes)[i], gk)
+        say(f"[dirichlet adjoint] dtype={dtype} weight={weight} n={n}: loss {el:.1e} du0 {eu:.1e} dk2 {ek:.1e}")
+        assert el <= tol and eu <= tol and ek <= tol
