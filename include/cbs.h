@@ -299,6 +299,10 @@ cbs_status cbs_autotune(cbs_plan plan, int32_t* tiles, void* stream);
  * size it applies to.  Synchronises the device. */
 cbs_status cbs_set_tile(cbs_plan plan, int n, int columns);
 
+/* Release a plan: waits for the plan's own streams (the lanes), then frees
+ * what cbs_setup allocated.  Work the caller queued on its own streams is
+ * the caller's to finish first; a caller-owned workspace may be reused once
+ * this returns.  A null plan is ignored. */
 void cbs_destroy(cbs_plan plan);
 const char* cbs_last_error(void);
 const char* cbs_version(void);

@@ -523,10 +523,18 @@ void drop_graphs(cbs_plan p) {
 
 void free_plan(cbs_plan p) {
   drop_graphs(p);
-  if (p->own_stream) hipStreamDestroy(p->own_stream);
+  if (p->own_stream) {
+    (void)hipStreamSynchronize(p->own_stream);
+    (void)hipStreamDestroy(p->own_stream);
+  }
   p->own_stream = nullptr;
   for (int l = 0; l < 2; ++l) {
-    if (p->lane_st[l]) hipStreamDestroy(p->lane_st[l]);
+    // the lanes may still run this plan's kernels: finish them before the
+    // plan's memory (or the caller's workspace) can be reused
+    if (p->lane_st[l]) {
+      (void)hipStreamSynchronize(p->lane_st[l]);
+      (void)hipStreamDestroy(p->lane_st[l]);
+    }
     if (p->ev_join[l]) hipEventDestroy(p->ev_join[l]);
     p->lane_st[l] = nullptr;
     p->ev_join[l] = nullptr;

@@ -189,3 +189,79 @@ def test_dirichlet_loss_and_adjoint_match_oracle(dtype, weight):
         ek = rel_err(_unpack(grad, sizes)[i], gk)
         say(f"[dirichlet adjoint] dtype={dtype} weight={weight} n={n}: loss {el:.1e} du0 {eu:.1e} dk2 {ek:.1e}")
         assert el <= tol and eu <= tol and ek <= tol
+
+
+def _tile_default(m):
+    # the column tile width compiled as default for transform length m
+    c = 2
+    while c * 2 <= 32 and c * 2 * m <= 2048 and m % (c * 2) == 0:
+        c *= 2
+    return c
+
+
+@pytest.mark.parametrize("which", ["half", "default", "double"])
+def test_dirichlet_tile_widths_and_autotune(which):
+    # column tiles over a length-2(n+1) transform, the last tile of an instance
+    # partial (n is odd): every compiled width, and the autotuner's pick, give
+    # the oracle's apply
+    sizes = [63, 127, 255, 511, 95, 143]
+    k2, src, u0 = _media(sizes, 850)
+    plan = _plan(k2, sizes, cbs.CBS_C64)
+    u = cbs.pack(u0, torch.complex64)
+    s = cbs.pack(src, torch.complex64)
+    refs = []
+    for i, n in enumerate(sizes):
+        v = O.potential(k2[i], plan.k0sq[i], plan.eps[i]) * O.as_c(u0[i]) + O.as_c(src[i])
+        refs.append(O.green_dirichlet(v, plan.k0sq[i], plan.eps[i]))
+    allowed = {}
+    for n in sizes:
+        c0 = _tile_default(2 * (n + 1))
+        allowed[n] = (c0 // 2, c0, c0 * 2)
+        c = {"half": c0 // 2, "default": c0, "double": c0 * 2}[which]
+        try:
+            plan.set_tile(c, n=n)
+        except cbs.CbsError as e:
+            assert e.status == cbs.CBS_ERR_ARG   # width not compiled for this length
+    for label in ("set", "autotuned"):
+        y = plan.apply(u, s)
+        torch.cuda.synchronize()
+        for i, n in enumerate(sizes):
+            e = rel_err(_unpack(y, sizes)[i], refs[i])
+            say(f"[dirichlet tiles] {which} {label} n={n}: {e:.1e}")
+            assert e <= TOL[cbs.CBS_C64]
+        if label == "set":
+            tiles = plan.autotune()
+            for n, c in zip(sizes, tiles):
+                assert c in allowed[n]
+
+
+def test_dirichlet_lanes_bitwise():
+    # 2,219,018 cells, above the 2^21 at which a batch splits into two lanes:
+    # lanes and one stream give bitwise the same sweeps and stationary solve
+    sizes = [511] * 8 + [255] * 2
+    assert sum(n * n for n in sizes) >= 1 << 21
+    k2, src, u0 = _media(sizes, 860)
+    # contrasts from weak to strong, so instances converge at different sweep
+    # counts and the work lists are compacted (the lanes rebuilt) on the way
+    rng = np.random.default_rng(861)
+    k2 = [100.0 + (4.0 + 6.0 * i) * S.gaussian_random_field(n, n / 8, rng) for i, n in enumerate(sizes)]
+    lanes = _plan(k2, sizes, cbs.CBS_C64)
+    single = _plan(k2, sizes, cbs.CBS_C64, lanes=False)
+    u = cbs.pack(u0, torch.complex64)
+    s = cbs.pack(src, torch.complex64)
+    ua, ub = u.clone(), u.clone()
+    na = lanes.sweep(ua, s, count=3, norms=True)
+    nb = single.sweep(ub, s, count=3, norms=True)
+    torch.cuda.synchronize()
+    assert torch.equal(ua, ub) and torch.equal(na, nb)
+    ua, ub = lanes.zeros(), single.zeros()
+    # the Born residual of these closed-cavity problems drops to ~1e-2 within
+    # ~100 sweeps and then decays slowly: a loose tolerance spreads the counts
+    ra = lanes.iterate(ua, s, max_sweeps=1500, rtol=1.5e-2, check_every=10)
+    rb = single.iterate(ub, s, max_sweeps=1500, rtol=1.5e-2, check_every=10)
+    say(f"[dirichlet lanes] sweeps {list(ra[0])}")
+    assert len(set(ra[0])) > 1
+    assert list(ra[0]) == list(rb[0]) and list(ra[1]) == list(rb[1]) and list(ra[2]) == list(rb[2])
+    assert torch.equal(ua, ub)
+    lanes.close()
+    single.close()
