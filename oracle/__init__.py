@@ -23,7 +23,9 @@ against the paper:
   * FGMRES (Saad 1993, cited in Sec. 5.1.3) on B u = G s with B = I - G V
     (Prop. 3.1) and a flexible right preconditioner of K CBS sweeps;
   * the metric-matched residual loss (Sec. 4.2) and its gradient by torch
-    autograd through this forward.
+    autograd through this forward;
+  * the convection-diffusion-reaction operators G_cdr, V_cdr, A_cdr and the
+    CDR metric-matched objective (App. C, "Convection-diffusion-reaction").
 
 Notation: the paper's eta is the damping called eps here.  Fields are
 (N, N) arrays indexed [y, x].
@@ -295,6 +297,147 @@ def cbs_iterate_dirichlet(k2, k0sq, eps, s, max_sweeps: int = 2500, rtol: float 
             return u, m, rel
         u = u + g * r
         m += 1
+
+
+# ---------------------------------------------------------------------------
+# Convection-diffusion-reaction (App. C, "Convection-diffusion-reaction")
+# ---------------------------------------------------------------------------
+#
+# L_cdr u = -div(kappa grad u) + v . grad u + sigma u with constant background
+# kappa0, v0 = (vx0, vy0), sigma0; L0 = -kappa0 Lap + v0 . grad + sigma0 and
+# V_cdr = L0 - L_cdr = div(dkappa grad) - dv . grad - dsigma.  On the
+# periodic grid every derivative is spectral: d/dx = F^-1 diag(i xi_x) F with
+# xi = 2 pi m / N on the signed index m of mode_index (Nyquist bin -N/2, as
+# for |xi|^2).  x is the second (column) axis of an (N, N) field, y the first.
+
+class CdrMedium:
+    """Coefficient fields (real (N, N) arrays) and background constants."""
+
+    def __init__(self, kappa, vx, vy, sigma, kappa0: float, vx0: float, vy0: float, sigma0: float):
+        self.kappa = torch.as_tensor(np.asarray(kappa), dtype=RDT)
+        self.vx = torch.as_tensor(np.asarray(vx), dtype=RDT)
+        self.vy = torch.as_tensor(np.asarray(vy), dtype=RDT)
+        self.sigma = torch.as_tensor(np.asarray(sigma), dtype=RDT)
+        self.kappa0, self.vx0, self.vy0, self.sigma0 = float(kappa0), float(vx0), float(vy0), float(sigma0)
+
+    @property
+    def n(self) -> int:
+        return self.kappa.shape[-1]
+
+
+def wavenumbers(n: int) -> torch.Tensor:
+    """xi = 2 pi m / N for DFT bin k, m = mode_index(k)."""
+    return 2.0 * math.pi * mode_index(n).to(RDT) / n
+
+
+def deriv_x(u) -> torch.Tensor:
+    """Spectral d/dx (along the second axis): F^-1 (i xi_x F u)."""
+    u = as_c(u)
+    xi = wavenumbers(u.shape[-1]).to(CDT)
+    return idft2(dft2(u) * (1j * xi)[None, :])
+
+
+def deriv_y(u) -> torch.Tensor:
+    """Spectral d/dy (along the first axis): F^-1 (i xi_y F u)."""
+    u = as_c(u)
+    xi = wavenumbers(u.shape[-1]).to(CDT)
+    return idft2(dft2(u) * (1j * xi)[:, None])
+
+
+def cdr_symbol(m: CdrMedium) -> torch.Tensor:
+    """L0 on DFT bin (ky, kx): kappa0 |xi|^2 + i v0 . xi + sigma0 (Eq. cdr_G_symbol's denominator)."""
+    xi = wavenumbers(m.n)
+    xx, yy = xi[None, :], xi[:, None]
+    return (m.kappa0 * (xx ** 2 + yy ** 2) + m.sigma0).to(CDT) + 1j * (m.vx0 * xx + m.vy0 * yy).to(CDT)
+
+
+def green_cdr(q, m: CdrMedium) -> torch.Tensor:
+    """G_cdr q = F^-1 (F q / L0(xi))  (Eq. cdr_G_symbol)."""
+    return idft2(dft2(as_c(q)) / cdr_symbol(m))
+
+
+def green_cdr_adjoint(q, m: CdrMedium) -> torch.Tensor:
+    """G_cdr^H q = F^-1 (F q / conj(L0(xi)))."""
+    return idft2(dft2(as_c(q)) / cdr_symbol(m).conj())
+
+
+def cdr_reference(u, m: CdrMedium) -> torch.Tensor:
+    """L0 u = -kappa0 Lap u + v0 . grad u + sigma0 u  (Eq. cdr_L0)."""
+    u = as_c(u)
+    return -m.kappa0 * (deriv_x(deriv_x(u)) + deriv_y(deriv_y(u))) \
+        + m.vx0 * deriv_x(u) + m.vy0 * deriv_y(u) + m.sigma0 * u
+
+
+def cdr_potential(u, m: CdrMedium) -> torch.Tensor:
+    """V_cdr u = div(dkappa grad u) - dv . grad u - dsigma u  (Eq. cdr_V)."""
+    u = as_c(u)
+    dk = (m.kappa - m.kappa0).to(CDT)
+    dvx, dvy = (m.vx - m.vx0).to(CDT), (m.vy - m.vy0).to(CDT)
+    ds = (m.sigma - m.sigma0).to(CDT)
+    ux, uy = deriv_x(u), deriv_y(u)
+    return deriv_x(dk * ux) + deriv_y(dk * uy) - (dvx * ux + dvy * uy) - ds * u
+
+
+def cdr_operator(u, m: CdrMedium) -> torch.Tensor:
+    """A_cdr u = -div(kappa grad u) + v . grad u + sigma u  (Eq. cdr_pde),
+    written from the PDE itself, not as L0 - V."""
+    u = as_c(u)
+    ux, uy = deriv_x(u), deriv_y(u)
+    k = m.kappa.to(CDT)
+    return -(deriv_x(k * ux) + deriv_y(k * uy)) + m.vx.to(CDT) * ux + m.vy.to(CDT) * uy \
+        + m.sigma.to(CDT) * u
+
+
+def cdr_apply(m: CdrMedium, u, s=None) -> torch.Tensor:
+    """G_cdr (V_cdr u + s)."""
+    q = cdr_potential(u, m)
+    if s is not None:
+        q = q + as_c(s)
+    return green_cdr(q, m)
+
+
+def cdr_residual(m: CdrMedium, u, s=None, rhs=None) -> torch.Tensor:
+    """Born residual G_cdr (V_cdr u + s) - u (+ rhs) = G_cdr (s - A_cdr u) (+ rhs)
+    (Eq. cdr_integral)."""
+    r = cdr_apply(m, u, s) - as_c(u)
+    if rhs is not None:
+        r = r + as_c(rhs)
+    return r
+
+
+def cdr_physical_residual(m: CdrMedium, u, s) -> torch.Tensor:
+    """s - A_cdr u."""
+    return as_c(s) - cdr_operator(u, m)
+
+
+def cdr_born_operator(m: CdrMedium, x) -> torch.Tensor:
+    """R x = (I - G_cdr V_cdr) x  (Eq. cdr_identity)."""
+    return as_c(x) - green_cdr(cdr_potential(x, m), m)
+
+
+def cdr_born_adjoint(m: CdrMedium, e) -> torch.Tensor:
+    """R^H e by reverse-mode autograd through R: the gradient (PyTorch's
+    convention d/dRe + i d/dIm) of Re <e, R x> with respect to x."""
+    e = as_c(e)
+    x = torch.zeros_like(e).requires_grad_(True)
+    val = torch.sum((e.conj() * cdr_born_operator(m, x)).real)
+    (g,) = torch.autograd.grad(val, x)
+    return g
+
+
+def cdr_loss(m: CdrMedium, x, r) -> torch.Tensor:
+    """|| G_cdr r - (I - G_cdr V_cdr) x ||^2, the residual of the metric-matched
+    objective L_bs^{R_cdr} (Eq. cdr_bs_loss) for a network output x = M(G r)."""
+    d = green_cdr(as_c(r), m) - cdr_born_operator(m, x)
+    return torch.sum(d.real ** 2 + d.imag ** 2)
+
+
+def cdr_loss_and_grad(m: CdrMedium, x, r):
+    """(loss, dl/dx) by autograd, PyTorch's complex-gradient convention."""
+    xt = as_c(x).clone().requires_grad_(True)
+    val = cdr_loss(m, xt, r)
+    (g,) = torch.autograd.grad(val, xt)
+    return float(val.detach()), g
 
 
 # ---------------------------------------------------------------------------
