@@ -155,6 +155,35 @@ cbs_status cbs_setup_ws(cbs_plan* plan, int batch, const int32_t* n, const void*
                         const double* k0sq, const double* eps, int dtype, int max_restart,
                         uint32_t flags, void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * cbs_setup_cdr -- plan for the periodic convection-diffusion-reaction
+ *   problem -div(kappa grad u) + v . grad u + sigma u = s (App. C,
+ *   "Convection-diffusion-reaction", Eqs. cdr_pde to cdr_G_symbol) with the
+ *   constant background L0 = -kappa0 Lap + v0 . grad + sigma0, G = L0^-1
+ *   (Fourier symbol 1/(kappa0 |xi|^2 + i v0 . xi + sigma0)) and
+ *   V = L0 - L = div(dkappa grad) - dv . grad - dsigma.  Derivatives are
+ *   spectral: d/dx = F^-1 diag(i xi_x) F, xi = 2 pi m / N on the signed mode
+ *   index m (Nyquist bin -N/2), x the fast (column) axis, h = 1.
+ *   kappa_sigma  device, packed complex fields in the plan's precision:
+ *                real part kappa, imaginary part sigma (copied)
+ *   velocity     device, packed complex fields: real part vx, imaginary vy
+ *   background   host double[4 * batch]: kappa0, vx0, vy0, sigma0 per
+ *                instance (finite; the symbol must not vanish on any bin,
+ *                else CBS_ERR_ILLCOND)
+ *   n            host int32[batch], grid sizes as for cbs_setup (periodic)
+ *   The coefficients are meant real; their imaginary parts are not used.
+ *   The plan owns its memory (no workspace form) and synchronises `stream`.
+ *   On such a plan cbs_apply, cbs_residual, cbs_helmholtz_residual (which
+ *   then returns s - A u with A the CDR operator above), cbs_born_adjoint,
+ *   cbs_plan_info (k0sq = kappa0, eps = sigma0), cbs_autotune, cbs_set_tile
+ *   and cbs_destroy apply; the CBS-step entry points (cbs_sweep,
+ *   cbs_iterate, fgmres_solve, cbs_npbs_step, cbs_adjoint_step,
+ *   cbs_loss_seed) return CBS_ERR_ARG.  Each apply or residual runs four
+ *   one-dimensional derivative passes and one transform pair.
+ */
+cbs_status cbs_setup_cdr(cbs_plan* plan, int batch, const int32_t* n, const void* kappa_sigma,
+                         const void* velocity, const double* background, int dtype, void* stream);
+
 /* Total packed cells (sum n[i]^2) and the per-instance k0^2 and eps in use
  * (host arrays of length batch, may be NULL). */
 cbs_status cbs_plan_info(cbs_plan plan, int64_t* cells, double* k0sq, double* eps);
@@ -265,6 +294,20 @@ cbs_status fgmres_solve(cbs_plan plan, void* u, const void* s, int restart, int 
  */
 cbs_status cbs_adjoint_step(cbs_plan plan, const void* u_m, const void* s, const void* lam_in,
                             void* lam_out, void* grad_k2, void* stream);
+
+/*
+ * cbs_born_adjoint -- out = R^H e with R = I - G V, the operator of the
+ *   metric-matched objective (Sec. 4.2; Prop. 3.1 for Helmholtz, Eq.
+ *   cdr_identity for convection-diffusion-reaction plans).  For the loss
+ *   l = || G s - R x ||^2 of a network output x its gradient is
+ *   dl/dx = -2 R^H (G s - R x), i.e. -2 cbs_born_adjoint of cbs_residual(x, s)
+ *   (PyTorch's convention d/dRe + i d/dIm).  Helmholtz and Dirichlet plans:
+ *   e - conj(V) G^H e (one transform pair); CDR plans: e - V^H G^H e with
+ *   V^H = Dx(dkappa Dx + dvx) + Dy(dkappa Dy + dvy) - dsigma (one transform
+ *   pair and four derivative passes).  e, out: device packed fields; out may
+ *   alias e.  Uses the plan's scratch fields, so calls on one plan serialise.
+ */
+cbs_status cbs_born_adjoint(cbs_plan plan, const void* e, void* out, void* stream);
 
 /*
  * cbs_loss_seed -- a residual loss of the iterate u_K, its adjoint seed

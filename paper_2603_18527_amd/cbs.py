@@ -43,6 +43,7 @@ SIGNATURES = {
     "cbs_setup": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp]),
     "cbs_setup_ws": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp,
                             ctypes.c_size_t, _vp]),
+    "cbs_setup_cdr": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "cbs_workspace_size": (_i32, [_i32, _vp, _i32, _i32, _u32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
@@ -53,6 +54,7 @@ SIGNATURES = {
     "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
     "fgmres_solve": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "cbs_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cbs_born_adjoint": (_i32, [_vp, _vp, _vp, _vp]),
     "cbs_loss_seed": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "cbs_autotune": (_i32, [_vp, _vp, _vp]),
     "cbs_set_tile": (_i32, [_vp, _i32, _i32]),
@@ -285,6 +287,12 @@ class Plan:
                                    _stream(stream)), allow_not_converged=True)
         return list(it), list(rel), list(stat)
 
+    def born_adjoint(self, e, out=None, stream=None):
+        """R^H e for R = I - G V (cbs_born_adjoint)."""
+        y = self.empty() if out is None else self._field(out, "out")
+        _check(load().cbs_born_adjoint(self._h, _ptr(self._field(e, "e")), _ptr(y), _stream(stream)))
+        return y
+
     def adjoint_step(self, u_m, s, lam_in, lam_out, grad_k2, stream=None):
         _check(load().cbs_adjoint_step(self._h, _ptr(self._field(u_m, "u_m")), _ptr(self._field(s, "s")),
                                        _ptr(self._field(lam_in, "lam_in")), _ptr(self._field(lam_out, "lam_out")),
@@ -309,6 +317,77 @@ class Plan:
 
     def set_tile(self, columns: int, n: int = 0):
         _check(load().cbs_set_tile(self._h, int(n), int(columns)))
+
+
+class CdrPlan(Plan):
+    """A batch of periodic convection-diffusion-reaction instances
+    -div(kappa grad u) + v . grad u + sigma u = s (cbs_setup_cdr).
+
+    kappa_sigma: packed complex tensor, real part kappa, imaginary part sigma;
+    velocity: packed complex tensor, real part vx, imaginary part vy (x is the
+    fast axis); background: per instance (kappa0, vx0, vy0, sigma0).  apply,
+    residual, born_adjoint and helmholtz_residual (here s - A u with the CDR
+    operator; also as physical_residual) run on it."""
+
+    def __init__(self, kappa_sigma: torch.Tensor, velocity: torch.Tensor, sizes: Sequence[int],
+                 background, dtype: int = CBS_C64, stream=None):
+        lib = load()
+        self.sizes = [int(n) for n in sizes]
+        self.batch = len(self.sizes)
+        self.dtype = dtype
+        self.tdtype = torch.complex64 if dtype == CBS_C64 else torch.complex128
+        self.cells = sum(n * n for n in self.sizes)
+        for name, t in (("kappa_sigma", kappa_sigma), ("velocity", velocity)):
+            if t.dtype != self.tdtype or t.numel() != self.cells or not t.is_cuda:
+                raise ValueError(f"{name} must be a packed CUDA tensor of the plan dtype")
+        bg = [tuple(float(v) for v in b) for b in _expand(background, self.batch)]
+        if any(len(b) != 4 for b in bg):
+            raise ValueError("background: (kappa0, vx0, vy0, sigma0) per instance")
+        n_arr = (ctypes.c_int32 * self.batch)(*self.sizes)
+        bg_arr = (ctypes.c_double * (4 * self.batch))(*[v for b in bg for v in b])
+        h = ctypes.c_void_p()
+        self.dirichlet = False
+        self._ws = None
+        _check(lib.cbs_setup_cdr(ctypes.byref(h), self.batch, n_arr, _ptr(kappa_sigma.contiguous()),
+                                 _ptr(velocity.contiguous()), bg_arr, dtype, _stream(stream)))
+        self._h = h
+        self.max_restart = 0
+        self.background = bg
+        self.k0sq = [b[0] for b in bg]
+        self.eps = [b[3] for b in bg]
+
+    def physical_residual(self, u, s, out=None, norms=True, store=True, stream=None):
+        """r = s - A u with the CDR operator, and per-instance sums |r|^2."""
+        return self.helmholtz_residual(u, s, out=out, norms=norms, store=store, stream=stream)
+
+
+class MetricMatchedLoss(torch.autograd.Function):
+    """ell_b = || G s - (I - G V) x ||^2 per instance: the residual of the
+    metric-matched objective (Sec. 4.2; Eq. cdr_bs_loss for CDR plans) for a
+    network output x (with s the residual being preconditioned).  Backward:
+    dl/dx = -2 R^H (G s - R x) by cbs_born_adjoint (PyTorch's convention)."""
+
+    @staticmethod
+    def forward(ctx, x, plan, s):
+        r, n2 = plan.residual(x.detach().contiguous(), s)
+        ctx.plan = plan
+        ctx.r = r
+        return n2
+
+    @staticmethod
+    def backward(ctx, gout):
+        plan, r = ctx.plan, ctx.r
+        g = plan.born_adjoint(r)
+        scale = torch.repeat_interleave(gout.to(torch.float64),
+                                        torch.tensor([n * n for n in plan.sizes], device=gout.device))
+        gx = g * (-2.0 * scale).to(g.real.dtype)
+        ctx.plan = None
+        return gx, None, None
+
+
+def metric_matched_loss(x, plan, s):
+    """Per-instance || G s - (I - G V) x ||^2 (float64), differentiable in x."""
+    return MetricMatchedLoss.apply(x, plan, s)
 
 
 _WEIGHTS = {"one": 0, "gamma": 1, "physical": 2}

@@ -158,6 +158,9 @@ struct cbs_plan_s {
   hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
   bool one_stream = false;           // CBS_FLAG_ONE_STREAM
   bool dirichlet = false;            // CBS_FLAG_DIRICHLET: DST-I instances
+  bool cdr = false;                  // convection-diffusion-reaction plan (cbs_setup_cdr)
+  void* d_k2b = nullptr;             // CDR: (dvx, dvy) per cell, operator precision
+  std::vector<double> vx0, vy0;      // CDR background velocity per instance
   double* d_mu = nullptr;            // Dirichlet eigenvalue table (all transform lengths)
   // FFT length that carries an instance of size n
   int tlen(int n) const { return dirichlet ? dst_len(n) : n; }
@@ -178,7 +181,9 @@ void build_items(cbs_plan p) {
     d.n = p->n[i];
     d.k0sq = p->k0sq.empty() ? 0.0 : p->k0sq[i];
     d.eps = p->eps.empty() ? 1.0 : p->eps[i];
-    d.kind = p->dirichlet ? KIND_DIRICHLET : KIND_PERIODIC;
+    d.kind = p->dirichlet ? KIND_DIRICHLET : (p->cdr ? KIND_CDR : KIND_PERIODIC);
+    d.vx0 = p->vx0.empty() ? 0.0 : p->vx0[i];
+    d.vy0 = p->vy0.empty() ? 0.0 : p->vy0[i];
     const int m = p->tlen(d.n);
     const int rpw = row_rpw(m);
     d.rpw = rpw;
@@ -1072,6 +1077,135 @@ cbs_status npbs_impl(cbs_plan p, void* u, const void* s, const void* wf, const v
   return CBS_OK;
 }
 
+// ---- convection-diffusion-reaction plans ---------------------------------------------------
+
+template <typename R>
+void launch_cdr_cols(cbs_plan p, const Params<R>& q, hipStream_t st) {
+  const cbs_plan_s::Items it = p->view->all();
+  Params<R> c = q;
+  if constexpr (sizeof(R) == 4) {
+    c.items = it.cols32;
+    launch_col_cdr(it.ncols32, p->col_lds32, st, c);
+  } else {
+    c.items = it.cols64;
+    launch_col_cdr(it.ncols64, p->col_lds64, st, c);
+  }
+}
+
+// out = V_cdr u + s (adj = 0) or out = e - V_cdr^H g (adj = 1; u = g, s = e):
+// four 1D derivative passes, scratch d_c (dx), d_e (dy), d_t (partial sum).
+// out may be d_t itself, or alias s.
+template <typename R>
+cbs_status cdr_vpass(cbs_plan p, const cpx<R>* u, const cpx<R>* s, cpx<R>* out, int adj, hipStream_t st) {
+  cpx<R>* dx = static_cast<cpx<R>*>(p->d_c);
+  cpx<R>* dy = static_cast<cpx<R>*>(p->d_e);
+  cpx<R>* t = static_cast<cpx<R>*>(p->d_t);
+  Params<R> q = base_params<R>(p);
+  q.k2b = static_cast<const cpx<R>*>(p->d_k2b);
+  q.cdr_adj = adj;
+  q.partials = nullptr;
+  q.items = p->view->rows;
+  const int nrow = p->view->nrows;
+  Params<R> a = q;  // dx = Dx u
+  a.pro = CPRO_A;
+  a.a = u;
+  a.epi = CEPI_STORE;
+  a.out = dx;
+  launch_row_cdr(nrow, st, a);
+  a.out = dy;  // dy = Dy u
+  launch_cdr_cols(p, a, st);
+  Params<R> c = q;  // t = Dx(dkappa dx [+ dvx g]) + q
+  c.pro = CPRO_WX;
+  c.a = dx;
+  c.b = dy;
+  c.u = u;
+  c.s = s;
+  c.epi = CEPI_Q;
+  c.out = t;
+  launch_row_cdr(nrow, st, c);
+  Params<R> d = q;  // out = t + Dy(dkappa dy [+ dvy g])  (adjoint: e - ...)
+  d.pro = CPRO_WY;
+  d.b = dy;
+  d.u = u;
+  d.s = s;
+  d.rhs = t;
+  d.epi = CEPI_ACC;
+  d.out = out;
+  launch_cdr_cols(p, d, st);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+// y = G (V u + s) (epi EPI_STORE) or r = G (V u + s) - u + rhs (EPI_RESID)
+template <typename R>
+cbs_status cdr_green_impl(cbs_plan p, const void* u, const void* s, const void* rhs, void* out,
+                          int epi, double* norm2, hipStream_t st) {
+  cpx<R>* t = static_cast<cpx<R>*>(p->d_t);
+  Params<R> q = base_params<R>(p);
+  if (u) {
+    CHK(cdr_vpass<R>(p, static_cast<const cpx<R>*>(u), static_cast<const cpx<R>*>(s), t, 0, st));
+    q.pro = PRO_A;
+    q.a = t;
+  } else {  // V 0 = 0: transform s itself (PRO_VU_S with u = NULL; s NULL reads as zero)
+    q.s = static_cast<const cpx<R>*>(s);
+  }
+  q.sym = SYM_CDR;
+  q.epi = epi;
+  q.u = static_cast<const cpx<R>*>(u);
+  q.rhs = static_cast<const cpx<R>*>(rhs);
+  q.out = static_cast<cpx<R>*>(out);
+  if (epi == EPI_STORE) q.partials = nullptr;
+  CHK(run_pipeline(p, q, st));
+  if (norm2) {
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
+    HIPCHK(hipGetLastError());
+  }
+  return CBS_OK;
+}
+
+// r = s - A u = (V u + s) - L0 u
+template <typename R>
+cbs_status cdr_physical_impl(cbs_plan p, const void* u, const void* s, void* r, double* norm2,
+                             hipStream_t st) {
+  cpx<R>* t = static_cast<cpx<R>*>(p->d_t);
+  CHK(cdr_vpass<R>(p, static_cast<const cpx<R>*>(u), static_cast<const cpx<R>*>(s), t, 0, st));
+  Params<R> q = base_params<R>(p);
+  q.pro = PRO_A;
+  q.a = static_cast<const cpx<R>*>(u);
+  q.sym = SYM_CDR_NEG_L0;
+  q.epi = EPI_RESID;  // -L0 u - 0 + t
+  q.u = nullptr;
+  q.rhs = t;
+  q.out = static_cast<cpx<R>*>(r);
+  CHK(run_pipeline(p, q, st));
+  if (norm2) {
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
+    HIPCHK(hipGetLastError());
+  }
+  return CBS_OK;
+}
+
+// out = R^H e for R = I - G V: e - V^H G^H e
+template <typename R>
+cbs_status born_adjoint_impl(cbs_plan p, const void* e, void* out, hipStream_t st) {
+  Params<R> q = base_params<R>(p);
+  q.pro = PRO_A;
+  q.a = static_cast<const cpx<R>*>(e);
+  q.partials = nullptr;
+  if (!p->cdr) {  // V is pointwise: the epilogue applies e - conj(V) z
+    q.sym = SYM_GREEN_CONJ;
+    q.epi = EPI_BORN_ADJ;
+    q.out = static_cast<cpx<R>*>(out);
+    return run_pipeline(p, q, st);
+  }
+  cpx<R>* g = inter_of<R>(p);  // G^H e, written over the spectral buffer it came from
+  q.sym = SYM_CDR_CONJ;
+  q.epi = EPI_STORE;
+  q.out = g;
+  CHK(run_pipeline(p, q, st));
+  return cdr_vpass<R>(p, g, static_cast<const cpx<R>*>(e), static_cast<cpx<R>*>(out), 1, st);
+}
+
 // ---- adjoint -------------------------------------------------------------------------------
 
 template <typename R>
@@ -1225,6 +1359,7 @@ std::vector<std::pair<void**, size_t>> buffer_requests(cbs_plan p) {
     req.push_back({&p->d_k2, cells * 8});
     req.push_back({&p->d_inter, cells * 8});
   }
+  if (p->cdr) req.push_back({&p->d_k2b, cells * oe});
   if (p->max_restart > 0) {
     const size_t m = size_t(p->max_restart);
     req.push_back({reinterpret_cast<void**>(&p->d_vbasis), cells * 16 * (m + 1)});
@@ -1249,9 +1384,17 @@ size_t request_bytes(const std::vector<std::pair<void**, size_t>>& req) {
   return total;
 }
 
+// Convection-diffusion-reaction setup data: the (vx, vy) field and the
+// background constants (kappa0, vx0, vy0, sigma0) per instance.
+struct CdrInit {
+  const void* velocity;
+  const double* background;
+};
+
 cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2,
                       const double* k0sq, const double* eps, int dtype, int max_restart,
-                      uint32_t flags, void* ws, size_t ws_bytes, void* stream);
+                      uint32_t flags, void* ws, size_t ws_bytes, void* stream,
+                      const CdrInit* cdr = nullptr);
 
 }  // namespace
 
@@ -1277,6 +1420,49 @@ cbs_status cbs_setup_ws(cbs_plan* out, int batch, const int32_t* n, const void* 
                     workspace_bytes, stream);
 }
 
+cbs_status cbs_setup_cdr(cbs_plan* out, int batch, const int32_t* n, const void* kappa_sigma,
+                         const void* velocity, const double* background, int dtype, void* stream) {
+  if (!out) return fail(CBS_ERR_ARG, "plan pointer is NULL");
+  *out = nullptr;
+  if (!kappa_sigma || !velocity || !background)
+    return fail(CBS_ERR_ARG, "kappa_sigma, velocity or background is NULL");
+  CHK(check_setup_args(batch, n, dtype, 0, 0));
+  for (int i = 0; i < batch; ++i) {
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(background[4 * i + k]))
+        return fail(CBS_ERR_ARG, "background constants must be finite (instance " + std::to_string(i) + ")");
+    // G_cdr needs L0(xi) = kappa0 |xi|^2 + sigma0 + i v0 . xi != 0 on every bin
+    const double k0 = background[4 * i], vx = background[4 * i + 1], vy = background[4 * i + 2],
+                 s0 = background[4 * i + 3];
+    const int nn = n[i];
+    const double h = 2.0 * M_PI / nn;
+    double lo = INFINITY, hi = 0.0;
+    for (int a = 0; a < nn; ++a) {
+      const double xy = (a >= nn / 2 ? a - nn : a) * h;
+      for (int b = 0; b < nn; ++b) {
+        const double xx = (b >= nn / 2 ? b - nn : b) * h;
+        const double re = k0 * (xx * xx + xy * xy) + s0, im = vx * xx + vy * xy;
+        const double m = std::sqrt(re * re + im * im);
+        lo = std::min(lo, m);
+        hi = std::max(hi, m);
+      }
+    }
+    if (!(lo > 1e-12 * hi))
+      return fail(CBS_ERR_ILLCOND, "instance " + std::to_string(i) +
+                                       ": the background symbol kappa0|xi|^2 + sigma0 + i v0.xi vanishes");
+  }
+  CdrInit c{velocity, background};
+  return setup_impl(out, batch, n, kappa_sigma, nullptr, nullptr, dtype, 0, CBS_FLAG_ONE_STREAM, nullptr, 0,
+                    stream, &c);
+}
+
+cbs_status cbs_born_adjoint(cbs_plan p, const void* e, void* out, void* stream) {
+  if (!p || !e || !out) return fail(CBS_ERR_ARG, "plan, e or out is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return born_adjoint_impl<float>(p, e, out, st);
+  return born_adjoint_impl<double>(p, e, out, st);
+}
+
 cbs_status cbs_workspace_size(int batch, const int32_t* n, int dtype, int max_restart,
                               uint32_t flags, size_t* bytes) {
   if (!bytes) return fail(CBS_ERR_ARG, "bytes is NULL");
@@ -1294,7 +1480,7 @@ namespace {
 
 cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2,
                       const double* k0sq, const double* eps, int dtype, int max_restart,
-                      uint32_t flags, void* ws, size_t ws_bytes, void* stream) {
+                      uint32_t flags, void* ws, size_t ws_bytes, void* stream, const CdrInit* cdr) {
   if (!out) return fail(CBS_ERR_ARG, "plan pointer is NULL");
   *out = nullptr;
   if (!k2) return fail(CBS_ERR_ARG, "k2 is NULL");
@@ -1308,6 +1494,7 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   cbs_plan p = new cbs_plan_s();
+  p->cdr = cdr != nullptr;
   init_layout(p, batch, n, dtype, max_restart, flags);
 
   auto bail = [&](cbs_status s, const std::string& m) {
@@ -1390,6 +1577,37 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
   BAILCHK(hipMemcpyAsync(p->d_tw32, t32.data(), kTwTotal * sizeof(cpx<float>), hipMemcpyHostToDevice, st));
   BAILCHK(hipMemcpyAsync(p->d_row_items, p->row_items.data(), p->row_items.size() * sizeof(int2),
                          hipMemcpyHostToDevice, st));
+  if (cdr) {
+    // (kappa, sigma) and (vx, vy) -> deviations from the background, in the
+    // operator precision only (no FP64 refinement runs on these plans)
+    const size_t oe = p->op_elem();
+    BAILCHK(hipMemcpyAsync(dtype == CBS_C64 ? p->d_k2 : static_cast<void*>(p->d_k2_64), k2, cells * oe,
+                           hipMemcpyDeviceToDevice, st));
+    BAILCHK(hipMemcpyAsync(p->d_k2b, cdr->velocity, cells * oe, hipMemcpyDeviceToDevice, st));
+    p->k0sq.assign(batch, 0.0);
+    p->eps.assign(batch, 0.0);
+    p->vx0.assign(batch, 0.0);
+    p->vy0.assign(batch, 0.0);
+    for (int i = 0; i < batch; ++i) {
+      p->k0sq[i] = cdr->background[4 * i];
+      p->vx0[i] = cdr->background[4 * i + 1];
+      p->vy0[i] = cdr->background[4 * i + 2];
+      p->eps[i] = cdr->background[4 * i + 3];
+    }
+    build_items(p);
+    cbs_status us = upload_items(p, st);
+    if (us != CBS_OK) { std::string m = g_err; return bail(us, m); }
+    const int nrow = int(p->row_items.size());
+    if (dtype == CBS_C64)
+      launch_cdr_split(nrow, st, p->d_inst, p->d_row_items, static_cast<cpx<float>*>(p->d_k2),
+                       static_cast<cpx<float>*>(p->d_k2b));
+    else
+      launch_cdr_split(nrow, st, p->d_inst, p->d_row_items, p->d_k2_64, static_cast<cpx<double>*>(p->d_k2b));
+    BAILCHK(hipGetLastError());
+    BAILCHK(hipStreamSynchronize(st));
+    *out = p;
+    return CBS_OK;
+  }
   if (dtype == CBS_C64) {
     BAILCHK(hipMemcpyAsync(p->d_k2, k2, cells * 8, hipMemcpyDeviceToDevice, st));
     launch_widen_all(st, static_cast<const cpx<float>*>(p->d_k2), p->d_k2_64, cells);
@@ -1476,6 +1694,10 @@ cbs_status cbs_apply(cbs_plan p, const void* u, const void* s, void* y, void* st
   if (!p || !y) return fail(CBS_ERR_ARG, "plan or y is NULL");
   if (y == u || y == s) return fail(CBS_ERR_ARG, "y must not alias u or s");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->cdr) {
+    if (p->dtype == CBS_C64) return cdr_green_impl<float>(p, u, s, nullptr, y, EPI_STORE, nullptr, st);
+    return cdr_green_impl<double>(p, u, s, nullptr, y, EPI_STORE, nullptr, st);
+  }
   if (p->dtype == CBS_C64) {
     Params<float> q = base_params<float>(p);
     q.u = static_cast<const cpx<float>*>(u);
@@ -1497,6 +1719,10 @@ cbs_status cbs_residual(cbs_plan p, const void* u, const void* s, const void* rh
   if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
   if (r && (r == u || r == s)) return fail(CBS_ERR_ARG, "r must not alias u or s");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->cdr) {
+    if (p->dtype == CBS_C64) return cdr_green_impl<float>(p, u, s, rhs, r, EPI_RESID, norm2, st);
+    return cdr_green_impl<double>(p, u, s, rhs, r, EPI_RESID, norm2, st);
+  }
   if (p->dtype == CBS_C64) return residual_impl<float>(p, u, s, rhs, r, norm2, st);
   return residual_impl<double>(p, u, s, rhs, r, norm2, st);
 }
@@ -1506,6 +1732,10 @@ cbs_status cbs_helmholtz_residual(cbs_plan p, const void* u, const void* s, void
   if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
   if (r && (r == u || r == s)) return fail(CBS_ERR_ARG, "r must not alias u or s");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->cdr) {
+    if (p->dtype == CBS_C64) return cdr_physical_impl<float>(p, u, s, r, norm2, st);
+    return cdr_physical_impl<double>(p, u, s, r, norm2, st);
+  }
   if (p->dtype == CBS_C64) {
     Params<float> q = base_params<float>(p);
     q.u = static_cast<const cpx<float>*>(u);
@@ -1534,6 +1764,7 @@ cbs_status cbs_helmholtz_residual(cbs_plan p, const void* u, const void* s, void
 
 cbs_status cbs_npbs_step(cbs_plan p, void* u, const void* s, const void* wf, const void* wloc,
                          int count, void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "cbs_npbs_step is not available for convection-diffusion-reaction plans");
   if (!p || !u || !wf) return fail(CBS_ERR_ARG, "plan, u or wf is NULL");
   if (u == s || u == wf || u == wloc) return fail(CBS_ERR_ARG, "u must not alias s, wf or wloc");
   if (count < 1 || count > 1000000) return fail(CBS_ERR_ARG, "count must be in [1, 1e6]");
@@ -1543,6 +1774,7 @@ cbs_status cbs_npbs_step(cbs_plan p, void* u, const void* s, const void* wf, con
 }
 
 cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm2, void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "cbs_sweep is not available for convection-diffusion-reaction plans");
   if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
   if (count < 1 || count > 1000000) return fail(CBS_ERR_ARG, "count must be in [1, 1e6]");
@@ -1554,6 +1786,7 @@ cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm
 cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
                        int check_every, int stop, int32_t* iters, double* relres, int32_t* status,
                        int use_graph, void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "cbs_iterate is not available for convection-diffusion-reaction plans");
   if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
   if (stop != CBS_STOP_BORN && stop != CBS_STOP_PHYSICAL)
     return fail(CBS_ERR_ARG, "stop must be CBS_STOP_BORN or CBS_STOP_PHYSICAL");
@@ -1583,6 +1816,7 @@ cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, doubl
 cbs_status fgmres_solve(cbs_plan p, void* u, const void* s, int restart, int inner_sweeps,
                         int max_iters, double rtol, int32_t* iters, double* relres,
                         int32_t* status, void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "fgmres_solve is not available for convection-diffusion-reaction plans");
   if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
   if (restart < 1 || inner_sweeps < 1 || inner_sweeps > 1000 || max_iters < 0 || !(rtol >= 0.0))
@@ -1598,6 +1832,7 @@ cbs_status fgmres_solve(cbs_plan p, void* u, const void* s, int restart, int inn
 
 cbs_status cbs_adjoint_step(cbs_plan p, const void* u_m, const void* s, const void* lam_in,
                             void* lam_out, void* grad_k2, void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "cbs_adjoint_step is not available for convection-diffusion-reaction plans");
   if (!p || !u_m || !lam_in || !lam_out || !grad_k2) return fail(CBS_ERR_ARG, "NULL argument");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == CBS_C64) return adjoint_impl<float>(p, u_m, s, lam_in, lam_out, grad_k2, st);
@@ -1606,6 +1841,7 @@ cbs_status cbs_adjoint_step(cbs_plan p, const void* u_m, const void* s, const vo
 
 cbs_status cbs_loss_seed(cbs_plan p, const void* u_k, const void* s, int weight_gamma, double* loss,
                          void* lam_out, void* grad_k2, void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "cbs_loss_seed is not available for convection-diffusion-reaction plans");
   if (!p || !u_k || !lam_out || !grad_k2) return fail(CBS_ERR_ARG, "NULL argument");
   if (weight_gamma < 0 || weight_gamma > 2)
     return fail(CBS_ERR_ARG, "weight must be 0 (W = 1), 1 (W = gamma) or 2 (physical residual)");
@@ -1649,10 +1885,12 @@ cbs_status cbs_autotune(cbs_plan p, int32_t* tiles, void* stream) {
       auto launch = [&]() {
         if (p->dtype == CBS_C64) {
           Params<float> q = base_params<float>(p);
+          if (p->cdr) q.sym = SYM_CDR;
           q.items = p->d_col_items32 + lo;
           launch_col(int(hi - lo), p->col_lds32, st, q);
         } else {
           Params<double> q = base_params<double>(p);
+          if (p->cdr) q.sym = SYM_CDR;
           q.items = p->d_col_items64 + lo;
           launch_col(int(hi - lo), p->col_lds64, st, q);
         }

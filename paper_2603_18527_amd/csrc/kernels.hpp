@@ -154,6 +154,11 @@ __device__ __forceinline__ double epilogue(const Params<R>& p, const InstDesc& d
       p.out[i] = p.u[i] + z + cmul(ld_or_zero(p.b, i), r);
       return 0.0;
     }
+    case EPI_BORN_ADJ: {
+      const Coef<R> c = coef(p, d, i);
+      p.out[i] = p.a[i] - cmulc(c.v, z);
+      return 0.0;
+    }
     default: {  // EPI_LAP: physical residual s - A u with A u = -Lap u - k^2 u
       const cpx<R> u = ld_or_zero(p.u, i);
       const cpx<R> au = z - cmul(p.k2[i], u);
@@ -381,6 +386,26 @@ __device__ __forceinline__ cpx<R> symbol_factor(int n, int k1, int k2, double k0
   return cpx<R>{a * sc, (mode == SYM_GREEN ? e : -e) * sc};
 }
 
+// CDR symbol on DFT bin (k1 = row bin -> xi_y, k2 = column bin -> xi_x), with
+// the 1/N^2 of the inverse transform.  L0 = a + i b, a = kappa0 |xi|^2 +
+// sigma0 and b = v0 . xi formed in FP64.
+template <typename R>
+__device__ __forceinline__ cpx<R> cdr_symbol_factor(int n, int k1, int k2, const InstDesc& d, int mode) {
+  const int my = k1 >= n / 2 ? k1 - n : k1;
+  const int mx = k2 >= n / 2 ? k2 - n : k2;
+  const double h = 6.283185307179586476925287 / double(n);
+  const double xy = double(my) * h, xx = double(mx) * h;
+  const R a = R(d.k0sq * (xx * xx + xy * xy) + d.eps);
+  const R b = R(d.vx0 * xx + d.vy0 * xy);
+  const R inv_n2 = R(1.0 / (double(n) * double(n)));
+  if (mode == SYM_CDR_NEG_L0) return cpx<R>{-a * inv_n2, -b * inv_n2};
+  R sc;
+  if constexpr (sizeof(R) == 4) sc = inv_n2 * __builtin_amdgcn_rcpf(a * a + b * b);
+  else sc = inv_n2 / (a * a + b * b);
+  // 1/L0 = (a - i b)/|L0|^2 ; 1/conj(L0) = (a + i b)/|L0|^2
+  return cpx<R>{a * sc, (mode == SYM_CDR ? -b : b) * sc};
+}
+
 // Column tile: C columns of one instance.  Thread tid works on column tid % C
 // (so the C threads of a row segment read or write C neighbouring elements)
 // and butterfly slot tid / C.  Between passes the tile sits in LDS
@@ -399,6 +424,7 @@ __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, 
   auto sym = [&](int e, cpx<R> v) {
     if (p.sym == SYM_TABLE)  // tabulated weights; 1/N^2 of the inverse transform
       return cscale(cmul(v, p.table[cbase + (long long)e * N]), R(1.0 / (double(N) * double(N))));
+    if (p.sym >= SYM_CDR) return cmul(v, cdr_symbol_factor<R>(N, e, kcol, d, p.sym));
     return cmul(v, symbol_factor<R>(N, e, kcol, d.k0sq, d.eps, p.sym));
   };
   auto st2 = [&](int e, cpx<R> v) { p.inter[cbase + (long long)e * N] = v; };

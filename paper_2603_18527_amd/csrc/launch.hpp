@@ -20,6 +20,16 @@ void launch_row_dst(int mode, int grid, hipStream_t st, const Params<float>& p);
 void launch_row_dst(int mode, int grid, hipStream_t st, const Params<double>& p);
 void launch_col_dst(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
 void launch_col_dst(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
+// convection-diffusion-reaction plans: 1D derivative passes (row: d/dx,
+// column: d/dy) and the coefficient split at setup
+void launch_row_cdr(int grid, hipStream_t st, const Params<float>& p);
+void launch_row_cdr(int grid, hipStream_t st, const Params<double>& p);
+void launch_col_cdr(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
+void launch_col_cdr(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
+void launch_cdr_split(int grid, hipStream_t st, const InstDesc* inst, const int2* items, cpx<float>* c1,
+                      cpx<float>* c2);
+void launch_cdr_split(int grid, hipStream_t st, const InstDesc* inst, const int2* items, cpx<double>* c1,
+                      cpx<double>* c2);
 void launch_pointwise(int grid, hipStream_t st, const PwParams<float>& p);
 void launch_pointwise(int grid, hipStream_t st, const PwParams<double>& p);
 void launch_zupdate(int grid, hipStream_t st, const KryParams& k, const cpx<float>* z, cpx<double>* x);

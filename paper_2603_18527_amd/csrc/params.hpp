@@ -20,7 +20,7 @@ __host__ __device__ constexpr int row_rpw(int n) {
 // Instance kinds: periodic N x N grid (FFT, App. D) or the n x n interior of
 // a unit square with homogeneous Dirichlet boundaries (five-point FD, DST-I,
 // App. C "Newton linear systems").
-enum InstKind { KIND_PERIODIC = 0, KIND_DIRICHLET = 1 };
+enum InstKind { KIND_PERIODIC = 0, KIND_DIRICHLET = 1, KIND_CDR = 2 };
 
 // Length of the FFT that carries a DST-I of length n (odd extension).
 __host__ __device__ constexpr int dst_len(int n) { return 2 * (n + 1); }
@@ -34,12 +34,24 @@ struct InstDesc {
   int ctile64;
   int kind;       // InstKind
   int rpw;        // rows per row work item
-  double k0sq;
-  double eps;
+  double k0sq;    // Helmholtz: k0^2; CDR: kappa0
+  double eps;     // Helmholtz: eta; CDR: sigma0
+  double vx0, vy0;  // CDR: background velocity (x = fast axis), zero otherwise
 };
 
 enum Pro { PRO_VU_S = 0, PRO_CONJG_A = 1, PRO_SEED = 2, PRO_U = 3, PRO_A = 4 };
-enum Sym { SYM_GREEN = 0, SYM_GREEN_CONJ = 1, SYM_LAP = 2, SYM_TABLE = 3 };
+// SYM_CDR*: convection-diffusion-reaction plans, L0(xi) = kappa0 |xi|^2 +
+// i v0 . xi + sigma0: 1/L0, 1/conj(L0) and -L0 (each with the 1/N^2 of the
+// inverse transform)
+enum Sym {
+  SYM_GREEN = 0,
+  SYM_GREEN_CONJ = 1,
+  SYM_LAP = 2,
+  SYM_TABLE = 3,
+  SYM_CDR = 4,
+  SYM_CDR_CONJ = 5,
+  SYM_CDR_NEG_L0 = 6
+};
 enum Epi {
   EPI_STORE = 0,
   EPI_RESID = 1,
@@ -49,8 +61,13 @@ enum Epi {
   EPI_SEED = 5,
   EPI_LAP = 6,
   EPI_PHYS_SEED = 7,
-  EPI_NPBS = 8
+  EPI_NPBS = 8,
+  EPI_BORN_ADJ = 9  // out = a - conj(V) z: R^H a for R = I - G V, z = G^H a
 };
+// Prologue / epilogue of the CDR derivative passes (the combinations are
+// listed with the kernels)
+enum CdrPro { CPRO_A = 0, CPRO_WX = 1, CPRO_WY = 2 };
+enum CdrEpi { CEPI_STORE = 0, CEPI_Q = 1, CEPI_ACC = 2 };
 // Instance masks: which status values let an instance run.
 enum MaskMode { MASK_RUNNING = 0, MASK_NOT_FINAL = 1, MASK_NONZERO = 2 };
 enum InstStatus { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_DIVERGED = 3, ST_PENDING = 4 };
@@ -95,6 +112,10 @@ struct Params {
   IterState chk;
   int check;
   int dst;  // nonzero: Dirichlet plan (DST-I kernels)
+  // convection-diffusion-reaction passes: k2 holds (dkappa, dsigma), k2b
+  // (dvx, dvy); cdr_adj selects the adjoint combination
+  const cpx<R>* k2b;
+  int cdr_adj;
 };
 
 

@@ -267,8 +267,50 @@ def newton_batch(count: int = 100, n: int = 63, seed_config: int = 6, amplitude:
     return out
 
 
+@dataclasses.dataclass
+class CdrProblem:
+    """One convection-diffusion-reaction instance: real coefficient fields,
+    background constants (kappa0, vx0, vy0, sigma0) and a source."""
+    n: int
+    kappa: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+    sigma: np.ndarray
+    background: tuple
+    source: np.ndarray
+
+
+def cdr_problem(n: int, rng: np.random.Generator, ell: Optional[float] = None,
+                kappa_range=(0.5, 1.5), v_mean=(0.4, -0.3), v_amp: float = 0.3,
+                sigma_range=(0.25, 0.75)) -> CdrProblem:
+    """Smooth random coefficients (periodic Gaussian random fields, correlation
+    n / 16 cells unless given): diffusivity and reaction in the given ranges,
+    velocity = v_mean + v_amp * (field in [-1, 1]) per component; background =
+    the coefficient means; complex random source."""
+    ell = max(2.0, n / 16.0) if ell is None else ell
+    unit = lambda: minmax_map(gaussian_random_field(n, ell, rng), -1.0, 1.0)
+    kappa = 0.5 * (kappa_range[0] + kappa_range[1]) + 0.5 * (kappa_range[1] - kappa_range[0]) * unit()
+    vx = v_mean[0] + v_amp * unit()
+    vy = v_mean[1] + v_amp * unit()
+    sigma = 0.5 * (sigma_range[0] + sigma_range[1]) + 0.5 * (sigma_range[1] - sigma_range[0]) * unit()
+    bg = (float(kappa.mean()), float(vx.mean()), float(vy.mean()), float(sigma.mean()))
+    return CdrProblem(n=n, kappa=kappa, vx=vx, vy=vy, sigma=sigma, background=bg,
+                      source=random_field_c(n, rng))
+
+
+def cdr_batch(count: int = 64, seed_config: int = 7, sizes=SIZES_RAGGED) -> List[CdrProblem]:
+    """Ragged convection-diffusion-reaction batch: N drawn uniformly from
+    `sizes` (as the ragged Helmholtz batch), coefficients as in cdr_problem."""
+    out = []
+    for i in range(count):
+        rng = rng_for(seed_config, i)
+        n = int(rng.choice(np.asarray(sizes)))
+        out.append(cdr_problem(n, rng))
+    return out
+
+
 def workload(name: str):
-    """Problems for a named workload: blob64, grf256, ragged64, diff16, layered1024, newton63."""
+    """Problems for a named workload: blob64, grf256, ragged64, diff16, layered1024, newton63, cdr64."""
     if name == "blob64":
         return [blob_problem()]
     if name == "grf256":
@@ -281,4 +323,6 @@ def workload(name: str):
         return layered_batch()
     if name == "newton63":
         return newton_batch()
+    if name == "cdr64":
+        return cdr_batch()
     raise KeyError(name)

@@ -1,0 +1,244 @@
+"""GPU convection-diffusion-reaction plans (App. C, "Convection-diffusion-
+reaction") against the FP64 oracle: G_cdr (V_cdr u + s), the Born residual
+with norms, the physical residual s - A_cdr u, the adjoint R^H e, and the
+metric-matched loss with its gradient through torch.autograd.  Bars: FP32
+plans 1e-5 relative (FP32 rounding of the transforms and of the four
+derivative passes), FP64 plans 1e-12.  Also R^H e on Helmholtz and Dirichlet
+plans, every column tile width, the larger sizes on a single Fourier mode
+(closed form), and the argument checks."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from paper_2603_18527_amd import cbs
+from gpu_helpers import plan_for, random_problem, rel_err, say, to_list
+
+pytestmark = pytest.mark.gpu
+
+TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
+TOL = {cbs.CBS_C64: 1e-5, cbs.CBS_C128: 1e-12}
+
+
+def _problems(sizes, seed):
+    return [S.cdr_problem(n, np.random.default_rng(seed + i)) for i, n in enumerate(sizes)]
+
+
+def _medium(p):
+    return O.CdrMedium(p.kappa, p.vx, p.vy, p.sigma, *p.background)
+
+
+def _plan(probs, dtype):
+    tdt = TDT[dtype]
+    ks = cbs.pack([p.kappa + 1j * p.sigma for p in probs], tdt)
+    vel = cbs.pack([p.vx + 1j * p.vy for p in probs], tdt)
+    return cbs.CdrPlan(ks, vel, [p.n for p in probs], [p.background for p in probs], dtype=dtype)
+
+
+def _unpack(t, sizes):
+    return [x.cpu().to(torch.complex128) for x in cbs.unpack(t, sizes)]
+
+
+SIZES = [64, 16, 128, 192, 32, 256]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_cdr_apply_residual_physical(dtype):
+    probs = _problems(SIZES, 900)
+    plan = _plan(probs, dtype)
+    tdt = TDT[dtype]
+    rng = np.random.default_rng(901)
+    u0 = [S.random_field_c(n, rng) for n in SIZES]
+    rh = [S.random_field_c(n, rng) for n in SIZES]
+    u = cbs.pack(u0, tdt)
+    s = cbs.pack([p.source for p in probs], tdt)
+    y = plan.apply(u, s)
+    r, n2 = plan.residual(u, s, rhs=cbs.pack(rh, tdt))
+    h, hn2 = plan.physical_residual(u, s)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        m = _medium(p)
+        ref = O.cdr_apply(m, u0[i], p.source)
+        e_apply = rel_err(_unpack(y, SIZES)[i], ref)
+        rref = O.cdr_residual(m, u0[i], p.source, rh[i])
+        e_res = rel_err(_unpack(r, SIZES)[i], rref)
+        e_n2 = abs(float(n2[i]) - float(torch.sum(torch.abs(rref) ** 2))) / float(n2[i])
+        href = O.cdr_physical_residual(m, u0[i], p.source)
+        e_phys = rel_err(_unpack(h, SIZES)[i], href)
+        e_hn2 = abs(float(hn2[i]) - float(torch.sum(torch.abs(href) ** 2))) / float(hn2[i])
+        say(f"[cdr] dtype={dtype} n={p.n}: apply {e_apply:.1e} resid {e_res:.1e} norm {e_n2:.1e} "
+            f"physical {e_phys:.1e} norm {e_hn2:.1e}")
+        for e in (e_apply, e_res, e_n2, e_phys, e_hn2):
+            assert e <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_cdr_born_adjoint(dtype):
+    sizes = [32, 64, 16]
+    probs = _problems(sizes, 910)
+    plan = _plan(probs, dtype)
+    tdt = TDT[dtype]
+    rng = np.random.default_rng(911)
+    e0 = [S.random_field_c(n, rng) for n in sizes]
+    e = cbs.pack(e0, tdt)
+    g = plan.born_adjoint(e)
+    g2 = e.clone()
+    plan.born_adjoint(g2, out=g2)   # in place
+    torch.cuda.synchronize()
+    assert torch.equal(g, g2)
+    for i, p in enumerate(probs):
+        ref = O.cdr_born_adjoint(_medium(p), e0[i])
+        err = rel_err(_unpack(g, sizes)[i], ref)
+        say(f"[cdr adjoint] dtype={dtype} n={p.n}: {err:.1e}")
+        assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_cdr_metric_matched_loss_and_gradient(dtype):
+    sizes = [32, 64]
+    probs = _problems(sizes, 920)
+    plan = _plan(probs, dtype)
+    tdt = TDT[dtype]
+    rng = np.random.default_rng(921)
+    x0 = [S.random_field_c(n, rng) for n in sizes]
+    x = cbs.pack(x0, tdt).requires_grad_(True)
+    s = cbs.pack([p.source for p in probs], tdt)
+    loss = cbs.metric_matched_loss(x, plan, s)
+    w = torch.tensor([0.7, 1.3], dtype=torch.float64, device="cuda")
+    (loss * w).sum().backward()
+    torch.cuda.synchronize()
+    tol = 1e-4 if dtype == cbs.CBS_C64 else 1e-10
+    for i, p in enumerate(probs):
+        val, gx = O.cdr_loss_and_grad(_medium(p), x0[i], p.source)
+        el = abs(float(loss[i]) - val) / val
+        eg = rel_err(_unpack(x.grad, sizes)[i], float(w[i]) * gx)
+        say(f"[cdr loss] dtype={dtype} n={p.n}: loss {el:.1e} grad {eg:.1e}")
+        assert el <= tol and eg <= tol
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_born_adjoint_helmholtz_and_dirichlet(dtype):
+    # R^H e = e - conj(V) G^H e on the other plan kinds, against autograd
+    # through the oracle's Born operator
+    tdt = TDT[dtype]
+    probs = [random_problem(n, seed=930 + n) for n in (64, 32)]
+    plan, k2 = plan_for(probs, dtype)
+    rng = np.random.default_rng(931)
+    e0 = [S.random_field_c(p.n, rng) for p in probs]
+    g = plan.born_adjoint(cbs.pack(e0, tdt))
+    torch.cuda.synchronize()
+    for i, (p, ki) in enumerate(zip(probs, to_list(k2, [q.n for q in probs]))):
+        xt = torch.zeros(p.n, p.n, dtype=torch.complex128, requires_grad=True)
+        val = torch.sum((O.as_c(e0[i]).conj() * O.born_operator(ki, plan.k0sq[i], plan.eps[i], xt)).real)
+        (ref,) = torch.autograd.grad(val, xt)
+        err = rel_err(_unpack(g, [q.n for q in probs])[i], ref)
+        say(f"[born adjoint helmholtz] dtype={dtype} n={p.n}: {err:.1e}")
+        assert err <= TOL[dtype]
+    sizes = [31, 15]
+    rng = np.random.default_rng(932)
+    k2d = [100.0 + 60.0 * S.gaussian_random_field(n, 4.0, rng) for n in sizes]
+    dplan = cbs.Plan(cbs.pack(k2d, tdt), sizes, dtype=dtype, dirichlet=True)
+    e1 = [S.random_field_c(n, rng) for n in sizes]
+    gd = dplan.born_adjoint(cbs.pack(e1, tdt))
+    torch.cuda.synchronize()
+    for i, n in enumerate(sizes):
+        xt = torch.zeros(n, n, dtype=torch.complex128, requires_grad=True)
+        bx = xt - O.green_dirichlet(O.potential(k2d[i], dplan.k0sq[i], dplan.eps[i]) * xt,
+                                    dplan.k0sq[i], dplan.eps[i])
+        val = torch.sum((O.as_c(e1[i]).conj() * bx).real)
+        (ref,) = torch.autograd.grad(val, xt)
+        err = rel_err(_unpack(gd, sizes)[i], ref)
+        say(f"[born adjoint dirichlet] dtype={dtype} n={n}: {err:.1e}")
+        assert err <= TOL[dtype]
+
+
+def _tile_default(m):
+    c = 2
+    while c * 2 <= 32 and c * 2 * m <= 2048 and m % (c * 2) == 0:
+        c *= 2
+    return c
+
+
+@pytest.mark.parametrize("which", ["half", "double"])
+def test_cdr_tile_widths(which):
+    sizes = [64, 128, 256, 512]
+    probs = _problems(sizes, 940)
+    plan = _plan(probs, cbs.CBS_C64)
+    rng = np.random.default_rng(941)
+    u0 = [S.random_field_c(n, rng) for n in sizes]
+    u = cbs.pack(u0, torch.complex64)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    for n in sizes:
+        c0 = _tile_default(n)
+        try:
+            plan.set_tile(c0 // 2 if which == "half" else c0 * 2, n=n)
+        except cbs.CbsError as e:
+            assert e.status == cbs.CBS_ERR_ARG
+    y = plan.apply(u, s)
+    g = plan.born_adjoint(u)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        m = _medium(p)
+        e1 = rel_err(_unpack(y, sizes)[i], O.cdr_apply(m, u0[i], p.source))
+        e2 = rel_err(_unpack(g, sizes)[i], O.cdr_born_adjoint(m, u0[i]))
+        say(f"[cdr tiles] {which} n={p.n}: apply {e1:.1e} adjoint {e2:.1e}")
+        assert e1 <= 1e-5 and e2 <= 1e-5
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_cdr_single_mode_large(n):
+    # homogeneous medium (V = 0): the apply of a Fourier mode is the mode over
+    # L0(xi) (closed form, any size); the physical residual of that solution
+    # for the mode as source vanishes
+    kx, ky = 37, -120
+    one = np.ones((n, n))
+    bg = (0.8, 0.5, -0.25, 0.3)
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    xx, yy = 2 * math.pi * kx / n, 2 * math.pi * ky / n
+    mode = np.exp(1j * (xx * x + yy * y))
+    lam = bg[0] * (xx ** 2 + yy ** 2) + 1j * (bg[1] * xx + bg[2] * yy) + bg[3]
+    plan = cbs.CdrPlan(cbs.pack([bg[0] * one + 1j * bg[3] * one], torch.complex64),
+                       cbs.pack([bg[1] * one + 1j * bg[2] * one], torch.complex64), [n], [bg])
+    s = cbs.pack([mode], torch.complex64)
+    yv = plan.apply(None, s)
+    sol = cbs.pack([mode / lam], torch.complex64)
+    _, hn2 = plan.physical_residual(sol, s, store=False)
+    torch.cuda.synchronize()
+    err = rel_err(yv.cpu().reshape(n, n).to(torch.complex128), torch.from_numpy(mode / lam))
+    say(f"[cdr mode] n={n}: apply {err:.1e} physical residual {math.sqrt(float(hn2[0]) / (n * n)):.1e}")
+    assert err <= 1e-5
+    assert math.sqrt(float(hn2[0]) / (n * n)) <= 1e-5
+
+
+def test_cdr_argument_checks():
+    probs = _problems([32], 950)
+    plan = _plan(probs, cbs.CBS_C64)
+    u = plan.zeros()
+    lib = cbs.load()
+    ptr = cbs._ptr
+    assert lib.cbs_sweep(plan._h, ptr(u), None, 1, None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_npbs_step(plan._h, ptr(u), None, ptr(u), None, 1, None) == cbs.CBS_ERR_ARG
+    with pytest.raises(cbs.CbsError) as e:
+        plan.iterate(u, u.clone())
+    assert e.value.status == cbs.CBS_ERR_ARG
+    with pytest.raises(cbs.CbsError) as e:
+        plan.loss_seed(u, u.clone())
+    assert e.value.status == cbs.CBS_ERR_ARG
+    # the background symbol vanishes at xi = 0 when sigma0 = 0 and (at xi = 0) v0 . xi = 0
+    one = np.ones((32, 32))
+    with pytest.raises(cbs.CbsError) as e:
+        cbs.CdrPlan(cbs.pack([one + 0j], torch.complex64), cbs.pack([0j * one], torch.complex64), [32],
+                    [(1.0, 0.3, 0.2, 0.0)])
+    assert e.value.status == cbs.CBS_ERR_ILLCOND
+    with pytest.raises(cbs.CbsError) as e:
+        cbs.CdrPlan(cbs.pack([one + 0j], torch.complex64), cbs.pack([0j * one], torch.complex64), [32],
+                    [(1.0, float("nan"), 0.2, 0.5)])
+    assert e.value.status == cbs.CBS_ERR_ARG
+    one48 = np.ones((48, 48))
+    with pytest.raises(cbs.CbsError) as e:
+        cbs.CdrPlan(cbs.pack([one48 + 0j], torch.complex64), cbs.pack([0j * one48], torch.complex64), [48],
+                    [(1.0, 0.0, 0.0, 0.5)])
+    assert e.value.status == cbs.CBS_ERR_SIZE
