@@ -268,7 +268,8 @@ def run_suite(args):
     """Solver runs on the five synthetic workloads (configs of the metric):
     blob64 CBS, grf256 FGMRES(30)+CBS(4) and CBS, ragged64 FGMRES batched,
     diff16 adjoint, layered1024 FGMRES(50)+CBS(4) in FP32 vs an FP64 GPU run;
-    and the Dirichlet (DST-I) Newton-system batch newton63.
+    the Dirichlet (DST-I) Newton-system batch newton63; and the
+    convection-diffusion-reaction batch cdr64 (apply and R^H e throughput).
     Errors against the FP64 oracle are evaluated on the host where the naive
     DFT is affordable (N <= 256)."""
     import oracle as O
@@ -433,6 +434,54 @@ def run_suite(args):
         fgmres20_k3=dict(seconds=dt, max_iterations=max(its), max_relres=max(rel),
                          all_converged=all(x == 1 for x in st), instance0_relres_oracle_eval=ev))
     print("# suite newton63 done", flush=True)
+    # 7. cdr64: convection-diffusion-reaction plans (App. C) on a ragged batch
+    #    of 64 instances (sizes as ragged64): G_cdr (V_cdr u + s) and R^H e
+    probs = S.cdr_batch()
+    sizes = [q.n for q in probs]
+    cells = sum(n * n for n in sizes)
+    ks = cbs.pack([q.kappa + 1j * q.sigma for q in probs], torch.complex64)
+    vel = cbs.pack([q.vx + 1j * q.vy for q in probs], torch.complex64)
+    plan = cbs.CdrPlan(ks, vel, sizes, [q.background for q in probs])
+    tiles = plan.autotune()
+    s = cbs.pack([q.source for q in probs], torch.complex64)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    x = torch.complex(torch.randn(cells, generator=g), torch.randn(cells, generator=g)).to(torch.complex64).cuda()
+    y = plan.empty()
+
+    def ev_time(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            best = min(best, a.elapsed_time(b) / reps)
+        return best * 1e-3
+
+    dta = ev_time(lambda: plan.apply(x, s, out=y))
+    dtg = ev_time(lambda: plan.born_adjoint(x, out=y))
+    i0 = next(i for i, n in enumerate(sizes) if n <= 256)
+    q0 = probs[i0]
+    m0 = O.CdrMedium(q0.kappa, q0.vx, q0.vy, q0.sigma, *q0.background)
+    yi = plan.apply(x, s)
+    off = sum(n * n for n in sizes[:i0])
+    xi = x.cpu()[off:off + q0.n ** 2].reshape(q0.n, q0.n)
+    si = s.cpu()[off:off + q0.n ** 2].reshape(q0.n, q0.n)
+    ref = O.cdr_apply(m0, xi, si)
+    got = yi.cpu()[off:off + q0.n ** 2].reshape(q0.n, q0.n).to(torch.complex128)
+    res["cdr64_apply"] = dict(
+        instances=len(sizes), cells=cells, column_tiles={str(n): t for n, t in sorted(set(zip(sizes, tiles)))},
+        apply_ms=dta * 1e3, apply_gcell_s=_gcell(cells, 1, dta),
+        apply_algorithmic_gbs=40.0 * cells / dta / 1e9,
+        born_adjoint_ms=dtg * 1e3, born_adjoint_gcell_s=_gcell(cells, 1, dtg),
+        note="40 algorithmic B/cell per apply: read u, (kappa, sigma), (vx, vy), s; write y",
+        instance_checked=i0, rel_err_vs_oracle=float(torch.linalg.vector_norm(got - ref)
+                                                     / torch.linalg.vector_norm(ref)))
+    print("# suite cdr64 done", flush=True)
     return res
 
 

@@ -178,8 +178,10 @@ cbs_status cbs_setup_ws(cbs_plan* plan, int batch, const int32_t* n, const void*
  *   cbs_plan_info (k0sq = kappa0, eps = sigma0), cbs_autotune, cbs_set_tile
  *   and cbs_destroy apply; the CBS-step entry points (cbs_sweep,
  *   cbs_iterate, fgmres_solve, cbs_npbs_step, cbs_adjoint_step,
- *   cbs_loss_seed) return CBS_ERR_ARG.  Each apply or residual runs four
- *   one-dimensional derivative passes and one transform pair.
+ *   cbs_loss_seed) return CBS_ERR_ARG.  Each apply or residual runs one
+ *   column pass (d/dy of dkappa d/dy, in LDS), one row pass (d/dx of dkappa
+ *   d/dx, fused with the forward row transform of G) and G's column and
+ *   inverse row passes.
  */
 cbs_status cbs_setup_cdr(cbs_plan* plan, int batch, const int32_t* n, const void* kappa_sigma,
                          const void* velocity, const double* background, int dtype, void* stream);
@@ -304,7 +306,7 @@ cbs_status cbs_adjoint_step(cbs_plan plan, const void* u_m, const void* s, const
  *   (PyTorch's convention d/dRe + i d/dIm).  Helmholtz and Dirichlet plans:
  *   e - conj(V) G^H e (one transform pair); CDR plans: e - V^H G^H e with
  *   V^H = Dx(dkappa Dx + dvx) + Dy(dkappa Dy + dvy) - dsigma (one transform
- *   pair and four derivative passes).  e, out: device packed fields; out may
+ *   pair, then one column and one row derivative pass).  e, out: device packed fields; out may
  *   alias e.  Uses the plan's scratch fields, so calls on one plan serialise.
  */
 cbs_status cbs_born_adjoint(cbs_plan plan, const void* e, void* out, void* stream);

@@ -1079,83 +1079,67 @@ cbs_status npbs_impl(cbs_plan p, void* u, const void* s, const void* wf, const v
 
 // ---- convection-diffusion-reaction plans ---------------------------------------------------
 
+// Column pass of V: p_y = Dy(dkappa Dy u) - dvy Dy u (adj 0) or
+// Dy(dkappa Dy g + dvy g) (adj 1), into d_e.
 template <typename R>
-void launch_cdr_cols(cbs_plan p, const Params<R>& q, hipStream_t st) {
+cpx<R>* cdr_col_pass(cbs_plan p, const cpx<R>* u, int adj, hipStream_t st) {
+  cpx<R>* py = static_cast<cpx<R>*>(p->d_e);
+  Params<R> c = base_params<R>(p);
+  c.k2b = static_cast<const cpx<R>*>(p->d_k2b);
+  c.partials = nullptr;
+  c.u = u;
+  c.out = py;
   const cbs_plan_s::Items it = p->view->all();
-  Params<R> c = q;
   if constexpr (sizeof(R) == 4) {
     c.items = it.cols32;
-    launch_col_cdr(it.ncols32, p->col_lds32, st, c);
+    launch_cdr_col(adj, it.ncols32, p->col_lds32, st, c);
   } else {
     c.items = it.cols64;
-    launch_col_cdr(it.ncols64, p->col_lds64, st, c);
+    launch_cdr_col(adj, it.ncols64, p->col_lds64, st, c);
   }
+  return py;
 }
 
-// out = V_cdr u + s (adj = 0) or out = e - V_cdr^H g (adj = 1; u = g, s = e):
-// four 1D derivative passes, scratch d_c (dx), d_e (dy), d_t (partial sum).
-// out may be d_t itself, or alias s.
+// Row pass of V (mode as in launch_cdr_row); py from cdr_col_pass.
 template <typename R>
-cbs_status cdr_vpass(cbs_plan p, const cpx<R>* u, const cpx<R>* s, cpx<R>* out, int adj, hipStream_t st) {
-  cpx<R>* dx = static_cast<cpx<R>*>(p->d_c);
-  cpx<R>* dy = static_cast<cpx<R>*>(p->d_e);
-  cpx<R>* t = static_cast<cpx<R>*>(p->d_t);
-  Params<R> q = base_params<R>(p);
-  q.k2b = static_cast<const cpx<R>*>(p->d_k2b);
-  q.cdr_adj = adj;
-  q.partials = nullptr;
-  q.items = p->view->rows;
-  const int nrow = p->view->nrows;
-  Params<R> a = q;  // dx = Dx u
-  a.pro = CPRO_A;
-  a.a = u;
-  a.epi = CEPI_STORE;
-  a.out = dx;
-  launch_row_cdr(nrow, st, a);
-  a.out = dy;  // dy = Dy u
-  launch_cdr_cols(p, a, st);
-  Params<R> c = q;  // t = Dx(dkappa dx [+ dvx g]) + q
-  c.pro = CPRO_WX;
-  c.a = dx;
-  c.b = dy;
-  c.u = u;
-  c.s = s;
-  c.epi = CEPI_Q;
-  c.out = t;
-  launch_row_cdr(nrow, st, c);
-  Params<R> d = q;  // out = t + Dy(dkappa dy [+ dvy g])  (adjoint: e - ...)
-  d.pro = CPRO_WY;
-  d.b = dy;
-  d.u = u;
-  d.s = s;
-  d.rhs = t;
-  d.epi = CEPI_ACC;
-  d.out = out;
-  launch_cdr_cols(p, d, st);
-  HIPCHK(hipGetLastError());
-  return CBS_OK;
+void cdr_row_pass(cbs_plan p, int mode, const cpx<R>* u, const cpx<R>* s, const cpx<R>* py, cpx<R>* out,
+                  hipStream_t st) {
+  Params<R> r = base_params<R>(p);
+  r.k2b = static_cast<const cpx<R>*>(p->d_k2b);
+  r.partials = nullptr;
+  r.items = p->view->rows;
+  r.u = u;
+  r.s = s;
+  r.b = py;
+  r.out = out;
+  launch_cdr_row(mode, p->view->nrows, st, r);
 }
 
-// y = G (V u + s) (epi EPI_STORE) or r = G (V u + s) - u + rhs (EPI_RESID)
+// y = G (V u + s) (epi EPI_STORE) or r = G (V u + s) - u + rhs (EPI_RESID):
+// column pass of V, row pass of V fused with the forward rows of G, the
+// Green column pass and the inverse rows with the epilogue.
 template <typename R>
 cbs_status cdr_green_impl(cbs_plan p, const void* u, const void* s, const void* rhs, void* out,
                           int epi, double* norm2, hipStream_t st) {
-  cpx<R>* t = static_cast<cpx<R>*>(p->d_t);
   Params<R> q = base_params<R>(p);
-  if (u) {
-    CHK(cdr_vpass<R>(p, static_cast<const cpx<R>*>(u), static_cast<const cpx<R>*>(s), t, 0, st));
-    q.pro = PRO_A;
-    q.a = t;
-  } else {  // V 0 = 0: transform s itself (PRO_VU_S with u = NULL; s NULL reads as zero)
-    q.s = static_cast<const cpx<R>*>(s);
-  }
   q.sym = SYM_CDR;
   q.epi = epi;
   q.u = static_cast<const cpx<R>*>(u);
   q.rhs = static_cast<const cpx<R>*>(rhs);
   q.out = static_cast<cpx<R>*>(out);
   if (epi == EPI_STORE) q.partials = nullptr;
-  CHK(run_pipeline(p, q, st));
+  if (u) {
+    const cpx<R>* uu = static_cast<const cpx<R>*>(u);
+    const cpx<R>* py = cdr_col_pass<R>(p, uu, 0, st);
+    cdr_row_pass<R>(p, 0, uu, static_cast<const cpx<R>*>(s), py, nullptr, st);
+    launch_cols(p, q, st);
+    q.items = p->view->rows;
+    launch_row(1, p->view->nrows, st, q);
+    HIPCHK(hipGetLastError());
+  } else {  // V 0 = 0: transform s itself (PRO_VU_S with u = NULL; s NULL reads as zero)
+    q.s = static_cast<const cpx<R>*>(s);
+    CHK(run_pipeline(p, q, st));
+  }
   if (norm2) {
     launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
     HIPCHK(hipGetLastError());
@@ -1167,11 +1151,13 @@ cbs_status cdr_green_impl(cbs_plan p, const void* u, const void* s, const void* 
 template <typename R>
 cbs_status cdr_physical_impl(cbs_plan p, const void* u, const void* s, void* r, double* norm2,
                              hipStream_t st) {
+  const cpx<R>* uu = static_cast<const cpx<R>*>(u);
   cpx<R>* t = static_cast<cpx<R>*>(p->d_t);
-  CHK(cdr_vpass<R>(p, static_cast<const cpx<R>*>(u), static_cast<const cpx<R>*>(s), t, 0, st));
+  const cpx<R>* py = cdr_col_pass<R>(p, uu, 0, st);
+  cdr_row_pass<R>(p, 1, uu, static_cast<const cpx<R>*>(s), py, t, st);
   Params<R> q = base_params<R>(p);
   q.pro = PRO_A;
-  q.a = static_cast<const cpx<R>*>(u);
+  q.a = uu;
   q.sym = SYM_CDR_NEG_L0;
   q.epi = EPI_RESID;  // -L0 u - 0 + t
   q.u = nullptr;
@@ -1203,7 +1189,10 @@ cbs_status born_adjoint_impl(cbs_plan p, const void* e, void* out, hipStream_t s
   q.epi = EPI_STORE;
   q.out = g;
   CHK(run_pipeline(p, q, st));
-  return cdr_vpass<R>(p, g, static_cast<const cpx<R>*>(e), static_cast<cpx<R>*>(out), 1, st);
+  const cpx<R>* py = cdr_col_pass<R>(p, g, 1, st);
+  cdr_row_pass<R>(p, 2, g, static_cast<const cpx<R>*>(e), py, static_cast<cpx<R>*>(out), st);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
 }
 
 // ---- adjoint -------------------------------------------------------------------------------

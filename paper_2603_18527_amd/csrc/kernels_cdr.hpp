@@ -1,27 +1,30 @@
-// One-dimensional spectral-derivative passes for convection-diffusion-reaction
-// plans (App. C, "Convection-diffusion-reaction").
+// Spectral-derivative passes for convection-diffusion-reaction plans (App. C,
+// "Convection-diffusion-reaction").
 //
 // V_cdr u = d/dx(dkappa du/dx) + d/dy(dkappa du/dy) - dv . grad u - dsigma u
-// needs derivatives of fields that are products with the coefficient fields,
-// so it cannot be folded into the one Fourier multiplier that G_cdr is.  A
-// derivative along x is diagonal after the row transform alone and one along
-// y after the column transform alone, so each derivative here is a single
-// pass: forward 1D transform, multiply by i xi / N (xi = 2 pi m / N on the
-// signed index m, Nyquist bin -N/2), inverse 1D transform, with a pointwise
-// prologue on the way in and a pointwise epilogue on the way out.
+// needs derivatives of products with the coefficient fields, so it is not
+// one Fourier multiplier as G_cdr is.  A derivative along x is diagonal after
+// the row transform alone and one along y after the column transform alone,
+// so each axis takes one pass that keeps its rows (or columns) in LDS:
+// forward 1D transform, times i xi / N (xi = 2 pi m / N on the signed index
+// m, Nyquist bin -N/2), inverse, the pointwise product with the coefficients,
+// forward, times i xi / N, inverse.
 //
-// V u + s (forward) and e - V^H g (adjoint, V^H = Dx(dkappa Dx + dvx) +
-// Dy(dkappa Dy + dvy) - dsigma for real coefficients, since D^H = -D) both
-// take four passes:
-//   1. row pass   dx = Dx a
-//   2. col pass   dy = Dy a
-//   3. row pass   t  = Dx(dkappa dx [+ dvx g]) + q,
-//                 q = -dvx dx - dvy dy - dsigma u + s   (forward)
-//                 q = -dsigma g                        (adjoint)
-//   4. col pass   w  = t + Dy(dkappa dy [+ dvy g]); out = w (forward) or
-//                 e - w (adjoint)
-// Field roles in Params: a = pass input / dx, b = dy, u = u (forward) or g
-// (adjoint), s = s (forward) or e (adjoint, pass 4), rhs = t (pass 4).
+//   column pass   p_y = Dy(dkappa Dy u) - dvy Dy u                 (forward)
+//                 p_y = Dy(dkappa Dy g + dvy g)                     (adjoint)
+//   row pass      t = Dx(dkappa Dx u) - dvx Dx u - dsigma u + s + p_y = V u + s
+//                 (MODE 0: then the forward row transform of t, i.e. the
+//                 first pass of G t, into the spectral buffer; MODE 1: t
+//                 itself into out)
+//                 out = e - (Dx(dkappa Dx g + dvx g) + p_y - dsigma g)
+//                 = e - V^H g   (MODE 2; V^H for real coefficients, D^H = -D)
+//
+// The term that is not differentiated a second time (-dvx Dx u ... on the
+// forward side) is formed at the middle step and parked in global memory
+// (the pass's own output rows or columns) until the last transform adds it;
+// the workgroup's barriers order the two accesses.
+// Field roles: u = u (forward) or g (adjoint); s = s (forward) or e
+// (adjoint); b = p_y (row pass); k2 = (dkappa, dsigma); k2b = (dvx, dvy).
 #pragma once
 #include "kernels.hpp"
 
@@ -35,41 +38,7 @@ __device__ __forceinline__ cpx<R> deriv_factor(int e, cpx<R> v) {
   return cpx<R>{-v.y * f, v.x * f};
 }
 
-template <typename R>
-__device__ __forceinline__ cpx<R> cdr_prologue(const Params<R>& p, long long i) {
-  if (p.pro == CPRO_A) return p.a[i];
-  const cpx<R> c1 = p.k2[i];  // (dkappa, dsigma)
-  if (p.pro == CPRO_WX) {
-    cpx<R> w = cscale(p.a[i], c1.x);
-    if (p.cdr_adj) w = w + cscale(p.u[i], p.k2b[i].x);
-    return w;
-  }
-  cpx<R> w = cscale(p.b[i], c1.x);  // CPRO_WY
-  if (p.cdr_adj) w = w + cscale(p.u[i], p.k2b[i].y);
-  return w;
-}
-
-template <typename R>
-__device__ __forceinline__ void cdr_epilogue(const Params<R>& p, long long i, cpx<R> v) {
-  if (p.epi == CEPI_STORE) {
-    p.out[i] = v;
-  } else if (p.epi == CEPI_Q) {
-    const cpx<R> c1 = p.k2[i];
-    const cpx<R> u = p.u[i];
-    cpx<R> q = cscale(u, -c1.y);
-    if (!p.cdr_adj) {
-      const cpx<R> c2 = p.k2b[i];
-      q = q - cscale(p.a[i], c2.x) - cscale(p.b[i], c2.y) + ld_or_zero(p.s, i);
-    }
-    p.out[i] = v + q;
-  } else {  // CEPI_ACC
-    const cpx<R> w = p.rhs[i] + v;
-    p.out[i] = p.cdr_adj ? p.s[i] - w : w;
-  }
-}
-
-// d/dx pass over a row tile (rows as in row_body)
-template <typename R, int N>
+template <typename R, int N, int MODE>
 __device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc& d, int row0, cpx<R>* lds) {
   using T = RowTile<N>;
   const int tid = threadIdx.x;
@@ -78,55 +47,91 @@ __device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc&
   const bool active = r < nrows;
   const long long rbase = d.off + (long long)(row0 + (active ? r : 0)) * N;
   cpx<R>* mine = lds + (active ? r : 0) * T::RS;
-  auto ld = [&](int e) { return cdr_prologue(p, rbase + e); };
-  auto mid = [&](int e, cpx<R> v) { return deriv_factor<R, N>(e, v); };
-  auto st2 = [&](int e, cpx<R> v) { cdr_epilogue(p, rbase + e, v); };
-  if constexpr (plan_bridgeable(N)) {
-    fft_run2<R, N, T::TPF, -1, 1>(mine, t, active, p.tw, ld, mid, st2);
+  cpx<R>* park = MODE == 0 ? p.inter : p.out;  // holds the undifferentiated part
+  auto ld_u = [&](int e) { return p.u[rbase + e]; };
+  auto ld_l = [&](int e) { return lds_ld(mine + lds_pos(e)); };
+  auto st_d = [&](int e, cpx<R> v) { mine[lds_pos(e)] = deriv_factor<R, N>(e, v); };
+  // middle step: dx -> dkappa dx (+ dvx g), and the rest of the row's terms
+  auto st_m = [&](int e, cpx<R> dx) {
+    const long long g = rbase + e;
+    const cpx<R> c1 = p.k2[g];
+    const cpx<R> c2 = p.k2b[g];
+    const cpx<R> u = p.u[g];
+    cpx<R> w = cscale(dx, c1.x);
+    if constexpr (MODE == 2) {
+      w = w + cscale(u, c2.x);
+    } else {
+      park[g] = p.b[g] - cscale(dx, c2.x) - cscale(u, c1.y) + ld_or_zero(p.s, g);
+    }
+    mine[lds_pos(e)] = w;
+  };
+  fft_run<R, N, T::TPF, -1, false, true>(mine, t, active, p.tw, ld_u, st_d);
+  fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_m);
+  fft_run<R, N, T::TPF, -1, true, true>(mine, t, active, p.tw, ld_l, st_d);
+  if constexpr (MODE == 2) {
+    auto st_f = [&](int e, cpx<R> v) {
+      const long long g = rbase + e;
+      const cpx<R> vh = v + p.b[g] - cscale(p.u[g], p.k2[g].y);
+      p.out[g] = p.s[g] - vh;
+    };
+    fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, p.tw, ld_l, st_f);
+  } else if constexpr (MODE == 1) {
+    auto st_f = [&](int e, cpx<R> v) { p.out[rbase + e] = v + p.out[rbase + e]; };
+    fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, p.tw, ld_l, st_f);
   } else {
-    auto st = [&](int e, cpx<R> v) { mine[lds_pos(e)] = mid(e, v); };
-    fft_run<R, N, T::TPF, -1, false, true>(mine, t, active, p.tw, ld, st);
-    auto ld2 = [&](int e) { return lds_ld(mine + lds_pos(e)); };
-    fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, p.tw, ld2, st2);
+    auto st_t = [&](int e, cpx<R> v) { mine[lds_pos(e)] = v + p.inter[rbase + e]; };
+    fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_t);
+    auto st_s = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
+    fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld_l, st_s);
   }
 }
 
-// d/dy pass over a column tile (C columns, layout as in col_body)
-template <typename R, int N, int C>
+// Column tile of C columns, layout as in col_body (element-interleaved)
+template <typename R, int N, int C, int ADJ>
 __device__ __forceinline__ void cdr_col_body(const Params<R>& p, const InstDesc& d, int col0, cpx<R>* lds) {
   constexpr int TPC = kThreads / C;
   const int tid = threadIdx.x;
   const int c = tid % C, tt = tid / C;
   const long long cbase = d.off + col0 + c;
   cpx<R>* mine = lds + c;
-  auto ld = [&](int e) { return cdr_prologue(p, cbase + (long long)e * N); };
-  auto mid = [&](int e, cpx<R> v) { return deriv_factor<R, N>(e, v); };
-  auto st2 = [&](int e, cpx<R> v) { cdr_epilogue(p, cbase + (long long)e * N, v); };
-  if constexpr (plan_bridgeable(N)) {
-    fft_run2<R, N, TPC, -1, 1, C>(mine, tt, true, p.tw, ld, mid, st2);
-  } else {
-    auto st = [&](int e, cpx<R> v) { mine[C * lds_pos(e)] = mid(e, v); };
-    fft_run<R, N, TPC, -1, false, true, C>(mine, tt, true, p.tw, ld, st);
-    auto ld2 = [&](int e) { return lds_ld(mine + C * lds_pos(e)); };
-    fft_run<R, N, TPC, 1, true, false, C>(mine, tt, true, p.tw, ld2, st2);
-  }
+  auto ld_u = [&](int e) { return p.u[cbase + (long long)e * N]; };
+  auto ld_l = [&](int e) { return lds_ld(mine + C * lds_pos(e)); };
+  auto st_d = [&](int e, cpx<R> v) { mine[C * lds_pos(e)] = deriv_factor<R, N>(e, v); };
+  auto st_m = [&](int e, cpx<R> dy) {
+    const long long g = cbase + (long long)e * N;
+    const cpx<R> c1 = p.k2[g];
+    const cpx<R> c2 = p.k2b[g];
+    cpx<R> w = cscale(dy, c1.x);
+    if constexpr (ADJ) w = w + cscale(p.u[g], c2.y);
+    else p.out[g] = cscale(dy, -c2.y);
+    mine[C * lds_pos(e)] = w;
+  };
+  auto st_f = [&](int e, cpx<R> v) {
+    const long long g = cbase + (long long)e * N;
+    if constexpr (ADJ) p.out[g] = v;
+    else p.out[g] = v + p.out[g];
+  };
+  fft_run<R, N, TPC, -1, false, true, C>(mine, tt, true, p.tw, ld_u, st_d);
+  fft_run<R, N, TPC, 1, true, true, C>(mine, tt, true, p.tw, ld_l, st_m);
+  fft_run<R, N, TPC, -1, true, true, C>(mine, tt, true, p.tw, ld_l, st_d);
+  fft_run<R, N, TPC, 1, true, false, C>(mine, tt, true, p.tw, ld_l, st_f);
 }
 
-template <typename R, int N>
+template <typename R, int N, int ADJ>
 __device__ __forceinline__ void cdr_col_dispatch_n(const Params<R>& p, const InstDesc& d, int col0,
                                                    cpx<R>* lds) {
   constexpr int C0 = col_tile_default(N);
   constexpr int EB = int(sizeof(cpx<R>));
   const int c = sizeof(R) == 4 ? d.ctile : d.ctile64;
   if constexpr (col_tile_valid(N, C0, EB))
-    if (c == C0) { cdr_col_body<R, N, C0>(p, d, col0, lds); return; }
+    if (c == C0) { cdr_col_body<R, N, C0, ADJ>(p, d, col0, lds); return; }
   if constexpr (col_tile_valid(N, C0 / 2, EB))
-    if (c == C0 / 2) { cdr_col_body<R, N, (C0 / 2 >= 2 ? C0 / 2 : 2)>(p, d, col0, lds); return; }
+    if (c == C0 / 2) { cdr_col_body<R, N, (C0 / 2 >= 2 ? C0 / 2 : 2), ADJ>(p, d, col0, lds); return; }
   if constexpr (col_tile_valid(N, C0 * 2, EB))
-    if (c == C0 * 2) { cdr_col_body<R, N, (C0 * 2 <= 32 ? C0 * 2 : 32)>(p, d, col0, lds); return; }
+    if (c == C0 * 2) { cdr_col_body<R, N, (C0 * 2 <= 32 ? C0 * 2 : 32), ADJ>(p, d, col0, lds); return; }
 }
 
-template <typename R>
+template <typename R, int MODE>
 __global__ __launch_bounds__(kThreads) void k_cdr_row(Params<R> p) {
   __shared__ cpx<R> lds[kRowLds];
   const int2 w = p.items[blockIdx.x];
@@ -134,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_cdr_row(Params<R> p) {
   switch (d.n) {
 #define CBS_CDR_ROW_CASE(N) \
   case N:                   \
-    cdr_row_body<R, N>(p, d, w.y, lds); \
+    cdr_row_body<R, N, MODE>(p, d, w.y, lds); \
     break;
     CBS_FOR_EACH_N(CBS_CDR_ROW_CASE)
 #undef CBS_CDR_ROW_CASE
@@ -143,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_cdr_row(Params<R> p) {
   }
 }
 
-template <typename R>
+template <typename R, int ADJ>
 __global__ __launch_bounds__(kThreads) void k_cdr_col(Params<R> p) {
   extern __shared__ float4 smem_raw[];
   cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_cdr_col(Params<R> p) {
   switch (d.n) {
 #define CBS_CDR_COL_CASE(N) \
   case N:                   \
-    cdr_col_dispatch_n<R, N>(p, d, w.y, lds); \
+    cdr_col_dispatch_n<R, N, ADJ>(p, d, w.y, lds); \
     break;
     CBS_FOR_EACH_N(CBS_CDR_COL_CASE)
 #undef CBS_CDR_COL_CASE

@@ -20,12 +20,13 @@ void launch_row_dst(int mode, int grid, hipStream_t st, const Params<float>& p);
 void launch_row_dst(int mode, int grid, hipStream_t st, const Params<double>& p);
 void launch_col_dst(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
 void launch_col_dst(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
-// convection-diffusion-reaction plans: 1D derivative passes (row: d/dx,
-// column: d/dy) and the coefficient split at setup
-void launch_row_cdr(int grid, hipStream_t st, const Params<float>& p);
-void launch_row_cdr(int grid, hipStream_t st, const Params<double>& p);
-void launch_col_cdr(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
-void launch_col_cdr(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
+// convection-diffusion-reaction plans: the row pass (mode 0: V u + s -> forward
+// rows; 1: V u + s; 2: e - V^H g), the column pass (adj 0 / 1) and the
+// coefficient split at setup
+void launch_cdr_row(int mode, int grid, hipStream_t st, const Params<float>& p);
+void launch_cdr_row(int mode, int grid, hipStream_t st, const Params<double>& p);
+void launch_cdr_col(int adj, int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p);
+void launch_cdr_col(int adj, int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p);
 void launch_cdr_split(int grid, hipStream_t st, const InstDesc* inst, const int2* items, cpx<float>* c1,
                       cpx<float>* c2);
 void launch_cdr_split(int grid, hipStream_t st, const InstDesc* inst, const int2* items, cpx<double>* c1,

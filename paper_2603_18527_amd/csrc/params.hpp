@@ -64,10 +64,6 @@ enum Epi {
   EPI_NPBS = 8,
   EPI_BORN_ADJ = 9  // out = a - conj(V) z: R^H a for R = I - G V, z = G^H a
 };
-// Prologue / epilogue of the CDR derivative passes (the combinations are
-// listed with the kernels)
-enum CdrPro { CPRO_A = 0, CPRO_WX = 1, CPRO_WY = 2 };
-enum CdrEpi { CEPI_STORE = 0, CEPI_Q = 1, CEPI_ACC = 2 };
 // Instance masks: which status values let an instance run.
 enum MaskMode { MASK_RUNNING = 0, MASK_NOT_FINAL = 1, MASK_NONZERO = 2 };
 enum InstStatus { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_DIVERGED = 3, ST_PENDING = 4 };
@@ -113,9 +109,8 @@ struct Params {
   int check;
   int dst;  // nonzero: Dirichlet plan (DST-I kernels)
   // convection-diffusion-reaction passes: k2 holds (dkappa, dsigma), k2b
-  // (dvx, dvy); cdr_adj selects the adjoint combination
+  // (dvx, dvy)
   const cpx<R>* k2b;
-  int cdr_adj;
 };
 
 
