@@ -63,12 +63,15 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
     the per-sweep HBM traffic record.
 
     Each counter is scaled by what it reads for the 1 GiB calibration copy
-    (the largest __amd_rocclr_copyBuffer dispatch).  That run makes, per lane
+    (the largest __amd_rocclr_copyBuffer dispatch).  Only dispatches from the
+    first k_row_fwd to the last k_row_inv before the NPBS steps count (the
+    autotuner before and the NPBS steps after launch k_col on grids that can
+    equal a lane's; the lanes join before the NPBS steps start).  In between
+    the run makes, per lane
     (two lanes, or one when the batch is not split), 62 k_col and 60
     k_row_sweep dispatches of the lane's grid (warm-up call of 2 sweeps, one
-    chain of 60); the autotuner's per-size-class k_col launches come 23 per
-    grid.  Per-sweep bytes: the bytes of every dispatch of a grid launched at
-    least that often, divided by the number of sweeps."""
+    chain of 60).  Per-sweep bytes: the bytes of every dispatch of a grid
+    launched at least that often, divided by the number of sweeps."""
     import csv
     import collections
     sweeps = {"k_row_sweep": 60, "k_col": 62}
@@ -77,6 +80,11 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         scale = (1 << 30) / (max(copies) * 1024.0)
+        t0 = min(int(r["Start_Timestamp"]) for r in rows if "k_row_fwd<float>" in r["Kernel_Name"])
+        tn = min([int(r["Start_Timestamp"]) for r in rows if "k_row_npbs" in r["Kernel_Name"]] + [1 << 62])
+        t1 = max(int(r["Start_Timestamp"]) for r in rows
+                 if "k_row_inv<float>" in r["Kernel_Name"] and int(r["Start_Timestamp"]) < tn)
+        rows = [r for r in rows if t0 <= int(r["Start_Timestamp"]) <= t1]
         out, grids = {}, {}
         for kern, tag in (("k_row_sweep", "k_row_sweep<float>"), ("k_col", "k_col<float")):
             by_grid = collections.defaultdict(list)
