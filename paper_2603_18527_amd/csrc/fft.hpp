@@ -324,9 +324,14 @@ __host__ __device__ constexpr bool plan_bridgeable(int n) {
   return plan_passes(n) >= 3 && plan_radix(n, 0) == plan_radix(n, plan_passes(n) - 1);
 }
 
-template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class LD, class MID, class ST>
-__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
-                                         const cpx<R>* __restrict__ tw, LD ld, MID mid, ST st) {
+// The bridge between two transforms: the last pass of one in direction D1
+// (reading LDS), `mid(e, v)` on each of its outputs, and the first pass of the
+// next in direction D2 (writing LDS), in registers.  Needs plan_bridgeable(N):
+// the last pass of transform 1 and the first pass of transform 2 then act on
+// the same elements j + q N/RAD in each thread.
+template <typename R, int N, int TPF, int D1, int D2, int ES, class MID>
+__device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw,
+                                           MID& mid) {
   static_assert(plan_bridgeable(N), "first and last radix differ");
   constexpr int PL = plan_passes(N) - 1;  // last pass index
   constexpr int RAD = plan_radix(N, PL);
@@ -334,9 +339,6 @@ __device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
   constexpr int NB = N / RAD;
   constexpr int PER = (NB + TPF - 1) / TPF;
   constexpr bool EXACT = (NB % TPF) == 0;
-  auto none = [](int, cpx<R>) {};
-  // transform 1, passes 0 .. PL-1 (the last of them writes LDS)
-  fft_pass<R, N, 0, PL, TPF, D1, false, false, ES>(buf, t, active, tw, ld, none);
   cpx<R> v[PER][RAD];
   if (active) {
 #pragma unroll
@@ -370,9 +372,32 @@ __device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
     }
   }
   __syncthreads();
+}
+
+template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class LD, class MID, class ST>
+__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
+                                         const cpx<R>* __restrict__ tw, LD ld, MID mid, ST st) {
+  static_assert(plan_bridgeable(N), "first and last radix differ");
+  constexpr int PL = plan_passes(N) - 1;  // last pass index
+  auto none = [](int, cpx<R>) {};
+  // transform 1, passes 0 .. PL-1 (the last of them writes LDS)
+  fft_pass<R, N, 0, PL, TPF, D1, false, false, ES>(buf, t, active, tw, ld, none);
+  fft_bridge<R, N, TPF, D1, D2, ES>(buf, t, active, tw, mid);
   // transform 2, passes 1 .. PL
   auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
   fft_pass<R, N, 1, PL + 1, TPF, D2, false, false, ES>(buf, t, active, tw, noload, st);
+}
+
+// Internal passes 1 .. PL-1 of a transform whose first and last passes are
+// bridges (LDS in, LDS out).
+template <typename R, int N, int TPF, int D, int ES>
+__device__ __forceinline__ void fft_inner(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw) {
+  constexpr int PL = plan_passes(N) - 1;
+  if constexpr (PL > 1) {
+    auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
+    auto none = [](int, cpx<R>) {};
+    fft_pass<R, N, 1, PL, TPF, D, false, false, ES>(buf, t, active, tw, noload, none);
+  }
 }
 
 }  // namespace cbs

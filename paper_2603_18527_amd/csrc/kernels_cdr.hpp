@@ -65,24 +65,57 @@ __device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc&
     }
     mine[lds_pos(e)] = w;
   };
-  fft_run<R, N, T::TPF, -1, false, true>(mine, t, active, p.tw, ld_u, st_d);
-  fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_m);
-  fft_run<R, N, T::TPF, -1, true, true>(mine, t, active, p.tw, ld_l, st_d);
-  if constexpr (MODE == 2) {
-    auto st_f = [&](int e, cpx<R> v) {
-      const long long g = rbase + e;
+  auto st_f = [&](int e, cpx<R> v) {
+    const long long g = rbase + e;
+    if constexpr (MODE == 2) {
       const cpx<R> vh = v + p.b[g] - cscale(p.u[g], p.k2[g].y);
       p.out[g] = p.s[g] - vh;
+    } else {
+      p.out[g] = v + p.out[g];
+    }
+  };
+  auto st_s = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
+  if constexpr (plan_bridgeable(N)) {
+    // the transforms chained through register bridges (fewer LDS round trips)
+    constexpr int PL = plan_passes(N) - 1;
+    auto none = [](int, cpx<R>) {};
+    auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
+    auto dmul = [&](int e, cpx<R> v) { return deriv_factor<R, N>(e, v); };
+    auto mmid = [&](int e, cpx<R> dx) {
+      const long long g = rbase + e;
+      const cpx<R> c1 = p.k2[g];
+      const cpx<R> c2 = p.k2b[g];
+      const cpx<R> u = p.u[g];
+      cpx<R> w = cscale(dx, c1.x);
+      if constexpr (MODE == 2) w = w + cscale(u, c2.x);
+      else park[g] = p.b[g] - cscale(dx, c2.x) - cscale(u, c1.y) + ld_or_zero(p.s, g);
+      return w;
     };
-    fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, p.tw, ld_l, st_f);
-  } else if constexpr (MODE == 1) {
-    auto st_f = [&](int e, cpx<R> v) { p.out[rbase + e] = v + p.out[rbase + e]; };
-    fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, p.tw, ld_l, st_f);
+    fft_pass<R, N, 0, PL, T::TPF, -1, false, false, 1>(mine, t, active, p.tw, ld_u, none);
+    fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, p.tw, dmul);
+    fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, p.tw);
+    fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, p.tw, mmid);
+    fft_inner<R, N, T::TPF, -1, 1>(mine, t, active, p.tw);
+    fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, p.tw, dmul);
+    if constexpr (MODE == 0) {
+      auto tmid = [&](int e, cpx<R> v) { return v + p.inter[rbase + e]; };
+      fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, p.tw);
+      fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, p.tw, tmid);
+      fft_pass<R, N, 1, PL + 1, T::TPF, -1, false, false, 1>(mine, t, active, p.tw, noload, st_s);
+    } else {
+      fft_pass<R, N, 1, PL + 1, T::TPF, 1, false, false, 1>(mine, t, active, p.tw, noload, st_f);
+    }
   } else {
-    auto st_t = [&](int e, cpx<R> v) { mine[lds_pos(e)] = v + p.inter[rbase + e]; };
-    fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_t);
-    auto st_s = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
-    fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld_l, st_s);
+    fft_run<R, N, T::TPF, -1, false, true>(mine, t, active, p.tw, ld_u, st_d);
+    fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_m);
+    fft_run<R, N, T::TPF, -1, true, true>(mine, t, active, p.tw, ld_l, st_d);
+    if constexpr (MODE == 0) {
+      auto st_t = [&](int e, cpx<R> v) { mine[lds_pos(e)] = v + p.inter[rbase + e]; };
+      fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_t);
+      fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld_l, st_s);
+    } else {
+      fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, p.tw, ld_l, st_f);
+    }
   }
 }
 
@@ -111,10 +144,33 @@ __device__ __forceinline__ void cdr_col_body(const Params<R>& p, const InstDesc&
     if constexpr (ADJ) p.out[g] = v;
     else p.out[g] = v + p.out[g];
   };
-  fft_run<R, N, TPC, -1, false, true, C>(mine, tt, true, p.tw, ld_u, st_d);
-  fft_run<R, N, TPC, 1, true, true, C>(mine, tt, true, p.tw, ld_l, st_m);
-  fft_run<R, N, TPC, -1, true, true, C>(mine, tt, true, p.tw, ld_l, st_d);
-  fft_run<R, N, TPC, 1, true, false, C>(mine, tt, true, p.tw, ld_l, st_f);
+  if constexpr (plan_bridgeable(N)) {
+    constexpr int PL = plan_passes(N) - 1;
+    auto none = [](int, cpx<R>) {};
+    auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
+    auto dmul = [&](int e, cpx<R> v) { return deriv_factor<R, N>(e, v); };
+    auto mmid = [&](int e, cpx<R> dy) {
+      const long long g = cbase + (long long)e * N;
+      const cpx<R> c1 = p.k2[g];
+      const cpx<R> c2 = p.k2b[g];
+      cpx<R> w = cscale(dy, c1.x);
+      if constexpr (ADJ) w = w + cscale(p.u[g], c2.y);
+      else p.out[g] = cscale(dy, -c2.y);
+      return w;
+    };
+    fft_pass<R, N, 0, PL, TPC, -1, false, false, C>(mine, tt, true, p.tw, ld_u, none);
+    fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, p.tw, dmul);
+    fft_inner<R, N, TPC, 1, C>(mine, tt, true, p.tw);
+    fft_bridge<R, N, TPC, 1, -1, C>(mine, tt, true, p.tw, mmid);
+    fft_inner<R, N, TPC, -1, C>(mine, tt, true, p.tw);
+    fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, p.tw, dmul);
+    fft_pass<R, N, 1, PL + 1, TPC, 1, false, false, C>(mine, tt, true, p.tw, noload, st_f);
+  } else {
+    fft_run<R, N, TPC, -1, false, true, C>(mine, tt, true, p.tw, ld_u, st_d);
+    fft_run<R, N, TPC, 1, true, true, C>(mine, tt, true, p.tw, ld_l, st_m);
+    fft_run<R, N, TPC, -1, true, true, C>(mine, tt, true, p.tw, ld_l, st_d);
+    fft_run<R, N, TPC, 1, true, false, C>(mine, tt, true, p.tw, ld_l, st_f);
+  }
 }
 
 template <typename R, int N, int ADJ>
