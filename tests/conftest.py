@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests call the C-ABI and are skipped (not failed) only when no GPU
-    # is visible; on a GPU machine a missing library is a hard failure.
+    # is visible; with a GPU present a missing library is a hard failure.
     try:
         import torch
         have_gpu = torch.cuda.is_available()

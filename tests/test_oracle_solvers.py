@@ -62,7 +62,7 @@ def test_physical_stop_rule():
     # s - A u = L_eta (G (V u + s) - u) (Prop. 3.1 key identity), here with
     # the Laplacian and k^2 on one side and the symbol lambda on the other;
     # (ii) the loop stops at the first sweep whose residual is <= rtol, with
-    # the numpy-built dense A as the judge of the returned iterate.
+    # the numpy-built dense A deciding on the returned iterate.
     p = _problem16(seed=3)
     eps = O.choose_eps(p.k2, p.k0sq)
     u, m, rel, hist = O.cbs_iterate(p.k2, p.k0sq, eps, p.source, max_sweeps=5000, rtol=1e-8,
