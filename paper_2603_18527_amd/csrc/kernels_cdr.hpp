@@ -30,6 +30,35 @@
 
 namespace cbs {
 
+// Twiddles of one transform length, held in LDS by the FP32 passes: each pass
+// of each of the chained transforms would otherwise fetch its twiddles from
+// memory again, and these passes are bound by that latency.
+__host__ __device__ constexpr int cdr_tw_max() {
+  const int sizes[] = {16, 32, 64, 128, 192, 256, 288, 384, 512, 1024};
+  int m = 0;
+  for (int n : sizes) m = tw_size(n) > m ? tw_size(n) : m;
+  return m;
+}
+constexpr int kCdrTwMax = cdr_tw_max();
+static_assert(kCdrTwMax % 2 == 0, "twiddle segments are copied as float4");
+
+// Copies the twiddle segment of length N into tws (FP32) and returns the
+// table base to pass to the FFT routines (offsets stay those of the global
+// table); FP64 passes keep the global table.
+template <typename R, int N>
+__device__ __forceinline__ const cpx<R>* cdr_twiddles(const cpx<R>* tw, float4* tws) {
+  if constexpr (sizeof(R) == 4) {
+    constexpr int S = tw_size(N);
+    static_assert(S % 2 == 0 && S <= kCdrTwMax, "twiddle segment");
+    const float4* src = reinterpret_cast<const float4*>(tw + tw_offset(N));
+    for (int i = threadIdx.x; i < S / 2; i += kThreads) tws[i] = src[i];
+    __syncthreads();
+    return reinterpret_cast<const cpx<R>*>(tws) - tw_offset(N);
+  } else {
+    return tw;
+  }
+}
+
 // i xi(e) / N * v for bin e of a length-N transform
 template <typename R, int N>
 __device__ __forceinline__ cpx<R> deriv_factor(int e, cpx<R> v) {
@@ -39,8 +68,10 @@ __device__ __forceinline__ cpx<R> deriv_factor(int e, cpx<R> v) {
 }
 
 template <typename R, int N, int MODE>
-__device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc& d, int row0, cpx<R>* lds) {
+__device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc& d, int row0, cpx<R>* lds,
+                                             float4* tws) {
   using T = RowTile<N>;
+  const cpx<R>* tw = cdr_twiddles<R, N>(p.tw, tws);
   const int tid = threadIdx.x;
   const int r = tid / T::TPF, t = tid - r * T::TPF;
   const int nrows = min(T::RPW, N - row0);
@@ -91,38 +122,40 @@ __device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc&
       else park[g] = p.b[g] - cscale(dx, c2.x) - cscale(u, c1.y) + ld_or_zero(p.s, g);
       return w;
     };
-    fft_pass<R, N, 0, PL, T::TPF, -1, false, false, 1>(mine, t, active, p.tw, ld_u, none);
-    fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, p.tw, dmul);
-    fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, p.tw);
-    fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, p.tw, mmid);
-    fft_inner<R, N, T::TPF, -1, 1>(mine, t, active, p.tw);
-    fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, p.tw, dmul);
+    fft_pass<R, N, 0, PL, T::TPF, -1, false, false, 1>(mine, t, active, tw, ld_u, none);
+    fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, tw, dmul);
+    fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, tw);
+    fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, tw, mmid);
+    fft_inner<R, N, T::TPF, -1, 1>(mine, t, active, tw);
+    fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, tw, dmul);
     if constexpr (MODE == 0) {
       auto tmid = [&](int e, cpx<R> v) { return v + p.inter[rbase + e]; };
-      fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, p.tw);
-      fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, p.tw, tmid);
-      fft_pass<R, N, 1, PL + 1, T::TPF, -1, false, false, 1>(mine, t, active, p.tw, noload, st_s);
+      fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, tw);
+      fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, tw, tmid);
+      fft_pass<R, N, 1, PL + 1, T::TPF, -1, false, false, 1>(mine, t, active, tw, noload, st_s);
     } else {
-      fft_pass<R, N, 1, PL + 1, T::TPF, 1, false, false, 1>(mine, t, active, p.tw, noload, st_f);
+      fft_pass<R, N, 1, PL + 1, T::TPF, 1, false, false, 1>(mine, t, active, tw, noload, st_f);
     }
   } else {
-    fft_run<R, N, T::TPF, -1, false, true>(mine, t, active, p.tw, ld_u, st_d);
-    fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_m);
-    fft_run<R, N, T::TPF, -1, true, true>(mine, t, active, p.tw, ld_l, st_d);
+    fft_run<R, N, T::TPF, -1, false, true>(mine, t, active, tw, ld_u, st_d);
+    fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, tw, ld_l, st_m);
+    fft_run<R, N, T::TPF, -1, true, true>(mine, t, active, tw, ld_l, st_d);
     if constexpr (MODE == 0) {
       auto st_t = [&](int e, cpx<R> v) { mine[lds_pos(e)] = v + p.inter[rbase + e]; };
-      fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, p.tw, ld_l, st_t);
-      fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, p.tw, ld_l, st_s);
+      fft_run<R, N, T::TPF, 1, true, true>(mine, t, active, tw, ld_l, st_t);
+      fft_run<R, N, T::TPF, -1, true, false>(mine, t, active, tw, ld_l, st_s);
     } else {
-      fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, p.tw, ld_l, st_f);
+      fft_run<R, N, T::TPF, 1, true, false>(mine, t, active, tw, ld_l, st_f);
     }
   }
 }
 
 // Column tile of C columns, layout as in col_body (element-interleaved)
 template <typename R, int N, int C, int ADJ>
-__device__ __forceinline__ void cdr_col_body(const Params<R>& p, const InstDesc& d, int col0, cpx<R>* lds) {
+__device__ __forceinline__ void cdr_col_body(const Params<R>& p, const InstDesc& d, int col0, cpx<R>* lds,
+                                             float4* tws) {
   constexpr int TPC = kThreads / C;
+  const cpx<R>* tw = cdr_twiddles<R, N>(p.tw, tws);
   const int tid = threadIdx.x;
   const int c = tid % C, tt = tid / C;
   const long long cbase = d.off + col0 + c;
@@ -158,44 +191,45 @@ __device__ __forceinline__ void cdr_col_body(const Params<R>& p, const InstDesc&
       else p.out[g] = cscale(dy, -c2.y);
       return w;
     };
-    fft_pass<R, N, 0, PL, TPC, -1, false, false, C>(mine, tt, true, p.tw, ld_u, none);
-    fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, p.tw, dmul);
-    fft_inner<R, N, TPC, 1, C>(mine, tt, true, p.tw);
-    fft_bridge<R, N, TPC, 1, -1, C>(mine, tt, true, p.tw, mmid);
-    fft_inner<R, N, TPC, -1, C>(mine, tt, true, p.tw);
-    fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, p.tw, dmul);
-    fft_pass<R, N, 1, PL + 1, TPC, 1, false, false, C>(mine, tt, true, p.tw, noload, st_f);
+    fft_pass<R, N, 0, PL, TPC, -1, false, false, C>(mine, tt, true, tw, ld_u, none);
+    fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, tw, dmul);
+    fft_inner<R, N, TPC, 1, C>(mine, tt, true, tw);
+    fft_bridge<R, N, TPC, 1, -1, C>(mine, tt, true, tw, mmid);
+    fft_inner<R, N, TPC, -1, C>(mine, tt, true, tw);
+    fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, tw, dmul);
+    fft_pass<R, N, 1, PL + 1, TPC, 1, false, false, C>(mine, tt, true, tw, noload, st_f);
   } else {
-    fft_run<R, N, TPC, -1, false, true, C>(mine, tt, true, p.tw, ld_u, st_d);
-    fft_run<R, N, TPC, 1, true, true, C>(mine, tt, true, p.tw, ld_l, st_m);
-    fft_run<R, N, TPC, -1, true, true, C>(mine, tt, true, p.tw, ld_l, st_d);
-    fft_run<R, N, TPC, 1, true, false, C>(mine, tt, true, p.tw, ld_l, st_f);
+    fft_run<R, N, TPC, -1, false, true, C>(mine, tt, true, tw, ld_u, st_d);
+    fft_run<R, N, TPC, 1, true, true, C>(mine, tt, true, tw, ld_l, st_m);
+    fft_run<R, N, TPC, -1, true, true, C>(mine, tt, true, tw, ld_l, st_d);
+    fft_run<R, N, TPC, 1, true, false, C>(mine, tt, true, tw, ld_l, st_f);
   }
 }
 
 template <typename R, int N, int ADJ>
 __device__ __forceinline__ void cdr_col_dispatch_n(const Params<R>& p, const InstDesc& d, int col0,
-                                                   cpx<R>* lds) {
+                                                   cpx<R>* lds, float4* tws) {
   constexpr int C0 = col_tile_default(N);
   constexpr int EB = int(sizeof(cpx<R>));
   const int c = sizeof(R) == 4 ? d.ctile : d.ctile64;
   if constexpr (col_tile_valid(N, C0, EB))
-    if (c == C0) { cdr_col_body<R, N, C0, ADJ>(p, d, col0, lds); return; }
+    if (c == C0) { cdr_col_body<R, N, C0, ADJ>(p, d, col0, lds, tws); return; }
   if constexpr (col_tile_valid(N, C0 / 2, EB))
-    if (c == C0 / 2) { cdr_col_body<R, N, (C0 / 2 >= 2 ? C0 / 2 : 2), ADJ>(p, d, col0, lds); return; }
+    if (c == C0 / 2) { cdr_col_body<R, N, (C0 / 2 >= 2 ? C0 / 2 : 2), ADJ>(p, d, col0, lds, tws); return; }
   if constexpr (col_tile_valid(N, C0 * 2, EB))
-    if (c == C0 * 2) { cdr_col_body<R, N, (C0 * 2 <= 32 ? C0 * 2 : 32), ADJ>(p, d, col0, lds); return; }
+    if (c == C0 * 2) { cdr_col_body<R, N, (C0 * 2 <= 32 ? C0 * 2 : 32), ADJ>(p, d, col0, lds, tws); return; }
 }
 
 template <typename R, int MODE>
 __global__ __launch_bounds__(kThreads) void k_cdr_row(Params<R> p) {
   __shared__ cpx<R> lds[kRowLds];
+  __shared__ float4 tws[sizeof(R) == 4 ? kCdrTwMax / 2 : 1];
   const int2 w = p.items[blockIdx.x];
   const InstDesc d = p.inst[w.x];
   switch (d.n) {
 #define CBS_CDR_ROW_CASE(N) \
   case N:                   \
-    cdr_row_body<R, N, MODE>(p, d, w.y, lds); \
+    cdr_row_body<R, N, MODE>(p, d, w.y, lds, tws); \
     break;
     CBS_FOR_EACH_N(CBS_CDR_ROW_CASE)
 #undef CBS_CDR_ROW_CASE
@@ -207,13 +241,14 @@ __global__ __launch_bounds__(kThreads) void k_cdr_row(Params<R> p) {
 template <typename R, int ADJ>
 __global__ __launch_bounds__(kThreads) void k_cdr_col(Params<R> p) {
   extern __shared__ float4 smem_raw[];
+  __shared__ float4 tws[sizeof(R) == 4 ? kCdrTwMax / 2 : 1];
   cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
   const int2 w = p.items[blockIdx.x];
   const InstDesc d = p.inst[w.x];
   switch (d.n) {
 #define CBS_CDR_COL_CASE(N) \
   case N:                   \
-    cdr_col_dispatch_n<R, N, ADJ>(p, d, w.y, lds); \
+    cdr_col_dispatch_n<R, N, ADJ>(p, d, w.y, lds, tws); \
     break;
     CBS_FOR_EACH_N(CBS_CDR_COL_CASE)
 #undef CBS_CDR_COL_CASE
