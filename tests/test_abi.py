@@ -110,3 +110,35 @@ def test_setup_ws_rejects_bad_workspace_without_gpu():
     assert setup(ctypes.c_void_p(1 << 20), need - 256) == cbs.CBS_ERR_WORKSPACE
     assert "need" in cbs.last_error()
     assert h.value is None
+
+
+def test_setup_cdr_argument_errors_without_gpu():
+    # every check below fails before the library touches the device
+    lib = cbs.load()
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)
+
+    def setup(sizes, bg, ks=fake, vel=fake, out=True, dtype=cbs.CBS_C64):
+        n = (ctypes.c_int32 * max(1, len(sizes)))(*sizes)
+        b = None if bg is None else (ctypes.c_double * len(bg))(*bg)
+        return lib.cbs_setup_cdr(ctypes.byref(h) if out else None, len(sizes), n, ks, vel, b, dtype, None)
+
+    good = [1.0, 0.3, -0.2, 0.5]
+    assert setup([64], good, out=False) == cbs.CBS_ERR_ARG
+    assert setup([64], good, ks=None) == cbs.CBS_ERR_ARG
+    assert setup([64], good, vel=None) == cbs.CBS_ERR_ARG
+    assert setup([64], None) == cbs.CBS_ERR_ARG
+    assert setup([], good) == cbs.CBS_ERR_ARG
+    assert setup([64], good, dtype=3) == cbs.CBS_ERR_ARG
+    assert setup([100], good) == cbs.CBS_ERR_SIZE
+    assert setup([64], [1.0, float("inf"), 0.0, 0.5]) == cbs.CBS_ERR_ARG
+    # sigma0 = 0: L0 vanishes at xi = 0
+    assert setup([64], [1.0, 0.3, -0.2, 0.0]) == cbs.CBS_ERR_ILLCOND
+    # kappa0 |xi|^2 + sigma0 = 0 on the bin xi = (2 pi / 64, 0) with v0 . xi = 0 there
+    a = 2 * 3.141592653589793 / 64
+    assert setup([64], [1.0, 0.0, 0.7, -a * a]) == cbs.CBS_ERR_ILLCOND
+    assert "vanishes" in cbs.last_error()
+    assert setup([64, 32], good + [1.0, 0.0, 0.0, 0.0]) == cbs.CBS_ERR_ILLCOND
+    assert "instance 1" in cbs.last_error()
+    assert h.value is None
+    assert lib.cbs_born_adjoint(None, fake, fake, None) == cbs.CBS_ERR_ARG
