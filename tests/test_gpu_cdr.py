@@ -242,3 +242,26 @@ def test_cdr_argument_checks():
         cbs.CdrPlan(cbs.pack([one48 + 0j], torch.complex64), cbs.pack([0j * one48], torch.complex64), [48],
                     [(1.0, 0.0, 0.0, 0.5)])
     assert e.value.status == cbs.CBS_ERR_SIZE
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_cdr_radix3_sizes(dtype):
+    # plans with radix-3 passes (288 = 8.4.3.3, 384 = 8.2.3.8) through the
+    # derivative passes, the Green pass and the adjoint
+    sizes = [288, 384]
+    probs = _problems(sizes, 960)
+    plan = _plan(probs, dtype)
+    tdt = TDT[dtype]
+    rng = np.random.default_rng(961)
+    u0 = [S.random_field_c(n, rng) for n in sizes]
+    u = cbs.pack(u0, tdt)
+    s = cbs.pack([p.source for p in probs], tdt)
+    y = plan.apply(u, s)
+    g = plan.born_adjoint(u)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        m = _medium(p)
+        e1 = rel_err(_unpack(y, sizes)[i], O.cdr_apply(m, u0[i], p.source))
+        e2 = rel_err(_unpack(g, sizes)[i], O.cdr_born_adjoint(m, u0[i]))
+        say(f"[cdr radix 3] dtype={dtype} n={p.n}: apply {e1:.1e} adjoint {e2:.1e}")
+        assert e1 <= TOL[dtype] and e2 <= TOL[dtype]
