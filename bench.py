@@ -617,6 +617,9 @@ def main():
             "sweeps_per_chain": chain,
             "algorithmic_bytes_per_sweep": BYTES_PER_CELL * cells,
             "event_ms_per_sweep": ev_ms,
+            # measured HBM bytes (counters) per cell and the DRAM-side rate they imply
+            "traffic_bytes_per_cell": None if traffic is None else traffic / cells,
+            "traffic_gbs": None if traffic is None else traffic / (ev_ms * 1e-3) / 1e9,
         },
     }
     line["npbs_step"] = npbs_throughput(plan, sizes, s)
