@@ -295,7 +295,7 @@ def fp64_physical_relres(p, plan, u, s):
 
 
 def cdr_throughput():
-    """Convection-diffusion-reaction plans (App. C) on a ragged batch of 64
+    """Convection-diffusion-reaction plans (App. B.1) on a ragged batch of 64
     instances (sizes as ragged64): G_cdr (V_cdr u + s) and R^H e, timed with
     HIP events on the launch stream; the FP32 apply is compared with an FP64
     plan of the same batch on the GPU."""

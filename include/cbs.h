@@ -157,8 +157,8 @@ cbs_status cbs_setup_ws(cbs_plan* plan, int batch, const int32_t* n, const void*
 
 /*
  * cbs_setup_cdr -- plan for the periodic convection-diffusion-reaction
- *   problem -div(kappa grad u) + v . grad u + sigma u = s (App. C,
- *   "Convection-diffusion-reaction", Eqs. cdr_pde to cdr_G_symbol) with the
+ *   problem -div(kappa grad u) + v . grad u + sigma u = s (App. B.1,
+ *   Eqs. cdr_pde to cdr_G_symbol; App. C "CDR case" restates the symbol) with the
  *   constant background L0 = -kappa0 Lap + v0 . grad + sigma0, G = L0^-1
  *   (Fourier symbol 1/(kappa0 |xi|^2 + i v0 . xi + sigma0)) and
  *   V = L0 - L = div(dkappa grad) - dv . grad - dsigma.  Derivatives are
@@ -189,6 +189,12 @@ cbs_status cbs_setup_cdr(cbs_plan* plan, int batch, const int32_t* n, const void
 /* Total packed cells (sum n[i]^2) and the per-instance k0^2 and eps in use
  * (host arrays of length batch, may be NULL). */
 cbs_status cbs_plan_info(cbs_plan plan, int64_t* cells, double* k0sq, double* eps);
+
+/* Execution layout of a plan (host outputs, nullable): the number of lane
+ * streams its sweep chains fork into (0 = the caller's stream only, else 2)
+ * and the column tile width each instance's column launches use (FP32
+ * kernels for CBS_C64 plans, FP64 kernels for CBS_C128 plans). */
+cbs_status cbs_plan_layout(cbs_plan plan, int32_t* lanes, int32_t* tiles);
 
 /*
  * cbs_apply -- y = G (V u + s)   (Sec. 4.1, the Born fixed-point map).

@@ -25,7 +25,7 @@ against the paper:
   * the metric-matched residual loss (Sec. 4.2) and its gradient by torch
     autograd through this forward;
   * the convection-diffusion-reaction operators G_cdr, V_cdr, A_cdr and the
-    CDR metric-matched objective (App. C, "Convection-diffusion-reaction").
+    CDR metric-matched objective (App. B.1, Eqs. cdr_pde to cdr_bs_loss_eq).
 
 Notation: the paper's eta is the damping called eps here.  Fields are
 (N, N) arrays indexed [y, x].
@@ -300,7 +300,8 @@ def cbs_iterate_dirichlet(k2, k0sq, eps, s, max_sweeps: int = 2500, rtol: float 
 
 
 # ---------------------------------------------------------------------------
-# Convection-diffusion-reaction (App. C, "Convection-diffusion-reaction")
+# Convection-diffusion-reaction (App. B.1, Eqs. cdr_pde to cdr_G_symbol;
+# App. C, "CDR case", restates the symbol)
 # ---------------------------------------------------------------------------
 #
 # L_cdr u = -div(kappa grad u) + v . grad u + sigma u with constant background
@@ -558,24 +559,23 @@ def fgmres(k2, k0sq, eps, s, x0=None, restart: int = 30, sweeps: int = 4,
 # ---------------------------------------------------------------------------
 
 def unrolled_loss(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma",
-                  normalise: bool = False, bc: str = "periodic") -> torch.Tensor:
+                  bc: str = "periodic") -> torch.Tensor:
     """ell = || W * (G s - (I - G V) u_K) ||^2 with u_{m+1} = u_m + gamma r(u_m).
 
     weight "gamma" uses W = gamma; "one" uses W = 1 (the residual of the
     metric-matched loss L_bs^{R_eta}, Sec. 4.2); "physical" measures the
     unpreconditioned residual instead, ell = || s - A u_K ||^2 (the residual
-    of L_dir, Sec. 4, and of L_bs^{l2}, Sec. 4.2).  With normalise=True the
-    squared norm is divided by ||G s||^2 (W residuals) or ||s||^2
-    (physical).  eps and k0^2 are constants; k2 and u0 may require grad.
+    of L_dir, Sec. 4, and of L_bs^{l2}, Sec. 4.2).  The ratio forms of these
+    losses divide by ||G s||^2 or ||s||^2, constants the caller applies.
+    eps and k0^2 are constants; k2 and u0 may require grad.
     bc="dirichlet" uses the five-point Dirichlet operators instead (the
     Newton-state instance of the metric-matched loss, App. B Eq. nl_bs_loss,
     with k^2 = 2 u_m).
     """
     if bc == "periodic":
-        sweep, resid, grn, hel = cbs_sweep, cbs_residual, green, helmholtz
+        sweep, resid, hel = cbs_sweep, cbs_residual, helmholtz
     elif bc == "dirichlet":
-        sweep, resid, grn, hel = (cbs_sweep_dirichlet, cbs_residual_dirichlet, green_dirichlet,
-                                  helmholtz_dirichlet)
+        sweep, resid, hel = cbs_sweep_dirichlet, cbs_residual_dirichlet, helmholtz_dirichlet
     else:
         raise ValueError(bc)
     u = as_c(u0) if not torch.is_tensor(u0) else u0
@@ -583,18 +583,13 @@ def unrolled_loss(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma",
         u = sweep(k2, k0sq, eps, u, s)
     if weight == "physical":
         r = as_c(s) - hel(k2, u)
-        den = as_c(s)
     else:
         r = resid(k2, k0sq, eps, u, s)
         if weight == "gamma":
             r = gamma(k2, k0sq, eps) * r
         elif weight != "one":
             raise ValueError(weight)
-        den = grn(as_c(s), k0sq, eps)
-    val = torch.sum(r.real ** 2 + r.imag ** 2)
-    if normalise:
-        val = val / torch.sum(den.real ** 2 + den.imag ** 2)
-    return val
+    return torch.sum(r.real ** 2 + r.imag ** 2)
 
 
 def loss_and_grad(k2, k0sq, eps, u0, s, steps: int, weight: str = "gamma", bc: str = "periodic"):

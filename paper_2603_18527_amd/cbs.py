@@ -46,6 +46,7 @@ SIGNATURES = {
     "cbs_setup_cdr": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "cbs_workspace_size": (_i32, [_i32, _vp, _i32, _i32, _u32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
+    "cbs_plan_layout": (_i32, [_vp, _vp, _vp]),
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
@@ -314,6 +315,13 @@ class Plan:
         t = (ctypes.c_int32 * self.batch)()
         _check(load().cbs_autotune(self._h, t, _stream(stream)))
         return list(t)
+
+    def layout(self):
+        """(lane streams used by sweep chains, column tile width per instance)."""
+        lanes = ctypes.c_int32()
+        t = (ctypes.c_int32 * self.batch)()
+        _check(load().cbs_plan_layout(self._h, ctypes.byref(lanes), t))
+        return int(lanes.value), list(t)
 
     def set_tile(self, columns: int, n: int = 0):
         _check(load().cbs_set_tile(self._h, int(n), int(columns)))

@@ -234,11 +234,38 @@ void build_items(cbs_plan p) {
   }
 }
 
-// Upper bound on column items (tile width 2 everywhere), for allocation.
+// Upper bound on column items (tile width 2 everywhere, the narrowest width
+// compiled), for allocation.  An instance of n columns has ceil(n / c) tiles:
+// Dirichlet sizes are odd and their last tile is partial.
 size_t max_col_items(cbs_plan p) {
   size_t m = 0;
-  for (int n : p->n) m += n / 2;
+  for (int n : p->n) m += (n + 1) / 2;
   return m;
+}
+
+// Capacity of each work-list buffer, in items.
+size_t item_capacity(cbs_plan p) { return std::max(max_col_items(p), p->row_items.size()); }
+
+// Every column list a plan can form (any compiled width of any size) fits the
+// work-list buffers; checked when the buffers are sized and before uploads.
+cbs_status check_item_capacity(cbs_plan p) {
+  const size_t cap = item_capacity(p);
+  for (int elem : {8, 16}) {
+    size_t worst = 0;
+    for (int n : p->n) {
+      const int m = p->tlen(n);
+      size_t most = 0;
+      for (int c = 2; c <= 32; c *= 2)
+        if (col_tile_valid(m, c, elem)) most = std::max(most, size_t((n + c - 1) / c));
+      worst += most;
+    }
+    if (worst > cap)
+      return fail(CBS_ERR_WORKSPACE, "work-list capacity " + std::to_string(cap) + " below " +
+                                         std::to_string(worst) + " column tiles");
+  }
+  if (p->row_items.size() > cap || p->col_items32.size() > cap || p->col_items64.size() > cap)
+    return fail(CBS_ERR_WORKSPACE, "work list longer than its buffer");
+  return CBS_OK;
 }
 
 void set_full_view(cbs_plan p) {
@@ -355,6 +382,7 @@ cbs_status build_compact_view(cbs_plan p, const std::vector<char>& keep, hipStre
 }
 
 cbs_status upload_items(cbs_plan p, hipStream_t st) {
+  CHK(check_item_capacity(p));
   set_full_view(p);
   CHK(build_lanes(p, p->full, std::vector<char>(p->batch, 1), st));
   HIPCHK(hipMemcpyAsync(p->d_inst, p->inst.data(), p->inst.size() * sizeof(InstDesc),
@@ -1357,7 +1385,7 @@ std::vector<std::pair<void**, size_t>> buffer_requests(cbs_plan p) {
     req.push_back({reinterpret_cast<void**>(&p->d_dots), 2 * (m + 2) * nrow * sizeof(double)});
   }
   // work lists (capacity: tile width 2 everywhere)
-  const size_t cap = std::max(max_col_items(p), nrow) * sizeof(int2);
+  const size_t cap = item_capacity(p) * sizeof(int2);
   for (int2** d : {&p->d_col_items32, &p->d_col_items64, &p->compact.rows, &p->compact.cols32,
                    &p->compact.cols64, &p->full.lrows, &p->full.lcols32, &p->full.lcols64,
                    &p->compact.lrows, &p->compact.lcols32, &p->compact.lcols64})
@@ -1459,6 +1487,7 @@ cbs_status cbs_workspace_size(int batch, const int32_t* n, int dtype, int max_re
   CHK(check_setup_args(batch, n, dtype, max_restart, flags));
   cbs_plan_s p;
   init_layout(&p, batch, n, dtype, max_restart, flags);
+  CHK(check_item_capacity(&p));
   *bytes = request_bytes(buffer_requests(&p));
   return CBS_OK;
 }
@@ -1656,6 +1685,14 @@ cbs_status cbs_plan_info(cbs_plan p, int64_t* cells, double* k0sq, double* eps) 
     if (k0sq) k0sq[i] = p->k0sq[i];
     if (eps) eps[i] = p->eps[i];
   }
+  return CBS_OK;
+}
+
+cbs_status cbs_plan_layout(cbs_plan p, int32_t* lanes, int32_t* tiles) {
+  if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
+  if (lanes) *lanes = p->full.nlanes;
+  if (tiles)
+    for (int i = 0; i < p->batch; ++i) tiles[i] = p->dtype == CBS_C64 ? p->inst[i].ctile : p->inst[i].ctile64;
   return CBS_OK;
 }
 

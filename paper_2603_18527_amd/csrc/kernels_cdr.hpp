@@ -1,5 +1,6 @@
-// Spectral-derivative passes for convection-diffusion-reaction plans (App. C,
-// "Convection-diffusion-reaction").
+// Spectral-derivative passes for convection-diffusion-reaction plans (App. B.1,
+// Eqs. cdr_pde, cdr_L0 and cdr_V; the symbol of G_cdr is Eq. cdr_G_symbol,
+// restated in App. C, "CDR case").
 //
 // V_cdr u = d/dx(dkappa du/dx) + d/dy(dkappa du/dy) - dv . grad u - dsigma u
 // needs derivatives of products with the coefficient fields, so it is not

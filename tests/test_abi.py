@@ -142,3 +142,23 @@ def test_setup_cdr_argument_errors_without_gpu():
     assert "instance 1" in cbs.last_error()
     assert h.value is None
     assert lib.cbs_born_adjoint(None, fake, fake, None) == cbs.CBS_ERR_ARG
+
+
+def test_workspace_covers_partial_dirichlet_column_tiles():
+    # Dirichlet sizes are odd, so an instance of n columns has ceil(n / c)
+    # column tiles.  At the narrowest compiled width (2) 32 instances of
+    # n = 255 need 32 * 128 work items per list; cbs_workspace_size checks
+    # every list it sizes against the tiles of every compiled width and
+    # fails with CBS_ERR_WORKSPACE if one would not fit.
+    for n in (143, 191, 255, 95, 7):
+        sizes = [n] * 32
+        ws = cbs.workspace_size(sizes, dirichlet=True)
+        assert ws > 0 and ws % 256 == 0
+        assert cbs.workspace_size(sizes + [n], dirichlet=True) > ws
+    # the lists of a ragged Dirichlet batch fit too
+    assert cbs.workspace_size([7, 255, 143, 191, 511, 63], dirichlet=True) > 0
+
+
+def test_plan_layout_null_plan():
+    lib = cbs.load()
+    assert lib.cbs_plan_layout(None, None, None) == cbs.CBS_ERR_ARG

@@ -1,5 +1,5 @@
-"""GPU convection-diffusion-reaction plans (App. C, "Convection-diffusion-
-reaction") against the FP64 oracle: G_cdr (V_cdr u + s), the Born residual
+"""GPU convection-diffusion-reaction plans (App. B.1, Eqs. cdr_pde to
+cdr_G_symbol) against the FP64 oracle: G_cdr (V_cdr u + s), the Born residual
 with norms, the physical residual s - A_cdr u, the adjoint R^H e, and the
 metric-matched loss with its gradient through torch.autograd.  Bars: FP32
 plans 1e-5 relative (FP32 rounding of the transforms and of the four

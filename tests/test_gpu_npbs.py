@@ -11,7 +11,7 @@ import torch
 import oracle as O
 import synthetic as S
 from paper_2603_18527_amd import cbs
-from gpu_helpers import plan_for, random_problem, rel_err, say, to_list
+from gpu_helpers import elem_err, plan_for, random_problem, rel_err, say, to_list
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,10 @@ def test_npbs_steps_match_oracle(dtype):
         for _ in range(3):
             x = O.npbs_step(ki, plan.k0sq[i], plan.eps[i], x, probs[i].source, wf[i], wl[i])
         e = rel_err(ug, x)
-        say(f"[npbs] dtype={dtype} instance {i} n={sizes[i]}: rel err {e:.2e}")
+        emax = elem_err(ug, x)
+        say(f"[npbs] dtype={dtype} instance {i} n={sizes[i]}: rel err {e:.2e}, max cell err / rms {emax:.2e}")
         assert e <= TOL[dtype]
+        assert emax <= 10 * TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])

@@ -15,7 +15,7 @@ import torch
 import oracle as O
 import synthetic as S
 from paper_2603_18527_amd import cbs
-from gpu_helpers import plan_for, random_problem, rel_err, say, to_list
+from gpu_helpers import elem_err, plan_for, random_problem, rel_err, say, to_list
 
 pytestmark = pytest.mark.gpu
 
@@ -51,8 +51,10 @@ def test_apply_each_size(n, dtype):
         assert abs(plan.eps[i] - O.choose_eps(ki, plan.k0sq[i])) <= 1e-12 * plan.eps[i]
         ref = O.cbs_apply(ki, plan.k0sq[i], plan.eps[i], ui, si)
         err = rel_err(yi, ref)
-        say(f"   instance {i}: rel err {err:.3e}")
+        emax = elem_err(yi, ref)
+        say(f"   instance {i}: rel err {err:.3e}, max cell err / rms {emax:.3e}")
         assert err <= TOL[dtype]
+        assert emax <= 10 * TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
@@ -218,10 +220,90 @@ def test_fused_sweep_chain(dtype):
             last = O.cbs_residual(ki, plan.k0sq[i], plan.eps[i], ref, si)
             ref = O.cbs_sweep(ki, plan.k0sq[i], plan.eps[i], ref, si)
         err = rel_err(gi, ref)
-        say(f"   instance {i}: rel err after 5 fused sweeps {err:.2e}")
+        emax = elem_err(gi, ref)
+        say(f"   instance {i}: rel err after 5 fused sweeps {err:.2e}, max cell err / rms {emax:.2e}")
         assert err <= TOL[dtype] * 10
+        assert emax <= TOL[dtype] * 100
         nref = float(torch.sum(torch.abs(last) ** 2))
         assert abs(float(n2[i]) - nref) <= 1e-4 * nref
+
+
+# The configuration the benchmark times: one plan of more than 2^21 cells, so
+# sweep chains fork into two lanes, with every size the ragged workloads use
+# and the column tiles a plan starts with (the widths the autotuner settles on
+# for these sizes), then again after cbs_autotune.  2,135,040 cells.
+BENCH_SIZES = [1024, 512, 512, 384, 384, 288, 256, 256, 192, 128]
+BENCH_SWEEPS = 5
+
+
+@pytest.fixture(scope="module")
+def bench_path_case():
+    assert sum(n * n for n in BENCH_SIZES) >= 1 << 21
+    probs = [random_problem(n, seed=1500 + i, source="point", cmax=1.5 + 0.3 * i, ppw=6.0 + (i % 6))
+             for i, n in enumerate(BENCH_SIZES)]
+    rng = np.random.default_rng(1501)
+    # inputs rounded to complex64 once: both precisions and the oracle see the same values
+    k2 = cbs.pack([p.k2 for p in probs], torch.complex64)
+    u = cbs.pack([S.random_field_c(p.n, rng) for p in probs], torch.complex64)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    k0sq = [p.k0sq for p in probs]
+    plan32 = cbs.Plan(k2, BENCH_SIZES, k0sq=k0sq)
+    eps = plan32.eps
+    refs, last = [], []
+    for i, (ki, ui, si) in enumerate(zip(to_list(k2, BENCH_SIZES), to_list(u, BENCH_SIZES),
+                                         to_list(s, BENCH_SIZES))):
+        x = ui
+        for m in range(BENCH_SWEEPS):
+            r = O.cbs_residual(ki, k0sq[i], eps[i], x, si)
+            x = x + O.gamma(ki, k0sq[i], eps[i]) * r
+        refs.append(x)
+        last.append(float(torch.sum(torch.abs(r) ** 2)))
+    yield dict(k2=k2, u=u, s=s, k0sq=k0sq, eps=eps, plan32=plan32, refs=refs, last=last)
+    plan32.close()
+
+
+def _check_chain(plan, case, dtype, label):
+    tdt = TDT[dtype]
+    x = case["u"].to(tdt)
+    n2 = plan.sweep(x, case["s"].to(tdt), count=BENCH_SWEEPS, norms=True)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, (gi, ref) in enumerate(zip(to_list(x, BENCH_SIZES), case["refs"])):
+        err, emax = rel_err(gi, ref), elem_err(gi, ref)
+        worst = max(worst, err)
+        say(f"   [{label}] n={BENCH_SIZES[i]}: rel err {err:.2e}, max cell err / rms {emax:.2e}")
+        assert err <= TOL[dtype] * 10
+        assert emax <= TOL[dtype] * 100
+        nref = case["last"][i]
+        assert abs(float(n2[i]) - nref) <= (1e-4 if dtype == cbs.CBS_C64 else 1e-10) * nref
+    return worst
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_sweep_chain_bench_path(bench_path_case, dtype):
+    # the multi-sweep chain (k_row_fwd, then k_col / k_row_sweep pairs, then
+    # k_col / k_row_inv) over two lanes, at the starting tiles and after
+    # autotuning, element by element against BENCH_SWEEPS oracle sweeps
+    case = bench_path_case
+    say(f"[bench-path sweeps] sizes={BENCH_SIZES} dtype={dtype}")
+    if dtype == cbs.CBS_C64:
+        plan = case["plan32"]
+    else:
+        plan = cbs.Plan(case["k2"].to(torch.complex128), BENCH_SIZES, k0sq=case["k0sq"],
+                        dtype=cbs.CBS_C128)
+        assert plan.eps == case["eps"]
+    lanes, tiles = plan.layout()
+    say(f"   lanes={lanes} tiles={dict(zip(BENCH_SIZES, tiles))}")
+    assert lanes == 2
+    if dtype == cbs.CBS_C64:
+        assert dict(zip(BENCH_SIZES, tiles)) == {1024: 4, 512: 8, 384: 4, 288: 4, 256: 8, 192: 8, 128: 8}
+    _check_chain(plan, case, dtype, "start tiles")
+    tuned = plan.autotune()
+    say(f"   autotuned tiles={dict(zip(BENCH_SIZES, tuned))}")
+    assert plan.layout() == (2, tuned)
+    _check_chain(plan, case, dtype, "autotuned")
+    if dtype != cbs.CBS_C64:
+        plan.close()
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])

@@ -1,5 +1,5 @@
-"""Pins of the oracle's convection-diffusion-reaction operators (App. C,
-"Convection-diffusion-reaction"): closed forms of spectral derivatives and of
+"""Pins of the oracle's convection-diffusion-reaction operators (App. B.1,
+Eqs. cdr_pde to cdr_G_symbol): closed forms of spectral derivatives and of
 A_cdr on band-limited fields, a single Fourier mode through G_cdr, the decay
 rates of the textbook 1D convection-diffusion Green's function (which fix the
 sign of the convection term), the split identity I - G V = G A with A taken
