@@ -264,7 +264,7 @@ def bench_path_case():
 
 def _check_chain(plan, case, dtype, label):
     tdt = TDT[dtype]
-    x = case["u"].to(tdt)
+    x = case["u"].to(tdt).clone()   # sweeps run in place
     n2 = plan.sweep(x, case["s"].to(tdt), count=BENCH_SWEEPS, norms=True)
     torch.cuda.synchronize()
     worst = 0.0
@@ -273,7 +273,7 @@ def _check_chain(plan, case, dtype, label):
         worst = max(worst, err)
         say(f"   [{label}] n={BENCH_SIZES[i]}: rel err {err:.2e}, max cell err / rms {emax:.2e}")
         assert err <= TOL[dtype] * 10
-        assert emax <= TOL[dtype] * 100
+        assert emax <= TOL[dtype] * 20
         nref = case["last"][i]
         assert abs(float(n2[i]) - nref) <= (1e-4 if dtype == cbs.CBS_C64 else 1e-10) * nref
     return worst
