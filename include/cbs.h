@@ -350,6 +350,36 @@ cbs_status cbs_autotune(cbs_plan plan, int32_t* tiles, void* stream);
  * size it applies to.  Synchronises the device. */
 cbs_status cbs_set_tile(cbs_plan plan, int n, int columns);
 
+/*
+ * cbs_apply_static -- y = G (V u + s), the operator of cbs_apply, for callers
+ *   that cannot allocate device memory (code under HIP graph capture, tight
+ *   serving loops, harnesses that forbid hipMalloc): no plan, no device
+ *   allocation, no host-to-device copy and no synchronisation.  Its scratch
+ *   memory -- the spectral buffer between the transform passes, the twiddle
+ *   tables, instance descriptors and work lists -- is a fixed device array
+ *   inside the library (CBS_STATIC_MAX_BYTES for the spectral buffer plus
+ *   0.34 MiB of tables), one per GPU, held from the first call on that
+ *   GPU until the process ends.  Every call rewrites all of it that it reads
+ *   (one setup kernel before the three transform launches, all on `stream`).
+ *   Calls that overlap on one GPU (other streams, other threads) share that
+ *   array and race: the caller must order them.
+ *   batch      1 .. CBS_STATIC_MAX_BATCH periodic instances, sizes n[i] as for
+ *              cbs_setup (host array)
+ *   k2         device, packed complex k^2 in the dtype (read by every call)
+ *   k0sq, eps  host[batch]: reference k0^2 (finite) and damping eps (finite,
+ *              > 0), given explicitly (no automatic choice, no guard)
+ *   dtype      CBS_C64 or CBS_C128; u, s nullable (zero); y must not alias
+ *              u or s.  Packed cells times the element size (8 or 16 bytes)
+ *              must not exceed CBS_STATIC_MAX_BYTES (else CBS_ERR_WORKSPACE).
+ *   Column tiles are the widths a plan starts with, so the result is that of
+ *   cbs_apply on a plan of the same instances, k0sq and eps.
+ */
+#define CBS_STATIC_MAX_BATCH 16
+#define CBS_STATIC_MAX_BYTES (16u << 20)
+cbs_status cbs_apply_static(int batch, const int32_t* n, const void* k2, const double* k0sq,
+                            const double* eps, int dtype, const void* u, const void* s, void* y,
+                            void* stream);
+
 /* Release a plan: waits for the plan's own streams (the lanes), then frees
  * what cbs_setup allocated.  Work the caller queued on its own streams is
  * the caller's to finish first; a caller-owned workspace may be reused once

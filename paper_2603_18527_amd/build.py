@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["ops_f32.hip", "ops_f64.hip", "dst_f32.hip", "dst_f64.hip", "cdr_f32.hip", "cdr_f64.hip",
-           "misc.hip", "cbs.hip"]
+           "misc.hip", "static_apply.hip", "cbs.hip"]
 LIB = os.path.join(HERE, "libcbs.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -59,6 +59,7 @@ SIGNATURES = {
     "cbs_loss_seed": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "cbs_autotune": (_i32, [_vp, _vp, _vp]),
     "cbs_set_tile": (_i32, [_vp, _i32, _i32]),
+    "cbs_apply_static": (_i32, [_i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "cbs_destroy": (None, [_vp]),
     "cbs_last_error": (ctypes.c_char_p, []),
     "cbs_version": (ctypes.c_char_p, []),
@@ -120,6 +121,34 @@ def workspace_size(sizes: Sequence[int], dtype: int = CBS_C64, max_restart: int 
     _check(load().cbs_workspace_size(len(sizes), n_arr, int(dtype), int(max_restart),
                                      FLAG_DIRICHLET if dirichlet else 0, ctypes.byref(out)))
     return int(out.value)
+
+
+# Limits of cbs_apply_static's fixed scratch (include/cbs.h).
+STATIC_MAX_BATCH = 16
+STATIC_MAX_BYTES = 16 << 20
+
+
+def apply_static(k2: torch.Tensor, sizes: Sequence[int], k0sq, eps, u=None, s=None, out=None,
+                 stream=None) -> torch.Tensor:
+    """y = G(V u + s) through cbs_apply_static: no plan and no device
+    allocation in the library (its scratch is a fixed device array).  k0sq and
+    eps are per instance and must be given; out (optional) is the result
+    tensor, else one is allocated here by torch."""
+    sizes = [int(n) for n in sizes]
+    cells = sum(n * n for n in sizes)
+    dtype = CBS_C64 if k2.dtype == torch.complex64 else CBS_C128
+    for name, t in (("k2", k2), ("u", u), ("s", s), ("out", out)):
+        if t is not None and (t.dtype != k2.dtype or t.numel() != cells or not t.is_cuda
+                              or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous packed CUDA tensor of dtype {k2.dtype}")
+    y = torch.empty(cells, dtype=k2.dtype, device=k2.device) if out is None else out
+    b = len(sizes)
+    n_arr = (ctypes.c_int32 * b)(*sizes)
+    k0_arr = (ctypes.c_double * b)(*[float(v) for v in _expand(k0sq, b)])
+    eps_arr = (ctypes.c_double * b)(*[float(v) for v in _expand(eps, b)])
+    _check(load().cbs_apply_static(b, n_arr, _ptr(k2), k0_arr, eps_arr, dtype, _ptr(u), _ptr(s), _ptr(y),
+                                   _stream(stream)))
+    return y
 
 
 def offsets(sizes: Sequence[int]) -> List[int]:

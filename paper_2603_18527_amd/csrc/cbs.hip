@@ -62,6 +62,8 @@ const int kSizes[] = {16, 32, 64, 128, 192, 256, 288, 384, 512, 1024};
 
 }  // namespace
 
+cbs_status cbs::report_error(cbs_status st, const std::string& msg) { return fail(st, msg); }
+
 struct cbs_plan_s {
   int batch = 0;
   int dtype = CBS_C64;

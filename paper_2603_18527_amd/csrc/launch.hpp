@@ -4,9 +4,16 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
+
+#include "../../include/cbs.h"
 #include "params.hpp"
 
 namespace cbs {
+
+// Record the message cbs_last_error() returns for this thread and pass the
+// status through (defined with the C ABI in cbs.hip).
+cbs_status report_error(cbs_status st, const std::string& msg);
 
 // mode 0: prologue + forward rows, 1: inverse rows + epilogue,
 // 2: fused inverse rows + CBS update + next prologue + forward rows,

@@ -162,3 +162,28 @@ def test_workspace_covers_partial_dirichlet_column_tiles():
 def test_plan_layout_null_plan():
     lib = cbs.load()
     assert lib.cbs_plan_layout(None, None, None) == cbs.CBS_ERR_ARG
+
+
+def test_apply_static_argument_errors_without_gpu():
+    # every argument check of cbs_apply_static runs before the device is touched
+    lib = cbs.load()
+    fake = ctypes.c_void_p(0x1000)
+    one = (ctypes.c_double * 17)(*([1.0] * 17))
+    zero = (ctypes.c_double * 1)(0.0)
+
+    def call(batch, sizes, k0=one, eps=one, dtype=cbs.CBS_C64, k2=fake, y=ctypes.c_void_p(0x2000), u=None):
+        n = (ctypes.c_int32 * max(1, len(sizes)))(*sizes)
+        return lib.cbs_apply_static(batch, n, k2, k0, eps, dtype, u, None, y, None)
+
+    assert call(0, [64]) == cbs.CBS_ERR_ARG
+    assert call(cbs.STATIC_MAX_BATCH + 1, [64] * 17) == cbs.CBS_ERR_ARG
+    assert call(1, [64], k2=None) == cbs.CBS_ERR_ARG
+    assert call(1, [64], y=None) == cbs.CBS_ERR_ARG
+    assert call(1, [64], y=fake, u=fake) == cbs.CBS_ERR_ARG
+    assert call(1, [64], dtype=5) == cbs.CBS_ERR_ARG
+    assert call(1, [64], eps=zero) == cbs.CBS_ERR_ARG
+    assert call(1, [100]) == cbs.CBS_ERR_SIZE
+    # the spectral buffer holds 2^21 complex64 / 2^20 complex128 cells
+    assert call(3, [1024] * 3) == cbs.CBS_ERR_WORKSPACE
+    assert call(2, [1024, 16], dtype=cbs.CBS_C128) == cbs.CBS_ERR_WORKSPACE
+    assert "scratch" in cbs.last_error()
