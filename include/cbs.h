@@ -30,10 +30,16 @@
  *    provides to cbs_setup_ws (cbs_workspace_size bytes).  No other call
  *    allocates device memory.
  *  * `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *    cbs_apply, cbs_residual, cbs_adjoint_step and cbs_loss_seed are
- *    stream-ordered and return without synchronising.  cbs_iterate and
- *    fgmres_solve run a host-driven loop on the stream and synchronise it
- *    before returning (their host outputs are then valid).
+ *    Operator calls (cbs_apply, cbs_residual, cbs_sweep, cbs_relres, the
+ *    adjoint and loss calls ...) and the solvers cbs_iterate_async and
+ *    fgmres_solve_async are stream-ordered: they only enqueue work, return
+ *    without synchronising, allocate nothing and can be captured into a
+ *    HIP graph; their outputs are device arrays.  cbs_iterate and
+ *    fgmres_solve run a host-driven loop instead (it reads each chunk's
+ *    status to stop early and to shrink the work lists to the running
+ *    instances) and synchronise the stream before returning host outputs.
+ *    Setup-class calls (cbs_setup*, cbs_autotune, cbs_set_tile,
+ *    cbs_destroy) synchronise.
  *  * Inputs are never modified, except the in/out solution u of the solvers.
  *
  * Errors
@@ -172,7 +178,8 @@ cbs_status cbs_setup_ws(cbs_plan* plan, int batch, const int32_t* n, const void*
  *                else CBS_ERR_ILLCOND)
  *   n            host int32[batch], grid sizes as for cbs_setup (periodic)
  *   The coefficients are meant real; their imaginary parts are not used.
- *   The plan owns its memory (no workspace form) and synchronises `stream`.
+ *   The plan allocates its memory (cbs_setup_cdr_ws: the caller provides
+ *   it) and synchronises `stream`.
  *   On such a plan cbs_apply, cbs_residual, cbs_helmholtz_residual (which
  *   then returns s - A u with A the CDR operator above), cbs_born_adjoint,
  *   cbs_plan_info (k0sq = kappa0, eps = sigma0), cbs_autotune, cbs_set_tile
@@ -185,6 +192,14 @@ cbs_status cbs_setup_ws(cbs_plan* plan, int batch, const int32_t* n, const void*
  */
 cbs_status cbs_setup_cdr(cbs_plan* plan, int batch, const int32_t* n, const void* kappa_sigma,
                          const void* velocity, const double* background, int dtype, void* stream);
+
+/* cbs_setup_cdr with caller-owned device memory (the plan then allocates
+ * nothing): workspace as for cbs_setup_ws, of at least
+ * cbs_workspace_size_cdr bytes (host-only query; touches no device). */
+cbs_status cbs_setup_cdr_ws(cbs_plan* plan, int batch, const int32_t* n, const void* kappa_sigma,
+                            const void* velocity, const double* background, int dtype, void* workspace,
+                            size_t workspace_bytes, void* stream);
+cbs_status cbs_workspace_size_cdr(int batch, const int32_t* n, int dtype, size_t* bytes);
 
 /* Total packed cells (sum n[i]^2) and the per-instance k0^2 and eps in use
  * (host arrays of length batch, may be NULL). */
@@ -250,6 +265,17 @@ cbs_status cbs_helmholtz_residual(cbs_plan plan, const void* u, const void* s, v
                                   double* norm2, void* stream);
 
 /*
+ * cbs_relres -- per-instance relative residual of a field u (FP64 sums):
+ *   stop CBS_STOP_BORN: ||G(V u + s) - u|| / ||G s|| (the preconditioned
+ *   residual, Sec. 4.1); CBS_STOP_PHYSICAL: the paper's unified rule
+ *   rTol = ||s - A u|| / ||s|| (Sec. 5; A as in cbs_helmholtz_residual, the
+ *   CDR operator on CDR plans).  u, s required; relres DEVICE double[batch].
+ *   Two transform pairs (Born) or one and a norm pass (physical).  Uses the
+ *   plan's scratch, so calls on one plan serialise.
+ */
+cbs_status cbs_relres(cbs_plan plan, const void* u, const void* s, int stop, double* relres, void* stream);
+
+/*
  * cbs_iterate -- stationary CBS (Sec. 3.1, Eq. CBS) per instance until its
  *   relative residual is at most rtol.
  *   u          device, in/out: initial guess and result
@@ -291,6 +317,28 @@ cbs_status fgmres_solve(cbs_plan plan, void* u, const void* s, int restart, int 
                         int32_t* status, void* stream);
 
 /*
+ * cbs_iterate_async, fgmres_solve_async -- the solvers above as stream-
+ *   ordered calls: no host synchronisation, nothing allocated, capturable
+ *   into a HIP graph.  iters, relres, status are DEVICE arrays [batch]
+ *   (nullable), valid once the stream reaches the end of the call; an
+ *   instance that did not finish within the budget reports
+ *   CBS_INST_MAX_ITERS.  Instead of stopping when every instance is done,
+ *   they enqueue a fixed budget -- ceil(max_sweeps / check_every) + 1 chunks
+ *   of cbs_iterate, ceil(max_iters / restart) + 1 restart cycles of
+ *   fgmres_solve -- in which finished instances are masked out of every
+ *   launch (their workgroups return at once), and the work lists are never
+ *   shrunk.  Results are the same as the host-driven calls' (graph replay
+ *   off) when the budget is not the binding limit.  Bounds: at most 1e5
+ *   chunks / 1e5 Arnoldi steps.
+ */
+cbs_status cbs_iterate_async(cbs_plan plan, void* u, const void* s, int max_sweeps, double rtol,
+                             int check_every, int stop, int32_t* iters, double* relres,
+                             int32_t* status, void* stream);
+cbs_status fgmres_solve_async(cbs_plan plan, void* u, const void* s, int restart, int inner_sweeps,
+                              int max_iters, double rtol, int32_t* iters, double* relres,
+                              int32_t* status, void* stream);
+
+/*
  * cbs_adjoint_step -- reverse step of u_{m+1} = u_m + gamma r(u_m) for the
  *   metric-matched loss (Sec. 4.2) and medium gradients.  With
  *   t = G^H(conj(gamma) lam_in), G^H = F^-1 diag(1/conj(lambda)) F:
@@ -316,6 +364,21 @@ cbs_status cbs_adjoint_step(cbs_plan plan, const void* u_m, const void* s, const
  *   alias e.  Uses the plan's scratch fields, so calls on one plan serialise.
  */
 cbs_status cbs_born_adjoint(cbs_plan plan, const void* e, void* out, void* stream);
+
+/*
+ * cbs_metric_matched_grad -- the residual of the metric-matched objective
+ *   for a network output x and the residual s it preconditions (Sec. 4.2,
+ *   Eq. L_bs^{R_eta}; Eq. cdr_bs_loss on CDR plans), with its gradient:
+ *     loss_i = || G s - (I - G V) x ||^2   (FP64 sums, DEVICE double[batch],
+ *              nullable)
+ *     grad   = -2 scale_i R^H (G s - R x),  R = I - G V
+ *   (PyTorch's convention d/dRe + i d/dIm).  scale: DEVICE double[batch] or
+ *   NULL (= 1), e.g. the upstream gradient of each instance's loss.  x, grad
+ *   required; s nullable (zero); grad may alias x, not s.  Uses the plan's
+ *   scratch fields, so calls on one plan serialise.
+ */
+cbs_status cbs_metric_matched_grad(cbs_plan plan, const void* x, const void* s, const double* scale,
+                                   double* loss, void* grad, void* stream);
 
 /*
  * cbs_loss_seed -- a residual loss of the iterate u_K, its adjoint seed

@@ -44,6 +44,9 @@ SIGNATURES = {
     "cbs_setup_ws": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _i32, _u32, _vp,
                             ctypes.c_size_t, _vp]),
     "cbs_setup_cdr": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "cbs_setup_cdr_ws": (_i32, [ctypes.POINTER(_vp), _i32, _vp, _vp, _vp, _vp, _i32, _vp, ctypes.c_size_t,
+                                _vp]),
+    "cbs_workspace_size_cdr": (_i32, [_i32, _vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_workspace_size": (_i32, [_i32, _vp, _i32, _i32, _u32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
     "cbs_plan_layout": (_i32, [_vp, _vp, _vp]),
@@ -52,10 +55,14 @@ SIGNATURES = {
     "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "cbs_npbs_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "cbs_helmholtz_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "cbs_relres": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "cbs_iterate": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
     "fgmres_solve": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
+    "cbs_iterate_async": (_i32, [_vp, _vp, _vp, _i32, _f64, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "fgmres_solve_async": (_i32, [_vp, _vp, _vp, _i32, _i32, _i32, _f64, _vp, _vp, _vp, _vp]),
     "cbs_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_born_adjoint": (_i32, [_vp, _vp, _vp, _vp]),
+    "cbs_metric_matched_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_loss_seed": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "cbs_autotune": (_i32, [_vp, _vp, _vp]),
     "cbs_set_tile": (_i32, [_vp, _i32, _i32]),
@@ -151,6 +158,14 @@ def apply_static(k2: torch.Tensor, sizes: Sequence[int], k0sq, eps, u=None, s=No
     return y
 
 
+def workspace_size_cdr(sizes: Sequence[int], dtype: int = CBS_C64) -> int:
+    """Device bytes of a convection-diffusion-reaction plan's workspace."""
+    n_arr = (ctypes.c_int32 * len(sizes))(*[int(n) for n in sizes])
+    out = ctypes.c_size_t()
+    _check(load().cbs_workspace_size_cdr(len(sizes), n_arr, int(dtype), ctypes.byref(out)))
+    return int(out.value)
+
+
 def offsets(sizes: Sequence[int]) -> List[int]:
     out, o = [], 0
     for n in sizes:
@@ -204,6 +219,7 @@ class Plan:
         if torch_workspace:
             self._ws = torch.empty(workspace_size(self.sizes, dtype, max_restart, dirichlet), dtype=torch.uint8,
                                    device="cuda")
+            self._ws_stream = torch.cuda.current_stream()
             st = lib.cbs_setup_ws(ctypes.byref(h), self.batch, n_arr, _ptr(k2), k0_arr, eps_arr, dtype,
                                   int(max_restart), flags, _ptr(self._ws), self._ws.numel(),
                                   _stream(stream))
@@ -221,15 +237,12 @@ class Plan:
         self.eps = list(epso)
 
     def __del__(self):
+        # cbs_destroy waits for the plan's own lane streams.  The workspace
+        # tensor goes back to torch's allocator, which orders its reuse after
+        # the work already queued on the streams the plan was called on
+        # (record_stream in _st), so no device-wide synchronisation is needed.
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
-            if getattr(self, "_ws", None) is not None:
-                # queued work of the plan (also on its lane streams) must end
-                # before torch may hand the workspace to someone else
-                try:
-                    torch.cuda.synchronize()
-                except Exception:
-                    pass
             _lib.cbs_destroy(h)
             self._h = None
         self._ws = None
@@ -238,6 +251,15 @@ class Plan:
         self.__del__()
 
     # -- helpers
+    def _st(self, stream):
+        """hipStream_t of a call; the workspace is marked in use on streams
+        other than the one it was allocated on."""
+        st = torch.cuda.current_stream() if stream is None else stream
+        ws = getattr(self, "_ws", None)
+        if ws is not None and st != self._ws_stream:
+            ws.record_stream(st)
+        return ctypes.c_void_p(st.cuda_stream)
+
     def _field(self, t, name):
         if t is None:
             return None
@@ -255,14 +277,14 @@ class Plan:
     def apply(self, u, s, out=None, stream=None):
         y = self.empty() if out is None else self._field(out, "out")
         _check(load().cbs_apply(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
-                                _ptr(y), _stream(stream)))
+                                _ptr(y), self._st(stream)))
         return y
 
     def residual(self, u, s, rhs=None, out=None, norms=True, store=True, stream=None):
         r = (self.empty() if out is None else self._field(out, "out")) if store else None
         n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None
         _check(load().cbs_residual(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
-                                   _ptr(self._field(rhs, "rhs")), _ptr(r), _ptr(n2), _stream(stream)))
+                                   _ptr(self._field(rhs, "rhs")), _ptr(r), _ptr(n2), self._st(stream)))
         return r, n2
 
     def helmholtz_residual(self, u, s, out=None, norms=True, store=True, stream=None):
@@ -270,20 +292,28 @@ class Plan:
         r = (self.empty() if out is None else self._field(out, "out")) if store else None
         n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None
         _check(load().cbs_helmholtz_residual(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
-                                             _ptr(r), _ptr(n2), _stream(stream)))
+                                             _ptr(r), _ptr(n2), self._st(stream)))
         return r, n2
 
+    def relres(self, u, s, stop="born", stream=None) -> torch.Tensor:
+        """Per-instance relative residual (FP64, on the device): "born" is
+        ||G(V u + s) - u|| / ||G s||, "physical" the paper's rTol
+        ||s - A u|| / ||s|| (cbs_relres)."""
+        if stop not in _STOPS:
+            raise ValueError(f"stop must be one of {sorted(_STOPS)}")
+        out = torch.empty(self.batch, dtype=torch.float64, device="cuda")
+        _check(load().cbs_relres(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")), _STOPS[stop],
+                                 _ptr(out), self._st(stream)))
+        return out
+
     def physical_relres(self, u, s, stream=None):
-        """The paper's rTol = ||s - A u|| / ||s|| per instance (FP64 sums)."""
-        _, n2 = self.helmholtz_residual(u, s, norms=True, store=False, stream=stream)
-        sn = torch.stack([torch.linalg.vector_norm(x.to(torch.complex128))
-                          for x in unpack(s, self.sizes)])
-        return (torch.sqrt(n2) / sn).cpu().tolist()
+        """The paper's rTol = ||s - A u|| / ||s|| per instance, as a list."""
+        return self.relres(u, s, "physical", stream).cpu().tolist()
 
     def sweep(self, u, s, count=1, norms=False, stream=None):
         n2 = torch.empty(self.batch, dtype=torch.float64, device="cuda") if norms else None
         _check(load().cbs_sweep(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
-                                int(count), _ptr(n2), _stream(stream)))
+                                int(count), _ptr(n2), self._st(stream)))
         return n2
 
     def npbs_step(self, u, s, wf, wloc=None, count=1, stream=None):
@@ -291,7 +321,7 @@ class Plan:
         M(r) = F^-1(wf * F r) + wloc * r (wf packed per instance on the DFT bins)."""
         _check(load().cbs_npbs_step(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
                                     _ptr(self._field(wf, "wf")), _ptr(self._field(wloc, "wloc")),
-                                    int(count), _stream(stream)))
+                                    int(count), self._st(stream)))
         return u
 
     def iterate(self, u, s, max_sweeps=2500, rtol=1e-6, check_every=50, use_graph=True, stream=None,
@@ -305,7 +335,7 @@ class Plan:
         _check(load().cbs_iterate(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
                                   int(max_sweeps), float(rtol), int(check_every), _STOPS[stop],
                                   it, rel, stat,
-                                  1 if use_graph else 0, _stream(stream)), allow_not_converged=True)
+                                  1 if use_graph else 0, self._st(stream)), allow_not_converged=True)
         return list(it), list(rel), list(stat)
 
     def fgmres(self, u, s, restart=30, sweeps=4, max_iters=2500, rtol=1e-6, stream=None):
@@ -314,19 +344,56 @@ class Plan:
         stat = (ctypes.c_int32 * self.batch)()
         _check(load().fgmres_solve(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
                                    int(restart), int(sweeps), int(max_iters), float(rtol), it, rel, stat,
-                                   _stream(stream)), allow_not_converged=True)
+                                   self._st(stream)), allow_not_converged=True)
         return list(it), list(rel), list(stat)
+
+    def iterate_async(self, u, s, max_sweeps=2500, rtol=1e-6, check_every=50, stop="born", stream=None):
+        """cbs_iterate_async: stream-ordered, no host synchronisation; returns
+        device tensors (iters int32, relres float64, status int32)."""
+        if stop not in _STOPS:
+            raise ValueError(f"stop must be one of {sorted(_STOPS)}")
+        it = torch.empty(self.batch, dtype=torch.int32, device="cuda")
+        rel = torch.empty(self.batch, dtype=torch.float64, device="cuda")
+        stat = torch.empty(self.batch, dtype=torch.int32, device="cuda")
+        _check(load().cbs_iterate_async(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                        int(max_sweeps), float(rtol), int(check_every), _STOPS[stop],
+                                        _ptr(it), _ptr(rel), _ptr(stat), self._st(stream)))
+        return it, rel, stat
+
+    def fgmres_async(self, u, s, restart=30, sweeps=4, max_iters=2500, rtol=1e-6, stream=None):
+        """fgmres_solve_async: stream-ordered; device tensors (iters, relres, status)."""
+        it = torch.empty(self.batch, dtype=torch.int32, device="cuda")
+        rel = torch.empty(self.batch, dtype=torch.float64, device="cuda")
+        stat = torch.empty(self.batch, dtype=torch.int32, device="cuda")
+        _check(load().fgmres_solve_async(self._h, _ptr(self._field(u, "u")), _ptr(self._field(s, "s")),
+                                         int(restart), int(sweeps), int(max_iters), float(rtol),
+                                         _ptr(it), _ptr(rel), _ptr(stat), self._st(stream)))
+        return it, rel, stat
+
+    def metric_matched_grad(self, x, s, scale=None, grad=None, stream=None):
+        """(loss, grad): loss_i = ||G s - (I - G V) x||^2 (float64, device) and
+        grad = -2 scale_i R^H (G s - R x) (cbs_metric_matched_grad); scale is
+        a float64 device tensor [batch] or None (= 1)."""
+        g = self.empty() if grad is None else self._field(grad, "grad")
+        loss = torch.empty(self.batch, dtype=torch.float64, device="cuda")
+        if scale is not None:
+            scale = scale.to(device="cuda", dtype=torch.float64).contiguous()
+            if scale.numel() != self.batch:
+                raise ValueError("scale: one value per instance")
+        _check(load().cbs_metric_matched_grad(self._h, _ptr(self._field(x, "x")), _ptr(self._field(s, "s")),
+                                              _ptr(scale), _ptr(loss), _ptr(g), self._st(stream)))
+        return loss, g
 
     def born_adjoint(self, e, out=None, stream=None):
         """R^H e for R = I - G V (cbs_born_adjoint)."""
         y = self.empty() if out is None else self._field(out, "out")
-        _check(load().cbs_born_adjoint(self._h, _ptr(self._field(e, "e")), _ptr(y), _stream(stream)))
+        _check(load().cbs_born_adjoint(self._h, _ptr(self._field(e, "e")), _ptr(y), self._st(stream)))
         return y
 
     def adjoint_step(self, u_m, s, lam_in, lam_out, grad_k2, stream=None):
         _check(load().cbs_adjoint_step(self._h, _ptr(self._field(u_m, "u_m")), _ptr(self._field(s, "s")),
                                        _ptr(self._field(lam_in, "lam_in")), _ptr(self._field(lam_out, "lam_out")),
-                                       _ptr(self._field(grad_k2, "grad_k2")), _stream(stream)))
+                                       _ptr(self._field(grad_k2, "grad_k2")), self._st(stream)))
 
     def loss_seed(self, u_k, s, weight="gamma", lam_out=None, grad_k2=None, stream=None):
         """weight: "gamma" (W = gamma), "one" (W = 1) or "physical" (s - A u_K);
@@ -336,13 +403,13 @@ class Plan:
         loss = torch.empty(self.batch, dtype=torch.float64, device="cuda")
         _check(load().cbs_loss_seed(self._h, _ptr(self._field(u_k, "u_k")), _ptr(self._field(s, "s")),
                                     _weight_code(weight), _ptr(loss), _ptr(lam), _ptr(grad),
-                                    _stream(stream)))
+                                    self._st(stream)))
         return loss, lam, grad
 
     def autotune(self, stream=None) -> List[int]:
         """Per-size-class column tile autotuning; returns the width per instance."""
         t = (ctypes.c_int32 * self.batch)()
-        _check(load().cbs_autotune(self._h, t, _stream(stream)))
+        _check(load().cbs_autotune(self._h, t, self._st(stream)))
         return list(t)
 
     def layout(self):
@@ -384,9 +451,11 @@ class CdrPlan(Plan):
         bg_arr = (ctypes.c_double * (4 * self.batch))(*[v for b in bg for v in b])
         h = ctypes.c_void_p()
         self.dirichlet = False
-        self._ws = None
-        _check(lib.cbs_setup_cdr(ctypes.byref(h), self.batch, n_arr, _ptr(kappa_sigma.contiguous()),
-                                 _ptr(velocity.contiguous()), bg_arr, dtype, _stream(stream)))
+        self._ws = torch.empty(workspace_size_cdr(self.sizes, dtype), dtype=torch.uint8, device="cuda")
+        self._ws_stream = torch.cuda.current_stream()
+        _check(lib.cbs_setup_cdr_ws(ctypes.byref(h), self.batch, n_arr, _ptr(kappa_sigma.contiguous()),
+                                    _ptr(velocity.contiguous()), bg_arr, dtype, _ptr(self._ws),
+                                    self._ws.numel(), _stream(stream)))
         self._h = h
         self.max_restart = 0
         self.background = bg
@@ -402,22 +471,21 @@ class MetricMatchedLoss(torch.autograd.Function):
     """ell_b = || G s - (I - G V) x ||^2 per instance: the residual of the
     metric-matched objective (Sec. 4.2; Eq. cdr_bs_loss for CDR plans) for a
     network output x (with s the residual being preconditioned).  Backward:
-    dl/dx = -2 R^H (G s - R x) by cbs_born_adjoint (PyTorch's convention)."""
+    dl/dx = -2 R^H (G s - R x) by cbs_metric_matched_grad (PyTorch's convention)."""
 
     @staticmethod
     def forward(ctx, x, plan, s):
-        r, n2 = plan.residual(x.detach().contiguous(), s)
+        x = x.detach().contiguous()
+        _, n2 = plan.residual(x, s, store=False)
         ctx.plan = plan
-        ctx.r = r
+        ctx.x = x
+        ctx.s = s
         return n2
 
     @staticmethod
     def backward(ctx, gout):
-        plan, r = ctx.plan, ctx.r
-        g = plan.born_adjoint(r)
-        scale = torch.repeat_interleave(gout.to(torch.float64),
-                                        torch.tensor([n * n for n in plan.sizes], device=gout.device))
-        gx = g * (-2.0 * scale).to(g.real.dtype)
+        # the library recomputes the residual and forms -2 gout_i R^H r
+        _, gx = ctx.plan.metric_matched_grad(ctx.x, ctx.s, scale=gout)
         ctx.plan = None
         return gx, None, None
 

@@ -106,6 +106,7 @@ struct cbs_plan_s {
   double* d_bnorm_phys = nullptr;  // ||s|| per instance (physical stop rule)
   double* d_rtol = nullptr;
   double* d_rtol32 = nullptr;      // rtol of the FP32 per-sweep estimate
+  double* d_tmp = nullptr;         // 2 x batch per-instance sums (cbs_relres)
   int* d_maxs = nullptr;
   // FGMRES
   cpx<double>* d_vbasis = nullptr;
@@ -614,16 +615,12 @@ cbs_status sweep_impl(cbs_plan p, void* u, const void* s, int count, double* nor
   return CBS_OK;
 }
 
-// One refinement chunk of stationary CBS:
-//   r64 = G(V u64 + s64) - u64 (FP64; narrowed into c), status check in FP64,
-//   e = gamma c, (chunk - 1) sweeps e <- e + gamma (G(V e) + c - e) in the
-//   operator precision with a per-sweep norm estimate, then u64 += e.
-// In exact arithmetic this is exactly `chunk` CBS sweeps from u64.
+// The FP64 residual of the FP64 iterate (narrowed into c) and the status
+// decision of every instance not yet final.
 template <typename R>
-cbs_status enqueue_chunk(cbs_plan p, int chunk, int stop, hipStream_t st) {
+cbs_status enqueue_check(cbs_plan p, int stop, hipStream_t st) {
   IterState is = iter_state(p);
   cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
-  cpx<R>* e = static_cast<cpx<R>*>(p->d_e);
   {
     Params<double> q = base_params<double>(p);
     q.u = p->d_u64;
@@ -652,6 +649,21 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, int stop, hipStream_t st) {
       launch_check64(p->batch, st, is, p->d_inst, p->d_partials);
     }
   }
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+// One refinement chunk of stationary CBS:
+//   r64 = G(V u64 + s64) - u64 (FP64; narrowed into c), status check in FP64,
+//   e = gamma c, (chunk - 1) sweeps e <- e + gamma (G(V e) + c - e) in the
+//   operator precision with a per-sweep norm estimate, then u64 += e.
+// In exact arithmetic this is exactly `chunk` CBS sweeps from u64.
+template <typename R>
+cbs_status enqueue_chunk(cbs_plan p, int chunk, int stop, hipStream_t st) {
+  IterState is = iter_state(p);
+  cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
+  cpx<R>* e = static_cast<cpx<R>*>(p->d_e);
+  CHK(enqueue_check<R>(p, stop, st));
   // The FP32 estimate of each sweep stops an instance early only under the
   // Born rule (it estimates the Born residual); it always counts the sweep.
   is.rtol = p->d_rtol32;
@@ -1027,6 +1039,104 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
   return CBS_OK;
 }
 
+// ---- stream-ordered solvers ----------------------------------------------------------------
+//
+// The same chunks and Arnoldi steps as the host-driven loops above, enqueued
+// for a fixed budget without any host synchronisation, so a caller can
+// overlap a solve with other work or capture it into a graph.  Instances
+// that finish early are masked out of every later launch (their workgroups
+// return at once); there is no compaction of the work lists.
+
+template <typename R>
+cbs_status solver_load(cbs_plan p, const void* u, const void* s, hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    launch_widen_all(st, static_cast<const cpx<float>*>(u), p->d_u64, p->cells);
+    launch_widen_all(st, static_cast<const cpx<float>*>(s), p->d_s64, p->cells);
+    HIPCHK(hipGetLastError());
+  } else {
+    HIPCHK(hipMemcpyAsync(p->d_u64, u, p->cells * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(p->d_s64, s, p->cells * 16, hipMemcpyDeviceToDevice, st));
+  }
+  return CBS_OK;
+}
+
+template <typename R>
+cbs_status solver_store(cbs_plan p, void* u, hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    PwParams<float> w{};
+    w.op = PW_NARROW;
+    w.x64 = p->d_u64;
+    w.e_out = static_cast<cpx<float>*>(u);
+    return launch_pw(p, w, st);
+  } else {
+    HIPCHK(hipMemcpyAsync(u, p->d_u64, p->cells * 16, hipMemcpyDeviceToDevice, st));
+    return CBS_OK;
+  }
+}
+
+template <typename R>
+cbs_status iterate_async_impl(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol, int chunk,
+                              int stop, int32_t* iters, double* relres, int32_t* status, hipStream_t st) {
+  const int B = p->batch;
+  p->view = &p->full;
+  FullViewOnExit restore{p};
+  CHK(solver_load<R>(p, u, s, st));
+  launch_solver_init(st, p->d_status, p->d_iters, p->d_relres, nullptr, p->d_rtol, p->d_rtol32, p->d_maxs, B,
+                     rtol, stop == CBS_STOP_PHYSICAL ? 0.0 : rtol, max_sweeps);
+  {
+    Params<double> q = base_params<double>(p);
+    q.s = p->d_s64;
+    q.epi = EPI_RESID;
+    CHK(run_pipeline(p, q, st));
+    launch_set_bnorm(B, st, iter_state(p), p->d_inst, p->d_partials);
+  }
+  if (stop == CBS_STOP_PHYSICAL) {
+    Params<double> q = base_params<double>(p);
+    q.s = p->d_s64;
+    q.pro = PRO_U;
+    q.sym = SYM_LAP;
+    q.epi = EPI_LAP;
+    CHK(run_pipeline(p, q, st));
+    IterState ip = iter_state(p);
+    ip.bnorm = p->d_bnorm_phys;
+    launch_set_bnorm(B, st, ip, p->d_inst, p->d_partials);
+  }
+  // ceil(max_sweeps / chunk) chunks bring every instance to a final status
+  // or to its sweep cap; one more chunk start and a last check confirm them
+  const long long nchunks = ((long long)max_sweeps + chunk - 1) / chunk + 1;
+  for (long long c = 0; c < nchunks; ++c) CHK(enqueue_chunk<R>(p, chunk, stop, st));
+  CHK(enqueue_check<R>(p, stop, st));
+  CHK(solver_store<R>(p, u, st));
+  launch_solver_out(st, iter_state(p), B, iters, relres, status);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+template <typename R>
+cbs_status fgmres_async_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, int max_iters,
+                             double rtol, int32_t* iters, double* relres, int32_t* status, hipStream_t st) {
+  const int B = p->batch;
+  p->view = &p->full;
+  FullViewOnExit restore{p};
+  CHK(solver_load<R>(p, u, s, st));
+  launch_solver_init(st, p->d_status, p->d_iters, p->d_relres, p->d_kjend, p->d_rtol, nullptr, p->d_maxs, B,
+                     rtol, 0.0, max_iters);
+  CHK(fg_restart(p, m, 1, st));
+  KryParams k = kry_params(p, m);
+  const long long ncycles = ((long long)max_iters + m - 1) / m + 1;
+  for (long long cycle = 0; cycle < ncycles; ++cycle) {
+    CHK(fg_restart(p, m, 0, st));
+    for (int j = 0; j < m; ++j) CHK(fg_step<R>(p, m, j, sweeps, st));
+    launch_backsolve(B, st, k);
+    launch_zupdate(int(p->row_items.size()), st, k, static_cast<const cpx<R>*>(p->d_zbasis), p->d_u64);
+  }
+  CHK(fg_restart(p, m, 0, st));  // true residual of the last update decides the status
+  CHK(solver_store<R>(p, u, st));
+  launch_solver_out(st, iter_state(p), B, iters, relres, status);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
 // ---- NPBS step with a linear Fourier layer ------------------------------------------------
 
 // count steps u <- u + F^-1(wf F r) + wloc r, r = G(V u + s) - u.  Periodic
@@ -1225,6 +1335,70 @@ cbs_status born_adjoint_impl(cbs_plan p, const void* e, void* out, hipStream_t s
   return CBS_OK;
 }
 
+// ---- residual norms and the metric-matched gradient ----------------------------------------
+
+// r = s - A u with the plan's physical operator (A u = -Lap u - k^2 u, or
+// the CDR operator), r nullable, and per-instance sums |r|^2.
+template <typename R>
+cbs_status physical_norm2(cbs_plan p, const void* u, const void* s, void* r, double* norm2, hipStream_t st) {
+  if (p->cdr) return cdr_physical_impl<R>(p, u, s, r, norm2, st);
+  Params<R> q = base_params<R>(p);
+  q.u = static_cast<const cpx<R>*>(u);
+  q.s = static_cast<const cpx<R>*>(s);
+  q.out = static_cast<cpx<R>*>(r);
+  q.pro = PRO_U;
+  q.sym = SYM_LAP;
+  q.epi = EPI_LAP;
+  CHK(run_pipeline(p, q, st));
+  if (norm2) {
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
+    HIPCHK(hipGetLastError());
+  }
+  return CBS_OK;
+}
+
+template <typename R>
+cbs_status relres_impl(cbs_plan p, const void* u, const void* s, int stop, double* relres, hipStream_t st) {
+  double* num = p->d_tmp;
+  double* den = p->d_tmp + p->batch;
+  if (stop == CBS_STOP_BORN) {
+    // ||G(V u + s) - u||^2 and ||G s||^2
+    if (p->cdr) {
+      CHK(cdr_green_impl<R>(p, u, s, nullptr, nullptr, EPI_RESID, num, st));
+      CHK(cdr_green_impl<R>(p, nullptr, s, nullptr, nullptr, EPI_RESID, den, st));
+    } else {
+      CHK(residual_impl<R>(p, u, s, nullptr, nullptr, num, st));
+      CHK(residual_impl<R>(p, nullptr, s, nullptr, nullptr, den, st));
+    }
+  } else {
+    // ||s - A u||^2 and ||s||^2
+    CHK(physical_norm2<R>(p, u, s, nullptr, num, st));
+    launch_norm2_rows(p->view->nrows, st, p->d_inst, p->view->rows, static_cast<const cpx<R>*>(s), p->d_partials);
+    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, den);
+  }
+  launch_ratio(p->batch, st, num, den, relres);
+  HIPCHK(hipGetLastError());
+  return CBS_OK;
+}
+
+// loss_i = ||G s - (I - G V) x||^2 (the Born residual r = G(V x + s) - x),
+// grad = -2 scale_i R^H r with R = I - G V.
+template <typename R>
+cbs_status mm_grad_impl(cbs_plan p, const void* x, const void* s, const double* scale, double* loss,
+                        void* grad, hipStream_t st) {
+  cpx<R>* r = static_cast<cpx<R>*>(p->d_t);
+  if (p->cdr) CHK(cdr_green_impl<R>(p, x, s, nullptr, r, EPI_RESID, loss, st));
+  else CHK(residual_impl<R>(p, x, s, nullptr, r, loss, st));
+  PwParams<R> w{};
+  w.op = PW_SCALE;
+  w.e_in = r;
+  w.e_out = r;
+  w.scale = scale;
+  w.factor = -2.0;
+  CHK(launch_pw(p, w, st));
+  return born_adjoint_impl<R>(p, r, grad, st);
+}
+
 // ---- adjoint -------------------------------------------------------------------------------
 
 template <typename R>
@@ -1366,6 +1540,7 @@ std::vector<std::pair<void**, size_t>> buffer_requests(cbs_plan p) {
       {reinterpret_cast<void**>(&p->d_bnorm), batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_rtol), sizeof(double)},
       {reinterpret_cast<void**>(&p->d_rtol32), sizeof(double)},
+      {reinterpret_cast<void**>(&p->d_tmp), 2 * batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_bnorm_phys), batch * sizeof(double)},
       {reinterpret_cast<void**>(&p->d_maxs), sizeof(int)},
       {reinterpret_cast<void**>(&p->d_scale), batch * sizeof(double)},
@@ -1439,18 +1614,19 @@ cbs_status cbs_setup_ws(cbs_plan* out, int batch, const int32_t* n, const void* 
                     workspace_bytes, stream);
 }
 
-cbs_status cbs_setup_cdr(cbs_plan* out, int batch, const int32_t* n, const void* kappa_sigma,
-                         const void* velocity, const double* background, int dtype, void* stream) {
-  if (!out) return fail(CBS_ERR_ARG, "plan pointer is NULL");
-  *out = nullptr;
-  if (!kappa_sigma || !velocity || !background)
-    return fail(CBS_ERR_ARG, "kappa_sigma, velocity or background is NULL");
+}  // extern "C"
+
+namespace {
+
+// Arguments of a convection-diffusion-reaction plan: finite background
+// constants whose symbol kappa0 |xi|^2 + sigma0 + i v0 . xi vanishes on no bin.
+cbs_status check_cdr_args(int batch, const int32_t* n, const double* background, int dtype) {
   CHK(check_setup_args(batch, n, dtype, 0, 0));
+  if (!background) return fail(CBS_ERR_ARG, "background is NULL");
   for (int i = 0; i < batch; ++i) {
     for (int k = 0; k < 4; ++k)
       if (!std::isfinite(background[4 * i + k]))
         return fail(CBS_ERR_ARG, "background constants must be finite (instance " + std::to_string(i) + ")");
-    // G_cdr needs L0(xi) = kappa0 |xi|^2 + sigma0 + i v0 . xi != 0 on every bin
     const double k0 = background[4 * i], vx = background[4 * i + 1], vy = background[4 * i + 2],
                  s0 = background[4 * i + 3];
     const int nn = n[i];
@@ -1470,9 +1646,52 @@ cbs_status cbs_setup_cdr(cbs_plan* out, int batch, const int32_t* n, const void*
       return fail(CBS_ERR_ILLCOND, "instance " + std::to_string(i) +
                                        ": the background symbol kappa0|xi|^2 + sigma0 + i v0.xi vanishes");
   }
+  return CBS_OK;
+}
+
+cbs_status setup_cdr_common(cbs_plan* out, int batch, const int32_t* n, const void* kappa_sigma,
+                            const void* velocity, const double* background, int dtype, void* ws,
+                            size_t ws_bytes, void* stream) {
+  if (!out) return fail(CBS_ERR_ARG, "plan pointer is NULL");
+  *out = nullptr;
+  if (!kappa_sigma || !velocity || !background)
+    return fail(CBS_ERR_ARG, "kappa_sigma, velocity or background is NULL");
+  CHK(check_cdr_args(batch, n, background, dtype));
   CdrInit c{velocity, background};
-  return setup_impl(out, batch, n, kappa_sigma, nullptr, nullptr, dtype, 0, CBS_FLAG_ONE_STREAM, nullptr, 0,
+  return setup_impl(out, batch, n, kappa_sigma, nullptr, nullptr, dtype, 0, CBS_FLAG_ONE_STREAM, ws, ws_bytes,
                     stream, &c);
+}
+
+}  // namespace
+
+extern "C" {
+
+cbs_status cbs_setup_cdr(cbs_plan* out, int batch, const int32_t* n, const void* kappa_sigma,
+                         const void* velocity, const double* background, int dtype, void* stream) {
+  return setup_cdr_common(out, batch, n, kappa_sigma, velocity, background, dtype, nullptr, 0, stream);
+}
+
+cbs_status cbs_setup_cdr_ws(cbs_plan* out, int batch, const int32_t* n, const void* kappa_sigma,
+                            const void* velocity, const double* background, int dtype, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+  if (!workspace) {
+    if (out) *out = nullptr;
+    return fail(CBS_ERR_ARG, "workspace is NULL");
+  }
+  return setup_cdr_common(out, batch, n, kappa_sigma, velocity, background, dtype, workspace, workspace_bytes,
+                          stream);
+}
+
+cbs_status cbs_workspace_size_cdr(int batch, const int32_t* n, int dtype, size_t* bytes) {
+  if (!bytes) return fail(CBS_ERR_ARG, "bytes is NULL");
+  *bytes = 0;
+  CHK(check_setup_args(batch, n, dtype, 0, 0));
+  cbs_plan_s p;
+  p.cdr = true;
+  init_layout(&p, batch, n, dtype, 0, CBS_FLAG_ONE_STREAM);
+  CHK(check_item_capacity(&p));
+  *bytes = request_bytes(buffer_requests(&p));
+  return CBS_OK;
 }
 
 cbs_status cbs_born_adjoint(cbs_plan p, const void* e, void* out, void* stream) {
@@ -1551,6 +1770,12 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
     p->d_inter = p->d_inter64;
   }
   p->compact.gen = 1;
+  {
+    // capture stream for cbs_iterate's graphs when the caller passes the
+    // null stream (the legacy null stream cannot be captured)
+    hipError_t e = hipStreamCreate(&p->own_stream);
+    if (e != hipSuccess) return bail(CBS_ERR_HIP, std::string("plan stream: ") + hipGetErrorString(e));
+  }
   if (lanes_wanted(p, std::vector<char>(batch, 1))) {
     for (int l = 0; l < 2; ++l) {
       hipError_t e = hipStreamCreateWithFlags(&p->lane_st[l], hipStreamNonBlocking);
@@ -1760,34 +1985,8 @@ cbs_status cbs_helmholtz_residual(cbs_plan p, const void* u, const void* s, void
   if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
   if (r && (r == u || r == s)) return fail(CBS_ERR_ARG, "r must not alias u or s");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (p->cdr) {
-    if (p->dtype == CBS_C64) return cdr_physical_impl<float>(p, u, s, r, norm2, st);
-    return cdr_physical_impl<double>(p, u, s, r, norm2, st);
-  }
-  if (p->dtype == CBS_C64) {
-    Params<float> q = base_params<float>(p);
-    q.u = static_cast<const cpx<float>*>(u);
-    q.s = static_cast<const cpx<float>*>(s);
-    q.out = static_cast<cpx<float>*>(r);
-    q.pro = PRO_U;
-    q.sym = SYM_LAP;
-    q.epi = EPI_LAP;
-    CHK(run_pipeline(p, q, st));
-  } else {
-    Params<double> q = base_params<double>(p);
-    q.u = static_cast<const cpx<double>*>(u);
-    q.s = static_cast<const cpx<double>*>(s);
-    q.out = static_cast<cpx<double>*>(r);
-    q.pro = PRO_U;
-    q.sym = SYM_LAP;
-    q.epi = EPI_LAP;
-    CHK(run_pipeline(p, q, st));
-  }
-  if (norm2) {
-    launch_instance_sums(p->batch, st, p->d_inst, p->d_partials, norm2);
-    HIPCHK(hipGetLastError());
-  }
-  return CBS_OK;
+  if (p->dtype == CBS_C64) return physical_norm2<float>(p, u, s, r, norm2, st);
+  return physical_norm2<double>(p, u, s, r, norm2, st);
 }
 
 cbs_status cbs_npbs_step(cbs_plan p, void* u, const void* s, const void* wf, const void* wloc,
@@ -1825,7 +2024,6 @@ cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, doubl
   if (use_graph && st == nullptr) {
     // The legacy null stream cannot be captured: run on a plan-owned stream
     // ordered after everything already queued on the null stream.
-    if (!p->own_stream) HIPCHK(hipStreamCreate(&p->own_stream));
     hipEvent_t ev;
     HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     hipError_t e1 = hipEventRecord(ev, nullptr);
@@ -1856,6 +2054,60 @@ cbs_status fgmres_solve(cbs_plan p, void* u, const void* s, int restart, int inn
   if (p->dtype == CBS_C64)
     return fgmres_impl<float>(p, u, s, restart, inner_sweeps, max_iters, rtol, iters, relres, status, st);
   return fgmres_impl<double>(p, u, s, restart, inner_sweeps, max_iters, rtol, iters, relres, status, st);
+}
+
+cbs_status cbs_iterate_async(cbs_plan p, void* u, const void* s, int max_sweeps, double rtol,
+                             int check_every, int stop, int32_t* iters, double* relres, int32_t* status,
+                             void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "cbs_iterate_async is not available for convection-diffusion-reaction plans");
+  if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
+  if (stop != CBS_STOP_BORN && stop != CBS_STOP_PHYSICAL)
+    return fail(CBS_ERR_ARG, "stop must be CBS_STOP_BORN or CBS_STOP_PHYSICAL");
+  if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
+  if (max_sweeps < 0 || check_every < 2 || check_every > 100000 || !(rtol >= 0.0))
+    return fail(CBS_ERR_ARG, "need max_sweeps >= 0, 2 <= check_every <= 1e5, rtol >= 0");
+  if ((long long)max_sweeps / check_every > 100000)
+    return fail(CBS_ERR_ARG, "max_sweeps / check_every must not exceed 1e5 chunks");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64)
+    return iterate_async_impl<float>(p, u, s, max_sweeps, rtol, check_every, stop, iters, relres, status, st);
+  return iterate_async_impl<double>(p, u, s, max_sweeps, rtol, check_every, stop, iters, relres, status, st);
+}
+
+cbs_status fgmres_solve_async(cbs_plan p, void* u, const void* s, int restart, int inner_sweeps,
+                              int max_iters, double rtol, int32_t* iters, double* relres, int32_t* status,
+                              void* stream) {
+  if (p && p->cdr) return fail(CBS_ERR_ARG, "fgmres_solve_async is not available for convection-diffusion-reaction plans");
+  if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
+  if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
+  if (restart < 1 || inner_sweeps < 1 || inner_sweeps > 1000 || max_iters < 0 || !(rtol >= 0.0))
+    return fail(CBS_ERR_ARG, "need restart >= 1, 1 <= inner_sweeps <= 1000, max_iters >= 0, rtol >= 0");
+  if (max_iters > 100000) return fail(CBS_ERR_ARG, "max_iters must not exceed 1e5");
+  if (restart > p->max_restart)
+    return fail(CBS_ERR_WORKSPACE, "restart " + std::to_string(restart) + " exceeds the plan's max_restart " +
+                                       std::to_string(p->max_restart));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64)
+    return fgmres_async_impl<float>(p, u, s, restart, inner_sweeps, max_iters, rtol, iters, relres, status, st);
+  return fgmres_async_impl<double>(p, u, s, restart, inner_sweeps, max_iters, rtol, iters, relres, status, st);
+}
+
+cbs_status cbs_relres(cbs_plan p, const void* u, const void* s, int stop, double* relres, void* stream) {
+  if (!p || !u || !s || !relres) return fail(CBS_ERR_ARG, "plan, u, s or relres is NULL");
+  if (stop != CBS_STOP_BORN && stop != CBS_STOP_PHYSICAL)
+    return fail(CBS_ERR_ARG, "stop must be CBS_STOP_BORN or CBS_STOP_PHYSICAL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return relres_impl<float>(p, u, s, stop, relres, st);
+  return relres_impl<double>(p, u, s, stop, relres, st);
+}
+
+cbs_status cbs_metric_matched_grad(cbs_plan p, const void* x, const void* s, const double* scale,
+                                   double* loss, void* grad, void* stream) {
+  if (!p || !x || !grad) return fail(CBS_ERR_ARG, "plan, x or grad is NULL");
+  if (grad == s) return fail(CBS_ERR_ARG, "grad must not alias s");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return mm_grad_impl<float>(p, x, s, scale, loss, grad, st);
+  return mm_grad_impl<double>(p, x, s, scale, loss, grad, st);
 }
 
 cbs_status cbs_adjoint_step(cbs_plan p, const void* u_m, const void* s, const void* lam_in,

@@ -491,7 +491,9 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
   const int cnt = nrows * n;
   const R ie = R(1.0 / d.eps);
   const R k0 = R(d.k0sq), ep = R(d.eps);
-  const double sc = (p.op == PW_SCALE64) ? p.scale[w.x] : 1.0;
+  const double sc = (p.op == PW_SCALE64) ? p.scale[w.x]
+                    : (p.op == PW_SCALE)  ? p.factor * (p.scale ? p.scale[w.x] : 1.0)
+                                          : 1.0;
   for (int j = threadIdx.x; j < cnt; j += kThreads) {
     const long long i = base + j;
     switch (p.op) {
@@ -528,6 +530,9 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
         p.e_out[i] = cpx<R>{R(x.x), R(x.y)};
         break;
       }
+      case PW_SCALE:
+        p.e_out[i] = cscale(p.e_in[i], R(sc));
+        break;
       default: {  // PW_SCALE64
         const cpx<double> x = p.x64[i];
         p.x64[i] = cpx<double>{x.x * sc, x.y * sc};

@@ -54,6 +54,20 @@ void launch_set_bnorm(int batch, hipStream_t st, const IterState& is, const Inst
 void launch_stats(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
                   const cpx<double>* k2, double* partials, int phase);
 void launch_widen_all(hipStream_t st, const cpx<float>* in, cpx<double>* out, long long count);
+// stream-ordered solver state: initial values, and the per-instance results
+// copied to the caller's device arrays (running / pending -> ST_MAXIT)
+void launch_solver_init(hipStream_t st, int* status, int* iters, double* relres, int* kjend,
+                        double* rtol_d, double* rtol32_d, int* max_d, int batch, double rtol,
+                        double rtol32, int max_count);
+void launch_solver_out(hipStream_t st, const IterState& is, int batch, int* o_iters, double* o_relres,
+                       int* o_status);
+// per-row-item partial sums of |x|^2 (then launch_instance_sums), and
+// out = sqrt(num / den) per instance
+void launch_norm2_rows(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
+                       const cpx<float>* x, double* partials);
+void launch_norm2_rows(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
+                       const cpx<double>* x, double* partials);
+void launch_ratio(int batch, hipStream_t st, const double* num, const double* den, double* out);
 void launch_dots(int grid, hipStream_t st, const KryParams& k);
 void launch_dots_finish(int batch, hipStream_t st, const KryParams& k);
 void launch_cgs_update(int grid, hipStream_t st, const KryParams& k);

@@ -395,6 +395,63 @@ __global__ void k_fg_restart(KryParams k, int batch, int first) {
   }
 }
 
+// ---- stream-ordered solver bookkeeping and field norms --------------------------------
+
+// Initial per-instance solver state (replaces host copies, so a solve can be
+// enqueued without synchronising and captured into a graph).
+__global__ void k_solver_init(int* status, int* iters, double* relres, int* kjend, double* rtol_d,
+                              double* rtol32_d, int* max_d, int batch, double rtol, double rtol32,
+                              int max_count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *rtol_d = rtol;
+    if (rtol32_d) *rtol32_d = rtol32;
+    *max_d = max_count;
+  }
+  if (i < batch) {
+    status[i] = ST_RUNNING;
+    iters[i] = 0;
+    relres[i] = 0.0;
+    if (kjend) kjend[i] = 0;
+  }
+}
+
+// Copy the per-instance results to the caller's device arrays; an instance
+// still running (or pending confirmation) when the budget ran out reports
+// ST_MAXIT.
+__global__ void k_solver_out(const int* status, const int* iters, const double* relres, int batch,
+                             int* o_iters, double* o_relres, int* o_status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  const int s = status[i];
+  if (o_iters) o_iters[i] = iters[i];
+  if (o_relres) o_relres[i] = relres[i];
+  if (o_status) o_status[i] = (s == ST_RUNNING || s == ST_PENDING) ? int(ST_MAXIT) : s;
+}
+
+// Partial sums of |x|^2 over one row work item (slot as for the row kernels).
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_norm2_rows(const InstDesc* inst, const int2* items,
+                                                         const cpx<R>* x, double* partials) {
+  __shared__ double red[kThreads / 64];
+  const int2 it = items[blockIdx.x];
+  const InstDesc d = inst[it.x];
+  long long base;
+  int cnt, slot;
+  item_range(d, it.y, base, cnt, slot);
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < cnt; j += kThreads) acc += double(cabs2(x[base + j]));
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) partials[slot] = t;
+}
+
+// out[i] = sqrt(num[i] / den[i]) (sqrt(num[i]) where den[i] is 0).
+__global__ void k_ratio(const double* num, const double* den, double* out, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch) return;
+  out[i] = den[i] > 0.0 ? sqrt(num[i] / den[i]) : sqrt(num[i]);
+}
+
 __global__ void k_widen_all(const cpx<float>* in, cpx<double>* out, long long count) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
        i += (long long)gridDim.x * blockDim.x) {
@@ -433,6 +490,28 @@ void launch_stats(int grid, hipStream_t st, const InstDesc* inst, const int2* it
 }
 void launch_widen_all(hipStream_t st, const cpx<float>* in, cpx<double>* out, long long count) {
   hipLaunchKernelGGL(k_widen_all, dim3(1024), dim3(256), 0, st, in, out, count);
+}
+void launch_solver_init(hipStream_t st, int* status, int* iters, double* relres, int* kjend,
+                        double* rtol_d, double* rtol32_d, int* max_d, int batch, double rtol,
+                        double rtol32, int max_count) {
+  hipLaunchKernelGGL(k_solver_init, dim3((batch + 255) / 256), dim3(256), 0, st, status, iters, relres, kjend,
+                     rtol_d, rtol32_d, max_d, batch, rtol, rtol32, max_count);
+}
+void launch_solver_out(hipStream_t st, const IterState& is, int batch, int* o_iters, double* o_relres,
+                       int* o_status) {
+  hipLaunchKernelGGL(k_solver_out, dim3((batch + 255) / 256), dim3(256), 0, st, is.status, is.iters,
+                     is.relres, batch, o_iters, o_relres, o_status);
+}
+void launch_norm2_rows(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
+                       const cpx<float>* x, double* partials) {
+  hipLaunchKernelGGL(k_norm2_rows<float>, dim3(grid), dim3(kThreads), 0, st, inst, items, x, partials);
+}
+void launch_norm2_rows(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
+                       const cpx<double>* x, double* partials) {
+  hipLaunchKernelGGL(k_norm2_rows<double>, dim3(grid), dim3(kThreads), 0, st, inst, items, x, partials);
+}
+void launch_ratio(int batch, hipStream_t st, const double* num, const double* den, double* out) {
+  hipLaunchKernelGGL(k_ratio, dim3((batch + 255) / 256), dim3(256), 0, st, num, den, out, batch);
 }
 void launch_dots(int grid, hipStream_t st, const KryParams& k) {
   hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kThreads), 0, st, k);

@@ -160,7 +160,8 @@ enum PwOp {
   PW_ADD_WIDE = 2,     // x64 += e_in
   PW_WIDEN = 3,        // x64 = e_in
   PW_NARROW = 4,       // e_out = (R) x64
-  PW_SCALE64 = 5       // x64 *= scale[instance] (FP64)
+  PW_SCALE64 = 5,      // x64 *= scale[instance] (FP64)
+  PW_SCALE = 6         // e_out = e_in * factor * scale[instance] (scale NULL: 1), operator precision
 };
 
 template <typename R>
@@ -173,7 +174,8 @@ struct PwParams {
   const cpx<R>* e_in;
   cpx<R>* e_out;
   cpx<R>* c_out;
-  const double* scale;  // per-instance factor for PW_SCALE64
+  const double* scale;  // per-instance factor for PW_SCALE64 / PW_SCALE
+  double factor;        // constant factor of PW_SCALE
   const int* mask;
   int mask_mode;
   int op;

@@ -65,6 +65,10 @@ def test_calls_with_null_plan_fail_cleanly():
     assert lib.fgmres_solve(None, None, None, 10, 4, 10, 1e-6, None, None, None, None) == cbs.CBS_ERR_ARG
     assert lib.cbs_adjoint_step(None, None, None, None, None, None, None) == cbs.CBS_ERR_ARG
     assert lib.cbs_set_tile(None, 0, 16) == cbs.CBS_ERR_ARG
+    assert lib.cbs_iterate_async(None, None, None, 10, 1e-6, 10, 0, None, None, None, None) == cbs.CBS_ERR_ARG
+    assert lib.fgmres_solve_async(None, None, None, 10, 4, 10, 1e-6, None, None, None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_relres(None, None, None, 0, None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_metric_matched_grad(None, None, None, None, None, None, None) == cbs.CBS_ERR_ARG
     lib.cbs_destroy(None)
 
 
@@ -187,3 +191,26 @@ def test_apply_static_argument_errors_without_gpu():
     assert call(3, [1024] * 3) == cbs.CBS_ERR_WORKSPACE
     assert call(2, [1024, 16], dtype=cbs.CBS_C128) == cbs.CBS_ERR_WORKSPACE
     assert "scratch" in cbs.last_error()
+
+
+def test_cdr_workspace_without_gpu():
+    # the CDR plan's workspace holds one more operator-precision field (the
+    # velocity) than a Helmholtz plan's, and no FGMRES bases
+    ws = cbs.workspace_size_cdr([64, 128])
+    assert ws > 0 and ws % 256 == 0
+    assert ws > cbs.workspace_size([64, 128])
+    assert cbs.workspace_size_cdr([64, 128], cbs.CBS_C128) > ws
+    lib = cbs.load()
+    out = ctypes.c_size_t()
+    assert lib.cbs_workspace_size_cdr(1, (ctypes.c_int32 * 1)(100), cbs.CBS_C64, ctypes.byref(out)) == \
+        cbs.CBS_ERR_SIZE
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int32 * 1)(64)
+    fake = ctypes.c_void_p(1 << 20)
+    bg = (ctypes.c_double * 4)(1.0, 0.1, 0.1, 0.5)
+    need = cbs.workspace_size_cdr([64])
+    assert lib.cbs_setup_cdr_ws(ctypes.byref(h), 1, n, fake, fake, bg, cbs.CBS_C64, None, need, None) == \
+        cbs.CBS_ERR_ARG
+    assert lib.cbs_setup_cdr_ws(ctypes.byref(h), 1, n, fake, fake, bg, cbs.CBS_C64, fake, need - 256, None) == \
+        cbs.CBS_ERR_WORKSPACE
+    assert h.value is None

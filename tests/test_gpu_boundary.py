@@ -1,0 +1,201 @@
+"""Stream-ordered and arithmetic-carrying entry points of the boundary:
+
+* cbs_iterate_async / fgmres_solve_async (fixed budget, device outputs, no
+  host synchronisation) against the host-driven cbs_iterate / fgmres_solve:
+  the same kernels run per instance (finished instances are masked instead of
+  compacted away), so results are bitwise equal, also for an instance that
+  runs out of its budget and on a plan with two lanes;
+* cbs_iterate_async captured into a graph and replayed several times, with
+  eager work in between, against the eager call;
+* cbs_relres against the oracle's Born and physical relative residuals
+  (periodic, Dirichlet and convection-diffusion-reaction plans);
+* cbs_metric_matched_grad against torch autograd through the oracle's Born
+  residual (Sec. 4.2, Eq. L_bs^{R_eta}): loss ||G s - (I - G V) x||^2 and
+  gradient, with a per-instance scale, on periodic and Dirichlet plans.
+Bars: FP32 plans 1e-5 relative, FP64 plans 1e-10 (gradient) / 1e-12."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+from paper_2603_18527_amd import cbs
+from gpu_helpers import plan_for, random_problem, rel_err, say, to_list
+
+pytestmark = pytest.mark.gpu
+
+TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
+
+
+def _host(t):
+    return [x for x in t.cpu().tolist()]
+
+
+@pytest.mark.parametrize("dtype,stop", [(cbs.CBS_C64, "born"), (cbs.CBS_C64, "physical"),
+                                        (cbs.CBS_C128, "born")])
+def test_iterate_async_equals_host_loop(dtype, stop):
+    sizes = [192, 64, 128, 64] if dtype == cbs.CBS_C64 else [64, 32, 128]
+    probs = [random_problem(n, seed=1200 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    s = cbs.pack([p.source for p in probs], TDT[dtype])
+    u1, u2 = plan.zeros(), plan.zeros()
+    a = plan.iterate(u1, s, max_sweeps=4000, rtol=1e-6, check_every=20, use_graph=False, stop=stop)
+    it, rel, st = plan.iterate_async(u2, s, max_sweeps=4000, rtol=1e-6, check_every=20, stop=stop)
+    torch.cuda.synchronize()
+    say(f"[iterate async] dtype={dtype} stop={stop}: host {a[0]} / async {_host(it)}")
+    assert a == (_host(it), _host(rel), _host(st))
+    assert all(x == cbs.INST_CONVERGED for x in a[2])
+    assert torch.equal(u1, u2)
+
+
+def test_iterate_async_budget_and_lanes():
+    # two 1024^2 instances: a plan with two lanes; 300 sweeps do not converge
+    sizes = [1024, 1024]
+    probs = [random_problem(n, seed=1250 + i, source="point", ppw=6.0) for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs)
+    assert plan.layout()[0] == 2
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    u1, u2 = plan.zeros(), plan.zeros()
+    a = plan.iterate(u1, s, max_sweeps=300, rtol=1e-9, check_every=50, use_graph=False)
+    it, rel, st = plan.iterate_async(u2, s, max_sweeps=300, rtol=1e-9, check_every=50)
+    torch.cuda.synchronize()
+    say(f"[iterate async lanes] host {a} / async {_host(it)} {_host(st)}")
+    assert a == (_host(it), _host(rel), _host(st))
+    assert all(x == cbs.INST_MAX_ITERS for x in a[2]) and all(k == 300 for k in a[0])
+    assert torch.equal(u1, u2)
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_fgmres_async_equals_host_loop(dtype):
+    sizes = [64, 128, 32]
+    probs = [random_problem(n, seed=1300 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype, restart=10)
+    s = cbs.pack([p.source for p in probs], TDT[dtype])
+    u1, u2 = plan.zeros(), plan.zeros()
+    a = plan.fgmres(u1, s, restart=10, sweeps=3, max_iters=500, rtol=1e-6)
+    it, rel, st = plan.fgmres_async(u2, s, restart=10, sweeps=3, max_iters=500, rtol=1e-6)
+    torch.cuda.synchronize()
+    say(f"[fgmres async] dtype={dtype}: host {a[0]} / async {_host(it)}")
+    assert a == (_host(it), _host(rel), _host(st))
+    assert all(x == cbs.INST_CONVERGED for x in a[2])
+    assert torch.equal(u1, u2)
+
+
+def test_iterate_async_graph_replay():
+    sizes = [128, 64]
+    probs = [random_problem(n, seed=1400 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    ref_u = plan.zeros()
+    ref = plan.iterate_async(ref_u, s, max_sweeps=3000, rtol=1e-6, check_every=25)
+    torch.cuda.synchronize()
+    ref = tuple(_host(t) for t in ref)
+    u = plan.zeros()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture, as torch asks
+        plan.iterate_async(u, s, max_sweeps=3000, rtol=1e-6, check_every=25)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        u.zero_()
+        out = plan.iterate_async(u, s, max_sweeps=3000, rtol=1e-6, check_every=25)
+    for rep in range(3):
+        u.fill_(1.0)           # eager work between the replays
+        plan.apply(u, s)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = tuple(_host(t) for t in out)
+        say(f"[graph replay {rep}] {got[0]} vs eager {ref[0]}")
+        assert got == ref
+        assert torch.equal(u, ref_u)
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_relres_matches_oracle(dtype):
+    tol = 1e-5 if dtype == cbs.CBS_C64 else 1e-12
+    sizes = [64, 32, 128]
+    probs = [random_problem(n, seed=1500 + i) for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    rng = np.random.default_rng(1501)
+    u = cbs.pack([S.random_field_c(n, rng) for n in sizes], TDT[dtype])
+    s = cbs.pack([p.source for p in probs], TDT[dtype])
+    born = _host(plan.relres(u, s, "born"))
+    phys = _host(plan.relres(u, s, "physical"))
+    for i, (ki, ui, si) in enumerate(zip(to_list(k2, sizes), to_list(u, sizes), to_list(s, sizes))):
+        rb = O.born_relres(ki, plan.k0sq[i], plan.eps[i], ui, si)
+        rp = O.physical_relres(ki, ui, si)
+        say(f"[relres] dtype={dtype} n={sizes[i]}: born {born[i]:.6e} / {rb:.6e}, physical {phys[i]:.6e} / {rp:.6e}")
+        assert abs(born[i] - rb) <= tol * rb and abs(phys[i] - rp) <= tol * rp
+    # Dirichlet plans (five-point L_D, DST-I reference)
+    dz = [31, 15]
+    rng = np.random.default_rng(1502)
+    kd = [100.0 + 60.0 * S.gaussian_random_field(n, 4.0, rng) for n in dz]
+    sd = [S.random_field_c(n, rng) for n in dz]
+    ud = [S.random_field_c(n, rng) for n in dz]
+    pd = cbs.Plan(cbs.pack(kd, TDT[dtype]), dz, dtype=dtype, dirichlet=True)
+    tdt = TDT[dtype]
+    gb = _host(pd.relres(cbs.pack(ud, tdt), cbs.pack(sd, tdt), "born"))
+    gp = _host(pd.relres(cbs.pack(ud, tdt), cbs.pack(sd, tdt), "physical"))
+    for i in range(len(dz)):
+        ki = O.as_c(kd[i])
+        rb = O.norm(O.cbs_residual_dirichlet(ki, pd.k0sq[i], pd.eps[i], ud[i], sd[i])) / \
+            O.norm(O.green_dirichlet(O.as_c(sd[i]), pd.k0sq[i], pd.eps[i]))
+        rp = O.norm(O.as_c(sd[i]) - O.helmholtz_dirichlet(ki, ud[i])) / O.norm(sd[i])
+        say(f"[relres dirichlet] n={dz[i]}: born {gb[i]:.6e} / {rb:.6e}, physical {gp[i]:.6e} / {rp:.6e}")
+        assert abs(gb[i] - rb) <= tol * rb and abs(gp[i] - rp) <= tol * rp
+
+
+def test_relres_cdr_physical():
+    sizes = [64, 32]
+    probs = [S.cdr_problem(n, np.random.default_rng(1600 + i)) for i, n in enumerate(sizes)]
+    ks = cbs.pack([p.kappa + 1j * p.sigma for p in probs], torch.complex128)
+    vel = cbs.pack([p.vx + 1j * p.vy for p in probs], torch.complex128)
+    plan = cbs.CdrPlan(ks, vel, sizes, [p.background for p in probs], dtype=cbs.CBS_C128)
+    rng = np.random.default_rng(1601)
+    u0 = [S.random_field_c(n, rng) for n in sizes]
+    got = _host(plan.relres(cbs.pack(u0, torch.complex128),
+                            cbs.pack([p.source for p in probs], torch.complex128), "physical"))
+    for i, p in enumerate(probs):
+        m = O.CdrMedium(p.kappa, p.vx, p.vy, p.sigma, *p.background)
+        ref = O.norm(O.cdr_physical_residual(m, u0[i], p.source)) / O.norm(p.source)
+        say(f"[relres cdr] n={p.n}: {got[i]:.6e} / {ref:.6e}")
+        assert abs(got[i] - ref) <= 1e-12 * ref
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_metric_matched_grad_matches_autograd(dtype, bc):
+    tol = 1e-5 if dtype == cbs.CBS_C64 else 1e-10
+    tdt = TDT[dtype]
+    rng = np.random.default_rng(1700)
+    if bc == "periodic":
+        sizes = [64, 32]
+        probs = [random_problem(n, seed=1701 + i) for i, n in enumerate(sizes)]
+        plan, k2 = plan_for(probs, dtype)
+        k2s = to_list(k2, sizes)
+        resid = O.cbs_residual
+    else:
+        sizes = [31, 63]
+        kd = [100.0 + 60.0 * S.gaussian_random_field(n, 4.0, rng) for n in sizes]
+        plan = cbs.Plan(cbs.pack(kd, tdt), sizes, dtype=dtype, dirichlet=True)
+        k2s = [O.as_c(k) for k in kd]
+        resid = O.cbs_residual_dirichlet
+    x0 = [S.random_field_c(n, rng) for n in sizes]
+    s0 = [S.random_field_c(n, rng) for n in sizes]
+    w = torch.tensor([0.7, 1.3], dtype=torch.float64, device="cuda")
+    loss, g = plan.metric_matched_grad(cbs.pack(x0, tdt), cbs.pack(s0, tdt), scale=w)
+    torch.cuda.synchronize()
+    gl = [x.cpu().to(torch.complex128) for x in cbs.unpack(g, sizes)]
+    for i in range(len(sizes)):
+        xt = O.as_c(x0[i]).clone().requires_grad_(True)
+        r = resid(k2s[i], plan.k0sq[i], plan.eps[i], xt, O.as_c(s0[i]))
+        val = torch.sum(r.real ** 2 + r.imag ** 2)
+        val.backward()
+        v = float(val.detach())
+        el = abs(float(loss[i]) - v) / v
+        eg = rel_err(gl[i], float(w[i]) * xt.grad)
+        say(f"[metric-matched grad] {bc} dtype={dtype} n={sizes[i]}: loss {el:.1e} grad {eg:.1e}")
+        assert el <= tol and eg <= tol
