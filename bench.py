@@ -6,7 +6,8 @@ random-field media of contrast 1.5-4, 32-cell sponge layers and seeded point
 sources (about 6.9 M cells).  A step is one batched CBS sweep over all
 instances (prologue V u + s, forward 2D FFT, Green symbol, inverse 2D FFT,
 epilogue u += gamma r with FP64 partial norms), issued as one set of launches
-covering the whole ragged batch.
+covering the whole ragged batch; the timed steps form one chain of fused
+sweeps replayed from a captured HIP graph.
 
 Printed: one JSON line with Gcell*CBS-apply/s (value), the HBM roofline of
 the sweep (32 algorithmic bytes per cell: read u, V, s, write u), the FP64
@@ -59,8 +60,10 @@ def measured_traffic(workload: str):
 
 def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str):
     """Turn two rocprofv3 --pmc runs of `bench.py --steps 60 --chain 60
-    --warmup 2 --calib-copy` (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into
-    the per-sweep HBM traffic record.
+    --warmup 2 --no-layered --no-graph --calib-copy` (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) into the per-sweep traffic record.  These counters count the
+    L2's requests to the data fabric, Infinity-Cache hits included: the bytes
+    a sweep moves between the L2s and memory, not DRAM-only bytes.
 
     Each counter is scaled by what it reads for the 1 GiB calibration copy
     (the largest __amd_rocclr_copyBuffer dispatch).  Only dispatches from the
@@ -102,7 +105,8 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
 
     fs, fetch, grids = load(fetch_csv, "FETCH_SIZE")
     ws, write, _ = load(write_csv, "WRITE_SIZE")
-    cmd = ("python -u bench.py --steps 60 --chain 60 --warmup 2 --no-cpu --no-solve --calib-copy")
+    cmd = ("python -u bench.py --steps 60 --chain 60 --warmup 2 --no-cpu --no-solve --no-layered --no-graph "
+           "--calib-copy")
     rec = {
         "workload": workload,
         "kernel_source_hash": kernel_source_hash(),
@@ -139,12 +143,22 @@ def build_workload(name: str):
     return probs, desc
 
 
-def cpu_baseline(probs, budget_s: float = 12.0, max_rounds: int = 200):
-    """Oracle (FP64, naive DFT) CBS sweeps on the host over a bounded sample:
-    one sweep of every instance in workload order, repeated until the time
-    budget is used (the first round's times are discarded as warm-up)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sweeps(probs, budget_s: float, max_rounds: int):
+    """Oracle (FP64, naive DFT) CBS sweeps of every instance in workload
+    order, repeated until the time budget is used; the first round's times
+    are discarded as warm-up.  Returns (cell-sweeps, seconds, sweeps)."""
     import oracle as O
-    threads = torch.get_num_threads()
     state = []
     for p in probs:
         eps = O.choose_eps(p.k2, p.k0sq)
@@ -164,14 +178,34 @@ def cpu_baseline(probs, budget_s: float = 12.0, max_rounds: int = 200):
                 sweeps += 1
         if rnd > 0 and t_total >= budget_s:
             break
+    return cells, t_total, sweeps
+
+
+def cpu_baseline(probs, budget_s: float = 12.0, budget_1t_s: float = 4.0, max_rounds: int = 200):
+    """The oracle timed on the host cores over a bounded sample of the
+    workload (all torch CPU threads), and the same with one thread on the
+    instances of one size (N = 256, or the smallest present)."""
+    threads = torch.get_num_threads()
+    cells, t_total, sweeps = _oracle_sweeps(probs, budget_s, max_rounds)
+    n1 = 256 if any(p.n == 256 for p in probs) else min(p.n for p in probs)
+    sub = [p for p in probs if p.n == n1][:2]
+    torch.set_num_threads(1)
+    try:
+        c1, t1, s1 = _oracle_sweeps(sub, budget_1t_s, max_rounds)
+    finally:
+        torch.set_num_threads(threads)
     return {
         "value": cells / t_total / 1e9,
         "unit": "Gcell*CBS-apply/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "host_logical_cpus": os.cpu_count(),
         "sample": f"{sweeps} FP64 oracle sweeps ({sweeps // len(probs)} per instance over all "
                   f"{len(probs)} instances, {cells} cell-sweeps, {t_total:.1f} s after one warm-up "
-                  f"round; torch CPU threads={threads}, host={os.cpu_count()} logical CPUs)",
+                  f"round; torch CPU threads={threads}, host={os.cpu_count()} logical CPUs, {cpu_model()})",
+        "one_thread": {"value": c1 / t1 / 1e9, "unit": "Gcell*CBS-apply/s", "cores": 1,
+                       "sample": f"{s1} oracle sweeps of {len(sub)} instance(s) of {n1}^2, {t1:.1f} s"},
     }
 
 
@@ -292,6 +326,97 @@ def fp64_physical_relres(p, plan, u, s):
                    guard=False)
     _, hn = p64.helmholtz_residual(u.to(c128), s.to(c128), store=False)
     return float(torch.sqrt(hn[0]) / torch.linalg.vector_norm(s.to(c128)))
+
+
+def time_sweeps(plan, s, steps: int, warmup: int, chain_len: int, graph: bool = True):
+    """`steps` CBS sweeps in place on a zero field, as chains of `chain_len`
+    fused sweeps (one cbs_sweep call each), after `warmup` untimed sweeps.
+    With graph=True the chain is captured once into a HIP graph during the
+    warm-up (the lanes' fork and join included) and replayed.  Wall time over
+    the whole timed region (synchronised before and after) and HIP events on
+    the launch stream (the lanes join back into it) around every chain."""
+    u = plan.zeros()
+    stream = torch.cuda.current_stream()
+    chain = max(1, min(chain_len, steps))
+    plan.sweep(u, s, count=max(1, warmup))
+    torch.cuda.synchronize()
+    run = lambda: plan.sweep(u, s, count=chain)
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            plan.sweep(u, s, count=chain)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            plan.sweep(u, s, count=chain)
+        torch.cuda.synchronize()
+        run = g.replay
+    nchains = max(1, steps // chain)
+    steps = nchains * chain
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nchains + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(nchains):
+        run()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    chain_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(nchains)]
+    return {"steps": steps, "chain": chain, "graph": graph, "wall_ms_per_sweep": wall * 1e3 / steps,
+            "event_ms_per_sweep": float(np.mean(chain_ms)) / chain}
+
+
+def layered_leg(fgmres: bool = True):
+    """8 x 1024^2 layered media (the high-wavenumber stress batch): the sweep
+    on a working set larger than the 256 MB Infinity Cache (u, k^2, s and the
+    spectral buffer: 268 MB), with its own roofline, and FGMRES(50) + 4 CBS
+    sweeps to 1e-6 in FP32 (FP64 Arnoldi) against an all-FP64 GPU run of the
+    same problems, error per instance."""
+    import synthetic as S
+    from paper_2603_18527_amd import cbs
+    probs = S.layered_batch()
+    sizes = [q.n for q in probs]
+    cells = sum(n * n for n in sizes)
+    k2 = cbs.pack([q.k2 for q in probs], torch.complex64)
+    s = cbs.pack([q.source for q in probs], torch.complex64)
+    plan = cbs.Plan(k2, sizes, k0sq=[q.k0sq for q in probs], max_restart=50 if fgmres else 0)
+    tiles = plan.autotune()
+    st = time_sweeps(plan, s, 100, 10, 50)
+    achieved = BYTES_PER_CELL * cells / (st["event_ms_per_sweep"] * 1e-3) / 1e9
+    out = {
+        "workload": "layered1024: 8 instances of 1024^2, 5 layers + 10% random field, 8 ppw, 64-cell sponge",
+        "cells": cells, "working_set_bytes": 4 * 8 * cells, "column_tile": tiles[0],
+        "sweep": {"value": cells / (st["wall_ms_per_sweep"] * 1e-3) / 1e9, "unit": "Gcell*CBS-apply/s",
+                  "steps": st["steps"], "ms_per_step": st["wall_ms_per_sweep"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "event_ms_per_sweep": st["event_ms_per_sweep"],
+                     "algorithmic_bytes_per_sweep": BYTES_PER_CELL * cells},
+    }
+    if fgmres:
+        sol = {}
+        for name, dtype, tdt in (("fp32", cbs.CBS_C64, torch.complex64), ("fp64", cbs.CBS_C128, torch.complex128)):
+            if name == "fp64":
+                del plan
+                plan = cbs.Plan(cbs.pack([q.k2 for q in probs], tdt), sizes, k0sq=[q.k0sq for q in probs],
+                                dtype=dtype, max_restart=50)
+                plan.autotune()
+            sv = cbs.pack([q.source for q in probs], tdt)
+            u = plan.zeros()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            its, rel, stt = plan.fgmres(u, sv, restart=50, sweeps=4, max_iters=3000, rtol=1e-6)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            out[f"fgmres50_k4_{name}"] = {"seconds": dt, "iterations": its, "relres": rel,
+                                          "all_converged": all(x == cbs.INST_CONVERGED for x in stt)}
+            sol[name] = u.to(torch.complex128)
+        out["fgmres_rel_err_fp32_vs_fp64_gpu"] = [
+            float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+            for a, b in zip(cbs.unpack(sol["fp32"], sizes), cbs.unpack(sol["fp64"], sizes))]
+    return out
 
 
 def cdr_throughput():
@@ -517,7 +642,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ragged64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-6 runs")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-6 and FGMRES runs")
+    ap.add_argument("--no-layered", action="store_true", help="skip the 8 x 1024^2 layered leg")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="issue the timed sweep chains directly instead of replaying a captured graph")
     ap.add_argument("--chain", type=int, default=50, help="sweeps fused per cbs_sweep call")
     ap.add_argument("--cdr", action="store_true",
                     help="only time the convection-diffusion-reaction apply / adjoint (cdr64 batch)")
@@ -566,27 +694,9 @@ def main():
     print(f"# workload {args.workload}: {len(sizes)} instances, {cells} cells, column tiles "
           f"{tile_by_size}", flush=True)
 
-    u = plan.zeros()
-    stream = torch.cuda.current_stream()
-    # Steps run as chains of `chain` fused sweeps (one cbs_sweep call each);
-    # HIP events on the launch stream bracket every chain.
-    chain = max(1, min(args.chain, args.steps))
-    plan.sweep(u, s, count=max(1, args.warmup))
-    torch.cuda.synchronize()
-    nchains = max(1, args.steps // chain)
-    steps = nchains * chain
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nchains + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(nchains):
-        plan.sweep(u, s, count=chain)
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    chain_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(nchains)]
-    ms_step = wall * 1e3 / steps
-    ev_ms = float(np.mean(chain_ms)) / chain
+    st = time_sweeps(plan, s, args.steps, args.warmup, args.chain, graph=not args.no_graph)
+    ms_step = st["wall_ms_per_sweep"]
+    ev_ms = st["event_ms_per_sweep"]
     value = cells / (ms_step * 1e-3) / 1e9
     achieved = BYTES_PER_CELL * cells / (ev_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
@@ -595,7 +705,7 @@ def main():
         "value": value,
         "unit": "Gcell*CBS-apply/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": st["steps"],
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
@@ -614,15 +724,23 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "kernel": "CBS sweep: k_col + k_row_sweep (fused inverse/forward rows) over the ragged batch",
-            "sweeps_per_chain": chain,
+            "sweeps_per_chain": st["chain"],
+            "chain_from_graph": st["graph"],
             "algorithmic_bytes_per_sweep": BYTES_PER_CELL * cells,
             "event_ms_per_sweep": ev_ms,
-            # measured HBM bytes (counters) per cell and the DRAM-side rate they imply
-            "traffic_bytes_per_cell": None if traffic is None else traffic / cells,
-            "traffic_gbs": None if traffic is None else traffic / (ev_ms * 1e-3) / 1e9,
+            # FETCH_SIZE / WRITE_SIZE count L2-to-fabric requests: Infinity-Cache
+            # hits included, so these are not DRAM-only bytes
+            "l2_fabric_bytes_per_cell": None if traffic is None else traffic / cells,
+            "l2_fabric_gbs": None if traffic is None else traffic / (ev_ms * 1e-3) / 1e9,
+            "working_set_bytes": 4 * 8 * cells,
         },
     }
     line["npbs_step"] = npbs_throughput(plan, sizes, s)
+    if not args.no_layered:
+        del plan
+        torch.cuda.empty_cache()
+        line["layered1024"] = layered_leg(fgmres=not args.no_solve)
+        plan = None
     if not args.no_solve:
         line["time_to_1e-6"] = time_to_solution(probs, k2, sizes, k0sq, s)
     if args.suite:

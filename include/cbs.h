@@ -206,10 +206,11 @@ cbs_status cbs_workspace_size_cdr(int batch, const int32_t* n, int dtype, size_t
 cbs_status cbs_plan_info(cbs_plan plan, int64_t* cells, double* k0sq, double* eps);
 
 /* Execution layout of a plan (host outputs, nullable): the number of lane
- * streams its sweep chains fork into (0 = the caller's stream only, else 2)
- * and the column tile width each instance's column launches use (FP32
- * kernels for CBS_C64 plans, FP64 kernels for CBS_C128 plans). */
-cbs_status cbs_plan_layout(cbs_plan plan, int32_t* lanes, int32_t* tiles);
+ * streams its sweep chains fork into (0 = the caller's stream only, else 2),
+ * the column tile width each instance's column launches use (FP32 kernels
+ * for CBS_C64 plans, FP64 kernels for CBS_C128 plans) and the threads per
+ * column workgroup of those launches (256 or 512). */
+cbs_status cbs_plan_layout(cbs_plan plan, int32_t* lanes, int32_t* tiles, int32_t* col_threads);
 
 /*
  * cbs_apply -- y = G (V u + s)   (Sec. 4.1, the Born fixed-point map).
@@ -400,8 +401,11 @@ cbs_status cbs_loss_seed(cbs_plan plan, const void* u_k, const void* s, int weig
 /*
  * cbs_autotune -- for every grid size in the batch, time the column pass at
  *   the tile widths compiled for that size (about 2048 / N columns rounded
- *   down to a power of two, and half and twice that) on this plan's own
- *   instances and keep the fastest.  The choice is appended as one JSON line
+ *   down to a power of two, and half and twice that; with 512 threads per
+ *   workgroup the default and twice it) on this plan's own instances, in
+ *   three interleaved rounds, and keep the fastest; the thread count is one
+ *   for the whole plan (the one whose per-size best widths sum to the least
+ *   time).  The choice is appended as one JSON line
  *   to the file named by the CBS_AUTOTUNE_CACHE environment variable when it
  *   is set.  tiles: host[batch], nullable: chosen width per instance.
  *   Synchronises `stream`.
@@ -410,8 +414,16 @@ cbs_status cbs_autotune(cbs_plan plan, int32_t* tiles, void* stream);
 
 /* Force the column tile width for grid size n (n = 0: every size in the
  * plan).  CBS_ERR_ARG if the width is not one of the widths compiled for a
- * size it applies to.  Synchronises the device. */
+ * size it applies to at the plan's column thread count.  Synchronises the
+ * device. */
 cbs_status cbs_set_tile(cbs_plan plan, int n, int columns);
+
+/* Threads per column workgroup of the plan's FP32 column launches: 256, or
+ * 512 (one radix-8 butterfly per thread and pass at the default or double
+ * width; CBS_C64 periodic Helmholtz plans only, else CBS_ERR_ARG).  Changing
+ * it puts every size back to the start width of that thread count.
+ * cbs_autotune chooses it too.  Synchronises the device. */
+cbs_status cbs_set_col_threads(cbs_plan plan, int threads);
 
 /*
  * cbs_apply_static -- y = G (V u + s), the operator of cbs_apply, for callers

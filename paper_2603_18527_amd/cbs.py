@@ -49,7 +49,7 @@ SIGNATURES = {
     "cbs_workspace_size_cdr": (_i32, [_i32, _vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_workspace_size": (_i32, [_i32, _vp, _i32, _i32, _u32, ctypes.POINTER(ctypes.c_size_t)]),
     "cbs_plan_info": (_i32, [_vp, _vp, _vp, _vp]),
-    "cbs_plan_layout": (_i32, [_vp, _vp, _vp]),
+    "cbs_plan_layout": (_i32, [_vp, _vp, _vp, _vp]),
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
@@ -66,6 +66,7 @@ SIGNATURES = {
     "cbs_loss_seed": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "cbs_autotune": (_i32, [_vp, _vp, _vp]),
     "cbs_set_tile": (_i32, [_vp, _i32, _i32]),
+    "cbs_set_col_threads": (_i32, [_vp, _i32]),
     "cbs_apply_static": (_i32, [_i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "cbs_destroy": (None, [_vp]),
     "cbs_last_error": (ctypes.c_char_p, []),
@@ -416,8 +417,17 @@ class Plan:
         """(lane streams used by sweep chains, column tile width per instance)."""
         lanes = ctypes.c_int32()
         t = (ctypes.c_int32 * self.batch)()
-        _check(load().cbs_plan_layout(self._h, ctypes.byref(lanes), t))
+        _check(load().cbs_plan_layout(self._h, ctypes.byref(lanes), t, None))
         return int(lanes.value), list(t)
+
+    def col_threads(self) -> int:
+        """Threads per workgroup of the plan's column launches (256 or 512)."""
+        thr = ctypes.c_int32()
+        _check(load().cbs_plan_layout(self._h, None, None, ctypes.byref(thr)))
+        return int(thr.value)
+
+    def set_col_threads(self, threads: int):
+        _check(load().cbs_set_col_threads(self._h, int(threads)))
 
     def set_tile(self, columns: int, n: int = 0):
         _check(load().cbs_set_tile(self._h, int(n), int(columns)))

@@ -70,6 +70,7 @@ struct cbs_plan_s {
   int max_restart = 0;
   int maxn = 0;
   std::map<int, int> ctile;  // column tile width per size class (FP32 kernels)
+  int col_threads32 = kThreads;  // threads per FP32 column workgroup (kColThreadsWide: FP32 periodic Helmholtz)
   long long cells = 0;
   std::vector<int> n;
   std::vector<long long> off;
@@ -194,7 +195,7 @@ void build_items(cbs_plan p) {
     d.nparts = (d.n + rpw - 1) / rpw;
     part += d.nparts;
     auto it = p->ctile.find(d.n);
-    d.ctile = it != p->ctile.end() ? it->second : col_tile_start(m);
+    d.ctile = it != p->ctile.end() ? it->second : col_tile_start_t(m, p->col_threads32);
     d.ctile64 = d.ctile;
     while (!col_tile_valid(m, d.ctile64, 16) && d.ctile64 > 2) d.ctile64 /= 2;
     p->inst.push_back(d);
@@ -422,6 +423,7 @@ Params<R> base_params(cbs_plan p) {
   q.epi = EPI_STORE;
   q.dst = p->dirichlet ? 1 : 0;
   q.mu = p->d_mu;
+  q.col_threads = sizeof(R) == 4 ? p->col_threads32 : kThreads;
   return q;
 }
 
@@ -1500,6 +1502,9 @@ void init_layout(cbs_plan p, int batch, const int32_t* n, int dtype, int max_res
   p->max_restart = max_restart;
   p->one_stream = (flags & CBS_FLAG_ONE_STREAM) != 0;
   p->dirichlet = (flags & CBS_FLAG_DIRICHLET) != 0;
+  // FP32 periodic Helmholtz plans start with the wide column workgroups
+  // (the faster ones on MI355X for the ragged and 1024^2 batches)
+  p->col_threads32 = (dtype == CBS_C64 && !p->dirichlet && !p->cdr) ? kColThreadsWide : kThreads;
   p->n.assign(n, n + batch);
   long long off = 0;
   for (int i = 0; i < batch; ++i) {
@@ -1903,6 +1908,201 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
 
 }  // namespace
 
+namespace {
+
+// ---- autotuning -----------------------------------------------------------------------------
+
+// Sizes present in the plan, largest first.
+std::vector<int> size_classes(cbs_plan p) {
+  std::vector<int> classes;
+  for (int n : p->n)
+    if (std::find(classes.begin(), classes.end(), n) == classes.end()) classes.push_back(n);
+  std::sort(classes.begin(), classes.end(), [](int a, int b) { return a > b; });
+  return classes;
+}
+
+// Tune on what the plan runs: chains of fused CBS sweeps over all its
+// instances, with its lanes, on scratch fields holding the plan's own k^2
+// (realistic magnitudes: all-zero fields run several per cent faster, which
+// would bias the comparison).  Configurations are timed in interleaved
+// rounds and each keeps its fastest round, since single timings of the same
+// configuration scatter by a few per cent.  First the thread count of the
+// FP32 column launches (each at its start widths), then, size by size, each
+// other compiled width against the current choice, kept only when more than
+// 2 % faster.
+template <typename R>
+cbs_status tune_by_sweeps(cbs_plan p, hipStream_t st, std::ostringstream& rec) {
+  const size_t bytes = size_t(p->cells) * p->op_elem();
+  HIPCHK(hipMemcpyAsync(p->d_e, k2_of<R>(p), bytes, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(p->d_c, k2_of<R>(p), bytes, hipMemcpyDeviceToDevice, st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int chain = 30;
+  struct Cfg {
+    int threads;
+    std::map<int, int> tiles;
+  };
+  auto timed = [&](const Cfg& c, double* per_sweep) -> cbs_status {
+    p->col_threads32 = c.threads;
+    p->ctile = c.tiles;
+    build_items(p);
+    drop_graphs(p);
+    CHK(upload_items(p, st));
+    CHK(sweep_impl<R>(p, p->d_e, p->d_c, 2, nullptr, st));  // warm-up
+    HIPCHK(hipEventRecord(e0, st));
+    CHK(sweep_impl<R>(p, p->d_e, p->d_c, chain, nullptr, st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    *per_sweep = double(ms) / chain;
+    return CBS_OK;
+  };
+  // fastest of `rounds` interleaved timings of each configuration
+  auto race = [&](const std::vector<Cfg>& cfgs, int rounds, std::vector<double>& best) -> cbs_status {
+    best.assign(cfgs.size(), 1e300);
+    for (int r = 0; r < rounds; ++r)
+      for (size_t k = 0; k < cfgs.size(); ++k) {
+        double ms = 0.0;
+        CHK(timed(cfgs[k], &ms));
+        best[k] = std::min(best[k], ms);
+      }
+    return CBS_OK;
+  };
+  const Cfg saved{p->col_threads32, p->ctile};
+  std::vector<Cfg> cfgs = {Cfg{kThreads, {}}};
+  if (sizeof(R) == 4 && !p->dirichlet) cfgs.push_back(Cfg{kColThreadsWide, {}});
+  std::vector<double> t;
+  cbs_status rc = race(cfgs, 4, t);
+  rec << "{\"dtype\": \"" << (sizeof(R) == 4 ? "c64" : "c128") << "\", \"by\": \"sweep chains\", \"configs\": [";
+  Cfg cur = cfgs[0];
+  double cur_ms = 1e300;
+  if (rc == CBS_OK) {
+    for (size_t k = 0; k < cfgs.size(); ++k) {
+      rec << (k ? ", " : "") << "{\"col_threads\": " << cfgs[k].threads << ", \"us_per_sweep\": " << t[k] * 1e3 << "}";
+      if (t[k] < cur_ms) {
+        cur_ms = t[k];
+        cur = cfgs[k];
+      }
+    }
+    const int thr_used = sizeof(R) == 4 ? cur.threads : kThreads;
+    for (int n : size_classes(p)) {
+      const int m = p->tlen(n);
+      const int start = col_tile_start_t(m, thr_used);
+      cur.tiles[n] = start;
+      for (int c : {col_tile_default(m) / 2, col_tile_default(m), col_tile_default(m) * 2}) {
+        if (c == cur.tiles[n] || c == start || !col_tile_valid_t(m, c, p->op_elem(), thr_used)) continue;
+        Cfg cand = cur;
+        cand.tiles[n] = c;
+        rc = race({cur, cand}, 3, t);
+        if (rc != CBS_OK) break;
+        rec << ", {\"n\": " << n << ", \"tile\": " << c << ", \"us_per_sweep\": " << t[1] * 1e3
+            << ", \"against\": " << t[0] * 1e3 << "}";
+        if (t[1] < 0.98 * t[0]) cur = cand;
+      }
+      if (rc != CBS_OK) break;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != CBS_OK) {
+    p->col_threads32 = saved.threads;
+    p->ctile = saved.tiles;
+    return rc;
+  }
+  p->col_threads32 = cur.threads;
+  p->ctile = cur.tiles;
+  rec << "], \"col_threads\": " << p->col_threads32 << ", \"tiles\": {";
+  bool first = true;
+  for (const auto& kv : p->ctile) {
+    rec << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+    first = false;
+  }
+  rec << "}}";
+  return CBS_OK;
+}
+
+// Convection-diffusion-reaction plans have no sweep: time the Green column
+// pass of each size class alone at its compiled widths, three interleaved
+// rounds, and keep each class's fastest.
+cbs_status tune_by_columns(cbs_plan p, hipStream_t st, std::ostringstream& rec) {
+  HIPCHK(hipMemsetAsync(p->d_inter, 0, p->cells * p->op_elem(), st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const std::vector<int> classes = size_classes(p);
+  std::map<int, std::map<int, double>> best_of;
+  cbs_status rc = CBS_OK;
+  for (int round = 0; round < 3 && rc == CBS_OK; ++round) {
+    for (int n : classes) {
+      const int m = p->tlen(n);
+      for (int c : {col_tile_default(m) / 2, col_tile_default(m), col_tile_default(m) * 2}) {
+        if (!col_tile_valid(m, c, p->op_elem())) continue;
+        p->ctile[n] = c;
+        build_items(p);
+        rc = upload_items(p, st);
+        if (rc != CBS_OK) break;
+        // the column items of size class n form one contiguous range
+        const std::vector<int2>& items = p->dtype == CBS_C64 ? p->col_items32 : p->col_items64;
+        size_t lo = items.size(), hi = 0;
+        for (size_t k = 0; k < items.size(); ++k)
+          if (p->n[items[k].x] == n) {
+            lo = std::min(lo, k);
+            hi = k + 1;
+          }
+        auto launch = [&]() {
+          if (p->dtype == CBS_C64) {
+            Params<float> q = base_params<float>(p);
+            q.sym = SYM_CDR;
+            q.items = p->d_col_items32 + lo;
+            launch_col(int(hi - lo), size_t(col_lds_elems(m, c)) * 8, st, q);
+          } else {
+            Params<double> q = base_params<double>(p);
+            q.sym = SYM_CDR;
+            q.items = p->d_col_items64 + lo;
+            launch_col(int(hi - lo), size_t(col_lds_elems(m, p->inst[items[lo].x].ctile64)) * 16, st, q);
+          }
+        };
+        for (int rep = 0; rep < 2; ++rep) launch();
+        HIPCHK(hipEventRecord(e0, st));
+        const int reps = 10;
+        for (int rep = 0; rep < reps; ++rep) launch();
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipGetLastError());
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const double per = double(ms) / reps;
+        auto it = best_of[n].find(c);
+        if (it == best_of[n].end() || per < it->second) best_of[n][c] = per;
+      }
+      if (rc != CBS_OK) break;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != CBS_OK) return rc;
+  rec << "{\"dtype\": \"" << (p->dtype == CBS_C64 ? "c64" : "c128") << "\", \"by\": \"column pass\", \"tiles\": {";
+  bool first = true;
+  for (int n : classes) {
+    int best = col_tile_start(p->tlen(n));
+    double best_ms = 1e300;
+    for (const auto& kv : best_of[n])
+      if (kv.second < best_ms) {
+        best_ms = kv.second;
+        best = kv.first;
+      }
+    p->ctile[n] = best;
+    rec << (first ? "" : ", ") << "\"" << n << "\": {\"tile\": " << best << ", \"col_ms\": " << best_ms << "}";
+    first = false;
+  }
+  rec << "}}";
+  return CBS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 cbs_status cbs_plan_info(cbs_plan p, int64_t* cells, double* k0sq, double* eps) {
@@ -1915,9 +2115,10 @@ cbs_status cbs_plan_info(cbs_plan p, int64_t* cells, double* k0sq, double* eps) 
   return CBS_OK;
 }
 
-cbs_status cbs_plan_layout(cbs_plan p, int32_t* lanes, int32_t* tiles) {
+cbs_status cbs_plan_layout(cbs_plan p, int32_t* lanes, int32_t* tiles, int32_t* col_threads) {
   if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
   if (lanes) *lanes = p->full.nlanes;
+  if (col_threads) *col_threads = p->dtype == CBS_C64 ? p->col_threads32 : kThreads;
   if (tiles)
     for (int i = 0; i < p->batch; ++i) tiles[i] = p->dtype == CBS_C64 ? p->inst[i].ctile : p->inst[i].ctile64;
   return CBS_OK;
@@ -1928,7 +2129,7 @@ cbs_status cbs_set_tile(cbs_plan p, int n, int columns) {
   bool any = false;
   for (int nn : p->n) {
     if (n != 0 && nn != n) continue;
-    if (!col_tile_valid(p->tlen(nn), columns, p->op_elem()))
+    if (!col_tile_valid_t(p->tlen(nn), columns, p->op_elem(), p->dtype == CBS_C64 ? p->col_threads32 : kThreads))
       return fail(CBS_ERR_ARG, "tile width " + std::to_string(columns) + " not available for size " +
                                    std::to_string(nn));
     any = true;
@@ -1936,6 +2137,24 @@ cbs_status cbs_set_tile(cbs_plan p, int n, int columns) {
   if (!any) return fail(CBS_ERR_ARG, "no instance of size " + std::to_string(n) + " in the plan");
   for (int nn : p->n)
     if (n == 0 || nn == n) p->ctile[nn] = columns;
+  build_items(p);
+  drop_graphs(p);
+  CHK(upload_items(p, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  return CBS_OK;
+}
+
+cbs_status cbs_set_col_threads(cbs_plan p, int threads) {
+  if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
+  if (threads != kThreads && threads != kColThreadsWide)
+    return fail(CBS_ERR_ARG, "threads must be " + std::to_string(kThreads) + " or " +
+                                 std::to_string(kColThreadsWide));
+  if (threads != kThreads && (p->dtype != CBS_C64 || p->dirichlet || p->cdr))
+    return fail(CBS_ERR_ARG, "wide column workgroups exist for FP32 periodic Helmholtz plans only");
+  if (threads != p->col_threads32) {
+    p->col_threads32 = threads;
+    p->ctile.clear();  // every size back to the start width of this thread count
+  }
   build_items(p);
   drop_graphs(p);
   CHK(upload_items(p, nullptr));
@@ -2133,81 +2352,21 @@ cbs_status cbs_loss_seed(cbs_plan p, const void* u_k, const void* s, int weight_
 cbs_status cbs_autotune(cbs_plan p, int32_t* tiles, void* stream) {
   if (!p) return fail(CBS_ERR_ARG, "plan is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIPCHK(hipMemsetAsync(p->d_inter, 0, p->cells * p->op_elem(), st));
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  std::vector<int> classes;
-  for (int n : p->n)
-    if (std::find(classes.begin(), classes.end(), n) == classes.end()) classes.push_back(n);
   std::ostringstream rec;
-  rec << "{\"dtype\": \"" << (p->dtype == CBS_C64 ? "c64" : "c128") << "\", \"tiles\": {";
-  bool first = true;
-  cbs_status rc = CBS_OK;
-  for (int n : classes) {
-    const int c0 = col_tile_default(p->tlen(n));
-    int best = c0;
-    double best_ms = 1e300;
-    for (int c : {c0 / 2, c0, c0 * 2}) {
-      if (!col_tile_valid(p->tlen(n), c, p->op_elem())) continue;
-      p->ctile[n] = c;
-      build_items(p);
-      rc = upload_items(p, st);
-      if (rc != CBS_OK) break;
-      // the column items of size class n form one contiguous range
-      const std::vector<int2>& items = p->dtype == CBS_C64 ? p->col_items32 : p->col_items64;
-      size_t lo = items.size(), hi = 0;
-      for (size_t k = 0; k < items.size(); ++k)
-        if (p->n[items[k].x] == n) {
-          lo = std::min(lo, k);
-          hi = k + 1;
-        }
-      auto launch = [&]() {
-        if (p->dtype == CBS_C64) {
-          Params<float> q = base_params<float>(p);
-          if (p->cdr) q.sym = SYM_CDR;
-          q.items = p->d_col_items32 + lo;
-          launch_col(int(hi - lo), p->col_lds32, st, q);
-        } else {
-          Params<double> q = base_params<double>(p);
-          if (p->cdr) q.sym = SYM_CDR;
-          q.items = p->d_col_items64 + lo;
-          launch_col(int(hi - lo), p->col_lds64, st, q);
-        }
-      };
-      for (int rep = 0; rep < 3; ++rep) launch();
-      HIPCHK(hipEventRecord(e0, st));
-      const int reps = 20;
-      for (int rep = 0; rep < reps; ++rep) launch();
-      HIPCHK(hipEventRecord(e1, st));
-      HIPCHK(hipEventSynchronize(e1));
-      HIPCHK(hipGetLastError());
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms / reps < best_ms) {
-        best_ms = ms / reps;
-        best = c;
-      }
-    }
-    if (rc != CBS_OK) break;
-    p->ctile[n] = best;
-    rec << (first ? "" : ", ") << "\"" << n << "\": {\"tile\": " << best << ", \"col_ms\": " << best_ms << "}";
-    first = false;
-  }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  cbs_status rc = p->cdr ? tune_by_columns(p, st, rec)
+                  : p->dtype == CBS_C64 ? tune_by_sweeps<float>(p, st, rec)
+                                        : tune_by_sweeps<double>(p, st, rec);
   if (rc != CBS_OK) return rc;
   build_items(p);
   drop_graphs(p);
   CHK(upload_items(p, st));
   HIPCHK(hipStreamSynchronize(st));
-  rec << "}}";
   if (const char* path = std::getenv("CBS_AUTOTUNE_CACHE")) {
     std::ofstream f(path, std::ios::app);
     if (f) f << rec.str() << "\n";
   }
   if (tiles)
-    for (int i = 0; i < p->batch; ++i) tiles[i] = p->inst[i].ctile;
+    for (int i = 0; i < p->batch; ++i) tiles[i] = p->dtype == CBS_C64 ? p->inst[i].ctile : p->inst[i].ctile64;
   return CBS_OK;
 }
 

@@ -411,10 +411,10 @@ __device__ __forceinline__ cpx<R> cdr_symbol_factor(int n, int k1, int k2, const
 // and butterfly slot tid / C.  Between passes the tile sits in LDS
 // element-interleaved (position x of column c at C * pos(x) + c), which keeps
 // every pass's LDS reads and writes free of bank conflicts on gfx950.
-template <typename R, int N, int C>
+template <typename R, int N, int C, int T = kThreads>
 __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, int col0,
                                          cpx<R>* lds) {
-  constexpr int TPC = kThreads / C;
+  constexpr int TPC = T / C;
   const int tid = threadIdx.x;
   const int c = tid % C, t = tid / C;
   const long long cbase = d.off + col0 + c;
@@ -440,22 +440,22 @@ __device__ __forceinline__ void col_body(const Params<R>& p, const InstDesc& d, 
   }
 }
 
-template <typename R, int N>
+template <typename R, int N, int T = kThreads>
 __device__ __forceinline__ void col_dispatch_n(const Params<R>& p, const InstDesc& d, int col0,
                                                cpx<R>* lds) {
   constexpr int C0 = col_tile_default(N);
   constexpr int EB = int(sizeof(cpx<R>));
   const int c = sizeof(R) == 4 ? d.ctile : d.ctile64;
-  if constexpr (col_tile_valid(N, C0, EB))
-    if (c == C0) { col_body<R, N, C0>(p, d, col0, lds); return; }
-  if constexpr (col_tile_valid(N, C0 / 2, EB))
-    if (c == C0 / 2) { col_body<R, N, (C0 / 2 >= 2 ? C0 / 2 : 2)>(p, d, col0, lds); return; }
-  if constexpr (col_tile_valid(N, C0 * 2, EB))
-    if (c == C0 * 2) { col_body<R, N, (C0 * 2 <= 32 ? C0 * 2 : 32)>(p, d, col0, lds); return; }
+  if constexpr (col_tile_valid_t(N, C0, EB, T))
+    if (c == C0) { col_body<R, N, C0, T>(p, d, col0, lds); return; }
+  if constexpr (T == kThreads && col_tile_valid(N, C0 / 2, EB))
+    if (c == C0 / 2) { col_body<R, N, (C0 / 2 >= 2 ? C0 / 2 : 2), T>(p, d, col0, lds); return; }
+  if constexpr (col_tile_valid_t(N, C0 * 2, EB, T))
+    if (c == C0 * 2) { col_body<R, N, (C0 * 2 <= 32 ? C0 * 2 : 32), T>(p, d, col0, lds); return; }
 }
 
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_col(Params<R> p) {
+template <typename R, int T>
+__device__ __forceinline__ void col_kernel_body(const Params<R>& p) {
   extern __shared__ float4 smem_raw[];
   cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
   const int2 w = p.items[blockIdx.x];
@@ -468,13 +468,24 @@ __global__ __launch_bounds__(kThreads) void k_col(Params<R> p) {
   switch (d.n) {
 #define CBS_COL_CASE(N) \
   case N:               \
-    col_dispatch_n<R, N>(p, d, w.y, lds); \
+    col_dispatch_n<R, N, T>(p, d, w.y, lds); \
     break;
     CBS_FOR_EACH_N(CBS_COL_CASE)
 #undef CBS_COL_CASE
     default:
       break;
   }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_col(Params<R> p) {
+  col_kernel_body<R, kThreads>(p);
+}
+
+// the same with kColThreadsWide threads per workgroup
+template <typename R>
+__global__ __launch_bounds__(kColThreadsWide) void k_col_wide(Params<R> p) {
+  col_kernel_body<R, kColThreadsWide>(p);
 }
 
 // ---- pointwise kernels over row work items ------------------------------------------

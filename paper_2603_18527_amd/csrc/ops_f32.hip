@@ -29,7 +29,10 @@ void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<float>&
     launch_col_dst(grid, lds_bytes, st, p);
     return;
   }
-  hipLaunchKernelGGL(k_col<float>, dim3(grid), dim3(kThreads), lds_bytes, st, p);
+  if (p.col_threads == kColThreadsWide)
+    hipLaunchKernelGGL(k_col_wide<float>, dim3(grid), dim3(kColThreadsWide), lds_bytes, st, p);
+  else
+    hipLaunchKernelGGL(k_col<float>, dim3(grid), dim3(kThreads), lds_bytes, st, p);
 }
 
 void launch_pointwise(int grid, hipStream_t st, const PwParams<float>& p) {

@@ -108,6 +108,7 @@ struct Params {
   IterState chk;
   int check;
   int dst;  // nonzero: Dirichlet plan (DST-I kernels)
+  int col_threads;  // threads per column workgroup: kThreads or kColThreadsWide (FP32 periodic)
   // convection-diffusion-reaction passes: k2 holds (dkappa, dsigma), k2b
   // (dvx, dvy)
   const cpx<R>* k2b;
@@ -139,6 +140,25 @@ __host__ __device__ constexpr bool col_tile_valid(int n, int c, int elem_bytes) 
   const int c0 = col_tile_default(n);
   return (c == c0 || c == c0 / 2 || c == c0 * 2) && c >= 2 && c <= 32 && n % c == 0 &&
          col_lds_elems(n, c) * elem_bytes <= kColLdsBytes;
+}
+
+// Column kernels of FP32 periodic Helmholtz plans also come with twice the
+// threads per workgroup (kColThreadsWide): one radix-8 butterfly per thread
+// and pass at the default-or-double width, fewer registers per thread and so
+// more waves per SIMD.  A plan uses one thread count for all its column
+// launches (every instance of a lane shares a launch).
+constexpr int kColThreadsWide = 2 * kThreads;
+__host__ __device__ constexpr bool col_tile_valid_t(int n, int c, int elem_bytes, int threads) {
+  if (threads == kThreads) return col_tile_valid(n, c, elem_bytes);
+  const int c0 = col_tile_default(n);
+  return threads == kColThreadsWide && (c == c0 || c == c0 * 2) && c >= 2 && c <= 32 && n % c == 0 &&
+         col_lds_elems(n, c) * elem_bytes <= kColLdsBytes;
+}
+// Width a plan starts with at a given thread count.
+__host__ __device__ constexpr int col_tile_start_t(int n, int threads) {
+  return threads == kThreads ? col_tile_start(n)
+         : col_tile_valid_t(n, col_tile_default(n) * 2, 8, threads) ? col_tile_default(n) * 2
+                                                                    : col_tile_default(n);
 }
 
 // Dirichlet eigenvalue table: for each supported transform length M the

@@ -165,7 +165,8 @@ def test_workspace_covers_partial_dirichlet_column_tiles():
 
 def test_plan_layout_null_plan():
     lib = cbs.load()
-    assert lib.cbs_plan_layout(None, None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_plan_layout(None, None, None, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_set_col_threads(None, 512) == cbs.CBS_ERR_ARG
 
 
 def test_apply_static_argument_errors_without_gpu():

@@ -173,16 +173,19 @@ def test_deterministic_repeat():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("threads", [256, 512])
 @pytest.mark.parametrize("which", ["half", "default", "double"])
-def test_column_tile_widths_agree(which):
+def test_column_tile_widths_agree(which, threads):
     # every compiled tile width (half / default / double of ~2048/N columns)
-    # gives the same apply as the width a plan starts with; the autotuner
-    # picks one of them per size
+    # at both column workgroup sizes gives the same apply as the width a plan
+    # starts with; the autotuner picks one of them per size
     sizes = (64, 128, 256, 512, 1024)
     probs = [random_problem(n, seed=300 + n) for n in sizes]
     plan, k2 = plan_for(probs)
     u, s = _inputs(probs, cbs.CBS_C64, seed=11)
     ref = plan.apply(u, s)
+    plan.set_col_threads(threads)
+    assert plan.col_threads() == threads
     default = {16: 16, 32: 32, 64: 32, 128: 16, 192: 8, 256: 8, 288: 4, 384: 4, 512: 4, 1024: 2}
     for n in sizes:
         c = {"half": default[n] // 2, "default": default[n], "double": default[n] * 2}[which]
@@ -293,13 +296,23 @@ def test_sweep_chain_bench_path(bench_path_case, dtype):
                         dtype=cbs.CBS_C128)
         assert plan.eps == case["eps"]
     lanes, tiles = plan.layout()
-    say(f"   lanes={lanes} tiles={dict(zip(BENCH_SIZES, tiles))}")
+    say(f"   lanes={lanes} tiles={dict(zip(BENCH_SIZES, tiles))} column threads {plan.col_threads()}")
     assert lanes == 2
     if dtype == cbs.CBS_C64:
-        assert dict(zip(BENCH_SIZES, tiles)) == {1024: 4, 512: 8, 384: 4, 288: 4, 256: 8, 192: 8, 128: 8}
-    _check_chain(plan, case, dtype, "start tiles")
+        # FP32 plans start with 512-thread column workgroups; the 256-thread
+        # kernels at their start widths are the other configuration the
+        # autotuner weighs
+        assert plan.col_threads() == 512
+        assert dict(zip(BENCH_SIZES, tiles)) == {1024: 4, 512: 8, 384: 8, 288: 8, 256: 16, 192: 16, 128: 32}
+        _check_chain(plan, case, dtype, "start tiles, 512 threads")
+        plan.set_col_threads(256)
+        assert dict(zip(BENCH_SIZES, plan.layout()[1])) == {1024: 4, 512: 8, 384: 4, 288: 4, 256: 8, 192: 8,
+                                                           128: 8}
+        _check_chain(plan, case, dtype, "start tiles, 256 threads")
+    else:
+        _check_chain(plan, case, dtype, "start tiles")
     tuned = plan.autotune()
-    say(f"   autotuned tiles={dict(zip(BENCH_SIZES, tuned))}")
+    say(f"   autotuned tiles={dict(zip(BENCH_SIZES, tuned))} column threads {plan.col_threads()}")
     assert plan.layout() == (2, tuned)
     _check_chain(plan, case, dtype, "autotuned")
     if dtype != cbs.CBS_C64:

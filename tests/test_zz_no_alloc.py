@@ -2,10 +2,11 @@
 fixed device array inside the library) against cbs_apply on a plan of the
 same instances, k0^2 and eps: two calls in a row, the second on a smaller
 batch, in FP32 and FP64.  Bar: the operator tolerance of the apply parity
-tests (relative L2 and per-cell).  The two entry points run the same kernels
-on the same column tiles; FP32 results come out bitwise equal, FP64 ones to
-rounding (the FP64 twiddles are evaluated on the device here, on the host for
-a plan).  Collected last: a failure here hides no other test."""
+tests (relative L2 and per-cell).  The two entry points run the same
+transform arithmetic (a plan may tile its column launches differently, which
+moves no result); FP32 results come out bitwise equal, FP64 ones to rounding
+(the FP64 twiddles are evaluated on the device here, on the host for a plan).
+Collected last: a failure here hides no other test."""
 import numpy as np
 import pytest
 import torch
