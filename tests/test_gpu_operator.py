@@ -179,7 +179,7 @@ def test_column_tile_widths_agree(which, threads):
     # every compiled tile width (half / default / double of ~2048/N columns)
     # at both column workgroup sizes gives the same apply as the width a plan
     # starts with; the autotuner picks one of them per size
-    sizes = (64, 128, 256, 512, 1024)
+    sizes = (64, 128, 192, 256, 288, 384, 512, 1024)
     probs = [random_problem(n, seed=300 + n) for n in sizes]
     plan, k2 = plan_for(probs)
     u, s = _inputs(probs, cbs.CBS_C64, seed=11)
@@ -195,6 +195,8 @@ def test_column_tile_widths_agree(which, threads):
             assert e.status == cbs.CBS_ERR_ARG   # width not compiled for this size
     y = plan.apply(u, s)
     torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(cbs.unpack(y, list(sizes)), cbs.unpack(ref, list(sizes)))):
+        say(f"[tiles {which} {threads}] n={sizes[i]} tile={plan.layout()[1][i]}: {rel_err(a.cpu(), b.cpu()):.2e}")
     assert rel_err(y.cpu(), ref.cpu()) <= 1e-6
     tiles = plan.autotune()
     for n, c in zip(sizes, tiles):
