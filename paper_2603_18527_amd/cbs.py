@@ -82,6 +82,31 @@ class CbsError(RuntimeError):
         self.status = status
 
 
+_deferred = []  # (plan handle, workspace) released after a graph capture
+
+
+def _capturing() -> bool:
+    try:
+        return torch.cuda.is_available() and torch.cuda.is_current_stream_capturing()
+    except Exception:
+        return False
+
+
+def _release(h, ws):
+    if _capturing():
+        _deferred.append((h, ws))
+        return
+    release_deferred()
+    _lib.cbs_destroy(h)
+
+
+def release_deferred():
+    """Destroy plans whose release was deferred during a graph capture."""
+    while _deferred and not _capturing():
+        h, _ = _deferred.pop()
+        _lib.cbs_destroy(h)
+
+
 def load(path: str = LIB_PATH):
     """Load libcbs.so (raises if it has not been built)."""
     global _lib
@@ -199,6 +224,7 @@ class Plan:
         dirichlet: instances are n x n interiors of the unit square with
         homogeneous Dirichlet boundaries (five-point FD, DST-I reference)."""
         lib = load()
+        release_deferred()
         self.sizes = [int(n) for n in sizes]
         self.batch = len(self.sizes)
         self.dtype = dtype
@@ -238,13 +264,16 @@ class Plan:
         self.eps = list(epso)
 
     def __del__(self):
-        # cbs_destroy waits for the plan's own lane streams.  The workspace
-        # tensor goes back to torch's allocator, which orders its reuse after
-        # the work already queued on the streams the plan was called on
+        # cbs_destroy waits for the plan's own streams.  The workspace tensor
+        # goes back to torch's allocator, which orders its reuse after the
+        # work already queued on the streams the plan was called on
         # (record_stream in _st), so no device-wide synchronisation is needed.
+        # A plan collected while a graph is being captured on this thread's
+        # stream (the collector can run inside the capture) is released
+        # later: stream synchronisation would invalidate the capture.
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
-            _lib.cbs_destroy(h)
+            _release(h, getattr(self, "_ws", None))
             self._h = None
         self._ws = None
 

@@ -14,6 +14,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace cbs {
 
 template <typename R>
@@ -238,6 +240,28 @@ __device__ __forceinline__ void twiddle(cpx<R>* v, int k, const cpx<R>* __restri
   for (int q = 1; q < RAD; ++q) v[q] = DIR < 0 ? cmul(w[q], v[q]) : cmulc(w[q], v[q]);
 }
 
+// Functors of the first pass (ld), the last pass (st) and a bridge (mid) may
+// also take the butterfly slot p and the element slot q of the thread's
+// registers: in a plan whose first and last radix agree, every one of these
+// stages gives thread t the same elements j + q N/r, j = t + p TPF, so a
+// functor can keep per-element values in registers indexed by (p, q) from
+// one stage to a later one.
+template <class F, typename R>
+__device__ __forceinline__ cpx<R> call_ld(F& f, int e, int p, int q) {
+  if constexpr (std::is_invocable_v<F&, int, int, int>) return f(e, p, q);
+  else return f(e);
+}
+template <class F, typename R>
+__device__ __forceinline__ void call_st(F& f, int e, cpx<R> v, int p, int q) {
+  if constexpr (std::is_invocable_v<F&, int, cpx<R>, int, int>) f(e, v, p, q);
+  else f(e, v);
+}
+template <class F, typename R>
+__device__ __forceinline__ cpx<R> call_mid(F& f, int e, cpx<R> v, int p, int q) {
+  if constexpr (std::is_invocable_v<F&, int, cpx<R>, int, int>) return f(e, v, p, q);
+  else return f(e, v);
+}
+
 // ---- one Stockham pass ----------------------------------------------------------
 //
 // TPF threads cooperate on one transform (t = 0..TPF-1); every thread of the
@@ -270,7 +294,7 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
       if (EXACT || j < NB) {
         if constexpr (FIRST) {
 #pragma unroll
-          for (int q = 0; q < RAD; ++q) v[p][q] = ld(j + q * NB);
+          for (int q = 0; q < RAD; ++q) v[p][q] = call_ld<LD, R>(ld, j + q * NB, p, q);
         } else {
           const int pj = lds_pos(j);
 #pragma unroll
@@ -291,7 +315,7 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
         const int o = (j / NS) * (NS * RAD) + k;
         if constexpr (LAST) {
 #pragma unroll
-          for (int q = 0; q < RAD; ++q) st(o + q * NS, v[p][q]);
+          for (int q = 0; q < RAD; ++q) call_st<ST, R>(st, o + q * NS, v[p][q], p, q);
         } else {
           const int po = lds_pos(o);
 #pragma unroll
@@ -361,7 +385,7 @@ __device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, cons
         twiddle<R, N, PL, D1>(v[p], j, tw);
         bfly<RAD, D1>(v[p]);
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) v[p][q] = mid(j + q * NS, v[p][q]);
+        for (int q = 0; q < RAD; ++q) v[p][q] = call_mid<MID, R>(mid, j + q * NS, v[p][q], p, q);
         // first pass of transform 2 reads the same elements j + q N/RAD
         bfly<RAD, D2>(v[p]);
         const int o = j * RAD;

@@ -21,9 +21,11 @@
 //                 = e - V^H g   (MODE 2; V^H for real coefficients, D^H = -D)
 //
 // The term that is not differentiated a second time (-dvx Dx u ... on the
-// forward side) is formed at the middle step and parked in global memory
-// (the pass's own output rows or columns) until the last transform adds it;
-// the workgroup's barriers order the two accesses.
+// forward side) is formed at the middle step and kept until the last
+// transform adds it: in registers when the plan's first and last radix agree
+// (each thread then holds the same elements at both stages), else parked in
+// global memory (the pass's own output rows or columns), the workgroup's
+// barriers ordering the two accesses.
 // Field roles: u = u (forward) or g (adjoint); s = s (forward) or e
 // (adjoint); b = p_y (row pass); k2 = (dkappa, dsigma); k2b = (dvx, dvy).
 #pragma once
@@ -108,34 +110,55 @@ __device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc&
   };
   auto st_s = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
   if constexpr (plan_bridgeable(N)) {
-    // the transforms chained through register bridges (fewer LDS round trips)
+    // The transforms chained through register bridges (fewer LDS round
+    // trips).  The first pass, every bridge and the last pass give this
+    // thread the same elements (slots p, q), so u and the part that is not
+    // differentiated again stay in registers between the stages instead of
+    // being parked in memory.
     constexpr int PL = plan_passes(N) - 1;
+    constexpr int RAD = plan_radix(N, 0);
+    constexpr int PER = (N / RAD + T::TPF - 1) / T::TPF;
+    cpx<R> ureg[PER][RAD];  // u (or g) at the thread's elements
+    cpx<R> preg[PER][RAD];  // the undifferentiated part
     auto none = [](int, cpx<R>) {};
     auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
+    auto ld_ur = [&](int e, int pp, int qq) {
+      const cpx<R> x = p.u[rbase + e];
+      ureg[pp][qq] = x;
+      return x;
+    };
     auto dmul = [&](int e, cpx<R> v) { return deriv_factor<R, N>(e, v); };
-    auto mmid = [&](int e, cpx<R> dx) {
+    auto mmid = [&](int e, cpx<R> dx, int pp, int qq) {
       const long long g = rbase + e;
       const cpx<R> c1 = p.k2[g];
       const cpx<R> c2 = p.k2b[g];
-      const cpx<R> u = p.u[g];
+      const cpx<R> u = ureg[pp][qq];
       cpx<R> w = cscale(dx, c1.x);
       if constexpr (MODE == 2) w = w + cscale(u, c2.x);
-      else park[g] = p.b[g] - cscale(dx, c2.x) - cscale(u, c1.y) + ld_or_zero(p.s, g);
+      else preg[pp][qq] = p.b[g] - cscale(dx, c2.x) - cscale(u, c1.y) + ld_or_zero(p.s, g);
       return w;
     };
-    fft_pass<R, N, 0, PL, T::TPF, -1, false, false, 1>(mine, t, active, tw, ld_u, none);
+    fft_pass<R, N, 0, PL, T::TPF, -1, false, false, 1>(mine, t, active, tw, ld_ur, none);
     fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, tw, dmul);
     fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, tw);
     fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, tw, mmid);
     fft_inner<R, N, T::TPF, -1, 1>(mine, t, active, tw);
     fft_bridge<R, N, T::TPF, -1, 1, 1>(mine, t, active, tw, dmul);
     if constexpr (MODE == 0) {
-      auto tmid = [&](int e, cpx<R> v) { return v + p.inter[rbase + e]; };
+      auto tmid = [&](int e, cpx<R> v, int pp, int qq) { return v + preg[pp][qq]; };
       fft_inner<R, N, T::TPF, 1, 1>(mine, t, active, tw);
       fft_bridge<R, N, T::TPF, 1, -1, 1>(mine, t, active, tw, tmid);
       fft_pass<R, N, 1, PL + 1, T::TPF, -1, false, false, 1>(mine, t, active, tw, noload, st_s);
+    } else if constexpr (MODE == 1) {
+      auto st_p = [&](int e, cpx<R> v, int pp, int qq) { p.out[rbase + e] = v + preg[pp][qq]; };
+      fft_pass<R, N, 1, PL + 1, T::TPF, 1, false, false, 1>(mine, t, active, tw, noload, st_p);
     } else {
-      fft_pass<R, N, 1, PL + 1, T::TPF, 1, false, false, 1>(mine, t, active, tw, noload, st_f);
+      auto st_a = [&](int e, cpx<R> v, int pp, int qq) {
+        const long long g = rbase + e;
+        const cpx<R> vh = v + p.b[g] - cscale(ureg[pp][qq], p.k2[g].y);
+        p.out[g] = p.s[g] - vh;
+      };
+      fft_pass<R, N, 1, PL + 1, T::TPF, 1, false, false, 1>(mine, t, active, tw, noload, st_a);
     }
   } else {
     fft_run<R, N, T::TPF, -1, false, true>(mine, t, active, tw, ld_u, st_d);
@@ -179,26 +202,41 @@ __device__ __forceinline__ void cdr_col_body(const Params<R>& p, const InstDesc&
     else p.out[g] = v + p.out[g];
   };
   if constexpr (plan_bridgeable(N)) {
+    // as in the row pass: u and the undifferentiated part in registers
     constexpr int PL = plan_passes(N) - 1;
+    constexpr int RAD = plan_radix(N, 0);
+    constexpr int PER = (N / RAD + TPC - 1) / TPC;
+    cpx<R> ureg[PER][RAD];
+    cpx<R> preg[PER][RAD];
     auto none = [](int, cpx<R>) {};
     auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
+    auto ld_ur = [&](int e, int pp, int qq) {
+      const cpx<R> x = p.u[cbase + (long long)e * N];
+      ureg[pp][qq] = x;
+      return x;
+    };
     auto dmul = [&](int e, cpx<R> v) { return deriv_factor<R, N>(e, v); };
-    auto mmid = [&](int e, cpx<R> dy) {
+    auto mmid = [&](int e, cpx<R> dy, int pp, int qq) {
       const long long g = cbase + (long long)e * N;
       const cpx<R> c1 = p.k2[g];
       const cpx<R> c2 = p.k2b[g];
       cpx<R> w = cscale(dy, c1.x);
-      if constexpr (ADJ) w = w + cscale(p.u[g], c2.y);
-      else p.out[g] = cscale(dy, -c2.y);
+      if constexpr (ADJ) w = w + cscale(ureg[pp][qq], c2.y);
+      else preg[pp][qq] = cscale(dy, -c2.y);
       return w;
     };
-    fft_pass<R, N, 0, PL, TPC, -1, false, false, C>(mine, tt, true, tw, ld_u, none);
+    auto st_p = [&](int e, cpx<R> v, int pp, int qq) {
+      const long long g = cbase + (long long)e * N;
+      if constexpr (ADJ) p.out[g] = v;
+      else p.out[g] = v + preg[pp][qq];
+    };
+    fft_pass<R, N, 0, PL, TPC, -1, false, false, C>(mine, tt, true, tw, ld_ur, none);
     fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, tw, dmul);
     fft_inner<R, N, TPC, 1, C>(mine, tt, true, tw);
     fft_bridge<R, N, TPC, 1, -1, C>(mine, tt, true, tw, mmid);
     fft_inner<R, N, TPC, -1, C>(mine, tt, true, tw);
     fft_bridge<R, N, TPC, -1, 1, C>(mine, tt, true, tw, dmul);
-    fft_pass<R, N, 1, PL + 1, TPC, 1, false, false, C>(mine, tt, true, tw, noload, st_f);
+    fft_pass<R, N, 1, PL + 1, TPC, 1, false, false, C>(mine, tt, true, tw, noload, st_p);
   } else {
     fft_run<R, N, TPC, -1, false, true, C>(mine, tt, true, tw, ld_u, st_d);
     fft_run<R, N, TPC, 1, true, true, C>(mine, tt, true, tw, ld_l, st_m);
