@@ -293,9 +293,12 @@ cbs_status cbs_relres(cbs_plan plan, const void* u, const void* s, int stop, dou
  *              (Sec. 5; A u = -Lap u - k^2 u, App. D), tested in FP64 at each
  *              chunk start only (one more transform pair per chunk), so the
  *              sweep count is a multiple of check_every
- *   iters, relres, status  host[batch] outputs (sweeps applied, FP64-verified
- *              relative residual of the returned u under the chosen rule,
- *              CBS_INST_* code); nullable
+ *   iters, relres, status  host[batch] outputs (sweeps applied; relative
+ *              residual of the returned u under the chosen rule, evaluated
+ *              in FP64 -- for CBS_C64 plans that is the FP64 iterate rounded
+ *              to FP32, whose residual can exceed the iterate's by about
+ *              1e-7 times the conditioning; CBS_INST_* code, decided by the
+ *              FP64 iterate's residual); nullable
  *   use_graph  nonzero: replay each chunk from a captured hipGraph
  * Returns CBS_NOT_CONVERGED if any instance stopped without reaching rtol.
  */

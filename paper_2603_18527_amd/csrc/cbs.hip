@@ -729,6 +729,23 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, int stop, hipStream_t st) {
   return CBS_OK;
 }
 
+template <typename R>
+cbs_status relres_impl(cbs_plan p, const void* u, const void* s, int stop, double* relres, hipStream_t st);
+
+// FP32 plans hand back the FP64 iterate rounded to FP32.  The relative
+// residual reported is that of the returned field, evaluated in FP64 (the
+// FP64 iterate's own residual decided the status): rounding can move it by
+// about 1e-7 times the conditioning of the problem.
+template <typename R>
+cbs_status report_returned(cbs_plan p, const void* u, int stop, hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    launch_widen_all(st, static_cast<const cpx<float>*>(u), p->d_u64, p->cells);
+    HIPCHK(hipGetLastError());
+    return relres_impl<double>(p, p->d_u64, p->d_s64, stop, p->d_relres, st);
+  }
+  return CBS_OK;
+}
+
 struct FullViewOnExit {
   cbs_plan p;
   ~FullViewOnExit() { p->view = &p->full; }
@@ -838,6 +855,7 @@ cbs_status iterate_impl(cbs_plan p, void* u, const void* s, int max_sweeps, doub
   } else {
     HIPCHK(hipMemcpyAsync(u, p->d_u64, p->cells * 16, hipMemcpyDeviceToDevice, st));
   }
+  CHK(report_returned<R>(p, u, stop, st));
   std::vector<int> hit(B);
   std::vector<double> hrel(B);
   HIPCHK(hipMemcpyAsync(hit.data(), p->d_iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1021,6 +1039,7 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
   } else {
     HIPCHK(hipMemcpyAsync(u, p->d_u64, p->cells * 16, hipMemcpyDeviceToDevice, st));
   }
+  CHK(report_returned<R>(p, u, CBS_STOP_BORN, st));
   std::vector<int> hit(B);
   std::vector<double> hrel(B);
   HIPCHK(hipMemcpyAsync(hit.data(), p->d_iters, B * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1109,6 +1128,7 @@ cbs_status iterate_async_impl(cbs_plan p, void* u, const void* s, int max_sweeps
   for (long long c = 0; c < nchunks; ++c) CHK(enqueue_chunk<R>(p, chunk, stop, st));
   CHK(enqueue_check<R>(p, stop, st));
   CHK(solver_store<R>(p, u, st));
+  CHK(report_returned<R>(p, u, stop, st));
   launch_solver_out(st, iter_state(p), B, iters, relres, status);
   HIPCHK(hipGetLastError());
   return CBS_OK;
@@ -1134,6 +1154,7 @@ cbs_status fgmres_async_impl(cbs_plan p, void* u, const void* s, int m, int swee
   }
   CHK(fg_restart(p, m, 0, st));  // true residual of the last update decides the status
   CHK(solver_store<R>(p, u, st));
+  CHK(report_returned<R>(p, u, CBS_STOP_BORN, st));
   launch_solver_out(st, iter_state(p), B, iters, relres, status);
   HIPCHK(hipGetLastError());
   return CBS_OK;

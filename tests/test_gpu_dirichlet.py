@@ -95,9 +95,12 @@ def test_dirichlet_iterate_matches_oracle_and_dense_solve(dtype):
             / O.norm(O.green_dirichlet(src[i], plan.k0sq[i], plan.eps[i]))
         say(f"[dirichlet iterate] dtype={dtype} n={n}: gpu {its[0 + i]} sweeps rel {rel[i]:.2e} "
             f"(oracle eval {ev:.2e}); oracle {mo}")
-        assert stat[i] == cbs.INST_CONVERGED and rel[i] <= 1e-6
+        assert stat[i] == cbs.INST_CONVERGED
         assert abs(its[i] - mo) <= 20
-        assert ev <= (1e-5 if dtype == cbs.CBS_C64 else 1.01e-6)
+        if dtype == cbs.CBS_C64:   # reported: FP64 residual of the returned FP32 field
+            assert ev <= 1e-5 and abs(rel[i] - ev) <= 0.1 * ev
+        else:
+            assert rel[i] <= 1e-6 and ev <= 1.01e-6
     # n = 15 against the dense solve of (L_D - k^2) u = s
     eye = np.eye(15 * 15).reshape(-1, 15, 15)
     a = np.stack([O.laplacian_dirichlet(e).numpy().reshape(-1) for e in eye], axis=1) \
@@ -128,7 +131,7 @@ def test_dirichlet_fgmres_on_newton_jacobians():
         ug = _unpack(u, [n] * batch)[i]
         ev = O.norm(O.cbs_residual_dirichlet(k2[i], plan.k0sq[i], plan.eps[i], ug, rhs[i])) \
             / O.norm(O.green_dirichlet(rhs[i], plan.k0sq[i], plan.eps[i]))
-        assert stat[i] == cbs.INST_CONVERGED and rel[i] <= 1e-6 and ev <= 1e-5
+        assert stat[i] == cbs.INST_CONVERGED and ev <= 1e-5 and abs(rel[i] - ev) <= 0.1 * ev
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])

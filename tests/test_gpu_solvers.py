@@ -1,13 +1,14 @@
 """GPU solvers against the FP64 oracle: stationary CBS (cbs_iterate) and
 FGMRES (fgmres_solve), single instances and ragged batches.
 
-Bar (per instance): the solvers keep their iterate in FP64 and report its FP64
-Born relative residual, which must be <= rtol.  The solution handed back in an
-FP32 (complex64) plan is that iterate rounded to FP32; rounding alone moves
-the residual by ~1e-7 * ||u|| / ||G s||, so the oracle's evaluation of the
-returned FP32 solution must be <= 1e-5 (ten times rtol).  FP64 plans return
-the iterate itself: the oracle's evaluation must match the reported value to
-1% and be <= rtol.  Sweep / Arnoldi-step counts match the oracle's (the
+Bar (per instance): the solvers keep their iterate in FP64 and stop when its
+FP64 Born relative residual is <= rtol.  The solution handed back in an FP32
+(complex64) plan is that iterate rounded to FP32; rounding alone moves the
+residual by ~1e-7 * ||u|| / ||G s||, so the oracle's evaluation of the
+returned FP32 solution must be <= 1e-5 (ten times rtol), and the reported
+value -- the FP64 residual of that returned solution -- must agree with the
+oracle's evaluation to 10 %.  FP64 plans return the iterate itself: the
+oracle's evaluation must match the reported value to 1% and be <= rtol.  Sweep / Arnoldi-step counts match the oracle's (the
 arithmetic is the same in exact arithmetic; FP32 noise and the check cadence
 move the stop by at most a chunk)."""
 import numpy as np
@@ -27,10 +28,14 @@ def _oracle_relres(k2, k0sq, eps, u, s):
 
 
 def _bar(dtype, reported, evaluated, rtol=1e-6):
-    assert reported <= rtol
     if dtype == cbs.CBS_C64:
+        # the reported value is the FP64 residual of the returned (FP32-
+        # rounded) solution: it agrees with the oracle's evaluation of that
+        # solution to 10 %, and rounding keeps it within ten times rtol
         assert evaluated <= 10 * rtol
+        assert abs(reported - evaluated) <= 0.1 * evaluated
     else:
+        assert reported <= rtol
         assert evaluated <= rtol * 1.01
         assert abs(reported - evaluated) <= 0.01 * evaluated
 
@@ -112,7 +117,7 @@ def test_iterate_physical_stop_rule(dtype):
     ev = O.physical_relres(ki, ug, si)
     say(f"[physical stop] dtype={dtype}: gpu {its[0]} sweeps rTol {rel[0]:.3e} (oracle eval {ev:.3e}); "
         f"oracle first <= rtol at {m}")
-    assert stat[0] == cbs.INST_CONVERGED and rel[0] <= rtol
+    assert stat[0] == cbs.INST_CONVERGED
     assert its[0] % k == 0 and hist[m] <= rtol < hist[m - 1]
     if dtype == cbs.CBS_C128:
         assert its[0] == expect
@@ -124,6 +129,7 @@ def test_iterate_physical_stop_rule(dtype):
         bound = 16 * 2.0 ** -24 * float((torch.linalg.vector_norm(lap) + torch.linalg.vector_norm(ku))
                                         / torch.linalg.vector_norm(si))
         assert ev <= rtol + bound
+        assert abs(ev - rel[0]) <= 0.1 * ev   # reported: FP64 residual of the returned field
     # the Born rule on the same problem is a different criterion
     u2 = plan.zeros()
     its_b, rel_b, _ = plan.iterate(u2, s, max_sweeps=5000, rtol=rtol, check_every=k)
@@ -259,11 +265,14 @@ def test_iterate_degenerate_cases():
     its, rel, stat = plan.iterate(u, s2, max_sweeps=2000, rtol=1e-6, check_every=10)
     assert stat[0] == cbs.INST_CONVERGED and stat[1] == cbs.INST_DIVERGED
     # FGMRES with restart 1 (steepest-descent-like) still reaches the tolerance
-    plan2, _ = plan_for(probs[:1], restart=1)
+    plan2, k2b = plan_for(probs[:1], restart=1)
     u = plan2.zeros()
     its, rel, stat = plan2.fgmres(u, cbs.pack([probs[0].source], torch.complex64), restart=1, sweeps=3,
                                   max_iters=5000, rtol=1e-6)
-    assert stat[0] == cbs.INST_CONVERGED and rel[0] <= 1e-6
+    ug = to_list(u, [probs[0].n])[0]
+    ev = O.born_relres(to_list(k2b, [probs[0].n])[0], plan2.k0sq[0], plan2.eps[0], ug, probs[0].source)
+    assert stat[0] == cbs.INST_CONVERGED
+    _bar(cbs.CBS_C64, rel[0], ev)
 
 
 def test_aliasing_and_argument_errors():
