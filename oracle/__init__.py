@@ -491,7 +491,10 @@ def born_operator(k2, k0sq, eps, x) -> torch.Tensor:
 
 def cbs_precondition(k2, k0sq, eps, v, sweeps: int) -> torch.Tensor:
     """P_K(v): K CBS sweeps z <- z + gamma (G V z + v - z) from z = 0, an
-    approximate inverse of B (K = 1 gives z = gamma v)."""
+    approximate inverse of B (K = 1 gives z = gamma v).  K = 0 stands for no
+    inner preconditioner, P_0 = I (GMRES on B itself)."""
+    if sweeps == 0:
+        return as_c(v).clone()
     z = torch.zeros_like(as_c(v))
     for _ in range(sweeps):
         z = cbs_sweep(k2, k0sq, eps, z, None, v)

@@ -62,3 +62,41 @@ def test_dirichlet_cbs_matches_dense_solve():
     ref = np.linalg.solve(a, s.reshape(-1)).reshape(n, n)
     assert np.max(np.abs(u.numpy() - ref)) <= 1e-9 * np.max(np.abs(ref))
     assert torch.max(torch.abs(O.helmholtz_dirichlet(k2, u) - O.as_c(s))) <= 1e-8 * np.max(np.abs(s))
+
+
+def _dense_dirichlet_laplacian(n):
+    # L_D = kron(L1, I) + kron(I, L1), L1 = tridiag(-1, 2, -1) / h^2
+    h = 1.0 / (n + 1)
+    l1 = (2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)) / h ** 2
+    return np.kron(l1, np.eye(n)) + np.kron(np.eye(n), l1)
+
+
+@pytest.mark.parametrize("k0sq", [-50.0, 10.0, 300.0])
+def test_undamped_green_is_the_inverse_reference(k0sq):
+    # eps = 0: G = (L_D - k0^2)^-1 (App. B.2, Eq. newton_ref with no damping),
+    # definite (k0^2 below the lowest eigenvalue 2 pi^2 ~ 19.6) or not
+    n = 15
+    rng = np.random.default_rng(7)
+    q = S.random_field_c(n, rng)
+    a = _dense_dirichlet_laplacian(n) - k0sq * np.eye(n * n)
+    ref = np.linalg.solve(a, q.reshape(-1)).reshape(n, n)
+    got = O.green_dirichlet(q, k0sq, 0.0).numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_newton_born_identity_undamped():
+    # I - G V = G J (Eq. newton_born_identity): with J = L_D - 2 diag(u_m),
+    # J_0 = L_D - k0^2, k0^2 = 2 mean(u_m) - alpha and V = J_0 - J = 2 u_m - k0^2,
+    # the Born residual G (V x + s) - x equals G (s - J x)
+    n = 15
+    rng = np.random.default_rng(8)
+    x1 = np.arange(1, n + 1) / (n + 1)
+    um = 5.0 + 3.0 * np.outer(np.sin(math.pi * x1), np.sin(2 * math.pi * x1))
+    k2, k0sq = 2.0 * um, 2.0 * um.mean() - 4.0
+    x = S.random_field_c(n, rng)
+    s = S.random_field_c(n, rng)
+    jac = _dense_dirichlet_laplacian(n) - np.diag(k2.reshape(-1))
+    g = np.linalg.inv(_dense_dirichlet_laplacian(n) - k0sq * np.eye(n * n))
+    ref = (g @ (s.reshape(-1) - jac @ x.reshape(-1))).reshape(n, n)
+    got = O.cbs_residual_dirichlet(k2, k0sq, 0.0, x, s).numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))

@@ -117,6 +117,26 @@ def test_fgmres_k1_equals_diagonal_gamma_preconditioner():
                           rtol=0, atol=1e-15)
 
 
+def test_gmres_without_inner_preconditioner():
+    # K = 0 is P_0 = I: GMRES on B x = b.  One step from x = 0 is the best
+    # multiple of b, with the closed-form residual
+    # ||b|| sqrt(1 - |<B b, b>|^2 / (||B b||^2 ||b||^2)); the full space
+    # (restart = number of unknowns) reaches LAPACK's solution.
+    p = _problem16(seed=5)
+    eps = O.choose_eps(p.k2, p.k0sq)
+    b = O.green(O.as_c(p.source), p.k0sq, eps)
+    bb = O.born_operator(p.k2, p.k0sq, eps, b)
+    c = complex(torch.sum(bb.conj() * b))
+    one = math.sqrt(1.0 - abs(c) ** 2 / (O.norm(bb) ** 2 * O.norm(b) ** 2))
+    x, its, rel = O.fgmres(p.k2, p.k0sq, eps, p.source, restart=10, sweeps=0, max_iters=1, rtol=0.0)
+    assert its == 1 and abs(rel - one) <= 1e-12 * one
+    assert torch.allclose(x, b * (c / O.norm(bb) ** 2), rtol=0, atol=1e-14 * float(torch.abs(b).max()))
+    ref = np.linalg.solve(_dense_helmholtz_numpy(p.k2), p.source.reshape(-1)).reshape(16, 16)
+    x, its, rel = O.fgmres(p.k2, p.k0sq, eps, p.source, restart=256, sweeps=0, max_iters=256, rtol=1e-11)
+    assert rel <= 1e-11 and its <= 256
+    assert np.max(np.abs(x.numpy() - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
 @pytest.mark.slow
 def test_outgoing_greens_function_with_sponge():
     # P4: homogeneous lossless interior, absorbing sponge: the field of a unit
