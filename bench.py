@@ -66,14 +66,15 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
     a sweep moves between the L2s and memory, not DRAM-only bytes.
 
     Each counter is scaled by what it reads for the 1 GiB calibration copy
-    (the largest __amd_rocclr_copyBuffer dispatch).  Only dispatches from the
-    first k_row_fwd to the last k_row_inv before the NPBS steps count (the
-    autotuner before and the NPBS steps after launch k_col on grids that can
-    equal a lane's; the lanes join before the NPBS steps start).  In between
+    (the largest __amd_rocclr_copyBuffer dispatch, issued after the
+    autotuner).  Only dispatches from the first k_row_fwd after that copy to
+    the last k_row_inv before the NPBS steps count (the autotuner's races
+    before and the NPBS steps after launch the sweep kernels on the lanes'
+    grids too; the lanes join before the NPBS steps start).  In between
     the run makes, per lane
-    (two lanes, or one when the batch is not split), 62 k_col and 60
-    k_row_sweep dispatches of the lane's grid (warm-up call of 2 sweeps, one
-    chain of 60).  Per-sweep bytes: the bytes of every dispatch of a grid
+    (two lanes, or one when the batch is not split), 62 column-pass (k_col or
+    k_col_wide, whichever the autotuner picked) and 60 k_row_sweep dispatches
+    of the lane's grid (warm-up call of 2 sweeps, one chain of 60).  Per-sweep bytes: the bytes of every dispatch of a grid
     launched at least that often, divided by the number of sweeps."""
     import csv
     import collections
@@ -83,16 +84,20 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         scale = (1 << 30) / (max(copies) * 1024.0)
-        t0 = min(int(r["Start_Timestamp"]) for r in rows if "k_row_fwd<float>" in r["Kernel_Name"])
+        tc = max(int(r["Start_Timestamp"]) for r in rows
+                 if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) == max(copies))
+        t0 = min(int(r["Start_Timestamp"]) for r in rows
+                 if "k_row_fwd<float>" in r["Kernel_Name"] and int(r["Start_Timestamp"]) > tc)
         tn = min([int(r["Start_Timestamp"]) for r in rows if "k_row_npbs" in r["Kernel_Name"]] + [1 << 62])
         t1 = max(int(r["Start_Timestamp"]) for r in rows
                  if "k_row_inv<float>" in r["Kernel_Name"] and int(r["Start_Timestamp"]) < tn)
         rows = [r for r in rows if t0 <= int(r["Start_Timestamp"]) <= t1]
         out, grids = {}, {}
-        for kern, tag in (("k_row_sweep", "k_row_sweep<float>"), ("k_col", "k_col<float")):
+        for kern, tags in (("k_row_sweep", ("k_row_sweep<float>",)),
+                           ("k_col", ("k_col<float>", "k_col_wide<float>"))):
             by_grid = collections.defaultdict(list)
             for r in rows:
-                if tag in r["Kernel_Name"]:
+                if any(t in r["Kernel_Name"] for t in tags):
                     by_grid[int(r["Grid_Size"])].append(float(r["Counter_Value"]))
             lanes = sorted(g for g, v in by_grid.items() if len(v) >= sweeps[kern])
             for g in lanes:
@@ -106,7 +111,7 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
     fs, fetch, grids = load(fetch_csv, "FETCH_SIZE")
     ws, write, _ = load(write_csv, "WRITE_SIZE")
     cmd = ("python -u bench.py --steps 60 --chain 60 --warmup 2 --no-cpu --no-solve --no-layered --no-graph "
-           "--calib-copy")
+           "--calib-copy" + ("" if workload == "ragged64" else f" --workload {workload}"))
     rec = {
         "workload": workload,
         "kernel_source_hash": kernel_source_hash(),
@@ -385,6 +390,7 @@ def layered_leg(fgmres: bool = True):
     plan = cbs.Plan(k2, sizes, k0sq=[q.k0sq for q in probs], max_restart=50 if fgmres else 0)
     tiles = plan.autotune()
     st = time_sweeps(plan, s, 100, 10, 50)
+    traffic = measured_traffic("layered1024")
     achieved = BYTES_PER_CELL * cells / (st["event_ms_per_sweep"] * 1e-3) / 1e9
     out = {
         "workload": "layered1024: 8 instances of 1024^2, 5 layers + 10% random field, 8 ppw, 64-cell sponge",
@@ -393,7 +399,12 @@ def layered_leg(fgmres: bool = True):
                   "steps": st["steps"], "ms_per_step": st["wall_ms_per_sweep"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "event_ms_per_sweep": st["event_ms_per_sweep"],
-                     "algorithmic_bytes_per_sweep": BYTES_PER_CELL * cells},
+                     "algorithmic_bytes_per_sweep": BYTES_PER_CELL * cells, "traffic": traffic,
+                     # L2-to-fabric bytes; the working set exceeds the Infinity
+                     # Cache, so nearly all of them reach DRAM
+                     "l2_fabric_bytes_per_cell": None if traffic is None else traffic / cells,
+                     "l2_fabric_gbs": None if traffic is None else
+                     traffic / (st["event_ms_per_sweep"] * 1e-3) / 1e9},
     }
     if fgmres:
         sol = {}
@@ -674,14 +685,6 @@ def main():
         raise SystemExit("no GPU visible")
 
     from paper_2603_18527_amd import cbs
-    if args.calib_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        print("# calibration copy: 1073741824 bytes read, 1073741824 bytes written", flush=True)
-        del a, b
     probs, desc = build_workload(args.workload)
     sizes = [p.n for p in probs]
     cells = sum(n * n for n in sizes)
@@ -691,6 +694,15 @@ def main():
     plan = cbs.Plan(k2, sizes, k0sq=k0sq)
     tiles = plan.autotune()
     tile_by_size = {str(n): t for n, t in sorted(set(zip(sizes, tiles)))}
+    if args.calib_copy:
+        # after the autotuner, so that the copy also marks where its races end
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("# calibration copy: 1073741824 bytes read, 1073741824 bytes written", flush=True)
+        del a, b
     print(f"# workload {args.workload}: {len(sizes)} instances, {cells} cells, column tiles "
           f"{tile_by_size}", flush=True)
 

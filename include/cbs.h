@@ -92,7 +92,8 @@ enum {
 enum {
   CBS_FLAG_NO_GUARD = 1u,   /* skip the eps / min|V| conditioning guard */
   CBS_FLAG_ONE_STREAM = 2u, /* enqueue every kernel on the caller's stream (no lanes) */
-  CBS_FLAG_DIRICHLET = 4u   /* Dirichlet instances: DST-I reference (see cbs_setup) */
+  CBS_FLAG_DIRICHLET = 4u,  /* Dirichlet instances: DST-I reference (see cbs_setup) */
+  CBS_FLAG_UNDAMPED = 8u    /* with CBS_FLAG_DIRICHLET: eps = 0, the reference L_D - k0^2 itself */
 };
 
 /*
@@ -121,8 +122,20 @@ enum {
  * 4/h^2 (sin^2(p pi h/2) + sin^2(q pi h/2)) - k0^2 - i eps.  Every call then
  * uses that G and L_D in place of the periodic ones.  n must satisfy
  * 2(n+1) in {16, ..., 1024} above: n in {7, 15, 31, 63, 95, 127, 143, 191,
- * 255, 511}.  (A Newton step J du = r with J = L_D - 2 diag(u) is the case
- * k^2 = 2u; k0^2 = 2 mean(u) - alpha gives the paper's reference Jacobian.)
+ * 255, 511}.  A Newton step J du = r with J = L_D - 2 diag(u) (App. B.2,
+ * Eq. newton_linear_system) is the case k^2 = 2u.  Without further flags the
+ * plan's reference is the damped L_D - (k0^2 + i eps), eps > 0.
+ * Undamped Dirichlet plans (CBS_FLAG_DIRICHLET | CBS_FLAG_UNDAMPED): eps = 0
+ * for every instance, so G = (L_D - k0^2)^-1 and V = k^2 - k0^2; with k0^2 =
+ * 2 mean(u) - alpha that G is the paper's J_{0,m}^-1 (App. B.2, Eq.
+ * newton_ref) and I - G V = G J (Eq. newton_born_identity).  eps must be
+ * NULL.  Setup rejects (CBS_ERR_ILLCOND) a reference with an eigenvalue
+ * mu_p + mu_q - k0^2 equal to zero, or, unless CBS_FLAG_NO_GUARD, within 1e-9
+ * of max(2 mu_n, |k0^2|).  Without damping there is no gamma = i V / eps:
+ * cbs_sweep, cbs_iterate(_async), FGMRES with inner sweeps, cbs_adjoint_step
+ * and the W = gamma seed return CBS_ERR_ARG; the apply, residuals, relres,
+ * NPBS steps, the metric-matched gradient, the Born adjoint and FGMRES with
+ * inner_sweeps = 0 (GMRES on I - G V) are available.
  * Lanes: a batch of at least two instances and 2^21 cells is split into two
  * lanes of about equal cell count.  Sweep chains (cbs_sweep, the sweeps of
  * cbs_iterate and of the FGMRES preconditioner) run each lane on a
@@ -314,6 +327,8 @@ cbs_status cbs_iterate(cbs_plan plan, void* u, const void* s, int max_sweeps, do
  *   Gram-Schmidt (applied twice), Hessenberg/Givens least squares and the true
  *   residual at each restart are FP64 on the GPU; operator applications run in
  *   the plan's dtype.  iters counts Arnoldi steps.  Outputs as in cbs_iterate.
+ *   inner_sweeps in [0, 1000]; 0 is no inner preconditioner (z_j = v_j: GMRES
+ *   on B itself), the only choice on undamped plans.
  *   restart must not exceed the plan's max_restart (else CBS_ERR_WORKSPACE).
  */
 cbs_status fgmres_solve(cbs_plan plan, void* u, const void* s, int restart, int inner_sweeps,

@@ -31,6 +31,7 @@ CBS_C128 = 1
 FLAG_NO_GUARD = 1
 FLAG_ONE_STREAM = 2
 FLAG_DIRICHLET = 4
+FLAG_UNDAMPED = 8
 INST_RUNNING, INST_CONVERGED, INST_MAX_ITERS, INST_DIVERGED = 0, 1, 2, 3
 
 SUPPORTED_SIZES = (16, 32, 64, 128, 192, 256, 288, 384, 512, 1024)
@@ -218,11 +219,14 @@ class Plan:
 
     def __init__(self, k2: torch.Tensor, sizes: Sequence[int], k0sq=None, eps=None,
                  dtype: int = CBS_C64, max_restart: int = 0, guard: bool = True, stream=None,
-                 lanes: bool = True, torch_workspace: bool = True, dirichlet: bool = False):
+                 lanes: bool = True, torch_workspace: bool = True, dirichlet: bool = False,
+                 undamped: bool = False):
         """torch_workspace: the plan's device memory is one torch tensor
         (cbs_setup_ws); False lets the library allocate it (cbs_setup).
         dirichlet: instances are n x n interiors of the unit square with
-        homogeneous Dirichlet boundaries (five-point FD, DST-I reference)."""
+        homogeneous Dirichlet boundaries (five-point FD, DST-I reference).
+        undamped (Dirichlet only): eps = 0, the reference L_D - k0^2 itself
+        (no sweeps; FGMRES with sweeps=0)."""
         lib = load()
         release_deferred()
         self.sizes = [int(n) for n in sizes]
@@ -240,8 +244,9 @@ class Plan:
             *[0.0 if v is None else float(v) for v in _expand(eps, self.batch)])
         h = ctypes.c_void_p()
         flags = ((0 if guard else FLAG_NO_GUARD) | (0 if lanes else FLAG_ONE_STREAM)
-                 | (FLAG_DIRICHLET if dirichlet else 0))
+                 | (FLAG_DIRICHLET if dirichlet else 0) | (FLAG_UNDAMPED if undamped else 0))
         self.dirichlet = bool(dirichlet)
+        self.undamped = bool(undamped)
         self._ws = None
         if torch_workspace:
             self._ws = torch.empty(workspace_size(self.sizes, dtype, max_restart, dirichlet), dtype=torch.uint8,
@@ -490,6 +495,7 @@ class CdrPlan(Plan):
         bg_arr = (ctypes.c_double * (4 * self.batch))(*[v for b in bg for v in b])
         h = ctypes.c_void_p()
         self.dirichlet = False
+        self.undamped = False
         self._ws = torch.empty(workspace_size_cdr(self.sizes, dtype), dtype=torch.uint8, device="cuda")
         self._ws_stream = torch.cuda.current_stream()
         _check(lib.cbs_setup_cdr_ws(ctypes.byref(h), self.batch, n_arr, _ptr(kappa_sigma.contiguous()),

@@ -162,6 +162,7 @@ struct cbs_plan_s {
   hipStream_t own_stream = nullptr;  // capture stream when the caller passes the null stream
   bool one_stream = false;           // CBS_FLAG_ONE_STREAM
   bool dirichlet = false;            // CBS_FLAG_DIRICHLET: DST-I instances
+  bool undamped = false;             // CBS_FLAG_UNDAMPED: eps = 0, no gamma
   bool cdr = false;                  // convection-diffusion-reaction plan (cbs_setup_cdr)
   void* d_k2b = nullptr;             // CDR: (dvx, dvy) per cell, operator precision
   std::vector<double> vx0, vy0;      // CDR background velocity per instance
@@ -469,39 +470,48 @@ cbs_status run_pipeline(cbs_plan p, Params<R> q, hipStream_t st) {
   return CBS_OK;
 }
 
-// `count` CBS sweeps in place on q.u (= q.out): forward rows, then
-// (count - 1) times [columns, fused inverse/forward rows], then columns and
-// inverse rows with the sweep epilogue.  The partial norms left behind are
-// those of the last sweep.
-template <typename R>
-void sweep_chain(cbs_plan p, const Params<R>& q, int count, hipStream_t st,
-                 const cbs_plan_s::Items& it) {
-  Params<R> f = q;
-  f.items = it.rows;
-  launch_row(0, it.nrows, st, f);
-  for (int k = 1; k < count; ++k) {
-    launch_cols(p, q, st, it);
-    launch_row(2, it.nrows, st, f);
-  }
-  launch_cols(p, q, st, it);
-  Params<R> e = q;
-  e.items = it.rows;
-  e.epi = EPI_SWEEP;
-  launch_row(1, it.nrows, st, e);
-}
-
-template <typename R>
-cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
+// Issue a chain of `steps` launch groups, step(k, stream, items), on the
+// view's lanes (between a fork and a join) or on `st` alone.  The lanes'
+// launches alternate step by step: queued lane by lane, the second lane's
+// first kernel would wait behind the host-side issue of the first lane's
+// whole chain (also when a graph replays the chain in capture order).
+template <typename F>
+cbs_status issue_chain(cbs_plan p, hipStream_t st, int steps, F&& step) {
   const cbs_plan_s::View& v = *p->view;
   if (v.nlanes) {
     CHK(lanes_fork(p, st));
-    for (int l = 0; l < v.nlanes; ++l) sweep_chain(p, q, count, p->lane_st[l], v.lane[l]);
+    for (int k = 0; k < steps; ++k)
+      for (int l = 0; l < v.nlanes; ++l) step(k, p->lane_st[l], v.lane[l]);
     HIPCHK(hipGetLastError());
     return lanes_join(p, st);
   }
-  sweep_chain(p, q, count, st, v.all());
+  const cbs_plan_s::Items all = v.all();
+  for (int k = 0; k < steps; ++k) step(k, st, all);
   HIPCHK(hipGetLastError());
   return CBS_OK;
+}
+
+// `count` CBS sweeps in place on q.u (= q.out), as count + 1 steps: forward
+// rows, then (count - 1) times [columns, fused inverse/forward rows], then
+// columns and inverse rows with the sweep epilogue.  The partial norms left
+// behind are those of the last sweep.
+template <typename R>
+cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
+  return issue_chain(p, st, count + 1, [&](int k, hipStream_t ls, const cbs_plan_s::Items& it) {
+    Params<R> f = q;
+    f.items = it.rows;
+    if (k == 0) {
+      launch_row(0, it.nrows, ls, f);
+      return;
+    }
+    launch_cols(p, q, ls, it);
+    if (k < count) {
+      launch_row(2, it.nrows, ls, f);
+    } else {
+      f.epi = EPI_SWEEP;
+      launch_row(1, it.nrows, ls, f);
+    }
+  });
 }
 
 template <typename R>
@@ -694,27 +704,23 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, int stop, hipStream_t st) {
     // Each lane checks only its own instances, so the lanes never wait on
     // each other inside the chunk.
     q.chk = is;
-    auto chain = [&](hipStream_t ls, const cbs_plan_s::Items& it, int ncheck, const int* ids) {
-      q.items = it.rows;
-      launch_row(0, it.nrows, ls, q);
-      for (int k = 1; k < chunk; ++k) {
-        q.check = k >= 2 ? 1 : 0;
-        launch_cols(p, q, ls, it);
-        q.check = 0;
-        q.items = it.rows;
-        launch_row(k + 1 < chunk ? 2 : 1, it.nrows, ls, q);
+    const bool lanes = p->view->nlanes != 0;
+    CHK(issue_chain(p, st, chunk + 1, [&](int k, hipStream_t ls, const cbs_plan_s::Items& it) {
+      Params<R> c = q;
+      c.items = it.rows;
+      if (k == 0) {
+        launch_row(0, it.nrows, ls, c);
+      } else if (k < chunk) {
+        c.check = k >= 2 ? 1 : 0;
+        launch_cols(p, c, ls, it);
+        c.check = 0;
+        launch_row(k + 1 < chunk ? 2 : 1, it.nrows, ls, c);
+      } else if (lanes) {
+        launch_check32(it.nids, it.ids, ls, is, p->d_inst, p->d_partials);
+      } else {
+        launch_check32(p->batch, nullptr, ls, is, p->d_inst, p->d_partials);
       }
-      launch_check32(ncheck, ids, ls, is, p->d_inst, p->d_partials);
-    };
-    const cbs_plan_s::View& v = *p->view;
-    if (v.nlanes) {
-      CHK(lanes_fork(p, st));
-      for (int l = 0; l < v.nlanes; ++l) chain(p->lane_st[l], v.lane[l], v.lane[l].nids, v.lane[l].ids);
-      HIPCHK(hipGetLastError());
-      CHK(lanes_join(p, st));
-    } else {
-      chain(st, v.all(), p->batch, nullptr);
-    }
+    }));
   }
   {
     PwParams<R> w{};
@@ -931,12 +937,18 @@ cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
   cpx<R>* z = static_cast<cpx<R>*>(p->d_zbasis) + (long long)j * p->cells;
   cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
   cpx<double>* w = p->d_vbasis + (long long)(j + 1) * p->cells;
-  // z_j = P_K(v_j): first sweep from zero is z = gamma v, then K-1 full sweeps
+  // z_j = P_K(v_j): first sweep from zero is z = gamma v, then K-1 full
+  // sweeps; K = 0 is no inner preconditioner, z_j = v_j
   {
     PwParams<R> pw{};
-    pw.op = PW_FIRST64;
-    pw.src64 = p->d_vbasis + (long long)j * p->cells;
-    pw.c_out = c;
+    if (sweeps == 0) {
+      pw.op = PW_NARROW;
+      pw.x64 = p->d_vbasis + (long long)j * p->cells;
+    } else {
+      pw.op = PW_FIRST64;
+      pw.src64 = p->d_vbasis + (long long)j * p->cells;
+      pw.c_out = c;
+    }
     pw.e_out = z;
     pw.mask = p->d_kactive;
     pw.mask_mode = MASK_NONZERO;
@@ -1169,26 +1181,25 @@ cbs_status fgmres_async_impl(cbs_plan p, void* u, const void* s, int m, int swee
 // the last step ends with inverse rows and the update.  Dirichlet plans run
 // the residual pipeline and the layer's pipeline one after the other.
 template <typename R>
-void npbs_chain(cbs_plan p, const Params<R>& base, int count, hipStream_t st,
-                const cbs_plan_s::Items& it) {
+void npbs_step(cbs_plan p, const Params<R>& base, int count, int k, hipStream_t st,
+               const cbs_plan_s::Items& it) {
   Params<R> g = base;
   g.items = it.rows;
-  launch_row(0, it.nrows, st, g);            // V u + s -> forward rows
+  if (k == 0) {
+    launch_row(0, it.nrows, st, g);          // V u + s -> forward rows
+    return;
+  }
   Params<R> m = base;
   m.sym = SYM_TABLE;
-  for (int k = 0; k < count; ++k) {
-    launch_cols(p, base, st, it);            // Green
-    g.items = it.rows;
-    launch_row(3, it.nrows, st, g);          // r = z - u -> forward rows of r
-    launch_cols(p, m, st, it);               // layer's spectral weights
-    m.items = it.rows;
-    if (k + 1 < count) {
-      launch_row(4, it.nrows, st, m);        // u += z + wloc r -> forward rows of V u + s
-    } else {
-      Params<R> e = m;
-      e.epi = EPI_NPBS;
-      launch_row(1, it.nrows, st, e);        // u += z + wloc r
-    }
+  m.items = it.rows;
+  launch_cols(p, base, st, it);              // Green
+  launch_row(3, it.nrows, st, g);            // r = z - u -> forward rows of r
+  launch_cols(p, m, st, it);                 // layer's spectral weights
+  if (k < count) {
+    launch_row(4, it.nrows, st, m);          // u += z + wloc r -> forward rows of V u + s
+  } else {
+    m.epi = EPI_NPBS;
+    launch_row(1, it.nrows, st, m);          // u += z + wloc r
   }
 }
 
@@ -1206,16 +1217,9 @@ cbs_status npbs_impl(cbs_plan p, void* u, const void* s, const void* wf, const v
     q.b = static_cast<const cpx<R>*>(wloc);
     q.table = static_cast<const cpx<R>*>(wf);
     q.partials = nullptr;
-    const cbs_plan_s::View& v = *p->view;
-    if (v.nlanes) {
-      CHK(lanes_fork(p, st));
-      for (int l = 0; l < v.nlanes; ++l) npbs_chain(p, q, count, p->lane_st[l], v.lane[l]);
-      HIPCHK(hipGetLastError());
-      return lanes_join(p, st);
-    }
-    npbs_chain(p, q, count, st, v.all());
-    HIPCHK(hipGetLastError());
-    return CBS_OK;
+    return issue_chain(p, st, count + 1, [&](int k, hipStream_t ls, const cbs_plan_s::Items& it) {
+      npbs_step(p, q, count, k, ls, it);
+    });
   }
   for (int k = 0; k < count; ++k) {
     Params<R> q = base_params<R>(p);
@@ -1506,9 +1510,12 @@ cbs_status check_setup_args(int batch, const int32_t* n, int dtype, int max_rest
   if (batch < 1 || !n) return fail(CBS_ERR_ARG, "batch < 1 or n NULL");
   if (dtype != CBS_C64 && dtype != CBS_C128) return fail(CBS_ERR_ARG, "dtype must be CBS_C64 or CBS_C128");
   if (max_restart < 0 || max_restart > 200) return fail(CBS_ERR_ARG, "max_restart must be in [0, 200]");
-  if (flags & ~uint32_t(CBS_FLAG_NO_GUARD | CBS_FLAG_ONE_STREAM | CBS_FLAG_DIRICHLET))
+  if (flags & ~uint32_t(CBS_FLAG_NO_GUARD | CBS_FLAG_ONE_STREAM | CBS_FLAG_DIRICHLET | CBS_FLAG_UNDAMPED))
     return fail(CBS_ERR_ARG, "unknown flag bits");
   const bool dir = (flags & CBS_FLAG_DIRICHLET) != 0;
+  if ((flags & CBS_FLAG_UNDAMPED) && !dir)
+    return fail(CBS_ERR_ARG, "CBS_FLAG_UNDAMPED needs CBS_FLAG_DIRICHLET (a periodic reference |xi|^2 - k0^2 "
+                             "vanishes or nearly vanishes on the grid without damping)");
   for (int i = 0; i < batch; ++i)
     if (n[i] < 1 || !supported_n(dir ? dst_len(n[i]) : n[i]))
       return fail(CBS_ERR_SIZE, std::string(dir ? "unsupported Dirichlet size " : "unsupported grid size ") +
@@ -1523,6 +1530,7 @@ void init_layout(cbs_plan p, int batch, const int32_t* n, int dtype, int max_res
   p->max_restart = max_restart;
   p->one_stream = (flags & CBS_FLAG_ONE_STREAM) != 0;
   p->dirichlet = (flags & CBS_FLAG_DIRICHLET) != 0;
+  p->undamped = (flags & CBS_FLAG_UNDAMPED) != 0;
   // FP32 periodic Helmholtz plans start with the wide column workgroups
   // (the faster ones on MI355X for the ragged and 1024^2 batches)
   p->col_threads32 = (dtype == CBS_C64 && !p->dirichlet && !p->cdr) ? kColThreadsWide : kThreads;
@@ -1617,6 +1625,10 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
                       const CdrInit* cdr = nullptr);
 
 }  // namespace
+
+constexpr const char* kNoGamma =
+    "an undamped plan (eps = 0) has no gamma = i V / eps: CBS sweeps, cbs_iterate, FGMRES inner sweeps, "
+    "the sweep adjoint and the W = gamma seed are not available";
 
 extern "C" {
 
@@ -1743,6 +1755,29 @@ cbs_status cbs_workspace_size(int batch, const int32_t* n, int dtype, int max_re
 
 namespace {
 
+// An undamped Dirichlet reference L_D - k0^2 (App. B.2, Eq. newton_ref: J_0
+// with no damping term) must be invertible: its eigenvalues mu_p + mu_q - k0^2,
+// mu_p = 4/h^2 sin^2(p pi h/2), p = 1..n, stay away from zero.  Exactly
+// singular is always rejected; closer than 1e-9 of the spectrum's scale
+// unless the guard is off.
+cbs_status check_undamped_reference(int n, double k0sq, int inst, bool no_guard) {
+  const double h = 1.0 / (n + 1);
+  std::vector<double> mu(n);
+  for (int q = 0; q < n; ++q) {
+    const double sn = std::sin((q + 1) * M_PI * h / 2);
+    mu[q] = 4.0 / (h * h) * sn * sn;
+  }
+  double dmin = INFINITY;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) dmin = std::min(dmin, std::fabs(mu[a] + mu[b] - k0sq));
+  const double scale = std::max(2.0 * mu[n - 1], std::fabs(k0sq));
+  if (!(dmin > 0.0) || (!no_guard && dmin < 1e-9 * scale))
+    return fail(CBS_ERR_ILLCOND, "instance " + std::to_string(inst) +
+                                     ": undamped reference L_D - k0^2 is singular or nearly so "
+                                     "(k0^2 at an eigenvalue of L_D)");
+  return CBS_OK;
+}
+
 cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2,
                       const double* k0sq, const double* eps, int dtype, int max_restart,
                       uint32_t flags, void* ws, size_t ws_bytes, void* stream, const CdrInit* cdr) {
@@ -1750,6 +1785,7 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
   *out = nullptr;
   if (!k2) return fail(CBS_ERR_ARG, "k2 is NULL");
   CHK(check_setup_args(batch, n, dtype, max_restart, flags));
+  if (eps && (flags & CBS_FLAG_UNDAMPED)) return fail(CBS_ERR_ARG, "eps must be NULL on an undamped plan");
   if (eps)
     for (int i = 0; i < batch; ++i)
       if (std::isnan(eps[i]) || std::isinf(eps[i])) return fail(CBS_ERR_ARG, "eps must be finite");
@@ -1902,7 +1938,12 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
   build_items(p);
   s = compute_stats(p, 1, st, a, b);
   if (s != CBS_OK) { std::string m = g_err; return bail(s, m); }
-  for (int i = 0; i < batch; ++i) {
+  for (int i = 0; i < batch && p->undamped; ++i) {
+    p->eps[i] = 0.0;
+    cbs_status us = check_undamped_reference(p->n[i], p->k0sq[i], i, (flags & CBS_FLAG_NO_GUARD) != 0);
+    if (us != CBS_OK) { std::string m = g_err; return bail(us, m); }
+  }
+  for (int i = 0; i < batch && !p->undamped; ++i) {
     const bool autoe = !eps || !(eps[i] > 0.0);
     p->eps[i] = autoe ? a[i] : eps[i];
     if (!(p->eps[i] > 0.0))
@@ -1911,9 +1952,11 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
       return bail(CBS_ERR_ILLCOND, "instance " + std::to_string(i) + ": eps below max|k^2-k0^2|");
   }
   build_items(p);
-  s = compute_stats(p, 2, st, a, b);
-  if (s != CBS_OK) { std::string m = g_err; return bail(s, m); }
-  for (int i = 0; i < batch; ++i)
+  if (!p->undamped) {
+    s = compute_stats(p, 2, st, a, b);
+    if (s != CBS_OK) { std::string m = g_err; return bail(s, m); }
+  }
+  for (int i = 0; i < batch && !p->undamped; ++i)
     if (!(flags & CBS_FLAG_NO_GUARD) && !(a[i] >= 1e-3 * p->eps[i]))
       return bail(CBS_ERR_ILLCOND,
                   "instance " + std::to_string(i) + ": min|V|/eps below 1e-3 (gamma ~ 0 stalls CBS)");
@@ -1991,6 +2034,9 @@ cbs_status tune_by_sweeps(cbs_plan p, hipStream_t st, std::ostringstream& rec) {
       }
     return CBS_OK;
   };
+  // The races time the plan's own sweep kernels on scratch fields whose
+  // values are discarded (on an undamped plan gamma = i V / 0 makes them
+  // non-finite, which does not change the kernels' timing).
   const Cfg saved{p->col_threads32, p->ctile};
   std::vector<Cfg> cfgs = {Cfg{kThreads, {}}};
   if (sizeof(R) == 4 && !p->dirichlet) cfgs.push_back(Cfg{kColThreadsWide, {}});
@@ -2245,6 +2291,7 @@ cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm
   if (!p || !u) return fail(CBS_ERR_ARG, "plan or u is NULL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
   if (count < 1 || count > 1000000) return fail(CBS_ERR_ARG, "count must be in [1, 1e6]");
+  if (p->undamped) return fail(CBS_ERR_ARG, kNoGamma);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == CBS_C64) return sweep_impl<float>(p, u, s, count, norm2, st);
   return sweep_impl<double>(p, u, s, count, norm2, st);
@@ -2260,6 +2307,7 @@ cbs_status cbs_iterate(cbs_plan p, void* u, const void* s, int max_sweeps, doubl
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
   if (max_sweeps < 0 || check_every < 2 || check_every > 100000 || !(rtol >= 0.0))
     return fail(CBS_ERR_ARG, "need max_sweeps >= 0, 2 <= check_every <= 1e5, rtol >= 0");
+  if (p->undamped) return fail(CBS_ERR_ARG, kNoGamma);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (use_graph && st == nullptr) {
     // The legacy null stream cannot be captured: run on a plan-owned stream
@@ -2285,8 +2333,9 @@ cbs_status fgmres_solve(cbs_plan p, void* u, const void* s, int restart, int inn
   if (p && p->cdr) return fail(CBS_ERR_ARG, "fgmres_solve is not available for convection-diffusion-reaction plans");
   if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
-  if (restart < 1 || inner_sweeps < 1 || inner_sweeps > 1000 || max_iters < 0 || !(rtol >= 0.0))
-    return fail(CBS_ERR_ARG, "need restart >= 1, 1 <= inner_sweeps <= 1000, max_iters >= 0, rtol >= 0");
+  if (restart < 1 || inner_sweeps < 0 || inner_sweeps > 1000 || max_iters < 0 || !(rtol >= 0.0))
+    return fail(CBS_ERR_ARG, "need restart >= 1, 0 <= inner_sweeps <= 1000, max_iters >= 0, rtol >= 0");
+  if (p->undamped && inner_sweeps > 0) return fail(CBS_ERR_ARG, kNoGamma);
   if (restart > p->max_restart)
     return fail(CBS_ERR_WORKSPACE, "restart " + std::to_string(restart) + " exceeds the plan's max_restart " +
                                        std::to_string(p->max_restart));
@@ -2308,6 +2357,7 @@ cbs_status cbs_iterate_async(cbs_plan p, void* u, const void* s, int max_sweeps,
     return fail(CBS_ERR_ARG, "need max_sweeps >= 0, 2 <= check_every <= 1e5, rtol >= 0");
   if ((long long)max_sweeps / check_every > 100000)
     return fail(CBS_ERR_ARG, "max_sweeps / check_every must not exceed 1e5 chunks");
+  if (p->undamped) return fail(CBS_ERR_ARG, kNoGamma);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == CBS_C64)
     return iterate_async_impl<float>(p, u, s, max_sweeps, rtol, check_every, stop, iters, relres, status, st);
@@ -2320,8 +2370,9 @@ cbs_status fgmres_solve_async(cbs_plan p, void* u, const void* s, int restart, i
   if (p && p->cdr) return fail(CBS_ERR_ARG, "fgmres_solve_async is not available for convection-diffusion-reaction plans");
   if (!p || !u || !s) return fail(CBS_ERR_ARG, "plan, u or s is NULL");
   if (u == s) return fail(CBS_ERR_ARG, "u must not alias s");
-  if (restart < 1 || inner_sweeps < 1 || inner_sweeps > 1000 || max_iters < 0 || !(rtol >= 0.0))
-    return fail(CBS_ERR_ARG, "need restart >= 1, 1 <= inner_sweeps <= 1000, max_iters >= 0, rtol >= 0");
+  if (restart < 1 || inner_sweeps < 0 || inner_sweeps > 1000 || max_iters < 0 || !(rtol >= 0.0))
+    return fail(CBS_ERR_ARG, "need restart >= 1, 0 <= inner_sweeps <= 1000, max_iters >= 0, rtol >= 0");
+  if (p->undamped && inner_sweeps > 0) return fail(CBS_ERR_ARG, kNoGamma);
   if (max_iters > 100000) return fail(CBS_ERR_ARG, "max_iters must not exceed 1e5");
   if (restart > p->max_restart)
     return fail(CBS_ERR_WORKSPACE, "restart " + std::to_string(restart) + " exceeds the plan's max_restart " +
@@ -2354,6 +2405,7 @@ cbs_status cbs_adjoint_step(cbs_plan p, const void* u_m, const void* s, const vo
                             void* lam_out, void* grad_k2, void* stream) {
   if (p && p->cdr) return fail(CBS_ERR_ARG, "cbs_adjoint_step is not available for convection-diffusion-reaction plans");
   if (!p || !u_m || !lam_in || !lam_out || !grad_k2) return fail(CBS_ERR_ARG, "NULL argument");
+  if (p->undamped) return fail(CBS_ERR_ARG, kNoGamma);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == CBS_C64) return adjoint_impl<float>(p, u_m, s, lam_in, lam_out, grad_k2, st);
   return adjoint_impl<double>(p, u_m, s, lam_in, lam_out, grad_k2, st);
@@ -2365,6 +2417,7 @@ cbs_status cbs_loss_seed(cbs_plan p, const void* u_k, const void* s, int weight_
   if (!p || !u_k || !lam_out || !grad_k2) return fail(CBS_ERR_ARG, "NULL argument");
   if (weight_gamma < 0 || weight_gamma > 2)
     return fail(CBS_ERR_ARG, "weight must be 0 (W = 1), 1 (W = gamma) or 2 (physical residual)");
+  if (p->undamped && weight_gamma == 1) return fail(CBS_ERR_ARG, kNoGamma);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == CBS_C64) return seed_impl<float>(p, u_k, s, weight_gamma, loss, lam_out, grad_k2, st);
   return seed_impl<double>(p, u_k, s, weight_gamma, loss, lam_out, grad_k2, st);

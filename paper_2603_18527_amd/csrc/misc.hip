@@ -197,32 +197,65 @@ __global__ __launch_bounds__(kThreads) void k_dots(KryParams k) {
   }
 }
 
-// coef_q = sum of partial dots; H[q][j] (+)= coef_q.
-__global__ void k_dots_finish(KryParams k, int batch) {
-  const int i = wave_instance();
+// coef_q = sum of partial dots; H[q][j] (+)= coef_q.  One workgroup per
+// instance, eight coefficients per round: each thread adds up its share of
+// the instance's partials (eight consecutive complex values per partial),
+// then the waves' sums meet in LDS.  The order of the additions depends only
+// on the instance's own partial count, never on the rest of the batch.
+__global__ __launch_bounds__(kThreads) void k_dots_finish(KryParams k, int batch) {
+  constexpr int QB = 8;
+  __shared__ double red[QB][2][kThreads / 64];
+  const int i = blockIdx.x;
   if (i >= batch || !k.active[i]) return;
   const InstDesc d = k.inst[i];
   const KryLayout L{k.m};
   double* s = k.kry + i * k.kstride;
-  const int lane = threadIdx.x & 63;
-  for (int q = 0; q <= k.j; ++q) {
-    double re = 0.0, im = 0.0;
-    for (int t = lane; t < d.nparts; t += 64) {
-      re += k.dots[2LL * ((long long)(d.part_off + t) * (k.m + 1) + q)];
-      im += k.dots[2LL * ((long long)(d.part_off + t) * (k.m + 1) + q) + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int q0 = 0; q0 <= k.j; q0 += QB) {
+    double re[QB], im[QB];
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+      re[qq] = 0.0;
+      im[qq] = 0.0;
     }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane != 0) continue;
-    s[L.coef() + 2 * q] = re;
-    s[L.coef() + 2 * q + 1] = im;
-    if (k.pass == 0) {
-      s[L.h(q, k.j)] = re;
-      s[L.h(q, k.j) + 1] = im;
-    } else {
-      s[L.h(q, k.j)] += re;
-      s[L.h(q, k.j) + 1] += im;
+    for (int t = threadIdx.x; t < d.nparts; t += kThreads) {
+      const double* row = k.dots + 2LL * ((long long)(d.part_off + t) * (k.m + 1) + q0);
+#pragma unroll
+      for (int qq = 0; qq < QB; ++qq) {
+        if (q0 + qq <= k.j) {
+          re[qq] += row[2 * qq];
+          im[qq] += row[2 * qq + 1];
+        }
+      }
     }
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+      re[qq] = wave_sum(re[qq]);
+      im[qq] = wave_sum(im[qq]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int qq = 0; qq < QB; ++qq) {
+        red[qq][0][wid] = re[qq];
+        red[qq][1][wid] = im[qq];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * QB) {
+      const int qq = threadIdx.x >> 1, c = threadIdx.x & 1;
+      const int q = q0 + qq;
+      if (q <= k.j) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) t += red[qq][c][w];
+        s[L.coef() + 2 * q + c] = t;
+        if (k.pass == 0)
+          s[L.h(q, k.j) + c] = t;
+        else
+          s[L.h(q, k.j) + c] += t;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -517,7 +550,7 @@ void launch_dots(int grid, hipStream_t st, const KryParams& k) {
   hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kThreads), 0, st, k);
 }
 void launch_dots_finish(int batch, hipStream_t st, const KryParams& k) {
-  hipLaunchKernelGGL(k_dots_finish, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);
+  hipLaunchKernelGGL(k_dots_finish, dim3(batch), dim3(kThreads), 0, st, k, batch);
 }
 void launch_cgs_update(int grid, hipStream_t st, const KryParams& k) {
   hipLaunchKernelGGL(k_cgs_update, dim3(grid), dim3(kThreads), 0, st, k);

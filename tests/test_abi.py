@@ -49,8 +49,19 @@ def test_setup_argument_errors_without_gpu():
     assert _setup(1, [64], k2=0) == cbs.CBS_ERR_ARG
     assert _setup(1, [64], dtype=7) == cbs.CBS_ERR_ARG
     assert _setup(1, [64], restart=-1) == cbs.CBS_ERR_ARG
-    assert _setup(1, [64], flags=8) == cbs.CBS_ERR_ARG
+    assert _setup(1, [64], flags=16) == cbs.CBS_ERR_ARG
     assert "flag" in cbs.last_error()
+    # undamped needs the Dirichlet reference, and takes no eps
+    assert _setup(1, [64], flags=cbs.FLAG_UNDAMPED) == cbs.CBS_ERR_ARG
+    assert "DIRICHLET" in cbs.last_error()
+    assert _setup(1, [64], flags=cbs.FLAG_UNDAMPED | cbs.FLAG_DIRICHLET) == cbs.CBS_ERR_SIZE
+    lib = cbs.load()
+    h = ctypes.c_void_p()
+    n = (ctypes.c_int32 * 1)(63)
+    eps = (ctypes.c_double * 1)(1.0)
+    assert lib.cbs_setup(ctypes.byref(h), 1, n, ctypes.c_void_p(1), None, eps, cbs.CBS_C64, 0,
+                         cbs.FLAG_UNDAMPED | cbs.FLAG_DIRICHLET, None) == cbs.CBS_ERR_ARG
+    assert "eps" in cbs.last_error()
     for bad in (8, 100, 2048, 0, -16):
         assert _setup(1, [bad]) == cbs.CBS_ERR_SIZE
         assert str(bad) in cbs.last_error()
