@@ -894,6 +894,7 @@ KryParams kry_params(cbs_plan p, int m) {
   k.kstride = p->kry_stride;
   k.m = m;
   k.dots = p->d_dots;
+  k.dstride = 4LL * (m + 1) + 4;
   k.partials = p->d_partials;
   k.scale = p->d_scale;
   k.active = p->d_kactive;
@@ -931,14 +932,15 @@ cbs_status fg_restart(cbs_plan p, int m, int first, hipStream_t st) {
   return CBS_OK;
 }
 
-// One Arnoldi step j for every active instance.
+// One Arnoldi step j for every active instance (Gram-Schmidt with delayed
+// reorthogonalisation: slot j holds u_j, the next vector after one pass).
 template <typename R>
 cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
   cpx<R>* z = static_cast<cpx<R>*>(p->d_zbasis) + (long long)j * p->cells;
   cpx<R>* c = static_cast<cpx<R>*>(p->d_c);
   cpx<double>* w = p->d_vbasis + (long long)(j + 1) * p->cells;
-  // z_j = P_K(v_j): first sweep from zero is z = gamma v, then K-1 full
-  // sweeps; K = 0 is no inner preconditioner, z_j = v_j
+  // z_j = P_K(u_j / ||u_j||) (u_0 = v_0 is normalised): first sweep from zero
+  // is z = gamma v, then K-1 full sweeps; K = 0 is no inner preconditioner
   {
     PwParams<R> pw{};
     if (sweeps == 0) {
@@ -949,6 +951,7 @@ cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
       pw.src64 = p->d_vbasis + (long long)j * p->cells;
       pw.c_out = c;
     }
+    pw.scale = j > 0 ? p->d_scale : nullptr;
     pw.e_out = z;
     pw.mask = p->d_kactive;
     pw.mask_mode = MASK_NONZERO;
@@ -976,29 +979,28 @@ cbs_status fg_step(cbs_plan p, int m, int j, int sweeps, hipStream_t st) {
     q.mask_mode = MASK_NONZERO;
     CHK(run_pipeline(p, q, st));
   }
-  // classical Gram-Schmidt, twice
   KryParams k = kry_params(p, m);
-  k.w = w;
   k.j = j;
   const int nrow = int(p->row_items.size());
-  for (int pass = 0; pass < 2; ++pass) {
-    k.pass = pass;
-    launch_dots(nrow, st, k);
-    launch_dots_finish(p->batch, st, k);
-    launch_cgs_update(nrow, st, k);
-  }
-  // norm, Givens, normalise v_{j+1} (the scale is computed before the mask drops)
-  launch_givens(p->batch, st, k);
+  launch_gs_dots(nrow, false, st, k);
+  launch_gs_finish(p->batch, false, st, k);
+  launch_gs_update(nrow, st, k);
+  launch_gs_check(p->batch, st, k);
   HIPCHK(hipGetLastError());
-  {
-    PwParams<double> pw{};
-    pw.op = PW_SCALE64;
-    pw.x64 = w;
-    pw.scale = p->d_scale;
-    pw.mask = p->d_kactive;
-    pw.mask_mode = MASK_NONZERO;
-    CHK(launch_pw(p, pw, st));
-  }
+  return CBS_OK;
+}
+
+// End of a cycle: reorthogonalise u_jend of every instance that ran steps,
+// finalise its last Hessenberg column, solve the small least-squares
+// problem and add Z y to the FP64 iterate.
+template <typename R>
+cbs_status fg_cycle_end(cbs_plan p, int m, hipStream_t st) {
+  KryParams k = kry_params(p, m);
+  launch_gs_dots(int(p->row_items.size()), true, st, k);
+  launch_gs_finish(p->batch, true, st, k);
+  launch_backsolve(p->batch, st, k);
+  launch_zupdate(int(p->row_items.size()), st, k, static_cast<const cpx<R>*>(p->d_zbasis), p->d_u64);
+  HIPCHK(hipGetLastError());
   return CBS_OK;
 }
 
@@ -1021,7 +1023,6 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
   HIPCHK(hipMemcpyAsync(p->d_rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(p->d_maxs, &max_iters, sizeof(int), hipMemcpyHostToDevice, st));
   CHK(fg_restart(p, m, 1, st));
-  KryParams k = kry_params(p, m);
   std::vector<int> hact(B), hstat(B);
   for (int cycle = 0; cycle < max_iters + 2; ++cycle) {
     CHK(fg_restart(p, m, 0, st));
@@ -1038,9 +1039,7 @@ cbs_status fgmres_impl(cbs_plan p, void* u, const void* s, int m, int sweeps, in
       for (int i = 0; i < B; ++i) act |= hact[i] != 0;
       if (!act) break;
     }
-    launch_backsolve(B, st, k);
-    launch_zupdate(int(p->row_items.size()), st, k, static_cast<const cpx<R>*>(p->d_zbasis), p->d_u64);
-    HIPCHK(hipGetLastError());
+    CHK(fg_cycle_end<R>(p, m, st));
   }
   if constexpr (sizeof(R) == 4) {
     PwParams<float> w{};
@@ -1156,13 +1155,11 @@ cbs_status fgmres_async_impl(cbs_plan p, void* u, const void* s, int m, int swee
   launch_solver_init(st, p->d_status, p->d_iters, p->d_relres, p->d_kjend, p->d_rtol, nullptr, p->d_maxs, B,
                      rtol, 0.0, max_iters);
   CHK(fg_restart(p, m, 1, st));
-  KryParams k = kry_params(p, m);
   const long long ncycles = ((long long)max_iters + m - 1) / m + 1;
   for (long long cycle = 0; cycle < ncycles; ++cycle) {
     CHK(fg_restart(p, m, 0, st));
     for (int j = 0; j < m; ++j) CHK(fg_step<R>(p, m, j, sweeps, st));
-    launch_backsolve(B, st, k);
-    launch_zupdate(int(p->row_items.size()), st, k, static_cast<const cpx<R>*>(p->d_zbasis), p->d_u64);
+    CHK(fg_cycle_end<R>(p, m, st));
   }
   CHK(fg_restart(p, m, 0, st));  // true residual of the last update decides the status
   CHK(solver_store<R>(p, u, st));
@@ -1593,7 +1590,7 @@ std::vector<std::pair<void**, size_t>> buffer_requests(cbs_plan p) {
     req.push_back({reinterpret_cast<void**>(&p->d_vbasis), cells * 16 * (m + 1)});
     req.push_back({&p->d_zbasis, cells * oe * m});
     req.push_back({reinterpret_cast<void**>(&p->d_kry), size_t(p->kry_stride) * batch * sizeof(double)});
-    req.push_back({reinterpret_cast<void**>(&p->d_dots), 2 * (m + 2) * nrow * sizeof(double)});
+    req.push_back({reinterpret_cast<void**>(&p->d_dots), (4 * (m + 1) + 4) * nrow * sizeof(double)});
   }
   // work lists (capacity: tile width 2 everywhere)
   const size_t cap = item_capacity(p) * sizeof(int2);

@@ -240,6 +240,57 @@ __device__ __forceinline__ void twiddle(cpx<R>* v, int k, const cpx<R>* __restri
   for (int q = 1; q < RAD; ++q) v[q] = DIR < 0 ? cmul(w[q], v[q]) : cmulc(w[q], v[q]);
 }
 
+// Twiddles of one transform length held q-major in LDS: for pass P (Ns > 1)
+// entry (q, k), q = 1..r-1, sits at twq_pass_offset(N, P) + (q - 1) Ns + k, so
+// the lanes of a wave, which work on consecutive butterflies k, read
+// consecutive LDS words (the per-k layout of the global table puts them
+// radp(r) entries apart, which serialises on the LDS banks).
+__host__ __device__ constexpr int twq_pass_size(int n, int p) {
+  return plan_ns(n, p) > 1 ? plan_ns(n, p) * (plan_radix(n, p) - 1) : 0;
+}
+__host__ __device__ constexpr int twq_pass_offset(int n, int p) {
+  int off = 0;
+  for (int i = 0; i < p; ++i) off += twq_pass_size(n, i);
+  return off;
+}
+__host__ __device__ constexpr int twq_size(int n) { return twq_pass_offset(n, plan_passes(n)); }
+
+template <typename R>
+struct TwQ {
+  const cpx<R>* base;  // LDS table of one transform length
+};
+
+template <typename R, int N, int P, int DIR>
+__device__ __forceinline__ void twiddle(cpx<R>* v, int k, TwQ<R> tw) {
+  constexpr int RAD = plan_radix(N, P);
+  constexpr int NS = plan_ns(N, P);
+  const cpx<R>* b = tw.base + twq_pass_offset(N, P) + k;
+#pragma unroll
+  for (int q = 1; q < RAD; ++q) {
+    const cpx<R> w = lds_ld(b + (q - 1) * NS);
+    v[q] = DIR < 0 ? cmul(w, v[q]) : cmulc(w, v[q]);
+  }
+}
+
+// Fills the q-major LDS table of length N from the global table (every
+// thread of the workgroup calls it; `nthreads` = the workgroup size; the
+// caller puts a barrier after it).
+template <typename R, int N, int P = 0>
+__device__ __forceinline__ void twq_fill(const cpx<R>* __restrict__ tw, cpx<R>* dst, int nthreads) {
+  if constexpr (P < plan_passes(N)) {
+    constexpr int NS = plan_ns(N, P);
+    constexpr int RP = radp(plan_radix(N, P));
+    if constexpr (NS > 1) {
+      constexpr int CNT = twq_pass_size(N, P);
+      for (int i = threadIdx.x; i < CNT; i += nthreads) {
+        const int q = i / NS + 1, k = i - (q - 1) * NS;
+        dst[twq_pass_offset(N, P) + i] = tw[tw_pass_offset(N, P) + k * RP + q];
+      }
+    }
+    twq_fill<R, N, P + 1>(tw, dst, nthreads);
+  }
+}
+
 // Functors of the first pass (ld), the last pass (st) and a bridge (mid) may
 // also take the butterfly slot p and the element slot q of the thread's
 // registers: in a plan whose first and last radix agree, every one of these
@@ -274,9 +325,8 @@ __device__ __forceinline__ cpx<R> call_mid(F& f, int e, cpx<R> v, int p, int q) 
 // LD_LDS / ST_LDS say that ld / st themselves touch this LDS buffer, which
 // adds the barriers an in-place pass needs.
 template <typename R, int N, int P, int PEND, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES,
-          class LD, class ST>
-__device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
-                                         const cpx<R>* __restrict__ tw, LD& ld, ST& st) {
+          class TW, class LD, class ST>
+__device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active, TW tw, LD& ld, ST& st) {
   constexpr int RAD = plan_radix(N, P);
   constexpr int NS = plan_ns(N, P);
   constexpr int NB = N / RAD;
@@ -330,10 +380,9 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active,
 }
 
 // Length-N transform (DIR = -1 forward, +1 inverse, unnormalised) from ld to st.
-template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES = 1, class LD,
+template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES = 1, class TW, class LD,
           class ST>
-__device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active,
-                                        const cpx<R>* __restrict__ tw, LD ld, ST st) {
+__device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active, TW tw, LD ld, ST st) {
   static_assert(plan_product(N) == N && plan_passes(N) >= 2, "no plan for this size");
   fft_pass<R, N, 0, plan_passes(N), TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
 }
@@ -353,9 +402,8 @@ __host__ __device__ constexpr bool plan_bridgeable(int n) {
 // next in direction D2 (writing LDS), in registers.  Needs plan_bridgeable(N):
 // the last pass of transform 1 and the first pass of transform 2 then act on
 // the same elements j + q N/RAD in each thread.
-template <typename R, int N, int TPF, int D1, int D2, int ES, class MID>
-__device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw,
-                                           MID& mid) {
+template <typename R, int N, int TPF, int D1, int D2, int ES, class TW, class MID>
+__device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, TW tw, MID& mid) {
   static_assert(plan_bridgeable(N), "first and last radix differ");
   constexpr int PL = plan_passes(N) - 1;  // last pass index
   constexpr int RAD = plan_radix(N, PL);
@@ -398,9 +446,8 @@ __device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, cons
   __syncthreads();
 }
 
-template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class LD, class MID, class ST>
-__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
-                                         const cpx<R>* __restrict__ tw, LD ld, MID mid, ST st) {
+template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class TW, class LD, class MID, class ST>
+__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active, TW tw, LD ld, MID mid, ST st) {
   static_assert(plan_bridgeable(N), "first and last radix differ");
   constexpr int PL = plan_passes(N) - 1;  // last pass index
   auto none = [](int, cpx<R>) {};
@@ -414,8 +461,8 @@ __device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active,
 
 // Internal passes 1 .. PL-1 of a transform whose first and last passes are
 // bridges (LDS in, LDS out).
-template <typename R, int N, int TPF, int D, int ES>
-__device__ __forceinline__ void fft_inner(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw) {
+template <typename R, int N, int TPF, int D, int ES, class TW>
+__device__ __forceinline__ void fft_inner(cpx<R>* buf, int t, bool active, TW tw) {
   constexpr int PL = plan_passes(N) - 1;
   if constexpr (PL > 1) {
     auto noload = [](int) { return cpx<R>{R(0), R(0)}; };

@@ -504,6 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
   const R k0 = R(d.k0sq), ep = R(d.eps);
   const double sc = (p.op == PW_SCALE64) ? p.scale[w.x]
                     : (p.op == PW_SCALE)  ? p.factor * (p.scale ? p.scale[w.x] : 1.0)
+                    : (p.op == PW_FIRST64 || p.op == PW_NARROW) ? (p.scale ? p.scale[w.x] : 1.0)
                                           : 1.0;
   for (int j = threadIdx.x; j < cnt; j += kThreads) {
     const long long i = base + j;
@@ -515,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
           v = p.e_in[i];
         } else {
           const cpx<double> x = p.src64[i];
-          v = cpx<R>{R(x.x), R(x.y)};
+          v = cpx<R>{R(x.x * sc), R(x.y * sc)};
           if (p.c_out) p.c_out[i] = v;
         }
         const cpx<R> k = p.k2[i];
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
       }
       case PW_NARROW: {
         const cpx<double> x = p.x64[i];
-        p.e_out[i] = cpx<R>{R(x.x), R(x.y)};
+        p.e_out[i] = cpx<R>{R(x.x * sc), R(x.y * sc)};
         break;
       }
       case PW_SCALE:

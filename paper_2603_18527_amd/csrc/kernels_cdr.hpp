@@ -43,20 +43,19 @@ __host__ __device__ constexpr int cdr_tw_max() {
   return m;
 }
 constexpr int kCdrTwMax = cdr_tw_max();
-static_assert(kCdrTwMax % 2 == 0, "twiddle segments are copied as float4");
+static_assert(kCdrTwMax % 2 == 0, "the LDS table is declared as float4 (16-byte aligned)");
 
-// Copies the twiddle segment of length N into tws (FP32) and returns the
-// table base to pass to the FFT routines (offsets stay those of the global
-// table); FP64 passes keep the global table.
+// FP32 passes copy the twiddles of length N into tws, q-major (conflict-free
+// LDS reads by consecutive butterflies), and run every transform from there;
+// FP64 passes keep the global table.
 template <typename R, int N>
-__device__ __forceinline__ const cpx<R>* cdr_twiddles(const cpx<R>* tw, float4* tws) {
+__device__ __forceinline__ auto cdr_twiddles(const cpx<R>* tw, float4* tws) {
   if constexpr (sizeof(R) == 4) {
-    constexpr int S = tw_size(N);
-    static_assert(S % 2 == 0 && S <= kCdrTwMax, "twiddle segment");
-    const float4* src = reinterpret_cast<const float4*>(tw + tw_offset(N));
-    for (int i = threadIdx.x; i < S / 2; i += kThreads) tws[i] = src[i];
+    static_assert(twq_size(N) <= kCdrTwMax, "twiddle table");
+    cpx<R>* dst = reinterpret_cast<cpx<R>*>(tws);
+    twq_fill<R, N>(tw, dst, kThreads);
     __syncthreads();
-    return reinterpret_cast<const cpx<R>*>(tws) - tw_offset(N);
+    return TwQ<R>{dst};
   } else {
     return tw;
   }
@@ -74,7 +73,7 @@ template <typename R, int N, int MODE>
 __device__ __forceinline__ void cdr_row_body(const Params<R>& p, const InstDesc& d, int row0, cpx<R>* lds,
                                              float4* tws) {
   using T = RowTile<N>;
-  const cpx<R>* tw = cdr_twiddles<R, N>(p.tw, tws);
+  const auto tw = cdr_twiddles<R, N>(p.tw, tws);
   const int tid = threadIdx.x;
   const int r = tid / T::TPF, t = tid - r * T::TPF;
   const int nrows = min(T::RPW, N - row0);
@@ -179,7 +178,7 @@ template <typename R, int N, int C, int ADJ>
 __device__ __forceinline__ void cdr_col_body(const Params<R>& p, const InstDesc& d, int col0, cpx<R>* lds,
                                              float4* tws) {
   constexpr int TPC = kThreads / C;
-  const cpx<R>* tw = cdr_twiddles<R, N>(p.tw, tws);
+  const auto tw = cdr_twiddles<R, N>(p.tw, tws);
   const int tid = threadIdx.x;
   const int c = tid % C, tt = tid / C;
   const long long cbase = d.off + col0 + c;

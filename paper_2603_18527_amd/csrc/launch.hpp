@@ -68,10 +68,10 @@ void launch_norm2_rows(int grid, hipStream_t st, const InstDesc* inst, const int
 void launch_norm2_rows(int grid, hipStream_t st, const InstDesc* inst, const int2* items,
                        const cpx<double>* x, double* partials);
 void launch_ratio(int batch, hipStream_t st, const double* num, const double* den, double* out);
-void launch_dots(int grid, hipStream_t st, const KryParams& k);
-void launch_dots_finish(int batch, hipStream_t st, const KryParams& k);
-void launch_cgs_update(int grid, hipStream_t st, const KryParams& k);
-void launch_givens(int batch, hipStream_t st, const KryParams& k);
+void launch_gs_dots(int grid, bool final_pass, hipStream_t st, const KryParams& k);
+void launch_gs_finish(int batch, bool final_pass, hipStream_t st, const KryParams& k);
+void launch_gs_update(int grid, hipStream_t st, const KryParams& k);
+void launch_gs_check(int batch, hipStream_t st, const KryParams& k);
 void launch_backsolve(int batch, hipStream_t st, const KryParams& k);
 void launch_fg_restart(int batch, hipStream_t st, const KryParams& k, int first);
 

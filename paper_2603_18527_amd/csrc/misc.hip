@@ -125,142 +125,286 @@ __global__ __launch_bounds__(kThreads) void k_stats(const InstDesc* inst, const 
   }
 }
 
-// ---- FGMRES: FP64 Arnoldi, CGS2, Givens least squares -------------------------------
+// ---- FGMRES: FP64 Arnoldi, Gram-Schmidt with delayed reorthogonalisation -------------
 //
 // Per-instance small dense state (doubles), restart length m:
 //   H  (m+1) x m complex, row-major        at 0
 //   cs m real, sn m complex                 (Givens rotations)
 //   g  m+1 complex                          (rotated beta e1)
 //   y  m complex                            (least-squares solution)
-//   coef m+1 complex                        (current Gram-Schmidt coefficients)
-//   sc 8 scalars: [0] beta [1] bnorm [2] estimate
-// Partial dot products <v_q, w> for q = 0..j over one row item, eight
-// vectors per workgroup reduction.
-__global__ __launch_bounds__(kThreads) void k_dots(KryParams k) {
-  constexpr int QB = 8;
-  __shared__ double red[QB][2][kThreads / 64];
+//   coef m+1 complex: t_q = <v_q, w>, and at q = j the coefficient of v_j
+//   coefs m+1 complex: s_q = <v_q, u_j>
+//   sc 8 scalars: [0] beta [1] bnorm [2] estimate [3] 1/r_jj [4] alpha
+//                 [5..6] <u_j, w>
+//
+// Classical Gram-Schmidt applied twice, with the second pass of each vector
+// carried out one step late so that a step reads the basis twice instead of
+// four times (the DCGS2 scheme of Swirydowicz et al., "Low synchronization
+// Gram-Schmidt and GMRES algorithms", 2020).  At the start of step j the
+// basis slots 0..j-1 hold the final orthonormal v_q; slot j holds u_j, the
+// next vector after one projection pass (slot 0 holds the final v_0).
+//   z_j = P_K(u_j / ||u_j||),  w = B z_j                  (flexible: any z_j)
+//   one pass over the basis: s = V^H u_j, t = V^H w, alpha = <u_j, u_j>,
+//                            beta = <u_j, w>
+//   r = sqrt(alpha - |s|^2), v_j = (u_j - V s) / r, <v_j, w> = (beta - s^H t) / r
+//   H[:, j-1] += s, H[j, j-1] = r   (column j-1 is now final: rotate it)
+//   H[:, j] = (t, <v_j, w>)         (first pass of column j)
+//   one pass over the basis: v_j into slot j, u_{j+1} = w - V t - <v_j, w> v_j
+//                            into slot j+1 with its partial |.|^2
+// The stopping test of step j uses column j before its second pass (the
+// correction is at rounding level); when an instance's cycle ends, a last
+// pass reorthogonalises u_{jend} and finalises column jend-1.
+
+// Partial dot products over one row item.  Step (FINAL false, step k.j of
+// the active instances): <v_q, u_j> and <v_q, w> for q < j, <u_j, u_j> and
+// <u_j, w>.  FINAL (cycle end, j = jend of each instance that ran steps):
+// <v_q, u_j> for q < j and <u_j, u_j>.  Per partial slot, k.dstride doubles:
+// t at 0, s at 2(m+1), the scalars at 4(m+1).
+template <bool FINAL>
+__global__ __launch_bounds__(kThreads) void k_gs_dots(KryParams k) {
+  constexpr int QB = 4;
+  __shared__ double red[4 * QB][kThreads / 64];
   const int2 it = k.items[blockIdx.x];
-  if (!k.active[it.x]) return;
+  int j;
+  if constexpr (FINAL) {
+    j = k.jend[it.x];
+    if (j <= 0) return;
+  } else {
+    if (!k.active[it.x]) return;
+    j = k.j;
+  }
   const InstDesc d = k.inst[it.x];
   long long base;
   int cnt, slot;
   item_range(d, it.y, base, cnt, slot);
   constexpr int PER = 2048 / kThreads;  // row_rpw(N) * N <= 2048 for every N
-  cpx<double> wv[PER];
+  const cpx<double>* ub = k.vbasis + (long long)j * k.cells + base;
+  const cpx<double>* wb = k.vbasis + (long long)(j + 1) * k.cells + base;
+  cpx<double> uv[PER], wv[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
-    const int j = threadIdx.x + e * kThreads;
-    wv[e] = j < cnt ? k.w[base + j] : cpx<double>{0.0, 0.0};
+    const int x = threadIdx.x + e * kThreads;
+    uv[e] = x < cnt ? ub[x] : cpx<double>{0.0, 0.0};
+    wv[e] = (!FINAL && x < cnt) ? wb[x] : cpx<double>{0.0, 0.0};
   }
+  double* out = k.dots + (long long)slot * k.dstride;
+  const int so = 2 * (k.m + 1), co = 4 * (k.m + 1);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int q0 = 0; q0 <= k.j; q0 += QB) {
-    double re[QB], im[QB];
+  {
+    double a = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      a += cabs2(uv[e]);
+      br += uv[e].x * wv[e].x + uv[e].y * wv[e].y;
+      bi += uv[e].x * wv[e].y - uv[e].y * wv[e].x;
+    }
+    a = wave_sum(a);
+    br = wave_sum(br);
+    bi = wave_sum(bi);
+    if (lane == 0) {
+      red[0][wid] = a;
+      red[1][wid] = br;
+      red[2][wid] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) t += red[threadIdx.x][w];
+      out[co + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+  for (int q0 = 0; q0 < j; q0 += QB) {
+    double acc[QB][4];
 #pragma unroll
     for (int qq = 0; qq < QB; ++qq) {
-      re[qq] = 0.0;
-      im[qq] = 0.0;
+      acc[qq][0] = acc[qq][1] = acc[qq][2] = acc[qq][3] = 0.0;
       const int q = q0 + qq;
-      if (q <= k.j) {
-        const cpx<double>* v = k.vbasis + q * k.cells + base;
+      if (q < j) {
+        const cpx<double>* v = k.vbasis + (long long)q * k.cells + base;
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-          const int j = threadIdx.x + e * kThreads;
-          if (j < cnt) {
-            const cpx<double> a = v[j];
-            re[qq] += a.x * wv[e].x + a.y * wv[e].y;
-            im[qq] += a.x * wv[e].y - a.y * wv[e].x;
+          const int x = threadIdx.x + e * kThreads;
+          if (x < cnt) {
+            const cpx<double> a = v[x];
+            acc[qq][0] += a.x * uv[e].x + a.y * uv[e].y;
+            acc[qq][1] += a.x * uv[e].y - a.y * uv[e].x;
+            if (!FINAL) {
+              acc[qq][2] += a.x * wv[e].x + a.y * wv[e].y;
+              acc[qq][3] += a.x * wv[e].y - a.y * wv[e].x;
+            }
           }
         }
       }
-      re[qq] = wave_sum(re[qq]);
-      im[qq] = wave_sum(im[qq]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[qq][c] = wave_sum(acc[qq][c]);
     }
     if (lane == 0) {
 #pragma unroll
-      for (int qq = 0; qq < QB; ++qq) {
-        red[qq][0][wid] = re[qq];
-        red[qq][1][wid] = im[qq];
-      }
+      for (int qq = 0; qq < QB; ++qq)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[4 * qq + c][wid] = acc[qq][c];
     }
     __syncthreads();
-    if (threadIdx.x < 2 * QB) {
-      const int qq = threadIdx.x >> 1, c = threadIdx.x & 1;
+    if (threadIdx.x < 4 * QB) {
+      const int qq = threadIdx.x >> 2, c = threadIdx.x & 3;
       const int q = q0 + qq;
-      if (q <= k.j) {
+      if (q < j && (!FINAL || c < 2)) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) t += red[qq][c][w];
-        k.dots[2LL * ((long long)slot * (k.m + 1) + q) + c] = t;
+        for (int w = 0; w < kThreads / 64; ++w) t += red[threadIdx.x][w];
+        // c 0, 1: s_q (with u); c 2, 3: t_q (with w)
+        out[(c < 2 ? so : 0) + 2 * q + (c & 1)] = t;
       }
     }
     __syncthreads();
   }
 }
 
-// coef_q = sum of partial dots; H[q][j] (+)= coef_q.  One workgroup per
-// instance, eight coefficients per round: each thread adds up its share of
-// the instance's partials (eight consecutive complex values per partial),
-// then the waves' sums meet in LDS.  The order of the additions depends only
-// on the instance's own partial count, never on the rest of the batch.
-__global__ __launch_bounds__(kThreads) void k_dots_finish(KryParams k, int batch) {
-  constexpr int QB = 8;
-  __shared__ double red[QB][2][kThreads / 64];
+// out[e] = sum over the instance's partial slots of dots[slot][first + e],
+// e < count (every thread of the workgroup calls it; 16 values per round).
+__device__ void sum_slots(const KryParams& k, const InstDesc& d, int first, int count, double* out) {
+  constexpr int VB = 16;
+  __shared__ double red[VB][kThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int e0 = 0; e0 < count; e0 += VB) {
+    double acc[VB];
+#pragma unroll
+    for (int v = 0; v < VB; ++v) acc[v] = 0.0;
+    for (int t = threadIdx.x; t < d.nparts; t += kThreads) {
+      const double* row = k.dots + (long long)(d.part_off + t) * k.dstride + first + e0;
+#pragma unroll
+      for (int v = 0; v < VB; ++v)
+        if (e0 + v < count) acc[v] += row[v];
+    }
+#pragma unroll
+    for (int v = 0; v < VB; ++v) acc[v] = wave_sum(acc[v]);
+    if (lane == 0) {
+#pragma unroll
+      for (int v = 0; v < VB; ++v) red[v][wid] = acc[v];
+    }
+    __syncthreads();
+    if (threadIdx.x < VB && e0 + threadIdx.x < count) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) t += red[threadIdx.x][w];
+      out[e0 + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Column c of H is final: apply rotations 0..c-1, form rotation c zeroing
+// H[c+1][c], rotate g; returns |g_{c+1}| / ||G s||.
+__device__ double givens_column(double* s, const KryLayout& L, int c) {
+  for (int q = 0; q < c; ++q) {
+    const double cq = s[L.cs() + q];
+    const cpx<double> sn{s[L.sn() + 2 * q], s[L.sn() + 2 * q + 1]};
+    const cpx<double> a{s[L.h(q, c)], s[L.h(q, c) + 1]};
+    const cpx<double> b{s[L.h(q + 1, c)], s[L.h(q + 1, c) + 1]};
+    const cpx<double> na = cscale(a, cq) + cmul(sn, b);
+    const cpx<double> nb = cscale(b, cq) - cmul(cconj(sn), a);
+    s[L.h(q, c)] = na.x;
+    s[L.h(q, c) + 1] = na.y;
+    s[L.h(q + 1, c)] = nb.x;
+    s[L.h(q + 1, c) + 1] = nb.y;
+  }
+  const cpx<double> a{s[L.h(c, c)], s[L.h(c, c) + 1]};
+  const cpx<double> b{s[L.h(c + 1, c)], s[L.h(c + 1, c) + 1]};
+  const double aa = sqrt(cabs2(a));
+  const double nu = sqrt(cabs2(a) + cabs2(b));
+  double cs;
+  cpx<double> sn;
+  if (aa == 0.0) {
+    cs = 0.0;
+    sn = cpx<double>{1.0, 0.0};
+  } else {
+    cs = aa / nu;
+    sn = cscale(cmul(a, cconj(b)), 1.0 / (aa * nu));
+  }
+  s[L.cs() + c] = cs;
+  s[L.sn() + 2 * c] = sn.x;
+  s[L.sn() + 2 * c + 1] = sn.y;
+  const cpx<double> na = cscale(a, cs) + cmul(sn, b);
+  s[L.h(c, c)] = na.x;
+  s[L.h(c, c) + 1] = na.y;
+  s[L.h(c + 1, c)] = 0.0;
+  s[L.h(c + 1, c) + 1] = 0.0;
+  const cpx<double> gc{s[L.g() + 2 * c], s[L.g() + 2 * c + 1]};
+  const cpx<double> g1 = cscale(cmul(cconj(sn), gc), -1.0);
+  const cpx<double> g0 = cscale(gc, cs);
+  s[L.g() + 2 * c] = g0.x;
+  s[L.g() + 2 * c + 1] = g0.y;
+  s[L.g() + 2 * (c + 1)] = g1.x;
+  s[L.g() + 2 * (c + 1) + 1] = g1.y;
+  return sqrt(cabs2(g1)) / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
+}
+
+// One workgroup per instance: reduce the partial dot products, then (one
+// thread) the norm r of the reorthogonalised u_j, the final column j-1 and
+// its rotation, and (step) the first pass of column j with the update
+// coefficients.
+template <bool FINAL>
+__global__ __launch_bounds__(kThreads) void k_gs_finish(KryParams k, int batch) {
   const int i = blockIdx.x;
-  if (i >= batch || !k.active[i]) return;
+  if (i >= batch) return;
+  int j;
+  if constexpr (FINAL) {
+    j = k.jend[i];
+    if (j <= 0) return;
+  } else {
+    if (!k.active[i]) return;
+    j = k.j;
+  }
   const InstDesc d = k.inst[i];
   const KryLayout L{k.m};
   double* s = k.kry + i * k.kstride;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int q0 = 0; q0 <= k.j; q0 += QB) {
-    double re[QB], im[QB];
-#pragma unroll
-    for (int qq = 0; qq < QB; ++qq) {
-      re[qq] = 0.0;
-      im[qq] = 0.0;
+  const int so = 2 * (k.m + 1), co = 4 * (k.m + 1);
+  if (!FINAL) sum_slots(k, d, 0, 2 * j, s + L.coef());
+  sum_slots(k, d, so, 2 * j, s + L.coefs());
+  sum_slots(k, d, co, FINAL ? 1 : 3, s + L.sc() + 4);
+  if (threadIdx.x != 0) return;
+  const double alpha = s[L.sc() + 4];
+  double r = 1.0;
+  if (j > 0) {
+    double ss = 0.0;
+    for (int q = 0; q < j; ++q) ss += s[L.coefs() + 2 * q] * s[L.coefs() + 2 * q] +
+                                      s[L.coefs() + 2 * q + 1] * s[L.coefs() + 2 * q + 1];
+    r = sqrt(fmax(alpha - ss, 0.0));
+    // column j-1 is final: add the second pass of u_j, then rotate it
+    for (int q = 0; q < j; ++q) {
+      s[L.h(q, j - 1)] += s[L.coefs() + 2 * q];
+      s[L.h(q, j - 1) + 1] += s[L.coefs() + 2 * q + 1];
     }
-    for (int t = threadIdx.x; t < d.nparts; t += kThreads) {
-      const double* row = k.dots + 2LL * ((long long)(d.part_off + t) * (k.m + 1) + q0);
-#pragma unroll
-      for (int qq = 0; qq < QB; ++qq) {
-        if (q0 + qq <= k.j) {
-          re[qq] += row[2 * qq];
-          im[qq] += row[2 * qq + 1];
-        }
-      }
-    }
-#pragma unroll
-    for (int qq = 0; qq < QB; ++qq) {
-      re[qq] = wave_sum(re[qq]);
-      im[qq] = wave_sum(im[qq]);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int qq = 0; qq < QB; ++qq) {
-        red[qq][0][wid] = re[qq];
-        red[qq][1][wid] = im[qq];
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < 2 * QB) {
-      const int qq = threadIdx.x >> 1, c = threadIdx.x & 1;
-      const int q = q0 + qq;
-      if (q <= k.j) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) t += red[qq][c][w];
-        s[L.coef() + 2 * q + c] = t;
-        if (k.pass == 0)
-          s[L.h(q, k.j) + c] = t;
-        else
-          s[L.h(q, k.j) + c] += t;
-      }
-    }
-    __syncthreads();
+    s[L.h(j, j - 1)] = r;
+    s[L.h(j, j - 1) + 1] = 0.0;
+    s[L.sc() + 2] = givens_column(s, L, j - 1);
   }
+  if (FINAL) return;
+  // <v_j, w> = (<u_j, w> - s^H t) / r
+  cpx<double> hj{s[L.sc() + 5], s[L.sc() + 6]};
+  for (int q = 0; q < j; ++q) {
+    const cpx<double> sq{s[L.coefs() + 2 * q], s[L.coefs() + 2 * q + 1]};
+    const cpx<double> tq{s[L.coef() + 2 * q], s[L.coef() + 2 * q + 1]};
+    hj = hj - cmulc(sq, tq);
+  }
+  const double ir = r > 0.0 ? 1.0 / r : 0.0;
+  hj = cscale(hj, ir);
+  s[L.coef() + 2 * j] = hj.x;
+  s[L.coef() + 2 * j + 1] = hj.y;
+  s[L.sc() + 3] = ir;
+  for (int q = 0; q < j; ++q) {
+    s[L.h(q, j)] = s[L.coef() + 2 * q];
+    s[L.h(q, j) + 1] = s[L.coef() + 2 * q + 1];
+  }
+  s[L.h(j, j)] = hj.x;
+  s[L.h(j, j) + 1] = hj.y;
 }
 
-// w -= sum_q coef_q v_q ; also the partial |w|^2 for the norm that follows.
-__global__ __launch_bounds__(kThreads) void k_cgs_update(KryParams k) {
+// v_j = (u_j - V s) / r into slot j (j > 0), u_{j+1} = w - V t - <v_j, w> v_j
+// into slot j+1, and its partial |.|^2.  One read of the basis.
+__global__ __launch_bounds__(kThreads) void k_gs_update(KryParams k) {
   __shared__ double red[kThreads / 64];
   const int2 it = k.items[blockIdx.x];
   if (!k.active[it.x]) return;
@@ -269,38 +413,56 @@ __global__ __launch_bounds__(kThreads) void k_cgs_update(KryParams k) {
   int cnt, slot;
   item_range(d, it.y, base, cnt, slot);
   const KryLayout L{k.m};
-  const double* s = k.kry + it.x * k.kstride + L.coef();
-  constexpr int PER = 2048 / kThreads;  // row_rpw(N) * N <= 2048 for every N
-  cpx<double> wv[PER];
+  const double* st = k.kry + it.x * k.kstride;
+  const double* ct = st + L.coef();
+  const double* cs = st + L.coefs();
+  const int j = k.j;
+  constexpr int PER = 2048 / kThreads;
+  cpx<double>* ub = const_cast<cpx<double>*>(k.vbasis) + (long long)j * k.cells + base;
+  cpx<double>* wb = const_cast<cpx<double>*>(k.vbasis) + (long long)(j + 1) * k.cells + base;
+  cpx<double> uv[PER], wv[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
-    const int j = threadIdx.x + e * kThreads;
-    wv[e] = j < cnt ? k.w[base + j] : cpx<double>{0.0, 0.0};
+    const int x = threadIdx.x + e * kThreads;
+    uv[e] = x < cnt ? ub[x] : cpx<double>{0.0, 0.0};
+    wv[e] = x < cnt ? wb[x] : cpx<double>{0.0, 0.0};
   }
-  for (int q = 0; q <= k.j; ++q) {
-    const cpx<double> c{s[2 * q], s[2 * q + 1]};
-    const cpx<double>* v = k.vbasis + q * k.cells + base;
+  for (int q = 0; q < j; ++q) {
+    const cpx<double> sq{cs[2 * q], cs[2 * q + 1]};
+    const cpx<double> tq{ct[2 * q], ct[2 * q + 1]};
+    const cpx<double>* v = k.vbasis + (long long)q * k.cells + base;
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      const int j = threadIdx.x + e * kThreads;
-      if (j < cnt) wv[e] = wv[e] - cmul(c, v[j]);
+      const int x = threadIdx.x + e * kThreads;
+      if (x < cnt) {
+        const cpx<double> a = v[x];
+        uv[e] = uv[e] - cmul(sq, a);
+        wv[e] = wv[e] - cmul(tq, a);
+      }
     }
   }
+  const double ir = st[L.sc() + 3];
+  const cpx<double> hj{ct[2 * j], ct[2 * j + 1]};
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
-    const int j = threadIdx.x + e * kThreads;
-    if (j < cnt) {
-      k.w[base + j] = wv[e];
-      acc += cabs2(wv[e]);
+    const int x = threadIdx.x + e * kThreads;
+    if (x < cnt) {
+      const cpx<double> vj = cscale(uv[e], ir);
+      if (j > 0) ub[x] = vj;
+      const cpx<double> nw = wv[e] - cmul(hj, vj);
+      wb[x] = nw;
+      acc += cabs2(nw);
     }
   }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) k.partials[slot] = t;
 }
 
-// h_{j+1,j} = ||w||; scale = 1/h; Givens update and residual estimate.
-__global__ void k_givens(KryParams k, int batch) {
+// Stopping test of step j: ||u_{j+1}|| (the scale of the next preconditioner
+// input), the rotations applied to column j as it stands after its first
+// pass, and the residual estimate |g_j| |sin| / ||G s||.
+__global__ void k_gs_check(KryParams k, int batch) {
   const int i = wave_instance();
   if (i >= batch || !k.active[i]) return;
   const InstDesc d = k.inst[i];
@@ -310,52 +472,19 @@ __global__ void k_givens(KryParams k, int batch) {
   if ((threadIdx.x & 63) != 0) return;
   const double hn = sqrt(sum);
   const int j = k.j;
-  s[L.h(j + 1, j)] = hn;
-  s[L.h(j + 1, j) + 1] = 0.0;
   k.scale[i] = hn > 0.0 ? 1.0 / hn : 0.0;
-  // apply previous rotations to column j
+  cpx<double> cur{s[L.h(0, j)], s[L.h(0, j) + 1]};
   for (int q = 0; q < j; ++q) {
-    const double c = s[L.cs() + q];
+    const double cq = s[L.cs() + q];
     const cpx<double> sn{s[L.sn() + 2 * q], s[L.sn() + 2 * q + 1]};
-    const cpx<double> a{s[L.h(q, j)], s[L.h(q, j) + 1]};
     const cpx<double> b{s[L.h(q + 1, j)], s[L.h(q + 1, j) + 1]};
-    const cpx<double> na = cscale(a, c) + cmul(sn, b);
-    const cpx<double> nb = cscale(b, c) - cmul(cconj(sn), a);
-    s[L.h(q, j)] = na.x;
-    s[L.h(q, j) + 1] = na.y;
-    s[L.h(q + 1, j)] = nb.x;
-    s[L.h(q + 1, j) + 1] = nb.y;
+    cur = cscale(b, cq) - cmul(cconj(sn), cur);
   }
-  // new rotation zeroing h_{j+1,j}
-  const cpx<double> a{s[L.h(j, j)], s[L.h(j, j) + 1]};
-  const cpx<double> b{s[L.h(j + 1, j)], s[L.h(j + 1, j) + 1]};
-  const double aa = sqrt(cabs2(a));
-  const double nu = sqrt(cabs2(a) + cabs2(b));
-  double c;
-  cpx<double> sn;
-  if (aa == 0.0) {
-    c = 0.0;
-    sn = cpx<double>{1.0, 0.0};
-  } else {
-    c = aa / nu;
-    sn = cscale(cmul(a, cconj(b)), 1.0 / (aa * nu));
-  }
-  s[L.cs() + j] = c;
-  s[L.sn() + 2 * j] = sn.x;
-  s[L.sn() + 2 * j + 1] = sn.y;
-  const cpx<double> na = cscale(a, c) + cmul(sn, b);
-  s[L.h(j, j)] = na.x;
-  s[L.h(j, j) + 1] = na.y;
-  s[L.h(j + 1, j)] = 0.0;
-  s[L.h(j + 1, j) + 1] = 0.0;
+  const double aa2 = cabs2(cur);
+  const double nu = sqrt(aa2 + hn * hn);
+  const double sabs = aa2 == 0.0 ? 1.0 : (nu > 0.0 ? hn / nu : 0.0);
   const cpx<double> gj{s[L.g() + 2 * j], s[L.g() + 2 * j + 1]};
-  const cpx<double> g1 = cscale(cmul(cconj(sn), gj), -1.0);
-  const cpx<double> g0 = cscale(gj, c);
-  s[L.g() + 2 * j] = g0.x;
-  s[L.g() + 2 * j + 1] = g0.y;
-  s[L.g() + 2 * (j + 1)] = g1.x;
-  s[L.g() + 2 * (j + 1) + 1] = g1.y;
-  const double est = sqrt(cabs2(g1)) / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
+  const double est = sqrt(cabs2(gj)) * sabs / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
   s[L.sc() + 2] = est;
   k.jend[i] = j + 1;
   k.iters[i] += 1;
@@ -546,17 +675,23 @@ void launch_norm2_rows(int grid, hipStream_t st, const InstDesc* inst, const int
 void launch_ratio(int batch, hipStream_t st, const double* num, const double* den, double* out) {
   hipLaunchKernelGGL(k_ratio, dim3((batch + 255) / 256), dim3(256), 0, st, num, den, out, batch);
 }
-void launch_dots(int grid, hipStream_t st, const KryParams& k) {
-  hipLaunchKernelGGL(k_dots, dim3(grid), dim3(kThreads), 0, st, k);
+void launch_gs_dots(int grid, bool final_pass, hipStream_t st, const KryParams& k) {
+  if (final_pass)
+    hipLaunchKernelGGL(k_gs_dots<true>, dim3(grid), dim3(kThreads), 0, st, k);
+  else
+    hipLaunchKernelGGL(k_gs_dots<false>, dim3(grid), dim3(kThreads), 0, st, k);
 }
-void launch_dots_finish(int batch, hipStream_t st, const KryParams& k) {
-  hipLaunchKernelGGL(k_dots_finish, dim3(batch), dim3(kThreads), 0, st, k, batch);
+void launch_gs_finish(int batch, bool final_pass, hipStream_t st, const KryParams& k) {
+  if (final_pass)
+    hipLaunchKernelGGL(k_gs_finish<true>, dim3(batch), dim3(kThreads), 0, st, k, batch);
+  else
+    hipLaunchKernelGGL(k_gs_finish<false>, dim3(batch), dim3(kThreads), 0, st, k, batch);
 }
-void launch_cgs_update(int grid, hipStream_t st, const KryParams& k) {
-  hipLaunchKernelGGL(k_cgs_update, dim3(grid), dim3(kThreads), 0, st, k);
+void launch_gs_update(int grid, hipStream_t st, const KryParams& k) {
+  hipLaunchKernelGGL(k_gs_update, dim3(grid), dim3(kThreads), 0, st, k);
 }
-void launch_givens(int batch, hipStream_t st, const KryParams& k) {
-  hipLaunchKernelGGL(k_givens, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);
+void launch_gs_check(int batch, hipStream_t st, const KryParams& k) {
+  hipLaunchKernelGGL(k_gs_check, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);
 }
 void launch_backsolve(int batch, hipStream_t st, const KryParams& k) {
   hipLaunchKernelGGL(k_backsolve, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);

@@ -176,10 +176,10 @@ constexpr int kMuTotal = mu_offset(1024) + 1024;
 
 enum PwOp {
   PW_GAMMA = 0,        // e_out = gamma * e_in
-  PW_FIRST64 = 1,      // c_out = (R) src64; e_out = gamma * c_out
+  PW_FIRST64 = 1,      // c_out = (R)(src64 * scale[instance]); e_out = gamma * c_out (scale NULL: 1)
   PW_ADD_WIDE = 2,     // x64 += e_in
   PW_WIDEN = 3,        // x64 = e_in
-  PW_NARROW = 4,       // e_out = (R) x64
+  PW_NARROW = 4,       // e_out = (R)(x64 * scale[instance]) (scale NULL: 1)
   PW_SCALE64 = 5,      // x64 *= scale[instance] (FP64)
   PW_SCALE = 6         // e_out = e_in * factor * scale[instance] (scale NULL: 1), operator precision
 };
@@ -194,7 +194,7 @@ struct PwParams {
   const cpx<R>* e_in;
   cpx<R>* e_out;
   cpx<R>* c_out;
-  const double* scale;  // per-instance factor for PW_SCALE64 / PW_SCALE
+  const double* scale;  // per-instance factor for PW_SCALE64 / PW_SCALE / PW_FIRST64 / PW_NARROW
   double factor;        // constant factor of PW_SCALE
   const int* mask;
   int mask_mode;
@@ -210,7 +210,8 @@ struct KryLayout {
   __host__ __device__ long long g() const { return sn() + 2LL * m; }
   __host__ __device__ long long y() const { return g() + 2LL * (m + 1); }
   __host__ __device__ long long coef() const { return y() + 2LL * m; }
-  __host__ __device__ long long sc() const { return coef() + 2LL * (m + 1); }
+  __host__ __device__ long long coefs() const { return coef() + 2LL * (m + 1); }
+  __host__ __device__ long long sc() const { return coefs() + 2LL * (m + 1); }
   __host__ __device__ long long size() const { return sc() + 8; }
 };
 
@@ -224,7 +225,8 @@ struct KryParams {
   long long kstride;
   int m;
   int j;                      // current Arnoldi column
-  double* dots;               // per partial slot: (m+1) complex partial dot products
+  double* dots;               // per partial slot: dstride doubles of partial dot products
+  long long dstride;          // 4 (m + 1) + 4: t, s (m + 1 complex each), alpha and <u, w>
   double* partials;           // per partial slot: one double
   double* scale;              // per instance
   int* active;                // per instance: 1 while in the Arnoldi cycle
@@ -234,7 +236,6 @@ struct KryParams {
   double* relres;             // per instance: last FP64 true relative residual
   const double* rtol;
   const int* max_iters;
-  int pass;                   // Gram-Schmidt pass 0 (sets H) or 1 (adds)
 };
 
 
