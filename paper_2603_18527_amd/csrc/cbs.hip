@@ -1506,7 +1506,8 @@ cbs_status seed_impl(cbs_plan p, const void* uk, const void* s, int wg, double* 
 cbs_status check_setup_args(int batch, const int32_t* n, int dtype, int max_restart, uint32_t flags) {
   if (batch < 1 || !n) return fail(CBS_ERR_ARG, "batch < 1 or n NULL");
   if (dtype != CBS_C64 && dtype != CBS_C128) return fail(CBS_ERR_ARG, "dtype must be CBS_C64 or CBS_C128");
-  if (max_restart < 0 || max_restart > 200) return fail(CBS_ERR_ARG, "max_restart must be in [0, 200]");
+  if (max_restart < 0 || max_restart > kMaxRestart)
+    return fail(CBS_ERR_ARG, "max_restart must be in [0, " + std::to_string(kMaxRestart) + "]");
   if (flags & ~uint32_t(CBS_FLAG_NO_GUARD | CBS_FLAG_ONE_STREAM | CBS_FLAG_DIRICHLET | CBS_FLAG_UNDAMPED))
     return fail(CBS_ERR_ARG, "unknown flag bits");
   const bool dir = (flags & CBS_FLAG_DIRICHLET) != 0;

@@ -296,49 +296,57 @@ __device__ void sum_slots(const KryParams& k, const InstDesc& d, int first, int 
 }
 
 // Column c of H is final: apply rotations 0..c-1, form rotation c zeroing
-// H[c+1][c], rotate g; returns |g_{c+1}| / ||G s||.
-__device__ double givens_column(double* s, const KryLayout& L, int c) {
-  for (int q = 0; q < c; ++q) {
-    const double cq = s[L.cs() + q];
-    const cpx<double> sn{s[L.sn() + 2 * q], s[L.sn() + 2 * q + 1]};
-    const cpx<double> a{s[L.h(q, c)], s[L.h(q, c) + 1]};
-    const cpx<double> b{s[L.h(q + 1, c)], s[L.h(q + 1, c) + 1]};
-    const cpx<double> na = cscale(a, cq) + cmul(sn, b);
-    const cpx<double> nb = cscale(b, cq) - cmul(cconj(sn), a);
-    s[L.h(q, c)] = na.x;
-    s[L.h(q, c) + 1] = na.y;
-    s[L.h(q + 1, c)] = nb.x;
-    s[L.h(q + 1, c) + 1] = nb.y;
+// H[c+1][c], rotate g, and store |g_{c+1}| / ||G s|| as the estimate.  Every
+// thread of the workgroup calls it: the column and the rotations are staged
+// in LDS, so the sequential chain of rotations (one thread) runs at LDS
+// latency instead of a dependent global access per rotation.
+__device__ void givens_column(double* s, const KryLayout& L, int c) {
+  __shared__ cpx<double> col[kMaxRestart + 1];
+  __shared__ cpx<double> sns[kMaxRestart];
+  __shared__ double css[kMaxRestart];
+  for (int q = threadIdx.x; q <= c + 1; q += blockDim.x) col[q] = cpx<double>{s[L.h(q, c)], s[L.h(q, c) + 1]};
+  for (int q = threadIdx.x; q < c; q += blockDim.x) {
+    css[q] = s[L.cs() + q];
+    sns[q] = cpx<double>{s[L.sn() + 2 * q], s[L.sn() + 2 * q + 1]};
   }
-  const cpx<double> a{s[L.h(c, c)], s[L.h(c, c) + 1]};
-  const cpx<double> b{s[L.h(c + 1, c)], s[L.h(c + 1, c) + 1]};
-  const double aa = sqrt(cabs2(a));
-  const double nu = sqrt(cabs2(a) + cabs2(b));
-  double cs;
-  cpx<double> sn;
-  if (aa == 0.0) {
-    cs = 0.0;
-    sn = cpx<double>{1.0, 0.0};
-  } else {
-    cs = aa / nu;
-    sn = cscale(cmul(a, cconj(b)), 1.0 / (aa * nu));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < c; ++q) {
+      const cpx<double> a = col[q], b = col[q + 1];
+      col[q] = cscale(a, css[q]) + cmul(sns[q], b);
+      col[q + 1] = cscale(b, css[q]) - cmul(cconj(sns[q]), a);
+    }
+    const cpx<double> a = col[c], b = col[c + 1];
+    const double aa = sqrt(cabs2(a));
+    const double nu = sqrt(cabs2(a) + cabs2(b));
+    double cs;
+    cpx<double> sn;
+    if (aa == 0.0) {
+      cs = 0.0;
+      sn = cpx<double>{1.0, 0.0};
+    } else {
+      cs = aa / nu;
+      sn = cscale(cmul(a, cconj(b)), 1.0 / (aa * nu));
+    }
+    s[L.cs() + c] = cs;
+    s[L.sn() + 2 * c] = sn.x;
+    s[L.sn() + 2 * c + 1] = sn.y;
+    col[c] = cscale(a, cs) + cmul(sn, b);
+    col[c + 1] = cpx<double>{0.0, 0.0};
+    const cpx<double> gc{s[L.g() + 2 * c], s[L.g() + 2 * c + 1]};
+    const cpx<double> g1 = cscale(cmul(cconj(sn), gc), -1.0);
+    const cpx<double> g0 = cscale(gc, cs);
+    s[L.g() + 2 * c] = g0.x;
+    s[L.g() + 2 * c + 1] = g0.y;
+    s[L.g() + 2 * (c + 1)] = g1.x;
+    s[L.g() + 2 * (c + 1) + 1] = g1.y;
+    s[L.sc() + 2] = sqrt(cabs2(g1)) / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
   }
-  s[L.cs() + c] = cs;
-  s[L.sn() + 2 * c] = sn.x;
-  s[L.sn() + 2 * c + 1] = sn.y;
-  const cpx<double> na = cscale(a, cs) + cmul(sn, b);
-  s[L.h(c, c)] = na.x;
-  s[L.h(c, c) + 1] = na.y;
-  s[L.h(c + 1, c)] = 0.0;
-  s[L.h(c + 1, c) + 1] = 0.0;
-  const cpx<double> gc{s[L.g() + 2 * c], s[L.g() + 2 * c + 1]};
-  const cpx<double> g1 = cscale(cmul(cconj(sn), gc), -1.0);
-  const cpx<double> g0 = cscale(gc, cs);
-  s[L.g() + 2 * c] = g0.x;
-  s[L.g() + 2 * c + 1] = g0.y;
-  s[L.g() + 2 * (c + 1)] = g1.x;
-  s[L.g() + 2 * (c + 1) + 1] = g1.y;
-  return sqrt(cabs2(g1)) / (s[L.sc() + 1] > 0.0 ? s[L.sc() + 1] : 1.0);
+  __syncthreads();
+  for (int q = threadIdx.x; q <= c + 1; q += blockDim.x) {
+    s[L.h(q, c)] = col[q].x;
+    s[L.h(q, c) + 1] = col[q].y;
+  }
 }
 
 // One workgroup per instance: reduce the partial dot products, then (one
@@ -364,42 +372,66 @@ __global__ __launch_bounds__(kThreads) void k_gs_finish(KryParams k, int batch) 
   if (!FINAL) sum_slots(k, d, 0, 2 * j, s + L.coef());
   sum_slots(k, d, so, 2 * j, s + L.coefs());
   sum_slots(k, d, co, FINAL ? 1 : 3, s + L.sc() + 4);
-  if (threadIdx.x != 0) return;
+  // |s|^2 and s^H t (workgroup sums; every thread gets them)
+  __shared__ double red[3][kThreads / 64];
+  __shared__ double tot[3];
+  double ss = 0.0, hr = 0.0, hi = 0.0;
+  for (int q = threadIdx.x; q < j; q += kThreads) {
+    const cpx<double> sq{s[L.coefs() + 2 * q], s[L.coefs() + 2 * q + 1]};
+    ss += cabs2(sq);
+    if (!FINAL) {
+      const cpx<double> p = cmulc(sq, cpx<double>{s[L.coef() + 2 * q], s[L.coef() + 2 * q + 1]});
+      hr += p.x;
+      hi += p.y;
+    }
+  }
+  ss = wave_sum(ss);
+  hr = wave_sum(hr);
+  hi = wave_sum(hi);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wid] = ss;
+    red[1][wid] = hr;
+    red[2][wid] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += red[threadIdx.x][w];
+    tot[threadIdx.x] = t;
+  }
+  __syncthreads();
   const double alpha = s[L.sc() + 4];
-  double r = 1.0;
+  const double r = j > 0 ? sqrt(fmax(alpha - tot[0], 0.0)) : 1.0;
   if (j > 0) {
-    double ss = 0.0;
-    for (int q = 0; q < j; ++q) ss += s[L.coefs() + 2 * q] * s[L.coefs() + 2 * q] +
-                                      s[L.coefs() + 2 * q + 1] * s[L.coefs() + 2 * q + 1];
-    r = sqrt(fmax(alpha - ss, 0.0));
     // column j-1 is final: add the second pass of u_j, then rotate it
-    for (int q = 0; q < j; ++q) {
+    for (int q = threadIdx.x; q < j; q += kThreads) {
       s[L.h(q, j - 1)] += s[L.coefs() + 2 * q];
       s[L.h(q, j - 1) + 1] += s[L.coefs() + 2 * q + 1];
     }
-    s[L.h(j, j - 1)] = r;
-    s[L.h(j, j - 1) + 1] = 0.0;
-    s[L.sc() + 2] = givens_column(s, L, j - 1);
+    if (threadIdx.x == 0) {
+      s[L.h(j, j - 1)] = r;
+      s[L.h(j, j - 1) + 1] = 0.0;
+    }
+    __syncthreads();
+    givens_column(s, L, j - 1);
   }
   if (FINAL) return;
-  // <v_j, w> = (<u_j, w> - s^H t) / r
-  cpx<double> hj{s[L.sc() + 5], s[L.sc() + 6]};
-  for (int q = 0; q < j; ++q) {
-    const cpx<double> sq{s[L.coefs() + 2 * q], s[L.coefs() + 2 * q + 1]};
-    const cpx<double> tq{s[L.coef() + 2 * q], s[L.coef() + 2 * q + 1]};
-    hj = hj - cmulc(sq, tq);
-  }
+  // <v_j, w> = (<u_j, w> - s^H t) / r; first pass of column j
   const double ir = r > 0.0 ? 1.0 / r : 0.0;
-  hj = cscale(hj, ir);
-  s[L.coef() + 2 * j] = hj.x;
-  s[L.coef() + 2 * j + 1] = hj.y;
-  s[L.sc() + 3] = ir;
-  for (int q = 0; q < j; ++q) {
+  const cpx<double> hj = cscale(cpx<double>{s[L.sc() + 5] - tot[1], s[L.sc() + 6] - tot[2]}, ir);
+  for (int q = threadIdx.x; q < j; q += kThreads) {
     s[L.h(q, j)] = s[L.coef() + 2 * q];
     s[L.h(q, j) + 1] = s[L.coef() + 2 * q + 1];
   }
-  s[L.h(j, j)] = hj.x;
-  s[L.h(j, j) + 1] = hj.y;
+  if (threadIdx.x == 0) {
+    s[L.coef() + 2 * j] = hj.x;
+    s[L.coef() + 2 * j + 1] = hj.y;
+    s[L.sc() + 3] = ir;
+    s[L.h(j, j)] = hj.x;
+    s[L.h(j, j) + 1] = hj.y;
+  }
 }
 
 // v_j = (u_j - V s) / r into slot j (j > 0), u_{j+1} = w - V t - <v_j, w> v_j
@@ -459,27 +491,36 @@ __global__ __launch_bounds__(kThreads) void k_gs_update(KryParams k) {
   if (threadIdx.x == 0) k.partials[slot] = t;
 }
 
-// Stopping test of step j: ||u_{j+1}|| (the scale of the next preconditioner
-// input), the rotations applied to column j as it stands after its first
-// pass, and the residual estimate |g_j| |sin| / ||G s||.
-__global__ void k_gs_check(KryParams k, int batch) {
-  const int i = wave_instance();
+// Stopping test of step j (one workgroup per instance): ||u_{j+1}|| (the
+// scale of the next preconditioner input), the rotations applied to column j
+// as it stands after its first pass (staged in LDS), and the residual
+// estimate |g_j| |sin| / ||G s||.
+__global__ __launch_bounds__(kThreads) void k_gs_check(KryParams k, int batch) {
+  __shared__ cpx<double> col[kMaxRestart + 1];
+  __shared__ cpx<double> sns[kMaxRestart];
+  __shared__ double css[kMaxRestart];
+  __shared__ double hsum;
+  const int i = blockIdx.x;
   if (i >= batch || !k.active[i]) return;
   const InstDesc d = k.inst[i];
   const KryLayout L{k.m};
   double* s = k.kry + i * k.kstride;
-  const double sum = instance_sum(k.partials, d);
-  if ((threadIdx.x & 63) != 0) return;
-  const double hn = sqrt(sum);
   const int j = k.j;
-  k.scale[i] = hn > 0.0 ? 1.0 / hn : 0.0;
-  cpx<double> cur{s[L.h(0, j)], s[L.h(0, j) + 1]};
-  for (int q = 0; q < j; ++q) {
-    const double cq = s[L.cs() + q];
-    const cpx<double> sn{s[L.sn() + 2 * q], s[L.sn() + 2 * q + 1]};
-    const cpx<double> b{s[L.h(q + 1, j)], s[L.h(q + 1, j) + 1]};
-    cur = cscale(b, cq) - cmul(cconj(sn), cur);
+  if (threadIdx.x < 64) {
+    const double sum = instance_sum(k.partials, d);
+    if (threadIdx.x == 0) hsum = sum;
   }
+  for (int q = threadIdx.x; q <= j; q += kThreads) col[q] = cpx<double>{s[L.h(q, j)], s[L.h(q, j) + 1]};
+  for (int q = threadIdx.x; q < j; q += kThreads) {
+    css[q] = s[L.cs() + q];
+    sns[q] = cpx<double>{s[L.sn() + 2 * q], s[L.sn() + 2 * q + 1]};
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(hsum);
+  k.scale[i] = hn > 0.0 ? 1.0 / hn : 0.0;
+  cpx<double> cur = col[0];
+  for (int q = 0; q < j; ++q) cur = cscale(col[q + 1], css[q]) - cmul(cconj(sns[q]), cur);
   const double aa2 = cabs2(cur);
   const double nu = sqrt(aa2 + hn * hn);
   const double sabs = aa2 == 0.0 ? 1.0 : (nu > 0.0 ? hn / nu : 0.0);
@@ -691,7 +732,7 @@ void launch_gs_update(int grid, hipStream_t st, const KryParams& k) {
   hipLaunchKernelGGL(k_gs_update, dim3(grid), dim3(kThreads), 0, st, k);
 }
 void launch_gs_check(int batch, hipStream_t st, const KryParams& k) {
-  hipLaunchKernelGGL(k_gs_check, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);
+  hipLaunchKernelGGL(k_gs_check, dim3(batch), dim3(kThreads), 0, st, k, batch);
 }
 void launch_backsolve(int batch, hipStream_t st, const KryParams& k) {
   hipLaunchKernelGGL(k_backsolve, dim3(inst_blocks(batch)), dim3(256), 0, st, k, batch);

@@ -202,6 +202,9 @@ struct PwParams {
 };
 
 
+// Largest FGMRES restart length a plan accepts.
+constexpr int kMaxRestart = 200;
+
 struct KryLayout {
   int m;
   __host__ __device__ long long h(int r, int c) const { return 2LL * (r * m + c); }
