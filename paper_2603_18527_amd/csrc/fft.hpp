@@ -326,7 +326,7 @@ __device__ __forceinline__ cpx<R> call_mid(F& f, int e, cpx<R> v, int p, int q) 
 // adds the barriers an in-place pass needs.
 template <typename R, int N, int P, int PEND, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES,
           class TW, class LD, class ST>
-__device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active, TW tw, LD& ld, ST& st) {
+__device__ __forceinline__ void fft_pass_t(cpx<R>* buf, int t, bool active, TW tw, LD& ld, ST& st) {
   constexpr int RAD = plan_radix(N, P);
   constexpr int NS = plan_ns(N, P);
   constexpr int NB = N / RAD;
@@ -376,15 +376,35 @@ __device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active, TW tw,
   }
   if constexpr (WRITES_LDS) __syncthreads();
   if constexpr (P + 1 < PEND)
-    fft_pass<R, N, P + 1, PEND, TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
+    fft_pass_t<R, N, P + 1, PEND, TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
+}
+
+// The passes above take the twiddle table as a restrict-qualified global
+// pointer (the table is never written while a kernel runs) or as a q-major
+// LDS table (TwQ).
+template <typename R, int N, int P, int PEND, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES,
+          class LD, class ST>
+__device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw,
+                                         LD& ld, ST& st) {
+  fft_pass_t<R, N, P, PEND, TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
+}
+template <typename R, int N, int P, int PEND, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES,
+          class LD, class ST>
+__device__ __forceinline__ void fft_pass(cpx<R>* buf, int t, bool active, TwQ<R> tw, LD& ld, ST& st) {
+  fft_pass_t<R, N, P, PEND, TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
 }
 
 // Length-N transform (DIR = -1 forward, +1 inverse, unnormalised) from ld to st.
-template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES = 1, class TW, class LD,
-          class ST>
-__device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active, TW tw, LD ld, ST st) {
+template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES = 1, class LD, class ST>
+__device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw,
+                                        LD ld, ST st) {
   static_assert(plan_product(N) == N && plan_passes(N) >= 2, "no plan for this size");
-  fft_pass<R, N, 0, plan_passes(N), TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
+  fft_pass_t<R, N, 0, plan_passes(N), TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
+}
+template <typename R, int N, int TPF, int DIR, bool LD_LDS, bool ST_LDS, int ES = 1, class LD, class ST>
+__device__ __forceinline__ void fft_run(cpx<R>* buf, int t, bool active, TwQ<R> tw, LD ld, ST st) {
+  static_assert(plan_product(N) == N && plan_passes(N) >= 2, "no plan for this size");
+  fft_pass_t<R, N, 0, plan_passes(N), TPF, DIR, LD_LDS, ST_LDS, ES>(buf, t, active, tw, ld, st);
 }
 
 // Two transforms back to back with an elementwise map between them, where the
@@ -403,7 +423,7 @@ __host__ __device__ constexpr bool plan_bridgeable(int n) {
 // the last pass of transform 1 and the first pass of transform 2 then act on
 // the same elements j + q N/RAD in each thread.
 template <typename R, int N, int TPF, int D1, int D2, int ES, class TW, class MID>
-__device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, TW tw, MID& mid) {
+__device__ __forceinline__ void fft_bridge_t(cpx<R>* buf, int t, bool active, TW tw, MID& mid) {
   static_assert(plan_bridgeable(N), "first and last radix differ");
   constexpr int PL = plan_passes(N) - 1;  // last pass index
   constexpr int RAD = plan_radix(N, PL);
@@ -446,29 +466,56 @@ __device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, TW t
   __syncthreads();
 }
 
-template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class TW, class LD, class MID, class ST>
-__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active, TW tw, LD ld, MID mid, ST st) {
+template <typename R, int N, int TPF, int D1, int D2, int ES, class MID>
+__device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw,
+                                           MID& mid) {
+  fft_bridge_t<R, N, TPF, D1, D2, ES>(buf, t, active, tw, mid);
+}
+template <typename R, int N, int TPF, int D1, int D2, int ES, class MID>
+__device__ __forceinline__ void fft_bridge(cpx<R>* buf, int t, bool active, TwQ<R> tw, MID& mid) {
+  fft_bridge_t<R, N, TPF, D1, D2, ES>(buf, t, active, tw, mid);
+}
+
+template <typename R, int N, int TPF, int D1, int D2, int ES, class TW, class LD, class MID, class ST>
+__device__ __forceinline__ void fft_run2_t(cpx<R>* buf, int t, bool active, TW tw, LD ld, MID mid, ST st) {
   static_assert(plan_bridgeable(N), "first and last radix differ");
   constexpr int PL = plan_passes(N) - 1;  // last pass index
   auto none = [](int, cpx<R>) {};
   // transform 1, passes 0 .. PL-1 (the last of them writes LDS)
-  fft_pass<R, N, 0, PL, TPF, D1, false, false, ES>(buf, t, active, tw, ld, none);
-  fft_bridge<R, N, TPF, D1, D2, ES>(buf, t, active, tw, mid);
+  fft_pass_t<R, N, 0, PL, TPF, D1, false, false, ES>(buf, t, active, tw, ld, none);
+  fft_bridge_t<R, N, TPF, D1, D2, ES>(buf, t, active, tw, mid);
   // transform 2, passes 1 .. PL
   auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
-  fft_pass<R, N, 1, PL + 1, TPF, D2, false, false, ES>(buf, t, active, tw, noload, st);
+  fft_pass_t<R, N, 1, PL + 1, TPF, D2, false, false, ES>(buf, t, active, tw, noload, st);
+}
+template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class LD, class MID, class ST>
+__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw,
+                                         LD ld, MID mid, ST st) {
+  fft_run2_t<R, N, TPF, D1, D2, ES>(buf, t, active, tw, ld, mid, st);
+}
+template <typename R, int N, int TPF, int D1, int D2, int ES = 1, class LD, class MID, class ST>
+__device__ __forceinline__ void fft_run2(cpx<R>* buf, int t, bool active, TwQ<R> tw, LD ld, MID mid, ST st) {
+  fft_run2_t<R, N, TPF, D1, D2, ES>(buf, t, active, tw, ld, mid, st);
 }
 
 // Internal passes 1 .. PL-1 of a transform whose first and last passes are
 // bridges (LDS in, LDS out).
 template <typename R, int N, int TPF, int D, int ES, class TW>
-__device__ __forceinline__ void fft_inner(cpx<R>* buf, int t, bool active, TW tw) {
+__device__ __forceinline__ void fft_inner_t(cpx<R>* buf, int t, bool active, TW tw) {
   constexpr int PL = plan_passes(N) - 1;
   if constexpr (PL > 1) {
     auto noload = [](int) { return cpx<R>{R(0), R(0)}; };
     auto none = [](int, cpx<R>) {};
-    fft_pass<R, N, 1, PL, TPF, D, false, false, ES>(buf, t, active, tw, noload, none);
+    fft_pass_t<R, N, 1, PL, TPF, D, false, false, ES>(buf, t, active, tw, noload, none);
   }
+}
+template <typename R, int N, int TPF, int D, int ES>
+__device__ __forceinline__ void fft_inner(cpx<R>* buf, int t, bool active, const cpx<R>* __restrict__ tw) {
+  fft_inner_t<R, N, TPF, D, ES>(buf, t, active, tw);
+}
+template <typename R, int N, int TPF, int D, int ES>
+__device__ __forceinline__ void fft_inner(cpx<R>* buf, int t, bool active, TwQ<R> tw) {
+  fft_inner_t<R, N, TPF, D, ES>(buf, t, active, tw);
 }
 
 }  // namespace cbs
