@@ -486,7 +486,8 @@ def run_suite(args):
     """Solver runs on the five synthetic workloads (configs of the metric):
     blob64 CBS, grf256 FGMRES(30)+CBS(4) and CBS, ragged64 FGMRES batched,
     diff16 adjoint, layered1024 FGMRES(50)+CBS(4) in FP32 vs an FP64 GPU run;
-    the Dirichlet (DST-I) Newton-system batch newton63; and the
+    the Dirichlet (DST-I) Newton-system batch newton64 (damped reference with
+    FGMRES + CBS sweeps, and the undamped reference with GMRES); and the
     convection-diffusion-reaction batch cdr64 (apply and R^H e throughput).
     Accuracy figures come from FP64 plans of the same problems on the GPU
     (parity with the FP64 CPU oracle is the test suite's job)."""
@@ -613,8 +614,9 @@ def run_suite(args):
         errs.append(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
     out["rel_err_fp32_vs_fp64_per_instance"] = errs
     res["layered1024_fgmres50_k4"] = out
-    # 6. newton63: Dirichlet (DST-I reference) Newton Jacobians J = L_D - 2 diag(u_m),
-    #    100 instances of 63^2 interior points; FGMRES(20) + 3 CBS sweeps to 1e-6
+    # 6. newton64: Dirichlet (DST-I reference) Newton Jacobians J = L_D - 2 diag(u_m),
+    #    100 instances of 64^2 interior points; FGMRES(20) + 3 CBS sweeps to 1e-6 with
+    #    the damped reference, GMRES(20) with the undamped J_0 = L_D - 2 mean(u_m)
     probs = S.newton_batch()
     sizes = [q.n for q in probs]
     cells = sum(n * n for n in sizes)
@@ -634,12 +636,18 @@ def run_suite(args):
     _, rn = p64.residual(u.to(c128), s.to(c128), store=False)
     _, bn = p64.residual(None, s.to(c128), store=False)
     ev = float(torch.max(torch.sqrt(rn / bn)))
-    res["newton63_dirichlet"] = dict(
+    k0u = [float(np.mean(np.real(q.k2))) for q in probs]   # k0^2 = 2 mean(u_m) = mean(k^2), alpha = 0
+    pu = cbs.Plan(k2, sizes, k0sq=k0u, dirichlet=True, undamped=True, max_restart=20)
+    uu = pu.zeros()
+    (itu, relu, stu), dtu = timed(lambda: pu.fgmres(uu, s, restart=20, sweeps=0, max_iters=2000, rtol=1e-6))
+    res["newton64_dirichlet"] = dict(
         instances=len(sizes), cells=cells, apply_ms=dta * 1e3, apply_gcell_s=_gcell(cells, 1, dta),
         sweep_ms=dts * 1e3, sweep_gcell_s=_gcell(cells, 1, dts),
         fgmres20_k3=dict(seconds=dt, max_iterations=max(its), max_relres=max(rel),
-                         all_converged=all(x == 1 for x in st), max_relres_fp64_gpu_eval=ev))
-    print("# suite newton63 done", flush=True)
+                         all_converged=all(x == 1 for x in st), max_relres_fp64_gpu_eval=ev),
+        undamped_gmres20=dict(seconds=dtu, max_iterations=max(itu), max_relres=max(relu),
+                              all_converged=all(x == 1 for x in stu)))
+    print("# suite newton64 done", flush=True)
     res["cdr64_apply"] = cdr_throughput()
     print("# suite cdr64 done", flush=True)
     return res

@@ -122,7 +122,9 @@ enum {
  * 4/h^2 (sin^2(p pi h/2) + sin^2(q pi h/2)) - k0^2 - i eps.  Every call then
  * uses that G and L_D in place of the periodic ones.  n must satisfy
  * 2(n+1) in {16, ..., 1024} above: n in {7, 15, 31, 63, 95, 127, 143, 191,
- * 255, 511}.  A Newton step J du = r with J = L_D - 2 diag(u) (App. B.2,
+ * 255, 511}, the DST-I riding on the FFT of the odd extension; or n = 64,
+ * the grid of the paper's Newton experiments (App. F), whose DST-I is formed
+ * directly (2(n+1) = 130 has no FFT plan).  A Newton step J du = r with J = L_D - 2 diag(u) (App. B.2,
  * Eq. newton_linear_system) is the case k^2 = 2u.  Without further flags the
  * plan's reference is the damped L_D - (k0^2 + i eps), eps > 0.
  * Undamped Dirichlet plans (CBS_FLAG_DIRICHLET | CBS_FLAG_UNDAMPED): eps = 0

@@ -36,7 +36,8 @@ INST_RUNNING, INST_CONVERGED, INST_MAX_ITERS, INST_DIVERGED = 0, 1, 2, 3
 
 SUPPORTED_SIZES = (16, 32, 64, 128, 192, 256, 288, 384, 512, 1024)
 # Dirichlet instance sizes n (interior points): 2(n + 1) is a supported FFT length
-SUPPORTED_DIRICHLET = tuple(m // 2 - 1 for m in SUPPORTED_SIZES)
+# n with 2(n+1) an FFT size, and n = 64 (direct DST-I)
+SUPPORTED_DIRICHLET = tuple(sorted([m // 2 - 1 for m in SUPPORTED_SIZES] + [64]))
 
 # Every symbol include/cbs.h declares, with its ctypes signature.
 _vp, _i32, _u32, _f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_double

@@ -168,7 +168,9 @@ struct cbs_plan_s {
   std::vector<double> vx0, vy0;      // CDR background velocity per instance
   double* d_mu = nullptr;            // Dirichlet eigenvalue table (all transform lengths)
   // FFT length that carries an instance of size n
-  int tlen(int n) const { return dirichlet ? dst_len(n) : n; }
+  // length of the 1D transforms along a row or column: the FFT of the odd
+  // extension for Dirichlet instances, n itself for the direct DST size
+  int tlen(int n) const { return dirichlet ? (n == kDstDirectN ? n : dst_len(n)) : n; }
   hipStream_t lane_st[2] = {nullptr, nullptr};  // non-blocking lane streams
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int op_elem() const { return dtype == CBS_C64 ? 8 : 16; }
@@ -1515,7 +1517,7 @@ cbs_status check_setup_args(int batch, const int32_t* n, int dtype, int max_rest
     return fail(CBS_ERR_ARG, "CBS_FLAG_UNDAMPED needs CBS_FLAG_DIRICHLET (a periodic reference |xi|^2 - k0^2 "
                              "vanishes or nearly vanishes on the grid without damping)");
   for (int i = 0; i < batch; ++i)
-    if (n[i] < 1 || !supported_n(dir ? dst_len(n[i]) : n[i]))
+    if (n[i] < 1 || !(dir ? (supported_n(dst_len(n[i])) || n[i] == kDstDirectN) : supported_n(n[i])))
       return fail(CBS_ERR_SIZE, std::string(dir ? "unsupported Dirichlet size " : "unsupported grid size ") +
                                     std::to_string(n[i]) + " (instance " + std::to_string(i) + ")");
   return CBS_OK;
@@ -1878,6 +1880,11 @@ cbs_status setup_impl(cbs_plan* out, int batch, const int32_t* n, const void* k2
       const double sn = std::sin(M_PI * double(q) / double(mm));
       mu[mu_offset(mm) + q] = double(mm) * double(mm) * sn * sn;
     }
+  for (int q = 0; q < kDstDirectM; ++q) {
+    const double sn = std::sin(M_PI * double(q) / double(kDstDirectM));
+    mu[kMuDirect + q] = double(kDstDirectM) * double(kDstDirectM) * sn * sn;
+    mu[kSinDirect + q] = std::sin(M_PI * double(q) / double(kDstDirectN + 1));
+  }
   BAILCHK(hipMemcpyAsync(p->d_mu, mu.data(), kMuTotal * sizeof(double), hipMemcpyHostToDevice, st));
   BAILCHK(hipMemcpyAsync(p->d_tw32, t32.data(), kTwTotal * sizeof(cpx<float>), hipMemcpyHostToDevice, st));
   BAILCHK(hipMemcpyAsync(p->d_row_items, p->row_items.data(), p->row_items.size() * sizeof(int2),

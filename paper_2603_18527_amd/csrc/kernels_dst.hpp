@@ -1,7 +1,7 @@
 // Row and column kernels for Dirichlet instances: the n x n interior of the
 // unit square with homogeneous Dirichlet boundaries, five-point finite
 // differences, h = 1/(n+1), whose reference operator the 2D DST-I
-// diagonalises (App. C, "Newton linear systems for nonlinear PDEs").
+// diagonalises (App. B.2 and App. C, Newton linear systems).
 //
 // A DST-I of length n rides on the length M = 2(n+1) FFT of the odd
 // extension x~ = (0, x_1..x_n, 0, -x_n..-x_1): its bins 1..n are
@@ -122,6 +122,150 @@ __device__ __forceinline__ void row_body_dst(const Params<R>& p, const InstDesc&
   }
 }
 
+// ---- direct DST-I for n = 64 -------------------------------------------------------
+//
+// The odd extension of n = 64 has length 130 = 2 5 13, which has no FFT plan
+// here, so its transforms are formed directly: (S x)_k = sum_j x_j
+// sin(pi (j+1)(k+1)/(n+1)) from a row or column held in LDS, each of TPL
+// threads forming n/TPL outputs, with sin(pi m/(n+1)), m < 2(n+1), tabulated
+// (the index (j+1)(k+1) mod 2(n+1) advances by k+1 per j).  With the unscaled
+// S both ways, S^-1 = (2/(n+1)) S = (4/M) S per dimension, so the symbol
+// carries 16/M^2 where the FFT path's factors -2i, +2i leave 1/M^2.
+template <typename R, int NN, int TPL, int ES>
+__device__ __forceinline__ void dst_direct(const cpx<R>* buf, int t, bool active, const R* sn,
+                                           cpx<R>* out) {
+  constexpr int K = NN / TPL;
+  constexpr int MM = 2 * (NN + 1);
+  static_assert(NN % TPL == 0, "outputs per thread");
+  int idx[K], inc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    out[q] = cpx<R>{R(0), R(0)};
+    inc[q] = t + q * TPL + 1;
+    idx[q] = inc[q];
+  }
+  if (!active) return;
+  for (int j = 0; j < NN; ++j) {
+    const cpx<R> x = lds_ld(buf + ES * lds_pos(j));
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const R w = sn[idx[q]];
+      out[q].x += x.x * w;
+      out[q].y += x.y * w;
+      idx[q] += inc[q];
+      if (idx[q] >= MM) idx[q] -= MM;
+    }
+  }
+}
+
+// Rows of the direct size: MODE 0, 1, 2 as in row_body_dst.
+template <typename R, int MODE>
+__device__ __forceinline__ void row_body_dst_direct(const Params<R>& p, const InstDesc& d, int row0,
+                                                    cpx<R>* lds, double* red, const R* sn) {
+  constexpr int NN = kDstDirectN;
+  using T = RowTile<NN>;
+  constexpr int K = NN / T::TPF;
+  const int tid = threadIdx.x;
+  const int r = tid / T::TPF, t = tid - r * T::TPF;
+  const int nrows = min(T::RPW, NN - row0);
+  const bool active = r < nrows;
+  const long long rbase = d.off + (long long)(row0 + (active ? r : 0)) * NN;
+  cpx<R>* mine = lds + (active ? r : 0) * T::RS;
+  if (active)
+    for (int j = t; j < NN; j += T::TPF) {
+      if constexpr (MODE == 0) mine[lds_pos(j)] = prologue(p, d, rbase + j);
+      else mine[lds_pos(j)] = p.inter[rbase + j];
+    }
+  __syncthreads();
+  cpx<R> o[K];
+  dst_direct<R, NN, T::TPF, 1>(mine, t, active, sn, o);
+  double acc = 0.0;
+  if constexpr (MODE == 0) {
+    if (active)
+#pragma unroll
+      for (int q = 0; q < K; ++q) p.inter[rbase + t + q * T::TPF] = o[q];
+  } else if constexpr (MODE == 1) {
+    if (active)
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc += epilogue(p, d, rbase + t + q * T::TPF, o[q]);
+  } else {
+    // u_new = u + gamma (z - u + rhs), written out; then V u_new + s forward
+    cpx<R> v[K];
+    if (active)
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const long long g = rbase + t + q * T::TPF;
+        const cpx<R> u = p.u[g];
+        const cpx<R> rres = o[q] - u + ld_or_zero(p.rhs, g);
+        const Coef<R> c = coef(p, d, g);
+        const cpx<R> un = u + cmul(c.gamma(), rres);
+        p.out[g] = un;
+        acc += double(cabs2(rres));
+        v[q] = cmul(c.v, un) + ld_or_zero(p.s, g);
+      }
+    __syncthreads();
+    if (active)
+#pragma unroll
+      for (int q = 0; q < K; ++q) mine[lds_pos(t + q * T::TPF)] = v[q];
+    __syncthreads();
+    dst_direct<R, NN, T::TPF, 1>(mine, t, active, sn, o);
+    if (active)
+#pragma unroll
+      for (int q = 0; q < K; ++q) p.inter[rbase + t + q * T::TPF] = o[q];
+  }
+  if (MODE != 0 && p.partials) {
+    const double s = block_sum(acc, red);
+    if (tid == 0) p.partials[d.part_off + row0 / T::RPW] = s;
+  }
+}
+
+// Column tile of C columns of the direct size: forward DST, symbol (x 16),
+// inverse DST, all in LDS.
+template <typename R, int C>
+__device__ __forceinline__ void col_body_dst_direct(const Params<R>& p, const InstDesc& d, int col0,
+                                                    cpx<R>* lds, const R* sn) {
+  constexpr int NN = kDstDirectN, M = kDstDirectM;
+  constexpr int TPC = kThreads / C;
+  constexpr int K = NN / TPC;
+  const int tid = threadIdx.x;
+  const int c = tid % C, t = tid / C;
+  const int kcol = col0 + c;
+  const bool active = kcol < NN;
+  const long long cbase = d.off + (active ? kcol : 0);
+  cpx<R>* mine = lds + c;
+  const double* mu = p.mu + kMuDirect;
+  if (active)
+    for (int j = t; j < NN; j += TPC) mine[C * lds_pos(j)] = p.inter[cbase + (long long)j * NN];
+  __syncthreads();
+  cpx<R> o[K];
+  dst_direct<R, NN, TPC, C>(mine, t, active, sn, o);
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int k = t + q * TPC;
+    if (p.sym == SYM_TABLE)
+      o[q] = cscale(cmul(o[q], p.table[cbase + (long long)k * NN]), R(16.0 / (double(M) * double(M))));
+    else
+      o[q] = cscale(cmul(o[q], dst_symbol_factor<R, M>(mu, p.sym, k + 1, kcol + 1, d.k0sq, d.eps)), R(16));
+  }
+  __syncthreads();
+  if (active)
+#pragma unroll
+    for (int q = 0; q < K; ++q) mine[C * lds_pos(t + q * TPC)] = o[q];
+  __syncthreads();
+  dst_direct<R, NN, TPC, C>(mine, t, active, sn, o);
+  if (active)
+#pragma unroll
+    for (int q = 0; q < K; ++q) p.inter[cbase + (long long)(t + q * TPC) * NN] = o[q];
+}
+
+// sin(pi m / (n+1)), m < 2(n+1), of the direct size into LDS (every thread
+// of the workgroup calls it).
+template <typename R>
+__device__ __forceinline__ void load_direct_sines(const Params<R>& p, R* sn) {
+  for (int m = threadIdx.x; m < kDstDirectM; m += kThreads) sn[m] = R(p.mu[kSinDirect + m]);
+  __syncthreads();
+}
+
 template <typename R, int MODE>
 __device__ __forceinline__ void row_dispatch_dst(const Params<R>& p) {
   __shared__ cpx<R> lds[kRowLds];
@@ -129,6 +273,12 @@ __device__ __forceinline__ void row_dispatch_dst(const Params<R>& p) {
   const int2 w = p.items[blockIdx.x];
   if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
   const InstDesc d = p.inst[w.x];
+  if (d.n == kDstDirectN) {
+    __shared__ R sn[kDstDirectM];
+    load_direct_sines(p, sn);
+    row_body_dst_direct<R, MODE>(p, d, w.y, lds, red, sn);
+    return;
+  }
   switch (dst_len(d.n)) {
 #define CBS_ROW_DST_CASE(M) \
   case M:                   \
@@ -214,6 +364,18 @@ __global__ __launch_bounds__(kThreads) void k_col_dst(Params<R> p) {
   if (p.check && w.y == 0 && threadIdx.x < 64) check32_instance(p.chk, p.inst, p.partials, w.x);
   if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
   const InstDesc d = p.inst[w.x];
+  if (d.n == kDstDirectN) {
+    __shared__ R sn[kDstDirectM];
+    load_direct_sines(p, sn);
+    // compiled widths for the length-64 columns: the default 32 and half of it
+    constexpr int C0 = col_tile_default(kDstDirectN);
+    static_assert(C0 == 32, "direct DST column widths");
+    if ((sizeof(R) == 4 ? d.ctile : d.ctile64) == C0 / 2)
+      col_body_dst_direct<R, C0 / 2>(p, d, w.y, lds, sn);
+    else
+      col_body_dst_direct<R, C0>(p, d, w.y, lds, sn);
+    return;
+  }
   switch (dst_len(d.n)) {
 #define CBS_COL_DST_CASE(M) \
   case M:                   \

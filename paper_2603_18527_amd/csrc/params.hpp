@@ -172,7 +172,15 @@ __host__ __device__ constexpr int mu_offset(int m) {
   }
   return -1;
 }
-constexpr int kMuTotal = mu_offset(1024) + 1024;
+// The Dirichlet size without an FFT plan for its odd extension (2(n+1) =
+// 130 = 2 5 13): n = 64, the grid of the paper's Newton experiments.  Its
+// DST-I is formed directly; the eigenvalue table of length M = 130 and
+// sin(pi m / (n+1)), m < M, follow the tables of the FFT lengths.
+constexpr int kDstDirectN = 64;
+constexpr int kDstDirectM = dst_len(kDstDirectN);
+constexpr int kMuDirect = mu_offset(1024) + 1024;
+constexpr int kSinDirect = kMuDirect + kDstDirectM;
+constexpr int kMuTotal = kSinDirect + kDstDirectM;
 
 enum PwOp {
   PW_GAMMA = 0,        // e_out = gamma * e_in

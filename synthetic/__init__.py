@@ -242,7 +242,7 @@ def random_field_c(n: int, rng: np.random.Generator, scale: float = 1.0) -> np.n
     return scale * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / math.sqrt(2.0)
 
 
-def newton_batch(count: int = 100, n: int = 63, seed_config: int = 6, amplitude: float = 4.0,
+def newton_batch(count: int = 100, n: int = 64, seed_config: int = 6, amplitude: float = 4.0,
                  level: float = 40.0):
     """Linearised Newton systems of -Lap u - u^2 - f = 0 on the unit square
     (App. B, App. F): Jacobians J = L_D - 2 diag(u_m) on n x n interior points
@@ -250,9 +250,8 @@ def newton_batch(count: int = 100, n: int = 63, seed_config: int = 6, amplitude:
     right-hand side r as source.  No Newton trajectories are available, so u_m
     is a smooth state built like the paper's perturbed initial guesses:
     level + amplitude * sum_{i,j<=4} c_ij sin(i pi x) sin(j pi y),
-    c_ij ~ N(0, 0.1^2); r is a circular complex normal probe.  n = 63 stands
-    in for the paper's 64 interior points (a DST-I of length n runs on an FFT
-    of length 2(n+1), and 130 has factors 5 and 13)."""
+    c_ij ~ N(0, 0.1^2); r is a circular complex normal probe.  n = 64 is the
+    paper's grid of interior points."""
     out = []
     x = np.arange(1, n + 1) / (n + 1)
     basis = [np.outer(np.sin((i + 1) * math.pi * x), np.sin((j + 1) * math.pi * x))
@@ -310,7 +309,7 @@ def cdr_batch(count: int = 64, seed_config: int = 7, sizes=SIZES_RAGGED) -> List
 
 
 def workload(name: str):
-    """Problems for a named workload: blob64, grf256, ragged64, diff16, layered1024, newton63, cdr64."""
+    """Problems for a named workload: blob64, grf256, ragged64, diff16, layered1024, newton64, cdr64."""
     if name == "blob64":
         return [blob_problem()]
     if name == "grf256":
@@ -321,7 +320,7 @@ def workload(name: str):
         return diff_batch()[0]
     if name == "layered1024":
         return layered_batch()
-    if name == "newton63":
+    if name == "newton64":
         return newton_batch()
     if name == "cdr64":
         return cdr_batch()

@@ -54,7 +54,17 @@ def test_setup_argument_errors_without_gpu():
     # undamped needs the Dirichlet reference, and takes no eps
     assert _setup(1, [64], flags=cbs.FLAG_UNDAMPED) == cbs.CBS_ERR_ARG
     assert "DIRICHLET" in cbs.last_error()
-    assert _setup(1, [64], flags=cbs.FLAG_UNDAMPED | cbs.FLAG_DIRICHLET) == cbs.CBS_ERR_SIZE
+    assert _setup(1, [65], flags=cbs.FLAG_UNDAMPED | cbs.FLAG_DIRICHLET) == cbs.CBS_ERR_SIZE
+    # Dirichlet sizes: 2(n+1) an FFT size, or n = 64 (direct DST-I); host-only size query
+    out = ctypes.c_size_t()
+    lib0 = cbs.load()
+    for n_ok in (7, 63, 64, 511):
+        n1 = (ctypes.c_int32 * 1)(n_ok)
+        assert lib0.cbs_workspace_size(1, n1, cbs.CBS_C64, 0, cbs.FLAG_DIRICHLET, ctypes.byref(out)) == cbs.CBS_OK
+    for n_bad in (8, 62, 65, 512):
+        n1 = (ctypes.c_int32 * 1)(n_bad)
+        assert lib0.cbs_workspace_size(1, n1, cbs.CBS_C64, 0, cbs.FLAG_DIRICHLET,
+                                       ctypes.byref(out)) == cbs.CBS_ERR_SIZE
     lib = cbs.load()
     h = ctypes.c_void_p()
     n = (ctypes.c_int32 * 1)(63)

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
 TOL = {cbs.CBS_C64: 1e-5, cbs.CBS_C128: 1e-12}
-ALL_N = [63, 7, 127, 31, 15, 255, 95, 143, 191, 511]
+ALL_N = [63, 7, 127, 64, 31, 15, 255, 95, 143, 191, 511, 64]
 
 
 def _media(sizes, seed, base=100.0, amp=60.0):
@@ -64,7 +64,7 @@ def test_dirichlet_apply_and_residual_all_sizes(dtype):
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
 def test_dirichlet_fused_sweeps(dtype):
-    sizes = [63, 31, 127, 15]
+    sizes = [63, 64, 31, 127, 15]
     k2, src, u0 = _media(sizes, 810)
     plan = _plan(k2, sizes, dtype)
     u = cbs.pack(u0, TDT[dtype])
@@ -81,7 +81,7 @@ def test_dirichlet_fused_sweeps(dtype):
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
 def test_dirichlet_iterate_matches_oracle_and_dense_solve(dtype):
-    sizes = [15, 31]
+    sizes = [15, 31, 64]
     k2, src, _ = _media(sizes, 4)
     plan = _plan(k2, sizes, dtype)
     u = plan.zeros()
@@ -137,7 +137,7 @@ def test_dirichlet_fgmres_on_newton_jacobians():
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
 def test_dirichlet_npbs_step(dtype):
     # spectral weights on DST bins: M(r) = S^-1 (W * S r) + w r
-    sizes = [31, 63]
+    sizes = [31, 64, 63]
     k2, src, u0 = _media(sizes, 830)
     rng = np.random.default_rng(831)
     wf = [0.3 * S.random_field_c(n, rng) for n in sizes]
@@ -159,9 +159,12 @@ def test_dirichlet_npbs_step(dtype):
 
 def test_dirichlet_sizes_checked():
     with pytest.raises(cbs.CbsError) as e:
-        _plan([np.ones((64, 64))], [64], cbs.CBS_C64)
+        _plan([np.ones((62, 62))], [62], cbs.CBS_C64)
     assert e.value.status == cbs.CBS_ERR_SIZE
-    assert cbs.SUPPORTED_DIRICHLET == (7, 15, 31, 63, 95, 127, 143, 191, 255, 511)
+    assert cbs.SUPPORTED_DIRICHLET == (7, 15, 31, 63, 64, 95, 127, 143, 191, 255, 511)
+    with pytest.raises(cbs.CbsError) as e:
+        _plan([np.ones((65, 65))], [65], cbs.CBS_C64)
+    assert e.value.status == cbs.CBS_ERR_SIZE
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
@@ -169,7 +172,7 @@ def test_dirichlet_sizes_checked():
 def test_dirichlet_loss_and_adjoint_match_oracle(dtype, weight):
     # Newton-state metric-matched loss (App. B, Eq. nl_bs_loss) and the
     # physical one, K = 6 unrolled steps, gradients w.r.t. u0 and k^2
-    sizes = [31, 15]
+    sizes = [31, 64, 15]
     k2, src, u0 = _media(sizes, 840)
     plan = _plan(k2, sizes, dtype)
     tdt = TDT[dtype]
@@ -207,7 +210,7 @@ def test_dirichlet_tile_widths_and_autotune(which):
     # column tiles over a length-2(n+1) transform, the last tile of an instance
     # partial (n is odd): every compiled width, and the autotuner's pick, give
     # the oracle's apply
-    sizes = [63, 127, 255, 511, 95, 143]
+    sizes = [63, 127, 255, 511, 95, 143, 64]
     k2, src, u0 = _media(sizes, 850)
     plan = _plan(k2, sizes, cbs.CBS_C64)
     u = cbs.pack(u0, torch.complex64)
@@ -218,7 +221,7 @@ def test_dirichlet_tile_widths_and_autotune(which):
         refs.append(O.green_dirichlet(v, plan.k0sq[i], plan.eps[i]))
     allowed = {}
     for n in sizes:
-        c0 = _tile_default(2 * (n + 1))
+        c0 = _tile_default(n if n == 64 else 2 * (n + 1))   # n = 64: direct DST, columns of 64
         allowed[n] = (c0 // 2, c0, c0 * 2)
         c = {"half": c0 // 2, "default": c0, "double": c0 * 2}[which]
         try:

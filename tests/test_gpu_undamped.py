@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 TDT = {cbs.CBS_C64: torch.complex64, cbs.CBS_C128: torch.complex128}
 TOL = {cbs.CBS_C64: 1e-5, cbs.CBS_C128: 1e-12}
-SIZES = [63, 7, 127, 31, 15, 255, 95, 143, 191, 511]
+SIZES = [63, 7, 127, 64, 31, 15, 255, 95, 143, 191, 511]
 ALPHA = 2.0
 
 
@@ -115,7 +115,7 @@ def test_undamped_metric_matched_grad(dtype):
     # loss || G s - (I - G V) x ||^2 and its gradient, against autograd
     # through the oracle's Born residual with eps = 0
     tol = 1e-5 if dtype == cbs.CBS_C64 else 1e-10
-    sizes = [31, 63]
+    sizes = [31, 64]
     k2, k0sq = _newton_states(sizes, 920)
     rng = np.random.default_rng(921)
     x0 = [S.random_field_c(n, rng) for n in sizes]
@@ -141,7 +141,7 @@ def test_undamped_metric_matched_grad(dtype):
 def test_undamped_gmres_on_newton_jacobians(dtype):
     # J du = r, J = L_D - 2 diag(u_m): GMRES(20) on G J du = G r, no inner
     # sweeps, to rtol 1e-6 of the Born relative residual
-    sizes = [63, 63, 127, 15]
+    sizes = [63, 64, 127, 15]
     k2, k0sq = _newton_states(sizes, 930)
     rng = np.random.default_rng(931)
     rhs = [S.random_field_c(n, rng) for n in sizes]
