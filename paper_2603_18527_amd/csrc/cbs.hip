@@ -192,7 +192,7 @@ void build_items(cbs_plan p) {
     d.vx0 = p->vx0.empty() ? 0.0 : p->vx0[i];
     d.vy0 = p->vy0.empty() ? 0.0 : p->vy0[i];
     const int m = p->tlen(d.n);
-    const int rpw = row_rpw(m);
+    const int rpw = (p->dirichlet && d.n == kDstDirectN) ? kDstDirectRPW : row_rpw(m);
     d.rpw = rpw;
     d.part_off = part;
     d.nparts = (d.n + rpw - 1) / rpw;

@@ -158,12 +158,19 @@ __device__ __forceinline__ void dst_direct(const cpx<R>* buf, int t, bool active
   }
 }
 
+struct DirectRowTile {
+  static constexpr int TPF = kDstDirectTPF;
+  static constexpr int RPW = kDstDirectRPW;
+  static constexpr int RS = lds_len(kDstDirectN);
+  static_assert(RPW * RS <= kRowLds, "row tile does not fit");
+};
+
 // Rows of the direct size: MODE 0, 1, 2 as in row_body_dst.
 template <typename R, int MODE>
 __device__ __forceinline__ void row_body_dst_direct(const Params<R>& p, const InstDesc& d, int row0,
                                                     cpx<R>* lds, double* red, const R* sn) {
   constexpr int NN = kDstDirectN;
-  using T = RowTile<NN>;
+  using T = DirectRowTile;
   constexpr int K = NN / T::TPF;
   const int tid = threadIdx.x;
   const int r = tid / T::TPF, t = tid - r * T::TPF;

@@ -178,6 +178,11 @@ __host__ __device__ constexpr int mu_offset(int m) {
 // sin(pi m / (n+1)), m < M, follow the tables of the FFT lengths.
 constexpr int kDstDirectN = 64;
 constexpr int kDstDirectM = dst_len(kDstDirectN);
+// Its row kernels give each row 32 threads (two outputs each), 8 rows per
+// workgroup: the direct sums are serial in the row length, so short chains
+// and more workgroups beat the FFT rows' 8 threads per row.
+constexpr int kDstDirectTPF = 32;
+constexpr int kDstDirectRPW = kThreads / kDstDirectTPF;
 constexpr int kMuDirect = mu_offset(1024) + 1024;
 constexpr int kSinDirect = kMuDirect + kDstDirectM;
 constexpr int kMuTotal = kSinDirect + kDstDirectM;
