@@ -2,9 +2,11 @@
 cbs_adjoint_step, and the BornResidualLoss autograd Function).
 
 * 32x32, K = 8, W = gamma and W = 1: loss, d/du0 and d/dk2 against the
-  oracle's autograd gradient.  FP64 plans: 1e-10 relative; FP32 plans: 1e-4
-  (16 FP32 operator applications in sequence, each ~2e-7 relative, with
-  cancellation in the gradient sums).
+  oracle's autograd gradient.  FP64 plans: 1e-10 relative; FP32 plans: 2e-5,
+  an error budget of 2K + 2 = 18 FP32 operator applications in sequence (the
+  K forward sweeps, the seed and the K adjoint steps), each within 5e-7 of
+  the exact operator (the FP32 apply parity is 2-4e-7): 18 x 5e-7 = 9e-6,
+  doubled.  Measured: 0.3-1.7e-6 (32x32), 2.1-2.3e-6 (16 x 256^2 against FP64).
 * Full size (16 instances of 256x256, contrast 2, K = 8, W = gamma): central
   differences (h = 1e-3, Richardson-extrapolated twice with h/2 and h/4) of the FP64 GPU
   loss on 32 random entries (16 of u0, real and imaginary parts, and 16 of
@@ -60,7 +62,7 @@ def test_adjoint_matches_oracle_gradient(dtype, weight):
     u0 = cbs.pack(u0s, tdt)
     s = cbs.pack([p.source for p in probs], tdt)
     loss, lam, grad = _unrolled(plan, u0, s, 8, weight)
-    tol = 1e-10 if dtype == cbs.CBS_C128 else 1e-4
+    tol = 1e-10 if dtype == cbs.CBS_C128 else 2e-5
     for i, (ki, ui, si, li, gi) in enumerate(zip(to_list(k2, sizes), to_list(u0, sizes), to_list(s, sizes),
                                                  to_list(lam, sizes), to_list(grad, sizes))):
         val, gu, gk = O.loss_and_grad(ki, plan.k0sq[i], plan.eps[i], ui, si, 8, weight)
@@ -86,7 +88,7 @@ def test_autograd_function_matches_direct_calls(weight):
         eps = O.choose_eps(ki, probs[i].k0sq)
         val, gu, gk = O.loss_and_grad(ki, probs[i].k0sq, eps, ui, si, 8, weight)
         w = [1.0, 0.5][i]
-        assert abs(float(loss[i]) - val) <= 1e-10 * val
+        assert abs(float(loss[i].detach()) - val) <= 1e-10 * val
         assert rel_err(gu_gpu, w * gu) <= 1e-10
         assert rel_err(gk_gpu, w * gk) <= 1e-10
 
@@ -118,7 +120,7 @@ def test_full_size_finite_differences_and_fp32_adjoint():
     e_grad = rel_err(grad32.cpu(), grad.cpu())
     e_loss = float(torch.max(torch.abs(loss32 - loss) / loss))
     say(f"   FP32 vs FP64 adjoint: loss {e_loss:.2e} du0 {e_lam:.2e} dk2 {e_grad:.2e}")
-    assert e_loss <= 1e-4 and e_lam <= 1e-4 and e_grad <= 1e-4
+    assert e_loss <= 2e-5 and e_lam <= 2e-5 and e_grad <= 2e-5
     rng = np.random.default_rng(2024)
     offs = cbs.offsets(sizes)
     lam_h = lam.cpu()

@@ -113,7 +113,7 @@ def test_cdr_metric_matched_loss_and_gradient(dtype):
     tol = 1e-4 if dtype == cbs.CBS_C64 else 1e-10
     for i, p in enumerate(probs):
         val, gx = O.cdr_loss_and_grad(_medium(p), x0[i], p.source)
-        el = abs(float(loss[i]) - val) / val
+        el = abs(float(loss[i].detach()) - val) / val
         eg = rel_err(_unpack(x.grad, sizes)[i], float(w[i]) * gx)
         say(f"[cdr loss] dtype={dtype} n={p.n}: loss {el:.1e} grad {eg:.1e}")
         assert el <= tol and eg <= tol

@@ -186,7 +186,7 @@ def test_dirichlet_loss_and_adjoint_match_oracle(dtype, weight):
     for m in range(5, -1, -1):
         plan.adjoint_step(us[m], s, lam, lam, grad)
     torch.cuda.synchronize()
-    tol = 1e-10 if dtype == cbs.CBS_C128 else 1e-4
+    tol = 1e-10 if dtype == cbs.CBS_C128 else 2e-5   # budget as in test_gpu_adjoint.py
     for i, n in enumerate(sizes):
         val, gu, gk = O.loss_and_grad(k2[i], plan.k0sq[i], plan.eps[i], u0[i], src[i], 6, weight,
                                       bc="dirichlet")
