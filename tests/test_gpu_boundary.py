@@ -5,8 +5,8 @@
   the same kernels run per instance (finished instances are masked instead of
   compacted away), so results are bitwise equal, also for an instance that
   runs out of its budget and on a plan with two lanes;
-* cbs_iterate_async captured into a graph and replayed several times, with
-  eager work in between, against the eager call;
+* cbs_iterate_async and fgmres_solve_async captured into graphs and replayed
+  several times, with eager work in between, against the eager calls;
 * cbs_relres against the oracle's Born and physical relative residuals
   (periodic, Dirichlet and convection-diffusion-reaction plans);
 * cbs_metric_matched_grad against torch autograd through the oracle's Born
@@ -109,6 +109,42 @@ def test_iterate_async_graph_replay():
         torch.cuda.synchronize()
         got = tuple(_host(t) for t in out)
         say(f"[graph replay {rep}] {got[0]} vs eager {ref[0]}")
+        assert got == ref
+        assert torch.equal(u, ref_u)
+
+
+def test_fgmres_async_graph_replay():
+    # the Arnoldi kernels (delayed reorthogonalisation, LDS-staged Givens
+    # chains) captured into a graph: three replays with eager work between
+    # them equal the eager call bitwise
+    sizes = [64, 128]
+    probs = [random_problem(n, seed=1450 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, restart=12)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    ref_u = plan.zeros()
+    ref = plan.fgmres_async(ref_u, s, restart=12, sweeps=2, max_iters=300, rtol=1e-6)
+    torch.cuda.synchronize()
+    ref = tuple(_host(t) for t in ref)
+    assert all(x == cbs.INST_CONVERGED for x in ref[2])
+    u = plan.zeros()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        plan.fgmres_async(u, s, restart=12, sweeps=2, max_iters=300, rtol=1e-6)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        u.zero_()
+        out = plan.fgmres_async(u, s, restart=12, sweeps=2, max_iters=300, rtol=1e-6)
+    for rep in range(3):
+        u.fill_(1.0)
+        plan.apply(u, s)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = tuple(_host(t) for t in out)
+        say(f"[fgmres graph replay {rep}] {got[0]} vs eager {ref[0]}")
         assert got == ref
         assert torch.equal(u, ref_u)
 
