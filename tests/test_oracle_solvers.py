@@ -56,6 +56,23 @@ def test_cbs_matches_dense_solve():
     assert O.physical_relres(p.k2, u, p.source) < 1e-10
 
 
+def test_cbs_and_fgmres_match_dense_solve_32():
+    # P6 at 32 x 32 (a 1024 x 1024 dense A): CBS and FGMRES(30) + P_4 both
+    # reach the LAPACK solution.
+    rng = np.random.default_rng(7)
+    c = S.minmax_map(S.gaussian_random_field(32, 4.0, rng), 1.0, 2.0)
+    src = S.gaussian_pulse(32, (13, 18), 1.5)
+    p = S.velocity_problem(c, 6, 6.0, src, cmin=1.0)
+    eps = O.choose_eps(p.k2, p.k0sq)
+    ref = np.linalg.solve(_dense_helmholtz_numpy(p.k2), p.source.reshape(-1)).reshape(32, 32)
+    u, m, rel = O.cbs_iterate(p.k2, p.k0sq, eps, p.source, max_sweeps=40000, rtol=1e-13)
+    assert rel <= 1e-13
+    assert np.max(np.abs(u.numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+    x, its, rel = O.fgmres(p.k2, p.k0sq, eps, p.source, restart=30, sweeps=4, max_iters=5000, rtol=1e-13)
+    assert rel <= 1e-13
+    assert np.max(np.abs(x.numpy() - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
 def test_physical_stop_rule():
     # The paper's unified stopping rule rTol = ||s - A u|| / ||s|| (Sec. 5).
     # Pins: (i) the physical residual is L_eta applied to the Born residual,
