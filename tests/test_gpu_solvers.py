@@ -193,6 +193,29 @@ def test_fgmres_small_matches_oracle(dtype):
         assert abs(its[0] - ito) <= 3
 
 
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_gmres_without_inner_sweeps_matches_oracle(dtype):
+    # K = 0: no inner preconditioner, GMRES on B u = G s (periodic plan)
+    p = random_problem(32, seed=93, source="point", cmax=2.0, ppw=8.0)
+    plan, k2 = plan_for([p], dtype, restart=20)
+    tdt = torch.complex64 if dtype == cbs.CBS_C64 else torch.complex128
+    s = cbs.pack([p.source], tdt)
+    u = plan.zeros()
+    its, rel, stat = plan.fgmres(u, s, restart=20, sweeps=0, max_iters=3000, rtol=1e-6)
+    ki, si = to_list(k2, [32])[0], to_list(s, [32])[0]
+    xo, ito, relo = O.fgmres(ki, plan.k0sq[0], plan.eps[0], si, restart=20, sweeps=0, max_iters=3000, rtol=1e-6)
+    ug = to_list(u, [32])[0]
+    ev = _oracle_relres(ki, plan.k0sq[0], plan.eps[0], ug, si)
+    say(f"[gmres K=0] dtype={dtype}: gpu its {its[0]} relres {rel[0]:.3e} (oracle eval {ev:.3e}); oracle its {ito}")
+    assert stat[0] == cbs.INST_CONVERGED
+    _bar(dtype, rel[0], ev)
+    if dtype == cbs.CBS_C128:
+        assert its[0] == ito
+        assert rel_err(ug, xo) <= 1e-8
+    else:
+        assert abs(its[0] - ito) <= 5
+
+
 def test_fgmres_grf256_full_size():
     # 256x256 random-field medium, FGMRES(30) with 4 CBS sweeps.
     say("[fgmres grf256]")
