@@ -216,6 +216,30 @@ def test_gmres_without_inner_sweeps_matches_oracle(dtype):
         assert abs(its[0] - ito) <= 5
 
 
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+@pytest.mark.parametrize("sweeps", [0, 2])
+def test_fgmres_one_step_on_an_eigenvector(dtype, sweeps):
+    # Homogeneous lossy medium k^2 = k0^2 + i kappa: V is a constant, B = I - G V
+    # is diagonal in Fourier space, so G s for one Fourier mode s is an
+    # eigenvector of B and of P_K: the first Arnoldi step spans the solution
+    # (the next Krylov vector vanishes up to rounding) and FGMRES stops there.
+    n, k0sq, kappa = 32, 0.8, 0.3
+    x = np.arange(n)
+    mode = np.exp(2j * np.pi * (3 * x[:, None] + 5 * x[None, :]) / n)
+    prob = S.homogeneous_lossy(n, k0sq, kappa, mode)
+    plan, k2 = plan_for([prob], dtype, restart=10, eps=[1.5 * kappa])
+    tdt = torch.complex64 if dtype == cbs.CBS_C64 else torch.complex128
+    s = cbs.pack([mode], tdt)
+    u = plan.zeros()
+    rtol = 1e-6 if dtype == cbs.CBS_C64 else 1e-12
+    its, rel, stat = plan.fgmres(u, s, restart=10, sweeps=sweeps, max_iters=50, rtol=rtol)
+    ki, si = to_list(k2, [n])[0], to_list(s, [n])[0]
+    ev = _oracle_relres(ki, k0sq, 1.5 * kappa, to_list(u, [n])[0], si)
+    say(f"[fgmres eigenvector] dtype={dtype} K={sweeps}: its {its[0]} rel {rel[0]:.2e} eval {ev:.2e}")
+    assert stat[0] == cbs.INST_CONVERGED and its[0] == 1
+    assert ev <= (1e-6 if dtype == cbs.CBS_C64 else 1e-12)
+
+
 def test_fgmres_grf256_full_size():
     # 256x256 random-field medium, FGMRES(30) with 4 CBS sweeps.
     say("[fgmres grf256]")
