@@ -7,7 +7,8 @@ sources (about 6.9 M cells).  A step is one batched CBS sweep over all
 instances (prologue V u + s, forward 2D FFT, Green symbol, inverse 2D FFT,
 epilogue u += gamma r with FP64 partial norms), issued as one set of launches
 covering the whole ragged batch; the timed steps form one chain of fused
-sweeps replayed from a captured HIP graph.
+sweeps issued with direct launches (--graph: replayed from a captured HIP
+graph).
 
 Printed: one JSON line with Gcell*CBS-apply/s (value), the HBM roofline of
 the sweep (32 algorithmic bytes per cell: read u, V, s, write u), the FP64
@@ -214,6 +215,44 @@ def cpu_baseline(probs, budget_s: float = 12.0, budget_1t_s: float = 4.0, max_ro
     }
 
 
+def lone_sweep_us(k2_i, s_i, n, k0sq_i, use_graph=True, sweeps=2000, chunk=50):
+    """Microseconds per sweep of one instance run alone by cbs_iterate (chunks
+    of `chunk` sweeps, replayed from a graph or launched directly), with a
+    tolerance no FP32 run reaches so that every sweep is run."""
+    from paper_2603_18527_amd import cbs
+    plan = cbs.Plan(k2_i, [n], k0sq=[k0sq_i])
+    try:
+        u = plan.zeros()
+        plan.iterate(u, s_i, max_sweeps=chunk, rtol=1e-30, check_every=chunk, use_graph=use_graph)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, _, _ = plan.iterate(u, s_i, max_sweeps=sweeps, rtol=1e-30, check_every=chunk,
+                                 use_graph=use_graph)
+        dt = time.perf_counter() - t0
+    finally:
+        plan.close()
+    return dt * 1e6 / max(1, its[0])
+
+
+def tail_probe(probs):
+    """Per-sweep cost of a lone instance of each grid size of the batch (the
+    convergence tail of a batched solve runs one or two such instances)."""
+    from paper_2603_18527_amd import cbs
+    out = {}
+    seen = set()
+    for p in probs:
+        if p.n in seen:
+            continue
+        seen.add(p.n)
+        k2 = cbs.pack([p.k2], torch.complex64)
+        s = cbs.pack([p.source], torch.complex64)
+        out[str(p.n)] = {"graph_us_per_sweep": lone_sweep_us(k2, s, p.n, p.k0sq, True),
+                         "direct_us_per_sweep": lone_sweep_us(k2, s, p.n, p.k0sq, False)}
+        print(f"# lone {p.n}^2: {out[str(p.n)]}", flush=True)
+    return out
+
+
 def time_to_solution(probs, plan_k2, sizes, k0sq, s_packed, rtol=1e-6, chunk=50, max_sweeps=20000):
     from paper_2603_18527_amd import cbs
     out = {}
@@ -237,8 +276,16 @@ def time_to_solution(probs, plan_k2, sizes, k0sq, s_packed, rtol=1e-6, chunk=50,
     out["sweeps_sorted_top8"] = sorted((int(k) for k in its), reverse=True)[:8]
     out["batched_all_converged"] = all(s == cbs.INST_CONVERGED for s in stat)
     out["batched_max_relres"] = float(max(rel))
-    # plain: a per-instance loop of plans with ordinary launches
+    # the slowest instance run alone: its sweep count times its lone per-sweep
+    # cost is the tail the batched time cannot go below
     offs = cbs.offsets(sizes)
+    i_slow = int(np.argmax(its))
+    n_slow = sizes[i_slow]
+    sl = slice(offs[i_slow], offs[i_slow] + n_slow * n_slow)
+    us = lone_sweep_us(plan_k2[sl].contiguous(), s_packed[sl].contiguous(), n_slow, k0sq[i_slow])
+    out["slowest_instance"] = {"n": n_slow, "sweeps": int(its[i_slow]), "lone_us_per_sweep": us,
+                               "lone_sweeps_s": us * 1e-6 * int(its[i_slow])}
+    # plain: a per-instance loop of plans with ordinary launches
     t_plain = 0.0
     t_512 = []
     for i, n in enumerate(sizes):
@@ -670,6 +717,8 @@ def main():
     ap.add_argument("--chain", type=int, default=50, help="sweeps fused per cbs_sweep call")
     ap.add_argument("--cdr", action="store_true",
                     help="only time the convection-diffusion-reaction apply / adjoint (cdr64 batch)")
+    ap.add_argument("--tail", action="store_true",
+                    help="only time one sweep of a lone instance of each grid size (graph and direct)")
     ap.add_argument("--suite", action="store_true",
                     help="also run the solver suite over all five synthetic workloads")
     ap.add_argument("--calib-copy", action="store_true",
@@ -686,6 +735,12 @@ def main():
         if not torch.cuda.is_available():
             raise SystemExit("no GPU visible")
         print(json.dumps({"cdr64_apply": cdr_throughput()}), flush=True)
+        return
+    if args.tail:
+        if not torch.cuda.is_available():
+            raise SystemExit("no GPU visible")
+        probs, _ = build_workload(args.workload)
+        print(json.dumps({"lone_instance_sweep": tail_probe(probs)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the instances of a batch "
