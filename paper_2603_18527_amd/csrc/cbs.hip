@@ -499,6 +499,8 @@ cbs_status issue_chain(cbs_plan p, hipStream_t st, int steps, F&& step) {
 // behind are those of the last sweep.
 template <typename R>
 cbs_status run_sweeps(cbs_plan p, Params<R> q, int count, hipStream_t st) {
+  // the fused sweep kernel reads rhs or s, not both
+  if (q.rhs && q.s) return fail(CBS_ERR_ARG, "a fused sweep takes rhs or s, not both");
   return issue_chain(p, st, count + 1, [&](int k, hipStream_t ls, const cbs_plan_s::Items& it) {
     Params<R> f = q;
     f.items = it.rows;
@@ -696,7 +698,7 @@ cbs_status enqueue_chunk(cbs_plan p, int chunk, int stop, hipStream_t st) {
   if (chunk > 1) {
     Params<R> q = base_params<R>(p);
     q.u = e;
-    q.rhs = c;
+    q.rhs = c;  // and no s: the fused sweep kernel reads one of the two
     q.out = e;
     q.epi = EPI_SWEEP;
     q.mask = p->d_status;

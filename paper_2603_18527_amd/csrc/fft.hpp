@@ -228,16 +228,27 @@ __device__ __forceinline__ void load_tw(const cpx<R>* __restrict__ p, cpx<R>* w)
   }
 }
 
-// Twiddle multiply of butterfly k of pass P: v[q] *= w^(q k) (forward) or
-// conj(w)^(q k) (inverse).
+// Twiddles w^(q k) of butterfly k of pass P, fetched into w[0 .. radp(r)),
+// and their multiply: v[q] *= w^(q k) (forward) or conj(w)^(q k) (inverse).
+// The passes fetch a butterfly's twiddles before they read its inputs, so
+// the fetch overlaps the LDS reads and the barrier that follows them.
+template <typename R, int N, int P>
+__device__ __forceinline__ void tw_fetch(cpx<R>* w, int k, const cpx<R>* __restrict__ tw) {
+  constexpr int RP = radp(plan_radix(N, P));
+  load_tw<R, RP>(tw + tw_pass_offset(N, P) + k * RP, w);
+}
+template <int RAD, int DIR, typename R>
+__device__ __forceinline__ void tw_apply(cpx<R>* v, const cpx<R>* w) {
+#pragma unroll
+  for (int q = 1; q < RAD; ++q) v[q] = DIR < 0 ? cmul(w[q], v[q]) : cmulc(w[q], v[q]);
+}
+
 template <typename R, int N, int P, int DIR>
 __device__ __forceinline__ void twiddle(cpx<R>* v, int k, const cpx<R>* __restrict__ tw) {
   constexpr int RAD = plan_radix(N, P);
-  constexpr int RP = radp(RAD);
-  cpx<R> w[RP];
-  load_tw<R, RP>(tw + tw_pass_offset(N, P) + k * RP, w);
-#pragma unroll
-  for (int q = 1; q < RAD; ++q) v[q] = DIR < 0 ? cmul(w[q], v[q]) : cmulc(w[q], v[q]);
+  cpx<R> w[radp(RAD)];
+  tw_fetch<R, N, P>(w, k, tw);
+  tw_apply<RAD, DIR>(v, w);
 }
 
 // Twiddles of one transform length held q-major in LDS: for pass P (Ns > 1)
@@ -260,16 +271,21 @@ struct TwQ {
   const cpx<R>* base;  // LDS table of one transform length
 };
 
-template <typename R, int N, int P, int DIR>
-__device__ __forceinline__ void twiddle(cpx<R>* v, int k, TwQ<R> tw) {
+template <typename R, int N, int P>
+__device__ __forceinline__ void tw_fetch(cpx<R>* w, int k, TwQ<R> tw) {
   constexpr int RAD = plan_radix(N, P);
   constexpr int NS = plan_ns(N, P);
   const cpx<R>* b = tw.base + twq_pass_offset(N, P) + k;
 #pragma unroll
-  for (int q = 1; q < RAD; ++q) {
-    const cpx<R> w = lds_ld(b + (q - 1) * NS);
-    v[q] = DIR < 0 ? cmul(w, v[q]) : cmulc(w, v[q]);
-  }
+  for (int q = 1; q < RAD; ++q) w[q] = lds_ld(b + (q - 1) * NS);
+}
+
+template <typename R, int N, int P, int DIR>
+__device__ __forceinline__ void twiddle(cpx<R>* v, int k, TwQ<R> tw) {
+  constexpr int RAD = plan_radix(N, P);
+  cpx<R> w[radp(RAD)];
+  tw_fetch<R, N, P>(w, k, tw);
+  tw_apply<RAD, DIR>(v, w);
 }
 
 // Fills the q-major LDS table of length N from the global table (every
@@ -313,6 +329,17 @@ __device__ __forceinline__ cpx<R> call_mid(F& f, int e, cpx<R> v, int p, int q) 
   else return f(e, v);
 }
 
+// A bridge functor may also have pre(e, p, q): the bridge calls it for all of
+// the thread's elements before it reads its inputs from LDS, so the functor
+// can issue every global load it needs up front.  Without it a functor that
+// loads and stores per element (an in-place update) gets its loads issued one
+// element at a time: the compiler cannot move the next element's loads above
+// a store that may alias them.
+template <class F, class = void>
+struct has_pre : std::false_type {};
+template <class F>
+struct has_pre<F, std::void_t<decltype(std::declval<F&>().pre(0, 0, 0))>> : std::true_type {};
+
 // ---- one Stockham pass ----------------------------------------------------------
 //
 // TPF threads cooperate on one transform (t = 0..TPF-1); every thread of the
@@ -337,11 +364,13 @@ __device__ __forceinline__ void fft_pass_t(cpx<R>* buf, int t, bool active, TW t
   constexpr bool READS_LDS = !FIRST || LD_LDS;
   constexpr bool WRITES_LDS = !LAST || ST_LDS;
   cpx<R> v[PER][RAD];
+  cpx<R> w[PER][radp(RAD)];
   if (active) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int j = t + p * TPF;
       if (EXACT || j < NB) {
+        if constexpr (NS > 1) tw_fetch<R, N, P>(w[p], j % NS, tw);
         if constexpr (FIRST) {
 #pragma unroll
           for (int q = 0; q < RAD; ++q) v[p][q] = call_ld<LD, R>(ld, j + q * NB, p, q);
@@ -360,7 +389,7 @@ __device__ __forceinline__ void fft_pass_t(cpx<R>* buf, int t, bool active, TW t
       const int j = t + p * TPF;
       if (EXACT || j < NB) {
         const int k = j % NS;
-        if constexpr (NS > 1) twiddle<R, N, P, DIR>(v[p], k, tw);
+        if constexpr (NS > 1) tw_apply<RAD, DIR>(v[p], w[p]);
         bfly<RAD, DIR>(v[p]);
         const int o = (j / NS) * (NS * RAD) + k;
         if constexpr (LAST) {
@@ -432,7 +461,23 @@ __device__ __forceinline__ void fft_bridge_t(cpx<R>* buf, int t, bool active, TW
   constexpr int PER = (NB + TPF - 1) / TPF;
   constexpr bool EXACT = (NB % TPF) == 0;
   cpx<R> v[PER][RAD];
+  cpx<R> w[PER][radp(RAD)];
   if (active) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int j = t + p * TPF;
+      if (EXACT || j < NB) tw_fetch<R, N, PL>(w[p], j, tw);
+    }
+    if constexpr (has_pre<MID>::value) {
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        const int j = t + p * TPF;
+        if (EXACT || j < NB) {
+#pragma unroll
+          for (int q = 0; q < RAD; ++q) mid.pre(j + q * NS, p, q);
+        }
+      }
+    }
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
       const int j = t + p * TPF;
@@ -450,7 +495,7 @@ __device__ __forceinline__ void fft_bridge_t(cpx<R>* buf, int t, bool active, TW
       const int j = t + p * TPF;
       if (EXACT || j < NB) {
         // last pass of transform 1: k = j (j < NS), outputs at j + q NS
-        twiddle<R, N, PL, D1>(v[p], j, tw);
+        tw_apply<RAD, D1>(v[p], w[p]);
         bfly<RAD, D1>(v[p]);
 #pragma unroll
         for (int q = 0; q < RAD; ++q) v[p][q] = call_mid<MID, R>(mid, j + q * NS, v[p][q], p, q);

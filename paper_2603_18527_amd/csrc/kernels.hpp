@@ -43,6 +43,14 @@ struct Coef {
 };
 
 template <typename R>
+__device__ __forceinline__ Coef<R> coef_of(const InstDesc& d, cpx<R> k) {
+  Coef<R> c;
+  c.v = {k.x - R(d.k0sq), k.y - R(d.eps)};
+  c.inv_eps = R(1.0 / d.eps);
+  return c;
+}
+
+template <typename R>
 __device__ __forceinline__ Coef<R> coef(const Params<R>& p, const InstDesc& d, long long i) {
   const cpx<R> k = p.k2[i];
   Coef<R> c;
@@ -232,6 +240,43 @@ struct RowTile {
   static_assert(RPW * RS <= kRowLds, "row tile does not fit");
 };
 
+// The bridge step of a fused sweep (MODE 2 with a bridged plan): for each of
+// the thread's elements, z from the inverse rows gives r = z - u + rhs and
+// u_new = u + gamma r (written), and the value returned is the next sweep's
+// V u_new + s.  A fused sweep takes rhs (correction sweeps) or s (plain
+// sweeps) or neither, never both (the host checks).  pre() loads u, k^2 and
+// that one field for all elements before the first store, without branches
+// (a field that is absent is read from u and scaled by zero), so that the
+// loads are in flight together.
+template <typename R, int PER, int RAD>
+struct SweepMid {
+  const Params<R>& p;
+  const InstDesc& d;
+  long long rbase;
+  double& acc;
+  cpx<R> u[PER][RAD], k[PER][RAD], a[PER][RAD];
+  // __host__ __device__, like the lambdas the bridge otherwise takes, so that
+  // the bridge's compile-time checks for the call forms see them
+  __host__ __device__ __forceinline__ void pre(int e, int pp, int qq) {
+    const long long g = rbase + e;
+    const cpx<R>* x = p.rhs ? p.rhs : p.s ? p.s : p.u;
+    u[pp][qq] = p.u[g];
+    k[pp][qq] = p.k2[g];
+    a[pp][qq] = x[g];
+  }
+  __host__ __device__ __forceinline__ cpx<R> operator()(int e, cpx<R> z, int pp, int qq) {
+    const R wr = p.rhs ? R(1) : R(0);
+    const R ws = !p.rhs && p.s ? R(1) : R(0);
+    const cpx<R> uu = u[pp][qq];
+    const cpx<R> rres = z - uu + cscale(a[pp][qq], wr);
+    const Coef<R> c = coef_of(d, k[pp][qq]);
+    const cpx<R> un = uu + cmul(c.gamma(), rres);
+    p.out[rbase + e] = un;
+    acc += double(cabs2(rres));
+    return cmul(c.v, un) + cscale(a[pp][qq], ws);
+  }
+};
+
 // MODE 0: prologue + forward rows -> spectral buffer;
 // MODE 1: spectral buffer -> inverse rows -> epilogue (with partial norms);
 // MODE 2: spectral buffer -> inverse rows -> sweep epilogue u += gamma r
@@ -305,7 +350,10 @@ __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, 
     };
     auto st2 = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
     if constexpr (plan_bridgeable(N)) {
-      fft_run2<R, N, T::TPF, 1, -1>(mine, t, active, p.tw, ld, update, st2);
+      constexpr int RAD = plan_radix(N, 0);
+      constexpr int PER = (N / RAD + T::TPF - 1) / T::TPF;
+      SweepMid<R, PER, RAD> mid{p, d, rbase, acc};
+      fft_run2<R, N, T::TPF, 1, -1>(mine, t, active, p.tw, ld, mid, st2);
     } else {
       auto st = [&](int e, cpx<R> z) { mine[lds_pos(e)] = update(e, z); };
       fft_run<R, N, T::TPF, 1, false, true>(mine, t, active, p.tw, ld, st);
