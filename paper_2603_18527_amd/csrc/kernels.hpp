@@ -372,8 +372,10 @@ __device__ __forceinline__ void row_dispatch(const Params<R>& p) {
   __shared__ cpx<R> lds[kRowLds];
   __shared__ double red[kThreads / 64];
   const int2 w = p.items[blockIdx.x];
-  if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
+  // the descriptor is loaded before the mask is tested, so the two loads are
+  // in flight together
   const InstDesc d = p.inst[w.x];
+  if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
   switch (d.n) {
 #define CBS_ROW_CASE(N) \
   case N:               \
@@ -510,9 +512,9 @@ __device__ __forceinline__ void col_kernel_body(const Params<R>& p) {
   // the first tile's workgroup checks the sweep the previous launch finished
   // (the instance's next row launch sees the result; whether the other tiles
   // of this launch see it only decides whether they do work nobody reads)
+  const InstDesc d = p.inst[w.x];
   if (p.check && w.y == 0 && threadIdx.x < 64) check32_instance(p.chk, p.inst, p.partials, w.x);
   if (!inst_enabled(p.mask, p.mask_mode, w.x)) return;
-  const InstDesc d = p.inst[w.x];
   switch (d.n) {
 #define CBS_COL_CASE(N) \
   case N:               \
