@@ -322,6 +322,38 @@ def test_sweep_chain_bench_path(bench_path_case, dtype):
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_iterate_chunk_bench_path(bench_path_case, dtype):
+    # cbs_iterate's chunk on the same batch (two lanes): the FP64 residual
+    # r0 = G(V u0 + s) - u0, then sweeps of the correction equation
+    # e <- e + gamma (G(V e) + r0 - e) (the sweep kernel with rhs, no s) and
+    # u0 + e.  From any u0 these are the plain CBS iterates in exact
+    # arithmetic (Sec. 3.1, Eq. CBS), so one chunk of BENCH_SWEEPS sweeps
+    # matches the oracle's BENCH_SWEEPS sweeps element by element.
+    case = bench_path_case
+    say(f"[bench-path iterate chunk] sizes={BENCH_SIZES} dtype={dtype}")
+    tdt = TDT[dtype]
+    if dtype == cbs.CBS_C64:
+        plan = case["plan32"]
+    else:
+        plan = cbs.Plan(case["k2"].to(torch.complex128), BENCH_SIZES, k0sq=case["k0sq"],
+                        dtype=cbs.CBS_C128)
+    assert plan.layout()[0] == 2
+    x = case["u"].to(tdt).clone()
+    its, rel, stat = plan.iterate(x, case["s"].to(tdt), max_sweeps=BENCH_SWEEPS, rtol=1e-30,
+                                  check_every=BENCH_SWEEPS)
+    torch.cuda.synchronize()
+    assert all(k == BENCH_SWEEPS for k in its), its
+    assert all(st != cbs.INST_CONVERGED for st in stat)
+    for i, (gi, ref) in enumerate(zip(to_list(x, BENCH_SIZES), case["refs"])):
+        err, emax = rel_err(gi, ref), elem_err(gi, ref)
+        say(f"   n={BENCH_SIZES[i]}: rel err {err:.2e}, max cell err / rms {emax:.2e}")
+        assert err <= TOL[dtype] * 10
+        assert emax <= TOL[dtype] * 20
+    if dtype != cbs.CBS_C64:
+        plan.close()
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
 def test_helmholtz_residual(dtype):
     # r = s - A u with the pseudospectral A; the paper's rTol on a converged
     # CBS solution agrees with the oracle's physical residual
