@@ -339,6 +339,19 @@ template <class F, class = void>
 struct has_pre : std::false_type {};
 template <class F>
 struct has_pre<F, std::void_t<decltype(std::declval<F&>().pre(0, 0, 0))>> : std::true_type {};
+// ... and post(e, p, q), which the bridge calls for all elements after the
+// functor has run on every one of them: a functor can keep its stores there,
+// so that no load of a later element waits behind a store of an earlier one.
+// A functor may bound how many elements run before their post() calls with
+// a constant kPostGroup (fewer loads in flight, fewer registers).
+template <class F, class = void>
+struct has_post : std::false_type {};
+template <class F>
+struct has_post<F, std::void_t<decltype(std::declval<F&>().post(0, 0, 0))>> : std::true_type {};
+template <class F, int RAD, class = void>
+struct post_group : std::integral_constant<int, RAD> {};
+template <class F, int RAD>
+struct post_group<F, RAD, std::void_t<decltype(F::kPostGroup)>> : std::integral_constant<int, F::kPostGroup> {};
 
 // ---- one Stockham pass ----------------------------------------------------------
 //
@@ -497,8 +510,20 @@ __device__ __forceinline__ void fft_bridge_t(cpx<R>* buf, int t, bool active, TW
         // last pass of transform 1: k = j (j < NS), outputs at j + q NS
         tw_apply<RAD, D1>(v[p], w[p]);
         bfly<RAD, D1>(v[p]);
+        if constexpr (has_post<MID>::value) {
+          constexpr int G = post_group<MID, RAD>::value;
+          static_assert(RAD % G == 0, "post group");
 #pragma unroll
-        for (int q = 0; q < RAD; ++q) v[p][q] = call_mid<MID, R>(mid, j + q * NS, v[p][q], p, q);
+          for (int q0 = 0; q0 < RAD; q0 += G) {
+#pragma unroll
+            for (int q = q0; q < q0 + G; ++q) v[p][q] = call_mid<MID, R>(mid, j + q * NS, v[p][q], p, q);
+#pragma unroll
+            for (int q = q0; q < q0 + G; ++q) mid.post(j + q * NS, p, q);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < RAD; ++q) v[p][q] = call_mid<MID, R>(mid, j + q * NS, v[p][q], p, q);
+        }
         // first pass of transform 2 reads the same elements j + q N/RAD
         bfly<RAD, D2>(v[p]);
         const int o = j * RAD;

@@ -277,6 +277,40 @@ struct SweepMid {
   }
 };
 
+// The bridge step of the two halves of a fused NPBS step (MODE 3: r = z - u,
+// kept in out2; MODE 4: u_new = u + z + W^loc r, written, and the next step's
+// V u_new + s returned).  The results are stored by post(), after the
+// functor has run on all of the thread's elements, so the loads of every
+// element can be issued ahead of the first store.
+template <typename R, int PER, int RAD, int MODE>
+struct NpbsMid {
+  static constexpr int kPostGroup = RAD % 4 == 0 ? 4 : RAD;
+  const Params<R>& p;
+  const InstDesc& d;
+  long long rbase;
+  cpx<R> res[PER][RAD];  // r (MODE 3) or u_new (MODE 4), stored by post()
+  // __host__ __device__, like the lambdas the bridge otherwise takes, so that
+  // the bridge's compile-time checks for the call forms see them
+  __host__ __device__ __forceinline__ cpx<R> operator()(int e, cpx<R> z, int pp, int qq) {
+    const long long g = rbase + e;
+    const cpx<R> u = p.u[g];
+    if constexpr (MODE == 3) {
+      const cpx<R> rr = z - u;
+      res[pp][qq] = rr;
+      return rr;
+    } else {
+      const cpx<R> un = u + z + cmul(ld_or_zero(p.b, g), p.a[g]);
+      res[pp][qq] = un;
+      const Coef<R> c = coef(p, d, g);
+      return cmul(c.v, un) + ld_or_zero(p.s, g);
+    }
+  }
+  __host__ __device__ __forceinline__ void post(int e, int pp, int qq) {
+    if constexpr (MODE == 3) p.out2[rbase + e] = res[pp][qq];
+    else p.out[rbase + e] = res[pp][qq];
+  }
+};
+
 // MODE 0: prologue + forward rows -> spectral buffer;
 // MODE 1: spectral buffer -> inverse rows -> epilogue (with partial norms);
 // MODE 2: spectral buffer -> inverse rows -> sweep epilogue u += gamma r
@@ -327,7 +361,10 @@ __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, 
     };
     auto st2 = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
     if constexpr (plan_bridgeable(N)) {
-      fft_run2<R, N, T::TPF, 1, -1>(mine, t, active, p.tw, ld, mid, st2);
+      constexpr int RAD = plan_radix(N, 0);
+      constexpr int PER = (N / RAD + T::TPF - 1) / T::TPF;
+      NpbsMid<R, PER, RAD, MODE> bm{p, d, rbase};
+      fft_run2<R, N, T::TPF, 1, -1>(mine, t, active, p.tw, ld, bm, st2);
     } else {
       auto st = [&](int e, cpx<R> z) { mine[lds_pos(e)] = mid(e, z); };
       fft_run<R, N, T::TPF, 1, false, true>(mine, t, active, p.tw, ld, st);
