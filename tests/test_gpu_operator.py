@@ -124,6 +124,29 @@ def test_null_source_and_null_u():
     assert rel_err(to_list(gv, [64])[0], ref_gv) <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_sweeps_without_source(dtype):
+    # s = None in the fused sweep chain (u <- u + gamma (G(V u) - u)), on sizes
+    # whose rows take the register-bridged path (128, 192) and the two-run
+    # path (64, 288), element by element against the oracle with s = 0
+    sizes = [64, 128, 192, 288]
+    probs = [random_problem(n, seed=70 + i) for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    u, _ = _inputs(probs, dtype, seed=71)
+    x = u.clone()
+    plan.sweep(x, None, count=3)
+    torch.cuda.synchronize()
+    for i, (ki, ui, gi) in enumerate(zip(to_list(k2, sizes), to_list(u, sizes), to_list(x, sizes))):
+        ref = ui
+        zero = torch.zeros_like(ui)
+        for _ in range(3):
+            ref = O.cbs_sweep(ki, plan.k0sq[i], plan.eps[i], ref, zero)
+        err, emax = rel_err(gi, ref), elem_err(gi, ref)
+        say(f"[sweep without source] dtype={dtype} n={sizes[i]}: rel err {err:.2e}, max cell err / rms {emax:.2e}")
+        assert err <= TOL[dtype] * 10
+        assert emax <= TOL[dtype] * 20
+
+
 def test_single_fourier_mode_closed_form_on_gpu():
     # With V = 0 (k^2 = k0^2 + i eps) the apply is G s; for s a Fourier mode
     # (Nyquist included) the result is s / lambda in closed form.
