@@ -331,6 +331,31 @@ def time_to_solution(probs, plan_k2, sizes, k0sq, s_packed, rtol=1e-6, chunk=50,
     return out
 
 
+def apply_throughput(plan, sizes, s, calls=20):
+    """cbs_apply y = G(V u + s) on the batch, `calls` independent calls back
+    to back (three launches each; the two lanes of a large batch overlap one
+    lane's column pass with the other's row passes): Gcell * apply / s and the
+    fraction of the HBM roofline at 32 algorithmic bytes per cell."""
+    cells = sum(n * n for n in sizes)
+    g = torch.Generator(device="cpu").manual_seed(2027)
+    u = torch.complex(torch.randn(cells, generator=g), torch.randn(cells, generator=g)).to(torch.complex64).cuda()
+    y = plan.empty()
+    for _ in range(3):
+        plan.apply(u, s, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(calls):
+        plan.apply(u, s, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    achieved = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
+    return {"unit": "Gcell*apply/s", "value": cells / (ms * 1e-3) / 1e9, "ms_per_apply": ms, "calls": calls,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS}}
+
+
 def npbs_throughput(plan, sizes, s, steps=20):
     """NPBS steps with a linear Fourier layer of seeded random weights (the
     learned preconditioner's residual branch; two transform pairs per step)
@@ -813,6 +838,7 @@ def main():
             "working_set_bytes": 4 * 8 * cells,
         },
     }
+    line["apply"] = apply_throughput(plan, sizes, s)
     line["npbs_step"] = npbs_throughput(plan, sizes, s)
     if not args.no_layered:
         del plan
