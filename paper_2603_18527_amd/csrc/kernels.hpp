@@ -279,9 +279,10 @@ struct SweepMid {
 
 // The bridge step of the two halves of a fused NPBS step (MODE 3: r = z - u,
 // kept in out2; MODE 4: u_new = u + z + W^loc r, written, and the next step's
-// V u_new + s returned).  The results are stored by post(), after the
-// functor has run on all of the thread's elements, so the loads of every
-// element can be issued ahead of the first store.
+// V u_new + s returned).  The results are stored by post(), which the
+// bridge calls after each group of kPostGroup elements, so a group's loads
+// are issued ahead of its stores (all eight at once need more registers than
+// the latency they hide is worth).
 template <typename R, int PER, int RAD, int MODE>
 struct NpbsMid {
   static constexpr int kPostGroup = RAD % 4 == 0 ? 4 : RAD;
