@@ -442,8 +442,22 @@ def time_sweeps(plan, s, steps: int, warmup: int, chain_len: int, graph: bool = 
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     chain_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(nchains)]
+    # the same timed region repeated (outside the region the line reports):
+    # median, min and max over 10 runs of `steps` sweeps by events
+    reps = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _k in range(nchains):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1) / steps)
     return {"steps": steps, "chain": chain, "graph": graph, "wall_ms_per_sweep": wall * 1e3 / steps,
-            "event_ms_per_sweep": float(np.mean(chain_ms)) / chain}
+            "event_ms_per_sweep": float(np.mean(chain_ms)) / chain,
+            "repeats_ms_per_sweep": {"runs": len(reps), "median": float(np.median(reps)),
+                                     "min": float(np.min(reps)), "max": float(np.max(reps))}}
 
 
 def layered_leg(fgmres: bool = True, graph: bool = False):
@@ -831,6 +845,11 @@ def main():
             "chain_from_graph": st["graph"],
             "algorithmic_bytes_per_sweep": BYTES_PER_CELL * cells,
             "event_ms_per_sweep": ev_ms,
+            # 10 further runs of the same region (median, min, max), and the
+            # fraction at their median
+            "repeats_ms_per_sweep": st["repeats_ms_per_sweep"],
+            "frac_at_repeat_median": BYTES_PER_CELL * cells / (st["repeats_ms_per_sweep"]["median"] * 1e-3) / 1e9
+                                     / HBM_PEAK_GBS,
             # FETCH_SIZE / WRITE_SIZE count L2-to-fabric requests: Infinity-Cache
             # hits included, so these are not DRAM-only bytes
             "l2_fabric_bytes_per_cell": None if traffic is None else traffic / cells,
