@@ -240,6 +240,35 @@ def test_fgmres_one_step_on_an_eigenvector(dtype, sweeps):
     assert ev <= (1e-6 if dtype == cbs.CBS_C64 else 1e-12)
 
 
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+@pytest.mark.parametrize("solver", ["iterate", "fgmres"])
+def test_zero_right_hand_side_in_a_batch(dtype, solver):
+    # Degenerate instance: s = 0 from u = 0 is solved by u = 0 (G s = 0, so
+    # the Born residual's reference norm is zero).  Beside an ordinary
+    # instance in the same batch it must stop at once with u exactly zero and
+    # no NaN, while the other instance converges as usual.
+    probs = [random_problem(64, seed=90, source="point"), random_problem(128, seed=91, source="point")]
+    tdt = torch.complex64 if dtype == cbs.CBS_C64 else torch.complex128
+    plan, k2 = plan_for(probs, dtype, restart=20)
+    src = [np.zeros((64, 64), np.complex128), probs[1].source]
+    s = cbs.pack(src, tdt)
+    u = plan.zeros()
+    if solver == "iterate":
+        its, rel, stat = plan.iterate(u, s, max_sweeps=5000, rtol=1e-6, check_every=25)
+    else:
+        its, rel, stat = plan.fgmres(u, s, restart=20, sweeps=3, max_iters=2000, rtol=1e-6)
+    torch.cuda.synchronize()
+    say(f"[zero rhs] {solver} dtype={dtype}: iterations {its}, relres {rel}, status {stat}")
+    u0, u1 = cbs.unpack(u, [64, 128])
+    assert stat[0] == cbs.INST_CONVERGED and its[0] == 0 and rel[0] == 0.0
+    assert bool(torch.all(u0 == 0))
+    assert stat[1] == cbs.INST_CONVERGED and its[1] > 0
+    assert bool(torch.all(torch.isfinite(torch.view_as_real(u1))))
+    ev = _oracle_relres(to_list(k2, [64, 128])[1], plan.k0sq[1], plan.eps[1], to_list(u, [64, 128])[1],
+                        to_list(s, [64, 128])[1])
+    _bar(dtype, rel[1], ev)
+
+
 def test_fgmres_grf256_full_size():
     # 256x256 random-field medium, FGMRES(30) with 4 CBS sweeps.
     say("[fgmres grf256]")
