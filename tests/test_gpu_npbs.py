@@ -51,6 +51,34 @@ def test_npbs_steps_match_oracle(dtype):
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_npbs_steps_bench_sizes_two_lanes(dtype):
+    # the fused NPBS chain at the benchmark's scale: a batch of 2^21+ cells
+    # with every bridged size 128..1024 and 288, so the plan runs two lanes,
+    # element by element against the oracle over two steps
+    sizes = [1024, 1024, 512, 384, 288, 256, 192, 128]
+    assert sum(n * n for n in sizes) >= 1 << 21
+    probs = [random_problem(n, seed=760 + i, source="point") for i, n in enumerate(sizes)]
+    plan, k2 = plan_for(probs, dtype)
+    assert plan.layout()[0] == 2
+    tdt = TDT[dtype]
+    rng = np.random.default_rng(761)
+    u0 = [S.random_field_c(n, rng) for n in sizes]
+    wf, wl = _weights(sizes, 762)
+    u = cbs.pack(u0, tdt)
+    s = cbs.pack([p.source for p in probs], tdt)
+    plan.npbs_step(u, s, cbs.pack(wf, tdt), cbs.pack(wl, tdt), count=2)
+    torch.cuda.synchronize()
+    for i, (ki, ug) in enumerate(zip(to_list(k2, sizes), to_list(u, sizes))):
+        x = O.as_c(u0[i])
+        for _ in range(2):
+            x = O.npbs_step(ki, plan.k0sq[i], plan.eps[i], x, probs[i].source, wf[i], wl[i])
+        e, emax = rel_err(ug, x), elem_err(ug, x)
+        say(f"[npbs bench sizes] dtype={dtype} n={sizes[i]}: rel err {e:.2e}, max cell err / rms {emax:.2e}")
+        assert e <= TOL[dtype]
+        assert emax <= 10 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
 def test_npbs_with_gamma_is_the_cbs_sweep(dtype):
     # Sec. 4.1: M = gamma gives the CBS step
     sizes = [64, 128]
