@@ -215,12 +215,13 @@ def cpu_baseline(probs, budget_s: float = 12.0, budget_1t_s: float = 4.0, max_ro
     }
 
 
-def lone_sweep_us(k2_i, s_i, n, k0sq_i, use_graph=True, sweeps=2000, chunk=50):
+def lone_sweep_us(k2_i, s_i, n, k0sq_i, use_graph=True, sweeps=2000, chunk=50, dtype=None):
     """Microseconds per sweep of one instance run alone by cbs_iterate (chunks
     of `chunk` sweeps, replayed from a graph or launched directly), with a
-    tolerance no FP32 run reaches so that every sweep is run."""
+    tolerance no run reaches so that every sweep is run."""
     from paper_2603_18527_amd import cbs
-    plan = cbs.Plan(k2_i, [n], k0sq=[k0sq_i])
+    dtype = cbs.CBS_C64 if dtype is None else dtype
+    plan = cbs.Plan(k2_i, [n], k0sq=[k0sq_i], dtype=dtype)
     try:
         u = plan.zeros()
         plan.iterate(u, s_i, max_sweeps=chunk, rtol=1e-30, check_every=chunk, use_graph=use_graph)
@@ -238,6 +239,7 @@ def lone_sweep_us(k2_i, s_i, n, k0sq_i, use_graph=True, sweeps=2000, chunk=50):
 def tail_probe(probs):
     """Per-sweep cost of a lone instance of each grid size of the batch (the
     convergence tail of a batched solve runs one or two such instances)."""
+    import synthetic as S
     from paper_2603_18527_amd import cbs
     out = {}
     seen = set()
@@ -250,6 +252,16 @@ def tail_probe(probs):
         out[str(p.n)] = {"graph_us_per_sweep": lone_sweep_us(k2, s, p.n, p.k0sq, True),
                          "direct_us_per_sweep": lone_sweep_us(k2, s, p.n, p.k0sq, False)}
         print(f"# lone {p.n}^2: {out[str(p.n)]}", flush=True)
+    # the shape of the paper's own CBS timing (one 288^2 instance, 256^2
+    # interior and a 16-cell layer, random-field medium), in FP64 and FP32
+    q = S.grf_problem(n=288, layer=16)
+    row = {}
+    for name, dt, tdt in (("fp64", cbs.CBS_C128, torch.complex128), ("fp32", cbs.CBS_C64, torch.complex64)):
+        k2 = cbs.pack([q.k2], tdt)
+        s = cbs.pack([q.source], tdt)
+        row[name + "_graph_us_per_sweep"] = lone_sweep_us(k2, s, 288, q.k0sq, True, dtype=dt)
+    out["288_grf"] = row
+    print(f"# lone 288^2 random field: {row}", flush=True)
     return out
 
 
