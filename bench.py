@@ -123,8 +123,8 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
         "bytes_written": write,
         "bytes_per_sweep": sum(fetch.values()) + sum(write.values()),
         "commands": [
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- " + cmd,
-            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- " + cmd,
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/pmc_fetch -o fetch -- " + cmd,
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/pmc_write -o write -- " + cmd,
         ],
     }
     with open(out_path, "w") as f:
