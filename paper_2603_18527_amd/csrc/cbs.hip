@@ -1433,6 +1433,26 @@ template <typename R>
 cbs_status adjoint_impl(cbs_plan p, const void* um, const void* s, const void* lam_in,
                         void* lam_out, void* grad, hipStream_t st) {
   cpx<R>* r = static_cast<cpx<R>*>(p->d_t);
+  if (!p->dirichlet && !p->cdr) {
+    // periodic plans: both transform pairs in three launches, each
+    // workgroup transforming both fields; r never leaves the registers
+    Params<R> q = base_params<R>(p);
+    q.u = static_cast<const cpx<R>*>(um);
+    q.s = static_cast<const cpx<R>*>(s);
+    q.a = static_cast<const cpx<R>*>(lam_in);
+    q.out = static_cast<cpx<R>*>(lam_out);
+    q.out2 = static_cast<cpx<R>*>(grad);
+    q.inter2 = r;  // the second spectral field
+    q.dual = 1;
+    q.sym = SYM_GREEN;
+    q.partials = nullptr;
+    q.items = p->view->rows;
+    launch_row(5, p->view->nrows, st, q);
+    launch_cols(p, q, st);
+    launch_row(6, p->view->nrows, st, q);
+    HIPCHK(hipGetLastError());
+    return CBS_OK;
+  }
   {
     Params<R> q = base_params<R>(p);
     q.u = static_cast<const cpx<R>*>(um);

@@ -344,6 +344,51 @@ __device__ __forceinline__ void row_body(const Params<R>& p, const InstDesc& d, 
       const double s = block_sum(acc, red);
       if (tid == 0) p.partials[d.part_off + row0 / T::RPW] = s;
     }
+  } else if constexpr (MODE == 5) {
+    // the adjoint step's two forward row transforms (Sec. 4.2): V u + s, whose
+    // Green transform gives the Born residual r, into inter, and
+    // conj(gamma) lambda into inter2
+    auto ld_a = [&](int e) {
+      const long long g = rbase + e;
+      const Coef<R> c = coef(p, d, g);
+      return cmul(c.v, p.u[g]) + ld_or_zero(p.s, g);
+    };
+    auto st_a = [&](int e, cpx<R> v) { p.inter[rbase + e] = v; };
+    fft_run<R, N, T::TPF, -1, false, false>(mine, t, active, p.tw, ld_a, st_a);
+    __syncthreads();  // the second transform reuses the rows' LDS
+    auto ld_b = [&](int e) {
+      const long long g = rbase + e;
+      const Coef<R> c = coef(p, d, g);
+      return cmul(c.gamma_conj(), p.a[g]);
+    };
+    auto st_b = [&](int e, cpx<R> v) { p.inter2[rbase + e] = v; };
+    fft_run<R, N, T::TPF, -1, false, false>(mine, t, active, p.tw, ld_b, st_b);
+  } else if constexpr (MODE == 6) {
+    // inverse rows of both: r = z_r - u stays in registers (the last pass of
+    // both transforms gives each thread the same cells in the same slots),
+    // then the adjoint epilogue of z = G^H(conj(gamma) lambda):
+    // lambda_out = lambda + conj(V) z - conj(gamma) lambda,
+    // grad += (-i/eps) lambda conj(r) + z conj(u)
+    constexpr int RL = plan_radix(N, plan_passes(N) - 1);
+    constexpr int PERL = (N / RL + T::TPF - 1) / T::TPF;
+    cpx<R> rr[PERL][RL];
+    auto ld_a = [&](int e) { return p.inter[rbase + e]; };
+    auto st_a = [&](int e, cpx<R> z, int pp, int qq) { rr[pp][qq] = z - p.u[rbase + e]; };
+    fft_run<R, N, T::TPF, 1, false, false>(mine, t, active, p.tw, ld_a, st_a);
+    __syncthreads();  // the second transform reuses the rows' LDS
+    auto ld_b = [&](int e) { return p.inter2[rbase + e]; };
+    auto st_b = [&](int e, cpx<R> z, int pp, int qq) {
+      const long long g = rbase + e;
+      const Coef<R> c = coef(p, d, g);
+      const cpx<R> lam = p.a[g];
+      const cpx<R> r = rr[pp][qq];
+      const cpx<R> u = p.u[g];
+      p.out[g] = lam + cmulc(c.v, z) - cmul(c.gamma_conj(), lam);
+      const cpx<R> lr = cmul(lam, cconj(r));
+      const cpx<R> g0 = cpx<R>{lr.y * c.inv_eps, -lr.x * c.inv_eps};
+      p.out2[g] = p.out2[g] + g0 + cmul(z, cconj(u));
+    };
+    fft_run<R, N, T::TPF, 1, false, false>(mine, t, active, p.tw, ld_b, st_b);
   } else if constexpr (MODE == 3 || MODE == 4) {
     auto ld = [&](int e) { return p.inter[rbase + e]; };
     auto mid = [&](int e, cpx<R> z) {
@@ -439,6 +484,17 @@ __global__ __launch_bounds__(kThreads) void k_row_inv(Params<R> p) {
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row_sweep(Params<R> p) {
   row_dispatch<R, 2>(p);
+}
+
+// the adjoint step's forward / inverse rows over two fields (periodic plans)
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_adj_fwd(Params<R> p) {
+  row_dispatch<R, 5>(p);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_adj_inv(Params<R> p) {
+  row_dispatch<R, 6>(p);
 }
 
 template <typename R>
@@ -562,6 +618,23 @@ __device__ __forceinline__ void col_kernel_body(const Params<R>& p) {
 #undef CBS_COL_CASE
     default:
       break;
+  }
+  if (p.dual) {
+    // the adjoint step's second field: the conjugate Green symbol on inter2
+    __syncthreads();  // the second tile reuses the LDS
+    Params<R> q = p;
+    q.inter = p.inter2;
+    q.sym = SYM_GREEN_CONJ;
+    switch (d.n) {
+#define CBS_COL_CASE2(N) \
+  case N:                \
+    col_dispatch_n<R, N, T>(q, d, w.y, lds); \
+    break;
+      CBS_FOR_EACH_N(CBS_COL_CASE2)
+#undef CBS_COL_CASE2
+      default:
+        break;
+    }
   }
 }
 

@@ -20,8 +20,12 @@ void launch_row(int mode, int grid, hipStream_t st, const Params<float>& p) {
     hipLaunchKernelGGL(k_row_sweep<float>, dim3(grid), dim3(kThreads), 0, st, p);
   else if (mode == 3)
     hipLaunchKernelGGL(k_row_npbs_a<float>, dim3(grid), dim3(kThreads), 0, st, p);
-  else
+  else if (mode == 4)
     hipLaunchKernelGGL(k_row_npbs_b<float>, dim3(grid), dim3(kThreads), 0, st, p);
+  else if (mode == 5)
+    hipLaunchKernelGGL(k_row_adj_fwd<float>, dim3(grid), dim3(kThreads), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_row_adj_inv<float>, dim3(grid), dim3(kThreads), 0, st, p);
 }
 
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<float>& p) {

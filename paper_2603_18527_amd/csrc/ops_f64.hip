@@ -20,8 +20,12 @@ void launch_row(int mode, int grid, hipStream_t st, const Params<double>& p) {
     hipLaunchKernelGGL(k_row_sweep<double>, dim3(grid), dim3(kThreads), 0, st, p);
   else if (mode == 3)
     hipLaunchKernelGGL(k_row_npbs_a<double>, dim3(grid), dim3(kThreads), 0, st, p);
-  else
+  else if (mode == 4)
     hipLaunchKernelGGL(k_row_npbs_b<double>, dim3(grid), dim3(kThreads), 0, st, p);
+  else if (mode == 5)
+    hipLaunchKernelGGL(k_row_adj_fwd<double>, dim3(grid), dim3(kThreads), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_row_adj_inv<double>, dim3(grid), dim3(kThreads), 0, st, p);
 }
 
 void launch_col(int grid, size_t lds_bytes, hipStream_t st, const Params<double>& p) {

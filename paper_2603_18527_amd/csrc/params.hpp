@@ -93,6 +93,11 @@ struct Params {
   const cpx<R>* table;  // SYM_TABLE: spectral weights on the DFT bins (packed like fields)
   const double* mu;     // Dirichlet plans: M^2 sin^2(pi p / M) per transform length M
   cpx<R>* inter;
+  // dual != 0 (the adjoint step of periodic plans): each launch also
+  // transforms a second field, spectral buffer inter2 (rows: MODE 5 / 6;
+  // columns: the conjugate Green symbol)
+  cpx<R>* inter2;
+  int dual;
   cpx<R>* out;
   cpx<R>* out2;
   cpx<float>* out_narrow;
