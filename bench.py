@@ -71,7 +71,9 @@ def traffic_record(fetch_csv: str, write_csv: str, workload: str, out_path: str)
     autotuner).  Only dispatches from the first k_row_fwd after that copy to
     the last k_row_inv before the NPBS steps count (the autotuner's races
     before and the NPBS steps after launch the sweep kernels on the lanes'
-    grids too; the lanes join before the NPBS steps start).  In between
+    grids too; the lanes join before the NPBS steps start; the cbs_apply calls
+    in the window launch on the whole batch's grids, which the count below
+    leaves out).  In between
     the run makes, per lane
     (two lanes, or one when the batch is not split), 62 column-pass (k_col or
     k_col_wide, whichever the autotuner picked) and 60 k_row_sweep dispatches
@@ -417,7 +419,7 @@ def fp64_physical_relres(p, plan, u, s):
     return float(torch.sqrt(hn[0]) / torch.linalg.vector_norm(s.to(c128)))
 
 
-def time_sweeps(plan, s, steps: int, warmup: int, chain_len: int, graph: bool = True):
+def time_sweeps(plan, s, steps: int, warmup: int, chain_len: int, graph: bool = True, repeats: int = 10):
     """`steps` CBS sweeps in place on a zero field, as chains of `chain_len`
     fused sweeps (one cbs_sweep call each), after `warmup` untimed sweeps.
     With graph=True the chain is captured once into a HIP graph during the
@@ -457,7 +459,7 @@ def time_sweeps(plan, s, steps: int, warmup: int, chain_len: int, graph: bool = 
     # the same timed region repeated (outside the region the line reports):
     # median, min and max over 10 runs of `steps` sweeps by events
     reps = []
-    for _ in range(10):
+    for _ in range(repeats):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
@@ -468,8 +470,9 @@ def time_sweeps(plan, s, steps: int, warmup: int, chain_len: int, graph: bool = 
         reps.append(e0.elapsed_time(e1) / steps)
     return {"steps": steps, "chain": chain, "graph": graph, "wall_ms_per_sweep": wall * 1e3 / steps,
             "event_ms_per_sweep": float(np.mean(chain_ms)) / chain,
-            "repeats_ms_per_sweep": {"runs": len(reps), "median": float(np.median(reps)),
-                                     "min": float(np.min(reps)), "max": float(np.max(reps))}}
+            "repeats_ms_per_sweep": None if not reps else
+            {"runs": len(reps), "median": float(np.median(reps)), "min": float(np.min(reps)),
+             "max": float(np.max(reps))}}
 
 
 def layered_leg(fgmres: bool = True, graph: bool = False):
@@ -823,7 +826,10 @@ def main():
           f"{tile_by_size}", flush=True)
 
     use_graph = args.graph and not args.no_graph
-    st = time_sweeps(plan, s, args.steps, args.warmup, args.chain, graph=use_graph)
+    # the counter runs (--calib-copy) count the dispatches of one timed chain
+    # per lane, so they skip the repeated runs
+    st = time_sweeps(plan, s, args.steps, args.warmup, args.chain, graph=use_graph,
+                     repeats=0 if args.calib_copy else 10)
     ms_step = st["wall_ms_per_sweep"]
     ev_ms = st["event_ms_per_sweep"]
     value = cells / (ms_step * 1e-3) / 1e9
@@ -860,8 +866,8 @@ def main():
             # 10 further runs of the same region (median, min, max), and the
             # fraction at their median
             "repeats_ms_per_sweep": st["repeats_ms_per_sweep"],
-            "frac_at_repeat_median": BYTES_PER_CELL * cells / (st["repeats_ms_per_sweep"]["median"] * 1e-3) / 1e9
-                                     / HBM_PEAK_GBS,
+            "frac_at_repeat_median": None if st["repeats_ms_per_sweep"] is None else
+            BYTES_PER_CELL * cells / (st["repeats_ms_per_sweep"]["median"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             # FETCH_SIZE / WRITE_SIZE count L2-to-fabric requests: Infinity-Cache
             # hits included, so these are not DRAM-only bytes
             "l2_fabric_bytes_per_cell": None if traffic is None else traffic / cells,
