@@ -668,11 +668,7 @@ def run_suite(args):
     plan = cbs.Plan(k2, sizes, k0sq=[q.k0sq for q in probs])
 
     def fwd_bwd():
-        us = [u0.clone()]
-        for _ in range(8):
-            x = us[-1].clone()
-            plan.sweep(x, s)
-            us.append(x)
+        us = plan.sweep_checkpoints(u0, s, 8)   # u_0..u_8, one fused chain
         loss, lam, grad = plan.loss_seed(us[-1], s, True)
         for m in range(7, -1, -1):
             plan.adjoint_step(us[m], s, lam, lam, grad)

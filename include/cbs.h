@@ -253,6 +253,20 @@ cbs_status cbs_residual(cbs_plan plan, const void* u, const void* s, const void*
 cbs_status cbs_sweep(cbs_plan plan, void* u, const void* s, int count, double* norm2, void* stream);
 
 /*
+ * cbs_sweep_checkpoints -- `count` CBS steps u_k = u_{k-1} + gamma (G (V
+ *   u_{k-1} + s) - u_{k-1}) (Sec. 3.1, Eq. CBS) keeping every iterate: the
+ *   checkpoints of the unrolled loss (Sec. 4.2) that cbs_adjoint_step reads
+ *   back.  The sweeps are fused as in cbs_sweep (two launches per sweep).
+ *   u_all  DEVICE, count + 1 packed fields back to back, field k at element
+ *          k * cbs_plan_cells: field 0 holds u_0 (read), fields 1..count
+ *          receive u_1..u_count.  Owned by the caller.
+ *   s      nullable (zero); must not lie inside u_all.
+ *   count in [1, 1e6].  Not for convection-diffusion-reaction or undamped
+ *   plans (CBS_ERR_ARG).  Stream-ordered.
+ */
+cbs_status cbs_sweep_checkpoints(cbs_plan plan, void* u_all, const void* s, int count, void* stream);
+
+/*
  * cbs_npbs_step -- `count` NPBS steps in place (Sec. 4.1, Eq. npbs_integral)
  *   with the linear Fourier layer of App. E (Eq. lfl) as the preconditioner:
  *     r = G(V u + s) - u,   u <- u + F^-1(wf * F r) + wloc * r

@@ -55,6 +55,7 @@ SIGNATURES = {
     "cbs_apply": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "cbs_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_sweep": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "cbs_sweep_checkpoints": (_i32, [_vp, _vp, _vp, _i32, _vp]),
     "cbs_npbs_step": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "cbs_helmholtz_residual": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cbs_relres": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
@@ -352,6 +353,15 @@ class Plan:
                                 int(count), _ptr(n2), self._st(stream)))
         return n2
 
+    def sweep_checkpoints(self, u0, s, count, stream=None):
+        """cbs_sweep_checkpoints: (count + 1, cells) tensor of u_0..u_count."""
+        u0 = self._field(u0, "u0")
+        u_all = torch.empty((int(count) + 1, self.cells), dtype=self.tdtype, device="cuda")
+        u_all[0].copy_(u0)
+        _check(load().cbs_sweep_checkpoints(self._h, _ptr(u_all), _ptr(self._field(s, "s")), int(count),
+                                            self._st(stream)))
+        return u_all
+
     def npbs_step(self, u, s, wf, wloc=None, count=1, stream=None):
         """count NPBS steps in place with the linear Fourier layer
         M(r) = F^-1(wf * F r) + wloc * r (wf packed per instance on the DFT bins)."""
@@ -578,11 +588,12 @@ class BornResidualLoss(torch.autograd.Function):
     def forward(ctx, u0, k2, s, sizes, steps, weight, k0sq, eps):
         dtype = CBS_C128 if k2.dtype == torch.complex128 else CBS_C64
         plan = Plan(k2.detach(), sizes, k0sq=k0sq, eps=eps, dtype=dtype)
-        us = [u0.detach().clone()]
-        for _ in range(int(steps)):
-            u = us[-1].clone()
-            plan.sweep(u, s)
-            us.append(u)
+        if int(steps) > 0:
+            # one fused chain that keeps every iterate (cbs_sweep_checkpoints)
+            u_all = plan.sweep_checkpoints(u0.detach(), s, int(steps))
+            us = [u_all[k] for k in range(int(steps) + 1)]
+        else:
+            us = [u0.detach().clone()]
         loss, lam, grad = plan.loss_seed(us[-1], s, weight)
         ctx.plan = plan
         ctx.us = us

@@ -631,6 +631,31 @@ cbs_status sweep_impl(cbs_plan p, void* u, const void* s, int count, double* nor
   return CBS_OK;
 }
 
+// `count` sweeps from field 0 of u_all, iterate k into field k: the chain of
+// run_sweeps with the update of step k reading field k - 1 and writing field k.
+template <typename R>
+cbs_status sweep_ckpt_impl(cbs_plan p, void* u_all, const void* s, int count, hipStream_t st) {
+  cpx<R>* f = static_cast<cpx<R>*>(u_all);
+  const long long cells = p->cells;
+  Params<R> q = base_params<R>(p);
+  q.s = static_cast<const cpx<R>*>(s);
+  q.epi = EPI_SWEEP;
+  q.partials = nullptr;
+  return issue_chain(p, st, count + 1, [&](int k, hipStream_t ls, const cbs_plan_s::Items& it) {
+    Params<R> c = q;
+    c.items = it.rows;
+    if (k == 0) {
+      c.u = f;
+      launch_row(0, it.nrows, ls, c);
+      return;
+    }
+    c.u = f + (long long)(k - 1) * cells;
+    c.out = f + (long long)k * cells;
+    launch_cols(p, c, ls, it);
+    launch_row(k < count ? 2 : 1, it.nrows, ls, c);
+  });
+}
+
 // The FP64 residual of the FP64 iterate (narrowed into c) and the status
 // decision of every instance not yet final.
 template <typename R>
@@ -2311,6 +2336,21 @@ cbs_status cbs_npbs_step(cbs_plan p, void* u, const void* s, const void* wf, con
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->dtype == CBS_C64) return npbs_impl<float>(p, u, s, wf, wloc, count, st);
   return npbs_impl<double>(p, u, s, wf, wloc, count, st);
+}
+
+cbs_status cbs_sweep_checkpoints(cbs_plan p, void* u_all, const void* s, int count, void* stream) {
+  if (p && p->cdr)
+    return fail(CBS_ERR_ARG, "cbs_sweep_checkpoints is not available for convection-diffusion-reaction plans");
+  if (!p || !u_all) return fail(CBS_ERR_ARG, "plan or u_all is NULL");
+  if (count < 1 || count > 1000000) return fail(CBS_ERR_ARG, "count must be in [1, 1e6]");
+  if (p->undamped) return fail(CBS_ERR_ARG, kNoGamma);
+  const size_t bytes = size_t(p->cells) * p->op_elem() * (size_t(count) + 1);
+  const char* lo = static_cast<const char*>(u_all);
+  const char* sp = static_cast<const char*>(s);
+  if (sp && sp >= lo && sp < lo + bytes) return fail(CBS_ERR_ARG, "s must not lie inside u_all");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->dtype == CBS_C64) return sweep_ckpt_impl<float>(p, u_all, s, count, st);
+  return sweep_ckpt_impl<double>(p, u_all, s, count, st);
 }
 
 cbs_status cbs_sweep(cbs_plan p, void* u, const void* s, int count, double* norm2, void* stream) {

@@ -345,6 +345,46 @@ def test_sweep_chain_bench_path(bench_path_case, dtype):
 
 
 @pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_sweep_checkpoints_bench_path(bench_path_case, dtype):
+    # cbs_sweep_checkpoints on the same batch (two lanes): the last iterate is
+    # bitwise the fused chain of cbs_sweep, and matches the oracle's sweeps
+    # element by element; the earlier ones agree with shorter chains to
+    # rounding (the chain's last sweep there ends in the inverse-row
+    # epilogue instead of the fused update)
+    case = bench_path_case
+    tdt = TDT[dtype]
+    if dtype == cbs.CBS_C64:
+        plan = case["plan32"]
+    else:
+        plan = cbs.Plan(case["k2"].to(torch.complex128), BENCH_SIZES, k0sq=case["k0sq"],
+                        dtype=cbs.CBS_C128)
+    assert plan.layout()[0] == 2
+    u0 = case["u"].to(tdt)
+    s = case["s"].to(tdt)
+    u_all = plan.sweep_checkpoints(u0, s, BENCH_SWEEPS)
+    x = u0.clone()
+    plan.sweep(x, s, count=BENCH_SWEEPS)
+    torch.cuda.synchronize()
+    assert torch.equal(u_all[0], u0)
+    assert torch.equal(u_all[BENCH_SWEEPS], x)
+    for i, (gi, ref) in enumerate(zip(to_list(u_all[BENCH_SWEEPS], BENCH_SIZES), case["refs"])):
+        assert rel_err(gi, ref) <= TOL[dtype] * 10
+        assert elem_err(gi, ref) <= TOL[dtype] * 20
+    for k in range(1, BENCH_SWEEPS):
+        y = u0.clone()
+        plan.sweep(y, s, count=k)
+        torch.cuda.synchronize()
+        e = rel_err(u_all[k].cpu(), y.cpu())
+        say(f"[sweep checkpoints] dtype={dtype} k={k}: against a chain of {k}: {e:.1e}")
+        assert e <= (1e-6 if dtype == cbs.CBS_C64 else 1e-14)
+    lib = cbs.load()
+    assert lib.cbs_sweep_checkpoints(plan._h, u_all.data_ptr(), s.data_ptr(), 0, None) == cbs.CBS_ERR_ARG
+    assert lib.cbs_sweep_checkpoints(plan._h, u_all.data_ptr(), u_all[1].data_ptr(), 1, None) == cbs.CBS_ERR_ARG
+    if dtype != cbs.CBS_C64:
+        plan.close()
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
 def test_iterate_chunk_bench_path(bench_path_case, dtype):
     # cbs_iterate's chunk on the same batch (two lanes): the FP64 residual
     # r0 = G(V u0 + s) - u0, then sweeps of the correction equation
