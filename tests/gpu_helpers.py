@@ -50,6 +50,15 @@ def elem_err(a, b):
     return float(torch.max(torch.abs(a - b))) / rms
 
 
+def peak_err(a, b):
+    """Largest per-cell error relative to the field's peak: max|a - b| / max|b|
+    (the bar for fields whose peak sits far above their RMS, where rounding
+    errors follow the local magnitude)."""
+    a = torch.as_tensor(a).to(torch.complex128)
+    b = torch.as_tensor(b).to(torch.complex128)
+    return float(torch.max(torch.abs(a - b))) / float(torch.max(torch.abs(b)))
+
+
 def random_problem(n, seed, layer=None, cmax=2.5, ppw=8.0, source="random"):
     rng = np.random.default_rng(seed)
     layer = max(1, n // 8) if layer is None else layer

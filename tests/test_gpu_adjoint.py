@@ -12,6 +12,14 @@ cbs_adjoint_step, and the BornResidualLoss autograd Function).
   loss on 32 random entries (16 of u0, real and imaginary parts, and 16 of
   Re k^2) against the FP64 GPU adjoint; and the FP32 adjoint against the
   FP64 one.
+* The solver suite's forward-backward (the same 16 x 256^2 batch, K = 8,
+  W = gamma, inputs rounded to FP32 once): one checkpointing chain
+  (cbs_sweep_checkpoints), the seed, then the fused adjoint steps; every
+  instance against the oracle's autograd gradient, in L2 and per cell
+  (relative to the field's peak).
+* Every register-bridged row schedule of the fused adjoint (1024, 512, 384,
+  256, 192, 128, and 288) in one batch, K = 3, W = gamma and physical,
+  against the oracle.
 """
 import numpy as np
 import pytest
@@ -20,7 +28,7 @@ import torch
 import oracle as O
 import synthetic as S
 from paper_2603_18527_amd import cbs
-from gpu_helpers import rel_err, say, to_list
+from gpu_helpers import peak_err, random_problem, rel_err, say, to_list
 
 pytestmark = pytest.mark.gpu
 
@@ -163,6 +171,75 @@ def test_full_size_finite_differences_and_fp32_adjoint():
         assert abs(r1a - an) <= 1e-4 * abs(an) + noise, (t, r1a, an)
         assert abs(rich - an) <= 1e-7 * abs(an) + noise, (t, rich, an, noise)
     say(f"   32 central differences: worst Richardson rel err {worst:.2e}")
+
+
+# bars against the FP64 oracle, the same for the relative L2 error and for
+# every cell's error relative to the field's peak (max|g - g_ref| <=
+# tol max|g_ref|): the FP32 budget is the one of the 32x32 case.  The gradient
+# fields peak 9-92 times above their RMS (point sources, the absorbing
+# layer's gamma), and their FP32 rounding errors follow the local magnitude:
+# per cell 1-2e-6 of the peak, as in L2.
+ADJ_TOL = {cbs.CBS_C64: 2e-5, cbs.CBS_C128: 1e-10}
+
+
+def _checkpointed(plan, u0, s, steps, weight):
+    # the order of the solver suite's forward-backward
+    us = plan.sweep_checkpoints(u0, s, steps)
+    loss, lam, grad = plan.loss_seed(us[steps], s, weight)
+    for m in range(steps - 1, -1, -1):
+        plan.adjoint_step(us[m], s, lam, lam, grad)
+    torch.cuda.synchronize()
+    return loss.cpu(), lam, grad
+
+
+def _against_oracle(plan, k2, u0, s, lam, grad, loss, sizes, steps, weight, dtype, label):
+    tol = ADJ_TOL[dtype]
+    for i, (ki, ui, si, li, gi) in enumerate(zip(to_list(k2, sizes), to_list(u0, sizes), to_list(s, sizes),
+                                                 to_list(lam, sizes), to_list(grad, sizes))):
+        val, gu, gk = O.loss_and_grad(ki, plan.k0sq[i], plan.eps[i], ui, si, steps, weight)
+        el = abs(float(loss[i]) - val) / val
+        eu, ek = rel_err(li, gu), rel_err(gi, gk)
+        pu, pk = peak_err(li, gu), peak_err(gi, gk)
+        say(f"   {label} instance {i} (n={sizes[i]}): loss {el:.1e} du0 {eu:.1e}/{pu:.1e} "
+            f"dk2 {ek:.1e}/{pk:.1e} (L2/per cell of the peak)")
+        assert el <= tol and eu <= tol and ek <= tol
+        assert pu <= tol and pk <= tol
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+def test_adjoint_suite_workload_matches_oracle(dtype):
+    say(f"[adjoint 16x256^2 vs oracle] dtype={dtype}")
+    probs, u0s, ss = S.diff_batch()
+    sizes = [p.n for p in probs]
+    tdt = TDT[dtype]
+    # inputs rounded to complex64 once: both precisions and the oracle see the same values
+    k2 = cbs.pack([p.k2 for p in probs], torch.complex64)
+    u0 = cbs.pack(u0s, torch.complex64)
+    s = cbs.pack(ss, torch.complex64)
+    plan = cbs.Plan(k2.to(tdt), sizes, k0sq=[p.k0sq for p in probs], dtype=dtype)
+    loss, lam, grad = _checkpointed(plan, u0.to(tdt), s.to(tdt), 8, "gamma")
+    _against_oracle(plan, k2, u0, s, lam, grad, loss, sizes, 8, "gamma", dtype, "diff16")
+    plan.close()
+
+
+BRIDGED_SIZES = [1024, 512, 384, 288, 256, 192, 128]
+
+
+@pytest.mark.parametrize("dtype", [cbs.CBS_C64, cbs.CBS_C128])
+@pytest.mark.parametrize("weight", ["gamma", "physical"])
+def test_adjoint_bridged_sizes_match_oracle(dtype, weight):
+    say(f"[adjoint sizes {BRIDGED_SIZES} vs oracle] dtype={dtype} weight={weight}")
+    probs = [random_problem(n, seed=2600 + i, source="point", cmax=1.5 + 0.2 * i, ppw=6.0 + i)
+             for i, n in enumerate(BRIDGED_SIZES)]
+    rng = np.random.default_rng(2601)
+    tdt = TDT[dtype]
+    k2 = cbs.pack([p.k2 for p in probs], torch.complex64)
+    u0 = cbs.pack([S.random_field_c(p.n, rng) for p in probs], torch.complex64)
+    s = cbs.pack([p.source for p in probs], torch.complex64)
+    plan = cbs.Plan(k2.to(tdt), BRIDGED_SIZES, k0sq=[p.k0sq for p in probs], dtype=dtype)
+    loss, lam, grad = _checkpointed(plan, u0.to(tdt), s.to(tdt), 3, weight)
+    _against_oracle(plan, k2, u0, s, lam, grad, loss, BRIDGED_SIZES, 3, weight, dtype, "bridged")
+    plan.close()
 
 
 def test_loss_seed_rejects_unknown_weight():
