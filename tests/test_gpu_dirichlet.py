@@ -13,7 +13,7 @@ import torch
 import oracle as O
 import synthetic as S
 from paper_2603_18527_amd import cbs
-from gpu_helpers import rel_err, say
+from gpu_helpers import peak_err, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -241,9 +241,11 @@ def test_dirichlet_tile_widths_and_autotune(which):
                 assert c in allowed[n]
 
 
-def test_dirichlet_lanes_bitwise():
+def test_dirichlet_lanes_bitwise_and_oracle():
     # 2,219,018 cells, above the 2^21 at which a batch splits into two lanes:
-    # lanes and one stream give bitwise the same sweeps and stationary solve
+    # lanes and one stream give bitwise the same sweeps and stationary solve,
+    # and the lanes' sweeps match the oracle's element by element at the
+    # largest Dirichlet size (511, transforms of length 1024) and at 255
     sizes = [511] * 8 + [255] * 2
     assert sum(n * n for n in sizes) >= 1 << 21
     k2, src, u0 = _media(sizes, 860)
@@ -260,6 +262,27 @@ def test_dirichlet_lanes_bitwise():
     nb = single.sweep(ub, s, count=3, norms=True)
     torch.cuda.synchronize()
     assert torch.equal(ua, ub) and torch.equal(na, nb)
+    # The oracle sees the FP32-rounded inputs of the plan.  These weak
+    # contrasts make the sweeps ill-conditioned for FP32: V = k^2 - k0^2 is
+    # formed from values of size k0^2 ~ 100 while |V| <= eps (0.08 to 1.4
+    # here), so an FP32 rounding of size u32 k0^2 is a relative error of
+    # u32 kappa in V and in gamma = iV/eps, kappa = k0^2 / eps (62 to 1230);
+    # the oracle's own three sweeps move by 1.5e-7 kappa when V is shifted by
+    # half an FP32 ulp of k0^2.  Bar: 1e-5 + 2 u32 kappa per sweep.
+    got = _unpack(ua, sizes)
+    r32 = _unpack(cbs.pack(k2, torch.complex64), sizes)
+    uu32 = _unpack(u, sizes)
+    s32 = _unpack(s, sizes)
+    for i in (0, 7, 8, 9):
+        x = uu32[i]
+        for _ in range(3):
+            x = O.cbs_sweep_dirichlet(r32[i].real.numpy(), lanes.k0sq[i], lanes.eps[i], x, s32[i])
+        kappa = lanes.k0sq[i] / lanes.eps[i]
+        bar = TOL[cbs.CBS_C64] + 2 * 2.0 ** -24 * kappa * 3
+        e, ep = rel_err(got[i], x), peak_err(got[i], x)
+        say(f"[dirichlet lanes] n={sizes[i]} kappa={kappa:.0f}: 3 sweeps against the oracle {e:.1e} "
+            f"(per cell of the peak {ep:.1e}; bar {bar:.1e})")
+        assert e <= bar and ep <= bar
     ua, ub = lanes.zeros(), single.zeros()
     # the Born residual of these closed-cavity problems drops to ~1e-2 within
     # ~100 sweeps and then decays slowly: a loose tolerance spreads the counts
