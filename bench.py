@@ -588,8 +588,10 @@ def run_suite(args):
     blob64 CBS, grf256 FGMRES(30)+CBS(4) and CBS, ragged64 FGMRES batched,
     diff16 adjoint, layered1024 FGMRES(50)+CBS(4) in FP32 vs an FP64 GPU run;
     the Dirichlet (DST-I) Newton-system batch newton64 (damped reference with
-    FGMRES + CBS sweeps, and the undamped reference with GMRES); and the
-    convection-diffusion-reaction batch cdr64 (apply and R^H e throughput).
+    FGMRES + CBS sweeps, and the undamped reference with GMRES); the DST-I
+    path at its largest size (9 x 511^2) beside a periodic 9 x 512^2 batch;
+    and the convection-diffusion-reaction batch cdr64 (apply and R^H e
+    throughput).
     Accuracy figures come from FP64 plans of the same problems on the GPU
     (parity with the FP64 CPU oracle is the test suite's job)."""
     import synthetic as S
@@ -745,6 +747,34 @@ def run_suite(args):
         undamped_gmres20=dict(seconds=dtu, max_iterations=max(itu), max_relres=max(relu),
                               all_converged=all(x == 1 for x in stu)))
     print("# suite newton64 done", flush=True)
+    # 7. dirichlet511: the DST-I path at its largest size, 9 x 511^2 interior
+    #    points (transforms of length 1024 on the odd extension), FP32 apply and
+    #    fused-sweep throughput against the 32 algorithmic B/cell of a sweep,
+    #    beside a periodic 9 x 512^2 batch of the same media recipe
+    #    (k^2 = 100 + 60 zeta, zeta a random field of correlation n/8); nine
+    #    instances put both batches above the two-lane threshold of 2^21 cells
+    big = {}
+    for name, n, dirichlet in (("dirichlet_511", 511, True), ("periodic_512", 512, False)):
+        k2l, srcl = [], []
+        for i in range(9):
+            rng = S.rng_for(7, i)
+            k2l.append(100.0 + 60.0 * S.gaussian_random_field(n, n / 8, rng))
+            srcl.append(S.random_field_c(n, rng))
+        sizes = [n] * 9
+        cells = 9 * n * n
+        plan = cbs.Plan(cbs.pack(k2l, torch.complex64), sizes, dirichlet=dirichlet)
+        s = cbs.pack(srcl, torch.complex64)
+        x = plan.zeros()
+        plan.apply(x, s)
+        dta = min(timed(lambda: [plan.apply(x, s) for _ in range(20)])[1] for _ in range(3)) / 20
+        plan.sweep(x, s, count=10)
+        dts = min(timed(lambda: plan.sweep(x, s, count=50))[1] for _ in range(3)) / 50
+        big[name] = dict(cells=cells, lanes=plan.layout()[0], apply_us=dta * 1e6, apply_gcell_s=_gcell(cells, 1, dta),
+                         sweep_us=dts * 1e6, sweep_gcell_s=_gcell(cells, 1, dts),
+                         sweep_frac_of_8tbs_by_32b=cells * 32 / dts / 8e12)
+        del plan
+    res["dirichlet511_vs_periodic512"] = big
+    print("# suite dirichlet511 done", flush=True)
     res["cdr64_apply"] = cdr_throughput()
     print("# suite cdr64 done", flush=True)
     return res
