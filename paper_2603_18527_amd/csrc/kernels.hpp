@@ -34,6 +34,17 @@ __device__ __forceinline__ cpx<R> ld_or_zero(const cpx<R>* p, long long i) {
   return p ? p[i] : cpx<R>{R(0), R(0)};
 }
 
+// Re V = Re k^2 - k0^2.  In FP32, k0^2 enters as two parts (hi, its rounding;
+// lo, the rest): Re k^2 - hi is exact while Re k^2 lies within a factor of two
+// of hi, so Re V carries one rounding of its own size instead of one of the
+// size of k0^2, which relative to |V| <= eps would be k0^2 / eps times larger.
+template <typename R>
+__device__ __forceinline__ R re_v(R kx, double k0sq) {
+  const R hi = R(k0sq);
+  if constexpr (sizeof(R) == 4) return (kx - hi) - R(k0sq - double(hi));
+  return kx - hi;
+}
+
 template <typename R>
 struct Coef {
   cpx<R> v;    // V = k^2 - k0^2 - i eps
@@ -45,7 +56,7 @@ struct Coef {
 template <typename R>
 __device__ __forceinline__ Coef<R> coef_of(const InstDesc& d, cpx<R> k) {
   Coef<R> c;
-  c.v = {k.x - R(d.k0sq), k.y - R(d.eps)};
+  c.v = {re_v(k.x, d.k0sq), k.y - R(d.eps)};
   c.inv_eps = R(1.0 / d.eps);
   return c;
 }
@@ -54,7 +65,7 @@ template <typename R>
 __device__ __forceinline__ Coef<R> coef(const Params<R>& p, const InstDesc& d, long long i) {
   const cpx<R> k = p.k2[i];
   Coef<R> c;
-  c.v = {k.x - R(d.k0sq), k.y - R(d.eps)};
+  c.v = {re_v(k.x, d.k0sq), k.y - R(d.eps)};
   c.inv_eps = R(1.0 / d.eps);
   return c;
 }
@@ -662,7 +673,7 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
   const long long base = d.off + (long long)w.y * n;
   const int cnt = nrows * n;
   const R ie = R(1.0 / d.eps);
-  const R k0 = R(d.k0sq), ep = R(d.eps);
+  const R ep = R(d.eps);
   const double sc = (p.op == PW_SCALE64) ? p.scale[w.x]
                     : (p.op == PW_SCALE)  ? p.factor * (p.scale ? p.scale[w.x] : 1.0)
                     : (p.op == PW_FIRST64 || p.op == PW_NARROW) ? (p.scale ? p.scale[w.x] : 1.0)
@@ -681,7 +692,7 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(PwParams<R> p) {
           if (p.c_out) p.c_out[i] = v;
         }
         const cpx<R> k = p.k2[i];
-        const cpx<R> g{-(k.y - ep) * ie, (k.x - k0) * ie};  // i V / eps
+        const cpx<R> g{-(k.y - ep) * ie, re_v(k.x, d.k0sq) * ie};  // i V / eps
         p.e_out[i] = cmul(g, v);
         break;
       }

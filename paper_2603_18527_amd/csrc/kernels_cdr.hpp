@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_cdr_split(const InstDesc* inst, co
   const int cnt = min(d.rpw, d.n - w.y) * d.n;
   for (int j = threadIdx.x; j < cnt; j += kThreads) {
     const cpx<R> a = c1[base + j], b = c2[base + j];
-    c1[base + j] = cpx<R>{a.x - R(d.k0sq), a.y - R(d.eps)};
+    c1[base + j] = cpx<R>{re_v(a.x, d.k0sq), a.y - R(d.eps)};
     c2[base + j] = cpx<R>{b.x - R(d.vx0), b.y - R(d.vy0)};
   }
 }
